@@ -1,0 +1,245 @@
+/*
+ * icl.h - C ABI of the MI355X (gfx950) stencil image library.
+ *
+ * The library implements the per-pixel neighbourhood kernels that the ImageCL
+ * paper (Falch & Elster, arXiv 1605.06399) generates and auto-tunes: a kernel is
+ * the work of one logical thread per pixel of an Image grid, reading a bounded
+ * neighbourhood with a boundary condition (Section 5), launched from a
+ * standalone host function (Section 5.1).  Each entry point below is such a host
+ * function for one stencil; the variant it launches (work-group shape, pixels
+ * per thread, LDS staging or direct loads, unrolling: the Table 1 parameters)
+ * is chosen per device by the library's auto-tuner (Section 4), or forced.
+ *
+ * Conventions shared by every entry point
+ *  - Images are 2-D, row-major, x (the paper's idx) fastest.  Pixel (x, y) of an
+ *    image lives at  base + y * pitch + x * elem_size ; pitches are in BYTES and
+ *    must satisfy pitch >= width * elem_size and pitch % elem_size == 0.
+ *  - Boundary: clamped (Section 5, Fig. 3a): a read outside the image returns
+ *    the closest pixel inside, i.e. x -> min(max(x, 0), width-1), same for y.
+ *  - Image, tap and workspace pointers are DEVICE pointers unless stated.
+ *    Filter taps are float32 in device memory and are read at run time, so taps
+ *    updated in place are seen by later calls and by graph replays.
+ *  - Correlation orientation: tap index k = (j+r)*(2r+1) + (i+r) multiplies the
+ *    input at offset (x+i, y+j); no flip.
+ *  - The caller owns every buffer.  Hot calls allocate nothing and never
+ *    synchronise; they enqueue on `stream` (a hipStream_t; NULL = the null
+ *    stream) and return.  Scratch memory is passed in as `workspace`, sized by
+ *    icl_workspace_size().
+ *  - Input and output images must not overlap (ICL_ERR_ALIAS): the paper's
+ *    language forbids aliasing and local-memory staging needs read-only inputs
+ *    (Section 5.2, memory spaces).
+ *  - Arithmetic is float32 with float32 accumulation; float16 / bfloat16 storage
+ *    is decoded exactly on load and rounded to nearest even on store.
+ *  - width == 0 or height == 0 is an empty image: the call returns ICL_OK and
+ *    touches nothing.  Negative sizes are ICL_ERR_INVALID_VALUE.
+ *  - Errors: arguments are checked on the host before anything is launched and
+ *    an icl_status is returned; no call aborts or throws.  A failing HIP call
+ *    returns ICL_ERR_HIP and its hipError_t is kept per thread
+ *    (icl_last_hip_error()).
+ */
+#ifndef ICL_H
+#define ICL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum icl_status {
+    ICL_OK = 0,
+    ICL_ERR_INVALID_VALUE = 1, /* null pointer, negative size, bad count or enum */
+    ICL_ERR_PITCH = 2,         /* pitch < width * elem or not a multiple of elem */
+    ICL_ERR_RADIUS = 3,        /* radius outside the supported range */
+    ICL_ERR_DTYPE = 4,         /* storage type not supported by this entry point */
+    ICL_ERR_ALIAS = 5,         /* an output overlaps an input */
+    ICL_ERR_WORKSPACE = 6,     /* workspace missing or smaller than icl_workspace_size() */
+    ICL_ERR_NO_DEVICE = 7,     /* no HIP device visible */
+    ICL_ERR_HIP = 8,           /* a HIP runtime call failed (see icl_last_hip_error) */
+    ICL_ERR_UNSUPPORTED = 9,   /* valid request this build does not implement */
+    ICL_ERR_TUNE_CACHE = 10    /* tune cache unreadable or written for another device */
+} icl_status;
+
+typedef enum icl_dtype { ICL_F32 = 0, ICL_F16 = 1, ICL_BF16 = 2 } icl_dtype;
+
+/* operations, for icl_workspace_size / icl_tune / variant control */
+typedef enum icl_op {
+    ICL_OP_CONV_SEP = 0,
+    ICL_OP_CONV2D = 1,
+    ICL_OP_HARRIS = 2,
+    ICL_OP_NMS = 3,
+    ICL_OP_CONV_SEP_BATCHED = 4,
+    ICL_OP_BANK_FWD = 5,
+    ICL_OP_BANK_BWD_INPUT = 6,
+    ICL_OP_BANK_BWD_FILTER = 7,
+    ICL_OP_SSE_LOSS = 8,
+    ICL_OP_COUNT = 9
+} icl_op;
+
+#define ICL_MAX_RADIUS 16          /* largest stencil radius accepted by the convolution calls */
+#define ICL_MAX_WINDOW_RADIUS 7    /* largest Harris window radius */
+#define ICL_MAX_NMS_RADIUS 7
+
+/* ------------------------------------------------------------------ library */
+
+/* Initialise the runtime side (device query, tune cache).  Optional: every call
+ * initialises lazily.  Returns ICL_ERR_NO_DEVICE when no GPU is visible. */
+icl_status icl_init(void);
+
+const char* icl_status_string(icl_status s);   /* static string, never NULL */
+int icl_last_hip_error(void);                   /* hipError_t of this thread's last failing HIP call */
+const char* icl_version(void);
+
+/* Scratch bytes an operation needs for the given problem (0 when none).  For
+ * ICL_OP_CONV_SEP this is the float32 row-pass intermediate of the two-pass
+ * variants; for ICL_OP_HARRIS the two float32 gradient images of the split
+ * (Sobel kernel + Harris kernel) variant; for ICL_OP_BANK_BWD_FILTER and
+ * ICL_OP_SSE_LOSS the per-block partial sums.  Callers that always pass this
+ * much workspace may use every variant.  `n` and `f` are the batch and filter
+ * counts of the filter-bank ops (ignored otherwise). */
+icl_status icl_workspace_size(icl_op op, int width, int height, int n, int f, int radius,
+                              icl_dtype dtype, size_t* bytes /* host */);
+
+/* ------------------------------------------------------------------ separable convolution
+ * Paper: Section 6, separable convolution benchmark (row kernel R and column
+ * kernel C, Table 2); the discussion names fusing the two passes with the
+ * intermediate in local memory as the optimisation ImageCL could not express.
+ *   T(x,y) = sum_{i=-r..r} taps_x[i+r] * src(x+i, y)
+ *   dst(x,y) = sum_{j=-r..r} taps_y[j+r] * T(x, y+j)        (reads clamped)
+ * T is kept in float32 (never rounded to the storage type).
+ *   src, dst      : device images of `dtype`, pitches in bytes
+ *   taps_x/taps_y : device float32 arrays of 2r+1 taps, r in [0, ICL_MAX_RADIUS]
+ *   workspace     : device scratch of icl_workspace_size(ICL_OP_CONV_SEP) bytes, or
+ *                   NULL / too small: then only the fused single-pass variants run
+ *                   (ICL_ERR_WORKSPACE if a two-pass variant is forced). */
+icl_status icl_conv_sep(const void* src, size_t src_pitch, void* dst, size_t dst_pitch,
+                        int width, int height, icl_dtype dtype,
+                        const float* taps_x, const float* taps_y, int radius,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------ 2-D correlation
+ * Paper: Section 6, non-separable convolution benchmark (Table 3): a full
+ * (2r+1)^2 filter whose taps are known only at run time.
+ *   dst(x,y) = sum_{j,i=-r..r} taps[(j+r)(2r+1) + (i+r)] * src(x+i, y+j)
+ *   taps : device float32, (2r+1)^2 values, row (j) major. */
+icl_status icl_conv2d(const void* src, size_t src_pitch, void* dst, size_t dst_pitch,
+                      int width, int height, icl_dtype dtype,
+                      const float* taps, int radius, void* stream);
+
+/* ------------------------------------------------------------------ Harris corner response
+ * Paper: Section 6, Harris corner detection, run there as a Sobel kernel
+ * (Table 4) followed by a Harris kernel that reads the gradient images dx, dy as
+ * Images (Table 5), so the window's reads are clamped on the gradient images.
+ *   Ix = sum s[j] d[i] src(x+i,y+j),  Iy = sum d[j] s[i] src(x+i,y+j),
+ *        s = (1,2,1), d = (-1,0,1)      (unnormalised Sobel)
+ *   Sxx = sum_{j,i} g[j] g[i] Ix^2(x+i, y+j), Syy likewise with Iy^2, Sxy with Ix*Iy
+ *   resp = Sxx*Syy - Sxy^2 - k*(Sxx+Syy)^2
+ *   src, resp    : float32 device images
+ *   window_taps  : device float32, 2*window_radius+1 taps g (window = outer product g g^T),
+ *                  window_radius in [0, ICL_MAX_WINDOW_RADIUS]
+ *   workspace    : icl_workspace_size(ICL_OP_HARRIS) bytes for the split variant, or NULL. */
+icl_status icl_harris(const float* src, size_t src_pitch, float* resp, size_t resp_pitch,
+                      int width, int height, const float* window_taps, int window_radius,
+                      float k, void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------ non-maximum suppression
+ * Final stage of corner detection (not defined in the paper; it thresholds the
+ * Harris response to a corner mask).
+ *   mask(x,y) = 1 if resp(x,y) > threshold and resp(x,y) >= resp(x+i,y+j) for all
+ *               |i|,|j| <= radius (reads clamped, so outside neighbours are ignored),
+ *               else 0.
+ *   resp : float32 device image;  mask : uint8 device image (pitch in bytes);
+ *   radius in [1, ICL_MAX_NMS_RADIUS]. */
+icl_status icl_nms(const float* resp, size_t resp_pitch, uint8_t* mask, size_t mask_pitch,
+                   int width, int height, int radius, float threshold, void* stream);
+
+/* ------------------------------------------------------------------ batched separable convolution
+ * Many images of uneven size, each with its own radius and taps, in ONE
+ * persistent kernel launch (work is a table of tiles, each naming its image).
+ * Same arithmetic as icl_conv_sep, per image, fused single pass. */
+typedef struct icl_image_desc {
+    const void* src;       /* device */
+    void* dst;             /* device */
+    size_t src_pitch;      /* bytes */
+    size_t dst_pitch;      /* bytes */
+    int width, height;
+    int radius;            /* 0 .. 7 */
+    const float* taps_x;   /* device, 2r+1 */
+    const float* taps_y;   /* device, 2r+1 */
+} icl_image_desc;
+
+typedef struct icl_batch_plan icl_batch_plan;   /* opaque */
+
+/* Validates every descriptor (host array of `count`), builds the tile table and
+ * uploads it (this call allocates device memory and synchronises; it is not
+ * capture-safe).  All images share `dtype`. */
+icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dtype dtype,
+                                 icl_batch_plan** plan /* host out */);
+/* One persistent launch over the plan's tiles.  Allocates nothing: capture-safe. */
+icl_status icl_conv_sep_batched(const icl_batch_plan* plan, void* stream);
+/* Number of tiles and total pixels of a plan (host out pointers, either may be NULL). */
+icl_status icl_batch_plan_info(const icl_batch_plan* plan, long long* tiles, long long* pixels);
+void icl_batch_plan_destroy(icl_batch_plan* plan);
+
+/* Capture icl_conv_sep_batched(plan) into a HIP graph and instantiate it.  The
+ * graph holds one kernel node; replaying it re-reads images and taps, so new
+ * data in the same buffers is picked up.  `*exec` is a hipGraphExec_t. */
+icl_status icl_batch_graph_create(const icl_batch_plan* plan, void** exec /* host out */);
+icl_status icl_graph_launch(void* exec, void* stream);
+void icl_graph_destroy(void* exec);
+
+/* ------------------------------------------------------------------ differentiable filter bank
+ * F learnable filters of radius r applied to N single-channel images (clamped
+ * correlation), with the adjoint kernels for backpropagation.  Dense NCHW
+ * float32 tensors, element offsets 64-bit:
+ *   x  [n][h][wd]   w [f][2r+1][2r+1]   y, gy [n][f][h][wd]   gx [n][h][wd]
+ *   forward      y[n,f,p]  = sum_k w[f,k] x[n, clamp(p+k)]
+ *   input grad   gx[n,q]   = sum over (f, p, k) with clamp(p+k) = q of w[f,k] gy[n,f,p]
+ *   filter grad  gw[f,k]   = sum_{n,p} gy[n,f,p] x[n, clamp(p+k)]   (fixed-order reduction)
+ * radius in [1, 4] and f in [1, 64] for this build. */
+icl_status icl_bank_fwd(const float* x, const float* w, float* y, int n, int f, int h, int wd,
+                        int radius, void* stream);
+icl_status icl_bank_bwd_input(const float* gy, const float* w, float* gx, int n, int f, int h, int wd,
+                              int radius, void* stream);
+icl_status icl_bank_bwd_filter(const float* gy, const float* x, float* gw, int n, int f, int h, int wd,
+                               int radius, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Sum-of-squares loss L = sum (y - t)^2 over `count` elements and its gradient
+ * gy = 2 (y - t) (gy may be NULL).  `loss` is a device float32 written with L;
+ * the reduction order is fixed, so results are reproducible run to run. */
+icl_status icl_sse_loss(const float* y, const float* t, float* gy, long long count, float* loss,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------ auto-tuning and variants
+ * The tuner plays the role of the paper's auto-tuner (Section 4 and the
+ * discussion of tuning cost): it runs every precompiled candidate variant of an
+ * operation on synthetic data of the given shape, rejects candidates whose
+ * output differs from the plain variant's, times the rest with HIP events on
+ * rotating buffers, and records the fastest in a per-device cache keyed by
+ * (device, op, dtype, radius, size class).  Candidates are compiled ahead of
+ * time, so a search costs only run time.
+ * icl_tune allocates, synchronises and must not be called during stream capture. */
+icl_status icl_tune(icl_op op, icl_dtype dtype, int radius, int width, int height, void* stream);
+/* Persist / reload the cache (JSON).  path NULL = $ICL_TUNE_CACHE or ~/.cache/icl/tune.json. */
+icl_status icl_tune_save(const char* path);
+icl_status icl_tune_load(const char* path);
+void icl_tune_clear(void);
+
+/* Variant table of an operation (index 0 is always the plain one-pixel-per-thread kernel). */
+int icl_variant_count(icl_op op);
+const char* icl_variant_name(icl_op op, int index);     /* NULL if out of range */
+/* Force a variant for every later call of `op` (-1 = back to tuned/default
+ * selection); the analogue of the paper's directives that force optimisations
+ * on or off.  A forced variant that cannot run a call (radius not compiled,
+ * missing workspace) makes that call return ICL_ERR_UNSUPPORTED / ICL_ERR_WORKSPACE. */
+icl_status icl_force_variant(icl_op op, int index);
+/* Variant the next call with these parameters would launch (host out). */
+icl_status icl_selected_variant(icl_op op, icl_dtype dtype, int radius, int width, int height,
+                                int* index);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ICL_H */

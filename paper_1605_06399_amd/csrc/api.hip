@@ -1,0 +1,426 @@
+// C-ABI entry points: argument validation on the host, variant selection and
+// launch.  The standalone host function of the paper's code generator
+// (Section 5.1) is the model: one call per stencil, plain pointers and sizes.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "icl_internal.hpp"
+
+using namespace icl;
+
+namespace icl {
+
+static thread_local int g_last_hip_error = 0;
+void set_hip_error(hipError_t e) { g_last_hip_error = (int)e; }
+
+static std::atomic<int> g_forced[ICL_OP_COUNT] = {};
+static std::once_flag g_force_env_once;
+static int g_device_state = -1;     // -1 unknown, 0 none, 1 ok
+static std::mutex g_init_mu;
+
+static const char* kOpNames[ICL_OP_COUNT] = {"conv_sep", "conv2d", "harris", "nms", "conv_sep_batched",
+                                             "bank_fwd", "bank_bwd_input", "bank_bwd_filter", "sse_loss"};
+
+// ICL_FORCE_VARIANT="conv_sep=1,conv2d=3": the analogue of the paper's directives
+// that force optimisations on or off.
+static void parse_force_env() {
+    for (int i = 0; i < ICL_OP_COUNT; ++i) g_forced[i] = -1;
+    const char* e = std::getenv("ICL_FORCE_VARIANT");
+    if (!e) return;
+    std::string s(e);
+    size_t pos = 0;
+    while (pos < s.size()) {
+        size_t end = s.find(',', pos);
+        if (end == std::string::npos) end = s.size();
+        const std::string item = s.substr(pos, end - pos);
+        const size_t eq = item.find('=');
+        if (eq != std::string::npos) {
+            const std::string name = item.substr(0, eq);
+            const int idx = std::atoi(item.c_str() + eq + 1);
+            for (int i = 0; i < ICL_OP_COUNT; ++i)
+                if (name == kOpNames[i]) g_forced[i] = idx;
+        }
+        pos = end + 1;
+    }
+}
+
+static void ensure_force_env() { std::call_once(g_force_env_once, parse_force_env); }
+
+bool variant_forced(icl_op op) {
+    ensure_force_env();
+    return g_forced[op].load() >= 0;
+}
+
+int select_variant(icl_op op, icl_dtype dt, int r, int W, int H, int fallback) {
+    ensure_force_env();
+    const int f = g_forced[op].load();
+    if (f >= 0) return f;
+    const int c = tune_cache_get(op, dt, r, W, H);
+    if (c >= 0) return c;
+    return fallback;
+}
+
+const char* op_name(icl_op op) { return (op >= 0 && op < ICL_OP_COUNT) ? kOpNames[op] : "?"; }
+
+icl_status device_ready() {
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    if (g_device_state < 0) {
+        int n = 0;
+        const hipError_t e = hipGetDeviceCount(&n);
+        g_device_state = (e == hipSuccess && n > 0) ? 1 : 0;
+    }
+    return g_device_state == 1 ? ICL_OK : ICL_ERR_NO_DEVICE;
+}
+
+}  // namespace icl
+
+namespace {
+
+bool dtype_ok(icl_dtype d) { return d == ICL_F32 || d == ICL_F16 || d == ICL_BF16; }
+
+// Image checks shared by the entry points (sizes already known to be >= 1).
+icl_status check_image(const void* p, size_t pitch, int W, int es) {
+    if (!p) return ICL_ERR_INVALID_VALUE;
+    if (pitch < (size_t)W * (size_t)es || pitch % (size_t)es) return ICL_ERR_PITCH;
+    return ICL_OK;
+}
+
+// Byte ranges [p, p + (H-1)*pitch + W*es) of two images intersect.
+bool overlaps(const void* a, size_t ap, int aes, const void* b, size_t bp, int bes, int W, int H) {
+    const uintptr_t a0 = (uintptr_t)a, a1 = a0 + (size_t)(H - 1) * ap + (size_t)W * aes;
+    const uintptr_t b0 = (uintptr_t)b, b1 = b0 + (size_t)(H - 1) * bp + (size_t)W * bes;
+    return a0 < b1 && b0 < a1;
+}
+
+bool range_overlaps(const void* a, size_t an, const void* b, size_t bn) {
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + bn && b0 < a0 + an;
+}
+
+// Run the chosen variant; fall back to the default (or plain) when a tuned choice
+// cannot run these arguments.  Forced choices never fall back.
+template <class A>
+icl_status dispatch(icl_op op, const Variant<A>* tab, int count, const A& a, int chosen, int deflt) {
+    const bool forced = variant_forced(op);
+    if (chosen < 0 || chosen >= count) {
+        if (forced) return ICL_ERR_UNSUPPORTED;
+        chosen = deflt;
+    }
+    if (!tab[chosen].supports(a)) {
+        if (forced) return ICL_ERR_UNSUPPORTED;
+        chosen = deflt;
+        if (!tab[chosen].supports(a)) {
+            chosen = 0;
+            if (!tab[0].supports(a)) return ICL_ERR_UNSUPPORTED;
+        }
+    }
+    return hip_status(tab[chosen].launch(a));
+}
+
+}  // namespace
+
+extern "C" {
+
+icl_status icl_init(void) { return device_ready(); }
+
+const char* icl_version(void) { return "icl 0.1 (gfx950)"; }
+
+int icl_last_hip_error(void) { return g_last_hip_error; }
+
+const char* icl_status_string(icl_status s) {
+    switch (s) {
+        case ICL_OK: return "ok";
+        case ICL_ERR_INVALID_VALUE: return "invalid value";
+        case ICL_ERR_PITCH: return "invalid pitch";
+        case ICL_ERR_RADIUS: return "radius out of range";
+        case ICL_ERR_DTYPE: return "unsupported storage type";
+        case ICL_ERR_ALIAS: return "output overlaps an input";
+        case ICL_ERR_WORKSPACE: return "workspace missing or too small";
+        case ICL_ERR_NO_DEVICE: return "no HIP device";
+        case ICL_ERR_HIP: return "HIP runtime error";
+        case ICL_ERR_UNSUPPORTED: return "unsupported request";
+        case ICL_ERR_TUNE_CACHE: return "tune cache unreadable or foreign";
+    }
+    return "unknown status";
+}
+
+icl_status icl_workspace_size(icl_op op, int width, int height, int n, int f, int radius, icl_dtype dtype,
+                              size_t* bytes) {
+    if (!bytes) return ICL_ERR_INVALID_VALUE;
+    if (width < 0 || height < 0 || n < 0 || f < 0) return ICL_ERR_INVALID_VALUE;
+    if (!dtype_ok(dtype)) return ICL_ERR_DTYPE;
+    *bytes = 0;
+    switch (op) {
+        case ICL_OP_CONV_SEP: *bytes = sep_workspace(width, height); break;
+        case ICL_OP_HARRIS: *bytes = harris_workspace(width, height); break;
+        case ICL_OP_BANK_BWD_FILTER:
+            if (radius < 1 || radius > 4) return ICL_ERR_RADIUS;
+            *bytes = bank_bwd_filter_workspace(n, f, height, width, radius);
+            break;
+        case ICL_OP_SSE_LOSS: *bytes = sse_workspace((long long)width * height); break;
+        case ICL_OP_CONV2D: case ICL_OP_NMS: case ICL_OP_CONV_SEP_BATCHED: case ICL_OP_BANK_FWD:
+        case ICL_OP_BANK_BWD_INPUT: break;
+        default: return ICL_ERR_INVALID_VALUE;
+    }
+    return ICL_OK;
+}
+
+icl_status icl_conv_sep(const void* src, size_t src_pitch, void* dst, size_t dst_pitch, int width, int height,
+                        icl_dtype dtype, const float* taps_x, const float* taps_y, int radius, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+    if (width < 0 || height < 0) return ICL_ERR_INVALID_VALUE;
+    if (!dtype_ok(dtype)) return ICL_ERR_DTYPE;
+    if (radius < 0 || radius > ICL_MAX_RADIUS) return ICL_ERR_RADIUS;
+    if (width == 0 || height == 0) return ICL_OK;
+    const int es = elem_size(dtype);
+    icl_status s;
+    if ((s = check_image(src, src_pitch, width, es)) != ICL_OK) return s;
+    if ((s = check_image(dst, dst_pitch, width, es)) != ICL_OK) return s;
+    if (!taps_x || !taps_y) return ICL_ERR_INVALID_VALUE;
+    if (overlaps(src, src_pitch, es, dst, dst_pitch, es, width, height)) return ICL_ERR_ALIAS;
+    if (workspace && (range_overlaps(workspace, workspace_bytes, dst,
+                                     (size_t)(height - 1) * dst_pitch + (size_t)width * es) ||
+                      range_overlaps(workspace, workspace_bytes, src,
+                                     (size_t)(height - 1) * src_pitch + (size_t)width * es)))
+        return ICL_ERR_ALIAS;
+    if ((s = device_ready()) != ICL_OK) return s;
+    SepArgs a{src, src_pitch, dst, dst_pitch, width, height, dtype, taps_x, taps_y, radius,
+              workspace, workspace_bytes, (hipStream_t)stream};
+    int count;
+    const Variant<SepArgs>* tab = sep_variants(&count);
+    const int deflt = sep_default(a);
+    const int v = select_variant(ICL_OP_CONV_SEP, dtype, radius, width, height, deflt);
+    // the two-pass variants (and every radius above the fused kernels' range) need the intermediate
+    const bool forced_two_pass = variant_forced(ICL_OP_CONV_SEP) && v == 0;
+    if ((forced_two_pass || !tab[deflt].supports(a)) && !tab[0].supports(a)) return ICL_ERR_WORKSPACE;
+    return dispatch(ICL_OP_CONV_SEP, tab, count, a, v, deflt);
+}
+
+icl_status icl_conv2d(const void* src, size_t src_pitch, void* dst, size_t dst_pitch, int width, int height,
+                      icl_dtype dtype, const float* taps, int radius, void* stream) {
+    if (width < 0 || height < 0) return ICL_ERR_INVALID_VALUE;
+    if (!dtype_ok(dtype)) return ICL_ERR_DTYPE;
+    if (radius < 0 || radius > ICL_MAX_RADIUS) return ICL_ERR_RADIUS;
+    if (width == 0 || height == 0) return ICL_OK;
+    const int es = elem_size(dtype);
+    icl_status s;
+    if ((s = check_image(src, src_pitch, width, es)) != ICL_OK) return s;
+    if ((s = check_image(dst, dst_pitch, width, es)) != ICL_OK) return s;
+    if (!taps) return ICL_ERR_INVALID_VALUE;
+    if (overlaps(src, src_pitch, es, dst, dst_pitch, es, width, height)) return ICL_ERR_ALIAS;
+    if ((s = device_ready()) != ICL_OK) return s;
+    Conv2dArgs a{src, src_pitch, dst, dst_pitch, width, height, dtype, taps, radius, (hipStream_t)stream};
+    int count;
+    const Variant<Conv2dArgs>* tab = conv2d_variants(&count);
+    const int deflt = conv2d_default(a);
+    return dispatch(ICL_OP_CONV2D, tab, count, a, select_variant(ICL_OP_CONV2D, dtype, radius, width, height, deflt),
+                    deflt);
+}
+
+icl_status icl_harris(const float* src, size_t src_pitch, float* resp, size_t resp_pitch, int width, int height,
+                      const float* window_taps, int window_radius, float k, void* workspace, size_t workspace_bytes,
+                      void* stream) {
+    if (width < 0 || height < 0) return ICL_ERR_INVALID_VALUE;
+    if (window_radius < 0 || window_radius > ICL_MAX_WINDOW_RADIUS) return ICL_ERR_RADIUS;
+    if (width == 0 || height == 0) return ICL_OK;
+    icl_status s;
+    if ((s = check_image(src, src_pitch, width, 4)) != ICL_OK) return s;
+    if ((s = check_image(resp, resp_pitch, width, 4)) != ICL_OK) return s;
+    if (!window_taps) return ICL_ERR_INVALID_VALUE;
+    if (overlaps(src, src_pitch, 4, resp, resp_pitch, 4, width, height)) return ICL_ERR_ALIAS;
+    if ((s = device_ready()) != ICL_OK) return s;
+    HarrisArgs a{src, src_pitch, resp, resp_pitch, width, height, window_taps, window_radius, k,
+                 workspace, workspace_bytes, (hipStream_t)stream};
+    int count;
+    const Variant<HarrisArgs>* tab = harris_variants(&count);
+    const int deflt = harris_default(a);
+    const int v = select_variant(ICL_OP_HARRIS, ICL_F32, window_radius, width, height, deflt);
+    const bool forced_split = variant_forced(ICL_OP_HARRIS) && v == 0;
+    if ((forced_split || !tab[deflt].supports(a)) && !tab[0].supports(a)) return ICL_ERR_WORKSPACE;
+    return dispatch(ICL_OP_HARRIS, tab, count, a, v, deflt);
+}
+
+icl_status icl_nms(const float* resp, size_t resp_pitch, uint8_t* mask, size_t mask_pitch, int width, int height,
+                   int radius, float threshold, void* stream) {
+    if (width < 0 || height < 0) return ICL_ERR_INVALID_VALUE;
+    if (radius < 1 || radius > ICL_MAX_NMS_RADIUS) return ICL_ERR_RADIUS;
+    if (width == 0 || height == 0) return ICL_OK;
+    icl_status s;
+    if ((s = check_image(resp, resp_pitch, width, 4)) != ICL_OK) return s;
+    if ((s = check_image(mask, mask_pitch, width, 1)) != ICL_OK) return s;
+    if (overlaps(resp, resp_pitch, 4, mask, mask_pitch, 1, width, height)) return ICL_ERR_ALIAS;
+    if ((s = device_ready()) != ICL_OK) return s;
+    NmsArgs a{resp, resp_pitch, mask, mask_pitch, width, height, radius, threshold, (hipStream_t)stream};
+    int count;
+    const Variant<NmsArgs>* tab = nms_variants(&count);
+    const int deflt = nms_default(a);
+    return dispatch(ICL_OP_NMS, tab, count, a, select_variant(ICL_OP_NMS, ICL_F32, radius, width, height, deflt), deflt);
+}
+
+// ------------------------------------------------------------------ filter bank
+static icl_status check_bank(int n, int f, int h, int wd, int radius) {
+    if (n < 0 || f < 1 || h < 0 || wd < 0) return ICL_ERR_INVALID_VALUE;
+    if (f > 64) return ICL_ERR_UNSUPPORTED;
+    if (radius < 1 || radius > 4) return ICL_ERR_RADIUS;
+    return ICL_OK;
+}
+
+icl_status icl_bank_fwd(const float* x, const float* w, float* y, int n, int f, int h, int wd, int radius,
+                        void* stream) {
+    icl_status s;
+    if ((s = check_bank(n, f, h, wd, radius)) != ICL_OK) return s;
+    if (n == 0 || h == 0 || wd == 0) return ICL_OK;
+    if (!x || !w || !y) return ICL_ERR_INVALID_VALUE;
+    const size_t hw = (size_t)h * wd;
+    if (range_overlaps(x, (size_t)n * hw * 4, y, (size_t)n * f * hw * 4) ||
+        range_overlaps(w, (size_t)f * (2 * radius + 1) * (2 * radius + 1) * 4, y, (size_t)n * f * hw * 4))
+        return ICL_ERR_ALIAS;
+    if ((s = device_ready()) != ICL_OK) return s;
+    BankArgs a{x, w, y, n, f, h, wd, radius, nullptr, 0, (hipStream_t)stream};
+    int count;
+    const Variant<BankArgs>* tab = bank_fwd_variants(&count);
+    return dispatch(ICL_OP_BANK_FWD, tab, count, a, select_variant(ICL_OP_BANK_FWD, ICL_F32, radius, wd, h, 0), 0);
+}
+
+icl_status icl_bank_bwd_input(const float* gy, const float* w, float* gx, int n, int f, int h, int wd, int radius,
+                              void* stream) {
+    icl_status s;
+    if ((s = check_bank(n, f, h, wd, radius)) != ICL_OK) return s;
+    if (n == 0 || h == 0 || wd == 0) return ICL_OK;
+    if (!gy || !w || !gx) return ICL_ERR_INVALID_VALUE;
+    const size_t hw = (size_t)h * wd;
+    if (range_overlaps(gy, (size_t)n * f * hw * 4, gx, (size_t)n * hw * 4) ||
+        range_overlaps(w, (size_t)f * (2 * radius + 1) * (2 * radius + 1) * 4, gx, (size_t)n * hw * 4))
+        return ICL_ERR_ALIAS;
+    if ((s = device_ready()) != ICL_OK) return s;
+    BankArgs a{gy, w, gx, n, f, h, wd, radius, nullptr, 0, (hipStream_t)stream};
+    int count;
+    const Variant<BankArgs>* tab = bank_bwd_input_variants(&count);
+    return dispatch(ICL_OP_BANK_BWD_INPUT, tab, count, a,
+                    select_variant(ICL_OP_BANK_BWD_INPUT, ICL_F32, radius, wd, h, 0), 0);
+}
+
+icl_status icl_bank_bwd_filter(const float* gy, const float* x, float* gw, int n, int f, int h, int wd, int radius,
+                               void* workspace, size_t workspace_bytes, void* stream) {
+    icl_status s;
+    if ((s = check_bank(n, f, h, wd, radius)) != ICL_OK) return s;
+    if (!gw) return ICL_ERR_INVALID_VALUE;
+    const size_t nk = (size_t)(2 * radius + 1) * (2 * radius + 1);
+    if (n == 0 || h == 0 || wd == 0) {
+        if ((s = device_ready()) != ICL_OK) return s;
+        return hip_status(zero_fill(gw, (size_t)f * nk, (hipStream_t)stream));
+    }
+    if (!gy || !x) return ICL_ERR_INVALID_VALUE;
+    const size_t need = bank_bwd_filter_workspace(n, f, h, wd, radius);
+    if (!workspace || workspace_bytes < need) return ICL_ERR_WORKSPACE;
+    const size_t hw = (size_t)h * wd;
+    if (range_overlaps(gw, (size_t)f * nk * 4, gy, (size_t)n * f * hw * 4) ||
+        range_overlaps(gw, (size_t)f * nk * 4, x, (size_t)n * hw * 4) ||
+        range_overlaps(workspace, need, gy, (size_t)n * f * hw * 4) ||
+        range_overlaps(workspace, need, x, (size_t)n * hw * 4) || range_overlaps(workspace, need, gw, (size_t)f * nk * 4))
+        return ICL_ERR_ALIAS;
+    if ((s = device_ready()) != ICL_OK) return s;
+    BankArgs a{gy, x, gw, n, f, h, wd, radius, workspace, workspace_bytes, (hipStream_t)stream};
+    int count;
+    const Variant<BankArgs>* tab = bank_bwd_filter_variants(&count);
+    return dispatch(ICL_OP_BANK_BWD_FILTER, tab, count, a,
+                    select_variant(ICL_OP_BANK_BWD_FILTER, ICL_F32, radius, wd, h, 0), 0);
+}
+
+icl_status icl_sse_loss(const float* y, const float* t, float* gy, long long count, float* loss, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+    if (count < 0) return ICL_ERR_INVALID_VALUE;
+    if (!loss) return ICL_ERR_INVALID_VALUE;
+    if (count > 0 && (!y || !t)) return ICL_ERR_INVALID_VALUE;
+    if (!workspace || workspace_bytes < sse_workspace(count)) return ICL_ERR_WORKSPACE;
+    const size_t nb = (size_t)count * 4;
+    if (gy && (range_overlaps(gy, nb, y, nb) || range_overlaps(gy, nb, t, nb))) return ICL_ERR_ALIAS;
+    icl_status s;
+    if ((s = device_ready()) != ICL_OK) return s;
+    return hip_status(sse_launch(y, t, gy, count, loss, workspace, workspace_bytes, (hipStream_t)stream));
+}
+
+// ------------------------------------------------------------------ variants
+int icl_variant_count(icl_op op) {
+    int c = 0;
+    switch (op) {
+        case ICL_OP_CONV_SEP: sep_variants(&c); break;
+        case ICL_OP_CONV2D: conv2d_variants(&c); break;
+        case ICL_OP_HARRIS: harris_variants(&c); break;
+        case ICL_OP_NMS: nms_variants(&c); break;
+        case ICL_OP_BANK_FWD: bank_fwd_variants(&c); break;
+        case ICL_OP_BANK_BWD_INPUT: bank_bwd_input_variants(&c); break;
+        case ICL_OP_BANK_BWD_FILTER: bank_bwd_filter_variants(&c); break;
+        case ICL_OP_CONV_SEP_BATCHED: case ICL_OP_SSE_LOSS: c = 1; break;
+        default: c = 0;
+    }
+    return c;
+}
+
+const char* icl_variant_name(icl_op op, int index) {
+    if (index < 0 || index >= icl_variant_count(op)) return nullptr;
+    int c = 0;
+    switch (op) {
+        case ICL_OP_CONV_SEP: return sep_variants(&c)[index].name;
+        case ICL_OP_CONV2D: return conv2d_variants(&c)[index].name;
+        case ICL_OP_HARRIS: return harris_variants(&c)[index].name;
+        case ICL_OP_NMS: return nms_variants(&c)[index].name;
+        case ICL_OP_BANK_FWD: return bank_fwd_variants(&c)[index].name;
+        case ICL_OP_BANK_BWD_INPUT: return bank_bwd_input_variants(&c)[index].name;
+        case ICL_OP_BANK_BWD_FILTER: return bank_bwd_filter_variants(&c)[index].name;
+        case ICL_OP_CONV_SEP_BATCHED: return "persistent_fused_t32";
+        case ICL_OP_SSE_LOSS: return "two_stage";
+        default: return nullptr;
+    }
+}
+
+icl_status icl_force_variant(icl_op op, int index) {
+    if (op < 0 || op >= ICL_OP_COUNT) return ICL_ERR_INVALID_VALUE;
+    if (index < -1 || index >= icl_variant_count(op)) return ICL_ERR_INVALID_VALUE;
+    ensure_force_env();
+    g_forced[op] = index;
+    return ICL_OK;
+}
+
+icl_status icl_selected_variant(icl_op op, icl_dtype dtype, int radius, int width, int height, int* index) {
+    if (!index || op < 0 || op >= ICL_OP_COUNT) return ICL_ERR_INVALID_VALUE;
+    int deflt = 0;
+    switch (op) {
+        case ICL_OP_CONV_SEP: {
+            SepArgs a{};
+            a.r = radius; a.W = width; a.H = height; a.dt = dtype;
+            deflt = sep_default(a);
+            break;
+        }
+        case ICL_OP_CONV2D: {
+            Conv2dArgs a{};
+            a.r = radius;
+            deflt = conv2d_default(a);
+            break;
+        }
+        case ICL_OP_HARRIS: {
+            HarrisArgs a{};
+            a.rg = radius;
+            deflt = harris_default(a);
+            break;
+        }
+        case ICL_OP_NMS: {
+            NmsArgs a{};
+            a.r = radius;
+            deflt = nms_default(a);
+            break;
+        }
+        default: break;
+    }
+    *index = select_variant(op, dtype, radius, width, height, deflt);
+    return ICL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,460 @@
+// Differentiable filter bank: F filters of radius r over N single-channel images
+// (clamped correlation) and its adjoints.  Dense NCHW float32 tensors.
+//
+//   forward      y[n,f,p]  = sum_k w[f,k] x[n, clamp(p+k)]
+//   input grad   gx[n,q]   = sum_{f,p,k : clamp(p+k) = q} w[f,k] gy[n,f,p]
+//                          = sum_{u : clamp(u) = q} z[n,u],
+//                z[n,u]    = sum_f sum_k w[f,k] gy0[n,f,u-k]       (gy0: gy extended by zero)
+//                i.e. a correlation of the zero-padded gy with the flipped filters on
+//                the padded grid, folded back onto the edge pixels it was clamped to.
+//   filter grad  gw[f,k]   = sum_{n,p} gy[n,f,p] x[n, clamp(p+k)]
+//
+// Kernels
+//   bank_fwd       : 64x64 output tile per 256-lane work-group; the x tile with its
+//                    r halo is staged in LDS once and reused by all F filters; each
+//                    lane keeps a 4x4 accumulator block (input-row-outer order).
+//   bank_bwd_in    : same tiling; for each filter the gy tile (zero outside the image)
+//                    is staged and correlated with the flipped filter; the F sums
+//                    accumulate in registers and are stored once.
+//   bank_bwd_fold  : one lane per edge pixel q adds z at the padded positions u != q
+//                    that clamp onto q (up to (r+1)^2 - 1 of them at a corner).
+//   bank_bwd_w1/w2 : filter gradient.  Stage 1: one wave per (image, 32x64 tile,
+//                    filter) accumulates all (2r+1)^2 taps over its 2048 pixels
+//                    (column-walk register reuse), reduces across the wave with a
+//                    butterfly, and writes one partial per tap.  Stage 2 sums the
+//                    partials of each (f, tap) in a fixed order: deterministic.
+#include "icl_device.hpp"
+#include "icl_internal.hpp"
+
+namespace icl {
+namespace {
+
+constexpr int BT = 64;           // fwd / bwd_in tile side
+constexpr int BPX = 4, BPY = 4;  // per-lane accumulator block (16 x 16 lanes)
+
+template <int R> struct BankTile {
+    static constexpr int RA = (R + 3) & ~3;
+    static constexpr int LW = BT + 2 * RA;
+    static constexpr int NR = BT + 2 * R;
+    static constexpr int WIN = BPX + 2 * RA;
+};
+
+// Stage rows y0-R .. y0+BT+R-1 and columns x0-RA .. x0+BT+RA-1 of a dense W-wide
+// plane into LDS.  ZERO_PAD: outside pixels read as 0; otherwise clamped.
+template <int R, bool ZERO_PAD>
+__device__ __forceinline__ void stage_plane(const float* __restrict__ plane, int W, int H, int x0, int y0,
+                                            bool vec, float* __restrict__ s) {
+    using G = BankTile<R>;
+    constexpr int LW = G::LW, NR = G::NR, RA = G::RA;
+    const int tid = threadIdx.x;
+    if (vec && x0 - RA >= 0 && x0 + BT + RA <= W) {
+        constexpr int C4 = LW / 4;
+        for (int idx = tid; idx < NR * C4; idx += 256) {
+            const int rr = idx / C4, c4 = idx - rr * C4;
+            const int yy = y0 - R + rr;
+            float4 v;
+            if (ZERO_PAD && (yy < 0 || yy >= H)) v = make_float4(0.f, 0.f, 0.f, 0.f);
+            else v = *reinterpret_cast<const float4*>(plane + (size_t)clampi(yy, H) * W + (x0 - RA + 4 * c4));
+            *reinterpret_cast<float4*>(&s[rr * LW + 4 * c4]) = v;
+        }
+    } else {
+        for (int idx = tid; idx < NR * LW; idx += 256) {
+            const int rr = idx / LW, c = idx - rr * LW;
+            const int yy = y0 - R + rr, xx = x0 - RA + c;
+            float v;
+            if (ZERO_PAD && (yy < 0 || yy >= H || xx < 0 || xx >= W)) v = 0.f;
+            else v = plane[(size_t)clampi(yy, H) * W + clampi(xx, W)];
+            s[rr * LW + c] = v;
+        }
+    }
+}
+
+// acc += correlation of the staged tile with taps wf (flat (2r+1)^2, row major);
+// FLIP reads the taps reversed (the adjoint's flipped filter).
+template <int R, bool FLIP>
+__device__ __forceinline__ void corr_block(const float* __restrict__ s, const float* __restrict__ wf,
+                                           float (&acc)[BPY][BPX]) {
+    using G = BankTile<R>;
+    constexpr int LW = G::LW, RA = G::RA, WIN = G::WIN, N = 2 * R + 1;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const float* base = s + (ty * BPY) * LW + tx * BPX;
+#pragma unroll 1
+    for (int q = 0; q < BPY + 2 * R; ++q) {
+        float win[WIN];
+#pragma unroll
+        for (int m = 0; m < WIN / 4; ++m) {
+            const float4 v = *reinterpret_cast<const float4*>(base + q * LW + 4 * m);
+            win[4 * m] = v.x; win[4 * m + 1] = v.y; win[4 * m + 2] = v.z; win[4 * m + 3] = v.w;
+        }
+#pragma unroll
+        for (int py = 0; py < BPY; ++py) {
+            const int j = q - py;
+            if (j < 0 || j >= N) continue;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const float c = FLIP ? wf[N * N - 1 - (j * N + i)] : wf[j * N + i];
+#pragma unroll
+                for (int px = 0; px < BPX; ++px) acc[py][px] = fmaf(c, win[RA - R + px + i], acc[py][px]);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void store_block(float* __restrict__ plane, int W, int H, int x0, int y0, bool vec,
+                                            const float (&acc)[BPY][BPX]) {
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int xb = x0 + tx * BPX;
+#pragma unroll
+    for (int py = 0; py < BPY; ++py) {
+        const int y = y0 + ty * BPY + py;
+        if (y >= H) break;
+        float* row = plane + (size_t)y * W;
+        if (vec && xb + BPX <= W) {
+            *reinterpret_cast<float4*>(row + xb) = make_float4(acc[py][0], acc[py][1], acc[py][2], acc[py][3]);
+        } else {
+#pragma unroll
+            for (int px = 0; px < BPX; ++px)
+                if (xb + px < W) row[xb + px] = acc[py][px];
+        }
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void bank_fwd_k(const float* __restrict__ x, const float* __restrict__ w,
+                                                  float* __restrict__ y, int F, int H, int W, int tiles_x,
+                                                  int tiles_img, int vec) {
+    using G = BankTile<R>;
+    __shared__ float s[G::NR * G::LW];
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int n = (int)(t / (unsigned)tiles_img), ti = (int)(t % (unsigned)tiles_img);
+    const int x0 = (ti % tiles_x) * BT, y0 = (ti / tiles_x) * BT;
+    const size_t hw = (size_t)H * W;
+    stage_plane<R, false>(x + (size_t)n * hw, W, H, x0, y0, vec, s);
+    __syncthreads();
+    constexpr int NK = (2 * R + 1) * (2 * R + 1);
+#pragma unroll 1
+    for (int f = 0; f < F; ++f) {
+        float acc[BPY][BPX] = {};
+        corr_block<R, false>(s, w + (size_t)f * NK, acc);
+        store_block(y + ((size_t)n * F + f) * hw, W, H, x0, y0, vec, acc);
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void bank_bwd_in_k(const float* __restrict__ gy, const float* __restrict__ w,
+                                                     float* __restrict__ gx, int F, int H, int W, int tiles_x,
+                                                     int tiles_img, int vec) {
+    using G = BankTile<R>;
+    __shared__ float s[G::NR * G::LW];
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int n = (int)(t / (unsigned)tiles_img), ti = (int)(t % (unsigned)tiles_img);
+    const int x0 = (ti % tiles_x) * BT, y0 = (ti / tiles_x) * BT;
+    const size_t hw = (size_t)H * W;
+    constexpr int NK = (2 * R + 1) * (2 * R + 1);
+    float acc[BPY][BPX] = {};
+#pragma unroll 1
+    for (int f = 0; f < F; ++f) {
+        if (f) __syncthreads();
+        stage_plane<R, true>(gy + ((size_t)n * F + f) * hw, W, H, x0, y0, vec, s);
+        __syncthreads();
+        corr_block<R, true>(s, w + (size_t)f * NK, acc);
+    }
+    store_block(gx + (size_t)n * hw, W, H, x0, y0, vec, acc);
+}
+
+// Edge fold: gx[q] += sum of z[u] over padded u != q with clamp(u) = q.
+__global__ __launch_bounds__(256) void bank_bwd_fold_k(const float* __restrict__ gy, const float* __restrict__ w,
+                                                       float* __restrict__ gx, int N, int F, int H, int W, int r,
+                                                       int per_img) {
+    const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= (long long)N * per_img) return;
+    const int n = (int)(gid / per_img);
+    int e = (int)(gid % per_img);
+    // enumerate the edge pixels: top row, bottom row, then the left and right columns between them
+    int qx, qy;
+    if (e < W) { qx = e; qy = 0; }
+    else if (H > 1 && e < 2 * W) { qx = e - W; qy = H - 1; }
+    else {
+        e -= (H > 1 ? 2 * W : W);
+        const int rows = H - 2;
+        if (e < rows) { qx = 0; qy = 1 + e; }
+        else { qx = W - 1; qy = 1 + (e - rows); }
+    }
+    const int lox = (qx == 0) ? -r : qx, hix = (qx == W - 1) ? W - 1 + r : qx;
+    const int loy = (qy == 0) ? -r : qy, hiy = (qy == H - 1) ? H - 1 + r : qy;
+    const int nk = 2 * r + 1;
+    const size_t hw = (size_t)H * W;
+    float extra = 0.f;
+    for (int uy = loy; uy <= hiy; ++uy)
+        for (int ux = lox; ux <= hix; ++ux) {
+            if (ux == qx && uy == qy) continue;
+            float z = 0.f;
+            for (int f = 0; f < F; ++f) {
+                const float* g = gy + ((size_t)n * F + f) * hw;
+                const float* wf = w + (size_t)f * nk * nk;
+                for (int j = -r; j <= r; ++j) {
+                    const int py = uy - j;
+                    if (py < 0 || py >= H) continue;
+                    for (int i = -r; i <= r; ++i) {
+                        const int px = ux - i;
+                        if (px < 0 || px >= W) continue;
+                        z = fmaf(wf[(j + r) * nk + (i + r)], g[(size_t)py * W + px], z);
+                    }
+                }
+            }
+            extra += z;
+        }
+    gx[(size_t)n * hw + (size_t)qy * W + qx] += extra;
+}
+
+int edge_pixels(int W, int H) {
+    if (H == 1) return W;
+    if (W == 1) return H;
+    return 2 * W + 2 * (H - 2);
+}
+
+// ------------------------------------------------------------------ filter gradient
+constexpr int GW_TW = 32, GW_TH = 64, GW_CH = 16;   // tile 32 cols x 64 rows, row chunks of 16
+
+template <int R> struct GwTile {
+    static constexpr int RA = (R + 3) & ~3;
+    static constexpr int LW = GW_TW + 2 * RA;
+    static constexpr int NR = GW_TH + 2 * R;
+};
+
+template <int R>
+__global__ __launch_bounds__(64) void bank_bwd_w1_k(const float* __restrict__ gy, const float* __restrict__ x,
+                                                    float* __restrict__ part, int F, int H, int W, int tiles_x,
+                                                    int tiles_img, int ntiles) {
+    using G = GwTile<R>;
+    constexpr int N = 2 * R + 1, LW = G::LW, NR = G::NR, RA = G::RA;
+    __shared__ float s[NR * LW];
+    // block -> (tile, filter); the F blocks of one tile are consecutive logical ids, kept on one XCD
+    const unsigned id = xcd_remap(blockIdx.x, gridDim.x);
+    const int f = (int)(id % (unsigned)F);
+    const int tile = (int)(id / (unsigned)F);
+    const int n = tile / tiles_img, ti = tile % tiles_img;
+    const int x0 = (ti % tiles_x) * GW_TW, y0 = (ti / tiles_x) * GW_TH;
+    const size_t hw = (size_t)H * W;
+    const float* xp = x + (size_t)n * hw;
+    const int lane = threadIdx.x;
+    for (int idx = lane; idx < NR * LW; idx += 64) {
+        const int rr = idx / LW, c = idx - rr * LW;
+        s[idx] = xp[(size_t)clampi(y0 - R + rr, H) * W + clampi(x0 - RA + c, W)];
+    }
+    __syncthreads();
+    const float* g = gy + ((size_t)n * F + f) * hw;
+    const int col = lane & 31, half = lane >> 5;
+    const int gx_ = x0 + col;
+    float acc[N][N];
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[j][i] = 0.f;
+#pragma unroll 1
+    for (int c = 0; c < GW_TH / 2 / GW_CH; ++c) {
+        const int r0 = half * (GW_TH / 2) + c * GW_CH;   // first tile row of this chunk
+        float gv[GW_CH];
+#pragma unroll
+        for (int py = 0; py < GW_CH; ++py) {
+            const int yy = y0 + r0 + py;
+            gv[py] = (gx_ < W && yy < H) ? g[(size_t)yy * W + gx_] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            float cv[GW_CH + 2 * R];
+#pragma unroll
+            for (int m = 0; m < GW_CH + 2 * R; ++m) cv[m] = s[(r0 + m) * LW + col + RA - R + i];
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+#pragma unroll
+                for (int py = 0; py < GW_CH; ++py) acc[j][i] = fmaf(gv[py], cv[py + j], acc[j][i]);
+        }
+    }
+    // butterfly over the wave (fixed order), lane 0 writes the (f, tile) partials
+    float* out = part + (size_t)f * N * N * ntiles + tile;
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            float v = acc[j][i];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) out[(size_t)(j * N + i) * ntiles] = v;
+        }
+}
+
+// gw[f,k] = sum over tiles of part[f][k][tile], fixed-order tree per (f, k)
+__global__ __launch_bounds__(256) void bank_bwd_w2_k(const float* __restrict__ part, float* __restrict__ gw,
+                                                     int ntiles) {
+    __shared__ float red[256];
+    const float* p = part + (size_t)blockIdx.x * ntiles;
+    float v = 0.f;
+    for (int t = threadIdx.x; t < ntiles; t += 256) v += p[t];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gw[blockIdx.x] = red[0];
+}
+
+// ------------------------------------------------------------------ launchers
+int bank_vec(const float* a, const float* b, int W) {
+    return ((uintptr_t)a % 16 == 0) && ((uintptr_t)b % 16 == 0) && (W % 4 == 0);
+}
+
+template <int R>
+hipError_t fwd_R(const BankArgs& a) {
+    const int tx = (a.w + BT - 1) / BT, ty = (a.h + BT - 1) / BT;
+    hipLaunchKernelGGL(bank_fwd_k<R>, dim3((unsigned)(a.n * tx * ty)), dim3(256), 0, a.st, a.a, a.b, a.out, a.f, a.h,
+                       a.w, tx, tx * ty, bank_vec(a.a, a.out, a.w));
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t bwd_in_R(const BankArgs& a) {
+    const int tx = (a.w + BT - 1) / BT, ty = (a.h + BT - 1) / BT;
+    hipLaunchKernelGGL(bank_bwd_in_k<R>, dim3((unsigned)(a.n * tx * ty)), dim3(256), 0, a.st, a.a, a.b, a.out, a.f,
+                       a.h, a.w, tx, tx * ty, bank_vec(a.a, a.out, a.w));
+    const int per = edge_pixels(a.w, a.h);
+    const long long tot = (long long)a.n * per;
+    hipLaunchKernelGGL(bank_bwd_fold_k, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, a.st, a.a, a.b, a.out, a.n,
+                       a.f, a.h, a.w, a.r, per);
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t bwd_w_R(const BankArgs& a) {
+    const int tx = (a.w + GW_TW - 1) / GW_TW, ty = (a.h + GW_TH - 1) / GW_TH;
+    const int ntiles = a.n * tx * ty;
+    float* part = static_cast<float*>(a.ws);
+    hipLaunchKernelGGL(bank_bwd_w1_k<R>, dim3((unsigned)(ntiles * a.f)), dim3(64), 0, a.st, a.a, a.b, part, a.f, a.h,
+                       a.w, tx, tx * ty, ntiles);
+    const int nk = (2 * R + 1) * (2 * R + 1);
+    hipLaunchKernelGGL(bank_bwd_w2_k, dim3((unsigned)(a.f * nk)), dim3(256), 0, a.st, part, a.out, ntiles);
+    return hipGetLastError();
+}
+
+#define ICL_BANK_SWITCH(FN)                   \
+    switch (a.r) {                            \
+        case 1: return FN<1>(a);              \
+        case 2: return FN<2>(a);              \
+        case 3: return FN<3>(a);              \
+        case 4: return FN<4>(a);              \
+        default: return hipErrorInvalidValue; \
+    }
+
+hipError_t launch_fwd(const BankArgs& a) { ICL_BANK_SWITCH(fwd_R) }
+hipError_t launch_bwd_in(const BankArgs& a) { ICL_BANK_SWITCH(bwd_in_R) }
+hipError_t launch_bwd_w(const BankArgs& a) { ICL_BANK_SWITCH(bwd_w_R) }
+
+bool supports_bank(const BankArgs& a) { return a.r >= 1 && a.r <= 4 && a.f >= 1 && a.f <= 64; }
+bool supports_bwd_w(const BankArgs& a) {
+    return supports_bank(a) && a.ws != nullptr && a.wsb >= bank_bwd_filter_workspace(a.n, a.f, a.h, a.w, a.r);
+}
+
+const Variant<BankArgs> kFwd[] = {{"tile64_p4x4", supports_bank, launch_fwd}};
+const Variant<BankArgs> kBwdIn[] = {{"tile64_p4x4_fold", supports_bank, launch_bwd_in}};
+const Variant<BankArgs> kBwdW[] = {{"wave_t32x64", supports_bwd_w, launch_bwd_w}};
+
+// ------------------------------------------------------------------ sum of squares loss
+constexpr int SSE_BLOCKS = 2048;
+
+__global__ __launch_bounds__(256) void sse_k1(const float* __restrict__ y, const float* __restrict__ t,
+                                              float* __restrict__ gy, long long count, float* __restrict__ part,
+                                              int vec) {
+    __shared__ float red[256];
+    float acc = 0.f;
+    const long long stride = (long long)gridDim.x * 256;
+    if (vec) {
+        const long long n4 = count / 4;
+        for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < n4; q += stride) {
+            const float4 a = reinterpret_cast<const float4*>(y)[q];
+            const float4 b = reinterpret_cast<const float4*>(t)[q];
+            const float4 d = make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+            acc = fmaf(d.x, d.x, acc); acc = fmaf(d.y, d.y, acc);
+            acc = fmaf(d.z, d.z, acc); acc = fmaf(d.w, d.w, acc);
+            if (gy) reinterpret_cast<float4*>(gy)[q] = make_float4(2.f * d.x, 2.f * d.y, 2.f * d.z, 2.f * d.w);
+        }
+        for (long long q = n4 * 4 + (long long)blockIdx.x * 256 + threadIdx.x; q < count; q += stride) {
+            const float d = y[q] - t[q];
+            acc = fmaf(d, d, acc);
+            if (gy) gy[q] = 2.f * d;
+        }
+    } else {
+        for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < count; q += stride) {
+            const float d = y[q] - t[q];
+            acc = fmaf(d, d, acc);
+            if (gy) gy[q] = 2.f * d;
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void sse_k2(const float* __restrict__ part, int nparts, float* __restrict__ loss) {
+    __shared__ float red[256];
+    float v = 0.f;
+    for (int q = threadIdx.x; q < nparts; q += 256) v += part[q];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0];
+}
+
+}  // namespace
+
+size_t bank_bwd_filter_workspace(int n, int f, int h, int w, int r) {
+    const size_t tx = (size_t)(w + GW_TW - 1) / GW_TW, ty = (size_t)(h + GW_TH - 1) / GW_TH;
+    const size_t nk = (size_t)(2 * r + 1) * (2 * r + 1);
+    return (size_t)n * tx * ty * (size_t)f * nk * sizeof(float);
+}
+
+size_t sse_workspace(long long) { return SSE_BLOCKS * sizeof(float); }
+
+namespace {
+__global__ __launch_bounds__(256) void zero_k(float* __restrict__ p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+}  // namespace
+
+hipError_t zero_fill(float* p, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t sse_launch(const float* y, const float* t, float* gy, long long count, float* loss, void* ws, size_t,
+                      hipStream_t st) {
+    float* part = static_cast<float*>(ws);
+    const int vec = ((uintptr_t)y % 16 == 0) && ((uintptr_t)t % 16 == 0) && (gy == nullptr || (uintptr_t)gy % 16 == 0);
+    hipLaunchKernelGGL(sse_k1, dim3(SSE_BLOCKS), dim3(256), 0, st, y, t, gy, count, part, vec);
+    hipLaunchKernelGGL(sse_k2, dim3(1), dim3(256), 0, st, part, SSE_BLOCKS, loss);
+    return hipGetLastError();
+}
+
+const Variant<BankArgs>* bank_fwd_variants(int* count) {
+    *count = 1;
+    return kFwd;
+}
+const Variant<BankArgs>* bank_bwd_input_variants(int* count) {
+    *count = 1;
+    return kBwdIn;
+}
+const Variant<BankArgs>* bank_bwd_filter_variants(int* count) {
+    *count = 1;
+    return kBwdW;
+}
+
+}  // namespace icl

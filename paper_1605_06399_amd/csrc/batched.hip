@@ -1,0 +1,266 @@
+// Batched separable convolution over images of uneven size and radius in one
+// persistent launch.  The host turns the batch into a table of 64x32 output
+// tiles, each naming its image; a grid sized to the device's resident capacity
+// walks the table with a fixed stride, and each tile runs the same fused
+// single-pass body as icl_conv_sep (row pass into LDS, column pass from LDS),
+// instantiated per radius and picked by a wave-uniform branch on the image's
+// radius.  Launch arguments are only the two tables, so the launch captures into
+// a HIP graph as one kernel node and replays re-read images and taps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "icl_device.hpp"
+#include "icl_internal.hpp"
+#include "sep_tile.hpp"
+
+namespace icl {
+
+struct DevImage {
+    const void* src;
+    void* dst;
+    unsigned long long sp, dp;
+    const float* tx;
+    const float* ty;
+    int W, H, r, vec_ok;
+};
+
+struct BatchTile {
+    int img, x0, y0, pad;
+};
+
+namespace {
+
+constexpr int BTH = 32;    // tile rows
+constexpr int BCX = 1;     // tile columns = 64 * BCX
+constexpr int RMAX = 7;
+
+template <class T>
+__global__ __launch_bounds__(256) void sep_batched_k(const DevImage* __restrict__ imgs,
+                                                     const BatchTile* __restrict__ tiles, int ntiles) {
+    __shared__ float lds[SepTile<RMAX, BTH, BCX>::LDS_FLOATS];
+    const int start = (int)xcd_remap(blockIdx.x, gridDim.x);
+    for (int t = start; t < ntiles; t += gridDim.x) {
+        const BatchTile bt = tiles[t];
+        const DevImage d = imgs[bt.img];
+        switch (d.r) {
+#define ICL_BATCH_CASE(R)                                                                                      \
+    case R: {                                                                                                  \
+        constexpr int RA = SepTile<R, BTH, BCX>::RA;                                                           \
+        const bool vec = d.vec_ok && bt.x0 - RA >= 0 && bt.x0 + 64 * BCX + RA <= d.W;                          \
+        sep_tile_body<T, R, BTH, BCX>(d.src, d.sp, d.dst, d.dp, d.W, d.H, d.tx, d.ty, bt.x0, bt.y0, vec, lds); \
+        break;                                                                                                 \
+    }
+            ICL_BATCH_CASE(0)
+            ICL_BATCH_CASE(1)
+            ICL_BATCH_CASE(2)
+            ICL_BATCH_CASE(3)
+            ICL_BATCH_CASE(4)
+            ICL_BATCH_CASE(5)
+            ICL_BATCH_CASE(6)
+            ICL_BATCH_CASE(7)
+#undef ICL_BATCH_CASE
+            default: break;
+        }
+        __syncthreads();   // LDS is reused by the next tile
+    }
+}
+
+}  // namespace
+}  // namespace icl
+
+using namespace icl;
+
+struct icl_batch_plan {
+    icl_dtype dt;
+    DevImage* d_imgs;
+    BatchTile* d_tiles;
+    int ntiles;
+    int grid;
+    long long pixels;
+};
+
+namespace {
+
+template <class T>
+const void* batched_kernel() {
+    return reinterpret_cast<const void*>(&sep_batched_k<T>);
+}
+
+const void* kernel_for(icl_dtype dt) {
+    switch (dt) {
+        case ICL_F32: return batched_kernel<F32>();
+        case ICL_F16: return batched_kernel<F16>();
+        default: return batched_kernel<BF16>();
+    }
+}
+
+bool ranges_overlap(uintptr_t a0, uintptr_t a1, uintptr_t b0, uintptr_t b1) { return a0 < b1 && b0 < a1; }
+
+}  // namespace
+
+extern "C" {
+
+icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dtype dtype, icl_batch_plan** plan) {
+    if (!plan) return ICL_ERR_INVALID_VALUE;
+    *plan = nullptr;
+    if (count < 0 || (count > 0 && !descs)) return ICL_ERR_INVALID_VALUE;
+    if (dtype != ICL_F32 && dtype != ICL_F16 && dtype != ICL_BF16) return ICL_ERR_DTYPE;
+    const int es = elem_size(dtype);
+    std::vector<DevImage> imgs;
+    std::vector<BatchTile> tiles;
+    long long pixels = 0;
+    const size_t al = 4 * (size_t)es;
+    for (int i = 0; i < count; ++i) {
+        const icl_image_desc& d = descs[i];
+        if (d.width < 0 || d.height < 0) return ICL_ERR_INVALID_VALUE;
+        if (d.radius < 0 || d.radius > RMAX) return ICL_ERR_RADIUS;
+        if (d.width == 0 || d.height == 0) {
+            imgs.push_back(DevImage{});
+            continue;
+        }
+        if (!d.src || !d.dst || !d.taps_x || !d.taps_y) return ICL_ERR_INVALID_VALUE;
+        if (d.src_pitch < (size_t)d.width * es || d.src_pitch % es || d.dst_pitch < (size_t)d.width * es ||
+            d.dst_pitch % es)
+            return ICL_ERR_PITCH;
+        const uintptr_t s0 = (uintptr_t)d.src, s1 = s0 + (size_t)(d.height - 1) * d.src_pitch + (size_t)d.width * es;
+        const uintptr_t o0 = (uintptr_t)d.dst, o1 = o0 + (size_t)(d.height - 1) * d.dst_pitch + (size_t)d.width * es;
+        if (ranges_overlap(s0, s1, o0, o1)) return ICL_ERR_ALIAS;
+        DevImage di;
+        di.src = d.src; di.dst = d.dst; di.sp = d.src_pitch; di.dp = d.dst_pitch;
+        di.tx = d.taps_x; di.ty = d.taps_y; di.W = d.width; di.H = d.height; di.r = d.radius;
+        di.vec_ok = ((uintptr_t)d.src % al == 0) && (d.src_pitch % al == 0);
+        imgs.push_back(di);
+        pixels += (long long)d.width * d.height;
+        const int tx = (d.width + 64 * BCX - 1) / (64 * BCX), ty = (d.height + BTH - 1) / BTH;
+        for (int y = 0; y < ty; ++y)
+            for (int x = 0; x < tx; ++x) tiles.push_back(BatchTile{i, x * 64 * BCX, y * BTH, 0});
+    }
+    // outputs of different images must not overlap each other or any input
+    {
+        std::vector<std::pair<uintptr_t, uintptr_t>> outs, ins;
+        for (const DevImage& d : imgs) {
+            if (!d.src) continue;
+            outs.push_back({(uintptr_t)d.dst, (uintptr_t)d.dst + (size_t)(d.H - 1) * d.dp + (size_t)d.W * es});
+            ins.push_back({(uintptr_t)d.src, (uintptr_t)d.src + (size_t)(d.H - 1) * d.sp + (size_t)d.W * es});
+        }
+        std::vector<std::pair<uintptr_t, uintptr_t>> so = outs;
+        std::sort(so.begin(), so.end());
+        for (size_t k = 1; k < so.size(); ++k)
+            if (so[k].first < so[k - 1].second) return ICL_ERR_ALIAS;
+        std::sort(ins.begin(), ins.end());
+        for (const auto& o : so) {
+            auto it = std::lower_bound(ins.begin(), ins.end(), std::make_pair(o.second, (uintptr_t)0));
+            // any input starting before o ends and ending after o starts overlaps
+            for (auto j = ins.begin(); j != it; ++j)
+                if (j->second > o.first) return ICL_ERR_ALIAS;
+        }
+    }
+    icl_status s = device_ready();
+    if (s != ICL_OK) return s;
+    icl_batch_plan* p = new (std::nothrow) icl_batch_plan{};
+    if (!p) return ICL_ERR_INVALID_VALUE;
+    p->dt = dtype;
+    p->ntiles = (int)tiles.size();
+    p->pixels = pixels;
+    hipError_t e = hipSuccess;
+    if (!imgs.empty()) e = hipMalloc(&p->d_imgs, imgs.size() * sizeof(DevImage));
+    if (e == hipSuccess && !tiles.empty()) e = hipMalloc(&p->d_tiles, tiles.size() * sizeof(BatchTile));
+    if (e == hipSuccess && !imgs.empty())
+        e = hipMemcpy(p->d_imgs, imgs.data(), imgs.size() * sizeof(DevImage), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !tiles.empty())
+        e = hipMemcpy(p->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
+    int per_cu = 0, dev = 0, cus = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(dtype), 256, 0);
+    if (e != hipSuccess) {
+        hipFree(p->d_imgs);
+        hipFree(p->d_tiles);
+        delete p;
+        return hip_status(e);
+    }
+    const long long resident = (long long)std::max(per_cu, 1) * std::max(cus, 1);
+    p->grid = (int)std::min<long long>(resident, std::max(p->ntiles, 1));
+    // a multiple of 8 keeps the XCD-aware remap a permutation of the grid
+    if (p->grid > 8) p->grid -= p->grid % 8;
+    *plan = p;
+    return ICL_OK;
+}
+
+icl_status icl_conv_sep_batched(const icl_batch_plan* plan, void* stream) {
+    if (!plan) return ICL_ERR_INVALID_VALUE;
+    if (plan->ntiles == 0) return ICL_OK;
+    hipStream_t st = (hipStream_t)stream;
+    switch (plan->dt) {
+        case ICL_F32:
+            hipLaunchKernelGGL(sep_batched_k<F32>, dim3(plan->grid), dim3(256), 0, st, plan->d_imgs, plan->d_tiles,
+                               plan->ntiles);
+            break;
+        case ICL_F16:
+            hipLaunchKernelGGL(sep_batched_k<F16>, dim3(plan->grid), dim3(256), 0, st, plan->d_imgs, plan->d_tiles,
+                               plan->ntiles);
+            break;
+        default:
+            hipLaunchKernelGGL(sep_batched_k<BF16>, dim3(plan->grid), dim3(256), 0, st, plan->d_imgs, plan->d_tiles,
+                               plan->ntiles);
+            break;
+    }
+    return hip_status(hipGetLastError());
+}
+
+icl_status icl_batch_plan_info(const icl_batch_plan* plan, long long* tiles, long long* pixels) {
+    if (!plan) return ICL_ERR_INVALID_VALUE;
+    if (tiles) *tiles = plan->ntiles;
+    if (pixels) *pixels = plan->pixels;
+    return ICL_OK;
+}
+
+void icl_batch_plan_destroy(icl_batch_plan* plan) {
+    if (!plan) return;
+    hipFree(plan->d_imgs);
+    hipFree(plan->d_tiles);
+    delete plan;
+}
+
+icl_status icl_batch_graph_create(const icl_batch_plan* plan, void** exec) {
+    if (!plan || !exec) return ICL_ERR_INVALID_VALUE;
+    *exec = nullptr;
+    icl_status s = device_ready();
+    if (s != ICL_OK) return s;
+    hipStream_t st = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_status(e);
+    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const icl_status ls = icl_conv_sep_batched(plan, st);
+        const hipError_t ee = hipStreamEndCapture(st, &graph);
+        if (ls != ICL_OK) {
+            if (graph) hipGraphDestroy(graph);
+            hipStreamDestroy(st);
+            return ls;
+        }
+        e = ee;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+    if (graph) hipGraphDestroy(graph);
+    hipStreamDestroy(st);
+    if (e != hipSuccess) return hip_status(e);
+    *exec = ge;
+    return ICL_OK;
+}
+
+icl_status icl_graph_launch(void* exec, void* stream) {
+    if (!exec) return ICL_ERR_INVALID_VALUE;
+    return hip_status(hipGraphLaunch((hipGraphExec_t)exec, (hipStream_t)stream));
+}
+
+void icl_graph_destroy(void* exec) {
+    if (exec) hipGraphExecDestroy((hipGraphExec_t)exec);
+}
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// Separable convolution with clamped reads (ImageCL paper, Section 6:
+// separable convolution benchmark, row kernel R and column kernel C, Table 2).
+//
+//   T(x,y)   = sum_i tx[i+r] * src(clamp(x+i), y)
+//   dst(x,y) = sum_j ty[j+r] * T(x, clamp(y+j))
+//
+// Variants
+//   plain2p           : the paper's naive code generation, twice: one thread per
+//                       pixel, 16x16 work-groups, clamp on every read, runtime tap
+//                       loop; the row pass writes a float32 intermediate to HBM.
+//   fused_t{TH}_c{CX} : one pass.  A work-group owns a 64*CX x TH output tile,
+//                       stages the (TH+2r) x (64*CX+2*RA) input rows it needs in
+//                       LDS (float4 loads for interior tiles), runs the row pass
+//                       four columns per lane into a second LDS tile, and the
+//                       column pass from LDS with TH/4 rows per lane.  The
+//                       intermediate never leaves the CU (the fusion the paper's
+//                       discussion credits for Halide's win).  CX = 2 gives each
+//                       lane two columns 64 apart (interleaved within the
+//                       work-group, Fig. 4c), keeping stores coalesced.
+#include "icl_device.hpp"
+#include "icl_internal.hpp"
+#include "sep_tile.hpp"
+
+namespace icl {
+namespace {
+
+// ------------------------------------------------------------------ plain two-pass
+template <class T>
+__global__ __launch_bounds__(256) void sep_row_plain(const void* __restrict__ src, size_t sp,
+                                                     float* __restrict__ tmp, int W, int H,
+                                                     const float* __restrict__ tx, int r) {
+    const int x = blockIdx.x * 16 + threadIdx.x % 16;
+    const int y = blockIdx.y * 16 + threadIdx.x / 16;
+    if (x >= W || y >= H) return;
+    float acc = 0.f;
+    for (int i = -r; i <= r; ++i)
+        acc += tx[i + r] * load_px<T>(src, (size_t)y * sp + (size_t)clampi(x + i, W) * T::size);
+    tmp[(size_t)y * W + x] = acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void sep_col_plain(const float* __restrict__ tmp, void* __restrict__ dst,
+                                                     size_t dp, int W, int H,
+                                                     const float* __restrict__ ty, int r) {
+    const int x = blockIdx.x * 16 + threadIdx.x % 16;
+    const int y = blockIdx.y * 16 + threadIdx.x / 16;
+    if (x >= W || y >= H) return;
+    float acc = 0.f;
+    for (int j = -r; j <= r; ++j) acc += ty[j + r] * tmp[(size_t)clampi(y + j, H) * W + x];
+    store_px<T>(dst, (size_t)y * dp + (size_t)x * T::size, acc);
+}
+
+template <class T>
+hipError_t launch_plain_T(const SepArgs& a) {
+    float* tmp = static_cast<float*>(a.ws);
+    dim3 grid((a.W + 15) / 16, (a.H + 15) / 16);
+    hipLaunchKernelGGL(sep_row_plain<T>, grid, dim3(256), 0, a.st, a.src, a.sp, tmp, a.W, a.H, a.tx, a.r);
+    hipLaunchKernelGGL(sep_col_plain<T>, grid, dim3(256), 0, a.st, tmp, a.dst, a.dp, a.W, a.H, a.ty, a.r);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain(const SepArgs& a) {
+    switch (a.dt) {
+        case ICL_F32: return launch_plain_T<F32>(a);
+        case ICL_F16: return launch_plain_T<F16>(a);
+        default: return launch_plain_T<BF16>(a);
+    }
+}
+
+bool supports_plain(const SepArgs& a) {
+    return a.ws != nullptr && a.wsb >= sep_workspace(a.W, a.H) && a.r >= 0 && a.r <= ICL_MAX_RADIUS;
+}
+
+}  // namespace
+
+namespace {
+
+template <class T, int R, int TH, int CX>
+__global__ __launch_bounds__(256) void sep_fused(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
+                                                 size_t dp, int W, int H, const float* __restrict__ tx,
+                                                 const float* __restrict__ ty, int tiles_x, int vec_ok) {
+    using G = SepTile<R, TH, CX>;
+    __shared__ float lds[G::LDS_FLOATS];
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int x0 = (int)(t % (unsigned)tiles_x) * G::TW;
+    const int y0 = (int)(t / (unsigned)tiles_x) * TH;
+    const bool vec = vec_ok && x0 - G::RA >= 0 && x0 + G::TW + G::RA <= W;
+    sep_tile_body<T, R, TH, CX>(src, sp, dst, dp, W, H, tx, ty, x0, y0, vec, lds);
+}
+
+template <class T, int R, int TH, int CX>
+hipError_t launch_fused_TR(const SepArgs& a) {
+    using G = SepTile<R, TH, CX>;
+    const int tiles_x = (a.W + G::TW - 1) / G::TW;
+    const int tiles_y = (a.H + TH - 1) / TH;
+    const size_t vec_align = 4 * (size_t)T::size;
+    const int vec_ok = ((uintptr_t)a.src % vec_align == 0) && (a.sp % vec_align == 0);
+    hipLaunchKernelGGL((sep_fused<T, R, TH, CX>), dim3(tiles_x * tiles_y), dim3(256), 0, a.st, a.src, a.sp,
+                       a.dst, a.dp, a.W, a.H, a.tx, a.ty, tiles_x, vec_ok);
+    return hipGetLastError();
+}
+
+template <class T, int TH, int CX>
+hipError_t launch_fused_T(const SepArgs& a) {
+    switch (a.r) {
+        case 0: return launch_fused_TR<T, 0, TH, CX>(a);
+        case 1: return launch_fused_TR<T, 1, TH, CX>(a);
+        case 2: return launch_fused_TR<T, 2, TH, CX>(a);
+        case 3: return launch_fused_TR<T, 3, TH, CX>(a);
+        case 4: return launch_fused_TR<T, 4, TH, CX>(a);
+        case 5: return launch_fused_TR<T, 5, TH, CX>(a);
+        case 6: return launch_fused_TR<T, 6, TH, CX>(a);
+        case 7: return launch_fused_TR<T, 7, TH, CX>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int TH, int CX>
+hipError_t launch_fused(const SepArgs& a) {
+    switch (a.dt) {
+        case ICL_F32: return launch_fused_T<F32, TH, CX>(a);
+        case ICL_F16: return launch_fused_T<F16, TH, CX>(a);
+        default: return launch_fused_T<BF16, TH, CX>(a);
+    }
+}
+
+bool supports_fused(const SepArgs& a) { return a.r >= 0 && a.r <= 7; }
+
+const Variant<SepArgs> kSep[] = {
+    {"plain2p", supports_plain, launch_plain},
+    {"fused_t32_c1", supports_fused, launch_fused<32, 1>},
+    {"fused_t64_c1", supports_fused, launch_fused<64, 1>},
+    {"fused_t32_c2", supports_fused, launch_fused<32, 2>},
+    {"fused_t16_c2", supports_fused, launch_fused<16, 2>},
+};
+
+}  // namespace
+
+size_t sep_workspace(int W, int H) { return (size_t)W * (size_t)H * sizeof(float); }
+
+const Variant<SepArgs>* sep_variants(int* count) {
+    *count = (int)(sizeof(kSep) / sizeof(kSep[0]));
+    return kSep;
+}
+
+int sep_default(const SepArgs& a) { return supports_fused(a) ? 1 : 0; }
+
+}  // namespace icl

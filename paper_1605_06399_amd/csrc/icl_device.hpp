@@ -1,0 +1,100 @@
+// Device-side helpers shared by the gfx950 stencil kernels: storage decode /
+// encode, clamped indexing and work-group ordering.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace icl {
+
+// ------------------------------------------------------------------ storage types
+// Pixel storage tags.  Arithmetic is always float32; these convert on load/store.
+struct F32 { using storage = float; static constexpr int size = 4; };
+struct F16 { using storage = _Float16; static constexpr int size = 2; };
+struct BF16 { using storage = uint16_t; static constexpr int size = 2; };
+
+__device__ __forceinline__ float decode(float v) { return v; }
+__device__ __forceinline__ float decode(_Float16 v) { return static_cast<float>(v); }
+__device__ __forceinline__ float decode_bf16(uint16_t b) {
+    return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+
+// bfloat16 round to nearest even (NaN stays a quiet NaN).
+__device__ __forceinline__ uint16_t encode_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+
+template <class T> __device__ __forceinline__ float load_px(const void* base, size_t off_bytes);
+template <> __device__ __forceinline__ float load_px<F32>(const void* base, size_t off) {
+    return *reinterpret_cast<const float*>(static_cast<const char*>(base) + off);
+}
+template <> __device__ __forceinline__ float load_px<F16>(const void* base, size_t off) {
+    return decode(*reinterpret_cast<const _Float16*>(static_cast<const char*>(base) + off));
+}
+template <> __device__ __forceinline__ float load_px<BF16>(const void* base, size_t off) {
+    return decode_bf16(*reinterpret_cast<const uint16_t*>(static_cast<const char*>(base) + off));
+}
+
+template <class T> __device__ __forceinline__ void store_px(void* base, size_t off, float v);
+template <> __device__ __forceinline__ void store_px<F32>(void* base, size_t off, float v) {
+    *reinterpret_cast<float*>(static_cast<char*>(base) + off) = v;
+}
+template <> __device__ __forceinline__ void store_px<F16>(void* base, size_t off, float v) {
+    *reinterpret_cast<_Float16*>(static_cast<char*>(base) + off) = static_cast<_Float16>(v);
+}
+template <> __device__ __forceinline__ void store_px<BF16>(void* base, size_t off, float v) {
+    *reinterpret_cast<uint16_t*>(static_cast<char*>(base) + off) = encode_bf16(v);
+}
+
+// Four consecutive pixels starting at a byte offset that is 4*size aligned.
+template <class T> __device__ __forceinline__ float4 load4(const void* base, size_t off);
+template <> __device__ __forceinline__ float4 load4<F32>(const void* base, size_t off) {
+    return *reinterpret_cast<const float4*>(static_cast<const char*>(base) + off);
+}
+template <> __device__ __forceinline__ float4 load4<F16>(const void* base, size_t off) {
+    const uint2 u = *reinterpret_cast<const uint2*>(static_cast<const char*>(base) + off);
+    _Float16 h[4];
+    __builtin_memcpy(h, &u, 8);
+    return make_float4(decode(h[0]), decode(h[1]), decode(h[2]), decode(h[3]));
+}
+template <> __device__ __forceinline__ float4 load4<BF16>(const void* base, size_t off) {
+    const uint2 u = *reinterpret_cast<const uint2*>(static_cast<const char*>(base) + off);
+    return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                       __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+}
+
+template <class T> __device__ __forceinline__ void store4(void* base, size_t off, float4 v);
+template <> __device__ __forceinline__ void store4<F32>(void* base, size_t off, float4 v) {
+    *reinterpret_cast<float4*>(static_cast<char*>(base) + off) = v;
+}
+template <> __device__ __forceinline__ void store4<F16>(void* base, size_t off, float4 v) {
+    _Float16 h[4] = {static_cast<_Float16>(v.x), static_cast<_Float16>(v.y),
+                     static_cast<_Float16>(v.z), static_cast<_Float16>(v.w)};
+    uint2 u;
+    __builtin_memcpy(&u, h, 8);
+    *reinterpret_cast<uint2*>(static_cast<char*>(base) + off) = u;
+}
+template <> __device__ __forceinline__ void store4<BF16>(void* base, size_t off, float4 v) {
+    uint2 u;
+    u.x = static_cast<uint32_t>(encode_bf16(v.x)) | (static_cast<uint32_t>(encode_bf16(v.y)) << 16);
+    u.y = static_cast<uint32_t>(encode_bf16(v.z)) | (static_cast<uint32_t>(encode_bf16(v.w)) << 16);
+    *reinterpret_cast<uint2*>(static_cast<char*>(base) + off) = u;
+}
+
+// ------------------------------------------------------------------ indexing
+// Closest in-range index along one axis (clamped boundary condition).
+__device__ __forceinline__ int clampi(int i, int n) { return min(max(i, 0), n - 1); }
+
+// Work-group order that keeps consecutive logical tiles on one XCD.  gfx950
+// dispatches work-groups round-robin over its 8 XCDs (each with a private L2), so
+// logical tile t is taken by the block whose hardware id places it on XCD t/(n/8).
+// Neighbouring tiles share halo rows; keeping them on one XCD serves the halo
+// from that XCD's L2.  Falls back to identity when n is not a multiple of 8.
+__device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned n) {
+    if (n % 8u) return bid;
+    return (bid % 8u) * (n / 8u) + bid / 8u;
+}
+
+}  // namespace icl

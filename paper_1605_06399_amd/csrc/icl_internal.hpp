@@ -1,0 +1,105 @@
+// Host-side internals: argument bundles, the variant registry and helpers
+// shared by the entry points, the kernels' launchers and the tuner.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/icl.h"
+
+namespace icl {
+
+inline int elem_size(icl_dtype d) { return d == ICL_F32 ? 4 : 2; }
+
+struct SepArgs {
+    const void* src; size_t sp; void* dst; size_t dp;
+    int W, H; icl_dtype dt;
+    const float* tx; const float* ty; int r;
+    void* ws; size_t wsb;
+    hipStream_t st;
+};
+
+struct Conv2dArgs {
+    const void* src; size_t sp; void* dst; size_t dp;
+    int W, H; icl_dtype dt;
+    const float* taps; int r;
+    hipStream_t st;
+};
+
+struct HarrisArgs {
+    const float* src; size_t sp; float* resp; size_t rp;
+    int W, H;
+    const float* g; int rg; float k;
+    void* ws; size_t wsb;
+    hipStream_t st;
+};
+
+struct NmsArgs {
+    const float* R; size_t rp; uint8_t* M; size_t mp;
+    int W, H; int r; float tau;
+    hipStream_t st;
+};
+
+struct BankArgs {
+    const float* a;   // x (fwd, bwd_filter) or gy (bwd_input)
+    const float* b;   // w (fwd, bwd_input) or x (bwd_filter: a = gy, b = x)
+    float* out;
+    int n, f, h, w, r;
+    void* ws; size_t wsb;
+    hipStream_t st;
+};
+
+// One precompiled candidate implementation of an operation.
+template <class A> struct Variant {
+    const char* name;
+    bool (*supports)(const A&);        // can this variant run these arguments?
+    hipError_t (*launch)(const A&);
+};
+
+// Variant tables (index 0 = plain one-pixel-per-thread kernel).
+const Variant<SepArgs>* sep_variants(int* count);
+const Variant<Conv2dArgs>* conv2d_variants(int* count);
+const Variant<HarrisArgs>* harris_variants(int* count);
+const Variant<NmsArgs>* nms_variants(int* count);
+const Variant<BankArgs>* bank_fwd_variants(int* count);
+const Variant<BankArgs>* bank_bwd_input_variants(int* count);
+const Variant<BankArgs>* bank_bwd_filter_variants(int* count);
+
+// Default choice when neither a forced variant nor a tune-cache entry applies.
+int sep_default(const SepArgs&);
+int conv2d_default(const Conv2dArgs&);
+int harris_default(const HarrisArgs&);
+int nms_default(const NmsArgs&);
+
+size_t sep_workspace(int W, int H);
+size_t harris_workspace(int W, int H);
+size_t bank_bwd_filter_workspace(int n, int f, int h, int w, int r);
+size_t sse_workspace(long long count);
+
+hipError_t sse_launch(const float* y, const float* t, float* gy, long long count, float* loss,
+                      void* ws, size_t wsb, hipStream_t st);
+
+// Variant selection shared by the entry points: forced > tune cache > default.
+int select_variant(icl_op op, icl_dtype dt, int r, int W, int H, int fallback);
+bool variant_forced(icl_op op);
+
+// Tuner hooks (tuner.cpp).
+void tune_cache_put(icl_op op, icl_dtype dt, int r, int W, int H, int variant, double us);
+int tune_cache_get(icl_op op, icl_dtype dt, int r, int W, int H);
+
+// Lazily checks that a HIP device is visible (ICL_ERR_NO_DEVICE otherwise).
+icl_status device_ready();
+const char* op_name(icl_op op);
+
+// Zero-fill `n` floats with a kernel (no memset node, so it is safe inside captured graphs).
+hipError_t zero_fill(float* p, size_t n, hipStream_t st);
+
+// Thread-local HIP error bookkeeping.
+void set_hip_error(hipError_t e);
+inline icl_status hip_status(hipError_t e) {
+    if (e == hipSuccess) return ICL_OK;
+    set_hip_error(e);
+    return ICL_ERR_HIP;
+}
+
+}  // namespace icl

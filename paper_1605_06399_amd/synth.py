@@ -46,6 +46,16 @@ def uniform01(s: int, n: int, offset: int = 0) -> np.ndarray:
     return ((v >> np.uint64(40)).astype(np.float64) * 2.0 ** -24).astype(np.float32)
 
 
+def uniform_large(s: int, n: int, lo: float = 0.0, hi: float = 1.0, chunk: int = 1 << 24) -> np.ndarray:
+    """Same values as lo + (hi - lo) * uniform01(s, n), generated in chunks to bound host memory."""
+    out = np.empty(n, dtype=np.float32)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        u = uniform01(s, b - a, offset=a)
+        out[a:b] = u if (lo, hi) == (0.0, 1.0) else (lo + (hi - lo) * u.astype(np.float64)).astype(np.float32)
+    return out
+
+
 def normal(s: int, n: int, std: float = 1.0) -> np.ndarray:
     """N(0, std^2) by Box-Muller in float64 (one normal per pair of draws), rounded to float32."""
     v = splitmix64(s, 2 * n)
@@ -97,7 +107,10 @@ def integer_image(config: int, height: int, width: int, hi: int = 255) -> np.nda
 # ----------------------------------------------------------------------------- taps
 
 def gaussian_taps(radius: int, sigma: float) -> np.ndarray:
-    """Sampled Gaussian exp(-i^2 / (2 sigma^2)), i = -r..r, normalised to sum 1 in float64, stored float32."""
+    """Sampled Gaussian exp(-i^2 / (2 sigma^2)), i = -r..r, normalised to sum 1 in float64, stored float32.
+    Radius 0 is the single tap 1."""
+    if radius == 0:
+        return np.ones(1, dtype=np.float32)
     i = np.arange(-radius, radius + 1, dtype=np.float64)
     g = np.exp(-(i * i) / (2.0 * sigma * sigma))
     return (g / g.sum()).astype(np.float32)
@@ -165,8 +178,39 @@ def batch_uneven(config: int = 4, count: int = 256, side_lo: int = 64, side_hi: 
 def bank_inputs(config: int = 5, n: int = 32, f: int = 16, h: int = 1024, w: int = 1024,
                 radius: int = 4, tap_std: float = 0.1):
     """Filter-bank workload: x [n,1,h,w] U[0,1), filters [f,2r+1,2r+1] N(0, std^2), target [n,f,h,w] U[0,1)."""
-    x = uniform01(seed(config, PIXELS), n * h * w).reshape(n, 1, h, w)
+    x = uniform_large(seed(config, PIXELS), n * h * w).reshape(n, 1, h, w)
     k = 2 * radius + 1
     wt = normal(seed(config, TAPS), f * k * k, std=tap_std).reshape(f, k, k)
-    t = uniform01(seed(config, TARGET), n * f * h * w).reshape(n, f, h, w)
+    t = uniform_large(seed(config, TARGET), n * f * h * w).reshape(n, f, h, w)
     return x, wt, t
+
+
+# ----------------------------------------------------------------------------- named workloads
+
+SWEEP_RADII = (1, 2, 3, 5, 7)
+
+
+def sweep_image(side: int = 4096) -> np.ndarray:
+    """Convolution sweep image: side x side float32, U[0,1)."""
+    return image_uniform(2, side, side)
+
+
+def sweep_taps_sep(r: int):
+    """Row and column taps of the sweep's separable filter of radius r: N(0,1) normalised to sum 1."""
+    return (normal_taps_normalised(2, 2 * r + 1, stream=10 * r),
+            normal_taps_normalised(2, 2 * r + 1, stream=10 * r + 1))
+
+
+def sweep_taps_2d(r: int) -> np.ndarray:
+    n = 2 * r + 1
+    return normal_taps_normalised(2, n * n, stream=10 * r + 2).reshape(n, n)
+
+
+def corner_image(side: int = 8192) -> np.ndarray:
+    """Harris workload: side x side U[0,1) noise plus 64 seeded bright rectangles."""
+    return image_with_rectangles(3, side, side, 64)
+
+
+def corner_window() -> np.ndarray:
+    """5x5 Gaussian window (sigma 1), as its 5 separable taps."""
+    return gaussian_taps(2, 1.0)

@@ -1,0 +1,240 @@
+"""torch-tensor front end of the C ABI.
+
+PyTorch supplies device memory and the current HIP stream; each function here
+checks devices, dtypes and strides, derives pitches in bytes and calls the
+library.  Nothing is computed in torch: outputs are allocated with
+``torch.empty`` and filled by the HIP kernels.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+
+_DT = {torch.float32: B.ICL_F32, torch.float16: B.ICL_F16, torch.bfloat16: B.ICL_BF16}
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _image(t: torch.Tensor, name: str):
+    """(pointer, pitch_bytes, width, height, icl dtype) of a 2-D row-major image view."""
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D (H, W)")
+    if t.stride(1) != 1 and t.shape[1] > 1:
+        raise ValueError(f"{name} rows must be contiguous (stride(1) == 1)")
+    es = t.element_size()
+    pitch = t.stride(0) * es if t.shape[0] > 1 else t.shape[1] * es
+    return t.data_ptr(), pitch, t.shape[1], t.shape[0]
+
+
+def _taps(t: torch.Tensor, n: int, name: str) -> int:
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be a contiguous float32 GPU tensor with {n} taps")
+    return t.data_ptr()
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(nbytes, 4) // 4 + 1, dtype=torch.float32, device=device)
+
+
+def conv_sep(x: torch.Tensor, taps_x: torch.Tensor, taps_y: torch.Tensor, out: torch.Tensor | None = None,
+             workspace: torch.Tensor | None = None) -> torch.Tensor:
+    r = (taps_x.numel() - 1) // 2
+    if out is None:
+        out = torch.empty_like(x, memory_format=torch.contiguous_format)
+    sp, spitch, W, H = _image(x, "x")
+    dp, dpitch, _, _ = _image(out, "out")
+    dt = _DT[x.dtype]
+    if workspace is None and r > 7:
+        _, nb = B.icl_workspace_size(B.ICL_OP_CONV_SEP, W, H, dtype=dt)
+        workspace = _workspace(nb, x.device)
+    ws, wsb = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None else (0, 0)
+    B.check(B.icl_conv_sep(sp, spitch, dp, dpitch, W, H, dt, _taps(taps_x, 2 * r + 1, "taps_x"),
+                           _taps(taps_y, 2 * r + 1, "taps_y"), r, ws, wsb, _stream()), "icl_conv_sep")
+    return out
+
+
+def conv2d(x: torch.Tensor, taps: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    n = taps.shape[-1]
+    r = (n - 1) // 2
+    if out is None:
+        out = torch.empty_like(x, memory_format=torch.contiguous_format)
+    sp, spitch, W, H = _image(x, "x")
+    dp, dpitch, _, _ = _image(out, "out")
+    B.check(B.icl_conv2d(sp, spitch, dp, dpitch, W, H, _DT[x.dtype], _taps(taps, n * n, "taps"), r, _stream()),
+            "icl_conv2d")
+    return out
+
+
+def harris(x: torch.Tensor, window_taps: torch.Tensor, k: float = 0.04, out: torch.Tensor | None = None,
+           workspace: torch.Tensor | None = None) -> torch.Tensor:
+    if x.dtype != torch.float32:
+        raise ValueError("harris takes a float32 image")
+    rg = (window_taps.numel() - 1) // 2
+    if out is None:
+        out = torch.empty_like(x, memory_format=torch.contiguous_format)
+    sp, spitch, W, H = _image(x, "x")
+    dp, dpitch, _, _ = _image(out, "out")
+    if workspace is None and rg > 3:
+        _, nb = B.icl_workspace_size(B.ICL_OP_HARRIS, W, H)
+        workspace = _workspace(nb, x.device)
+    ws, wsb = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None else (0, 0)
+    B.check(B.icl_harris(sp, spitch, dp, dpitch, W, H, _taps(window_taps, 2 * rg + 1, "window_taps"), rg, float(k),
+                         ws, wsb, _stream()), "icl_harris")
+    return out
+
+
+def nms(resp: torch.Tensor, threshold: float, radius: int = 1, out: torch.Tensor | None = None) -> torch.Tensor:
+    if resp.dtype != torch.float32:
+        raise ValueError("nms takes a float32 response")
+    if out is None:
+        out = torch.empty(resp.shape, dtype=torch.uint8, device=resp.device)
+    sp, spitch, W, H = _image(resp, "resp")
+    dp, dpitch, _, _ = _image(out, "out")
+    B.check(B.icl_nms(sp, spitch, dp, dpitch, W, H, int(radius), float(threshold), _stream()), "icl_nms")
+    return out
+
+
+def tune(op: int, dtype: torch.dtype, radius: int, width: int, height: int) -> None:
+    B.check(B.icl_tune(op, _DT[dtype], radius, width, height, _stream()), "icl_tune")
+
+
+# ----------------------------------------------------------------------------- batched
+
+class BatchPlan:
+    """Tile table for a batch of uneven images, launched as one persistent kernel.
+
+    ``images`` / ``outputs`` are 2-D GPU tensors of one dtype; ``taps`` are float32
+    GPU tensors (2r+1), used for both passes of each image.  The plan keeps
+    references to all of them, so the pointers it uploaded stay valid.
+    """
+
+    def __init__(self, images, outputs, taps_x, taps_y=None):
+        taps_y = taps_x if taps_y is None else taps_y
+        self._keep = (list(images), list(outputs), list(taps_x), list(taps_y))
+        dts = {t.dtype for t in images} | {t.dtype for t in outputs}
+        if len(dts) != 1:
+            raise ValueError("all images and outputs must share one dtype")
+        self.dtype = dts.pop()
+        descs = []
+        for x, y, tx, ty in zip(*self._keep):
+            sp, spitch, W, H = _image(x, "image")
+            dp, dpitch, W2, H2 = _image(y, "output")
+            if (W, H) != (W2, H2):
+                raise ValueError("output shape differs from its image")
+            r = (tx.numel() - 1) // 2
+            descs.append(B.icl_image_desc(sp, dp, spitch, dpitch, W, H, r, _taps(tx, 2 * r + 1, "taps_x"),
+                                          _taps(ty, 2 * r + 1, "taps_y")))
+        st, self.handle = B.icl_batch_plan_create(descs, _DT[self.dtype])
+        B.check(st, "icl_batch_plan_create")
+        _, self.tiles, self.pixels = B.icl_batch_plan_info(self.handle)
+        self._graph = None
+
+    def launch(self) -> None:
+        B.check(B.icl_conv_sep_batched(self.handle, _stream()), "icl_conv_sep_batched")
+
+    def graph(self):
+        """hipGraphExec holding the single persistent launch (created once)."""
+        if self._graph is None:
+            st, g = B.icl_batch_graph_create(self.handle)
+            B.check(st, "icl_batch_graph_create")
+            self._graph = g
+        return self._graph
+
+    def replay(self) -> None:
+        B.check(B.icl_graph_launch(self.graph(), _stream()), "icl_graph_launch")
+
+    def close(self) -> None:
+        if self._graph is not None:
+            B.icl_graph_destroy(self._graph)
+            self._graph = None
+        if self.handle:
+            B.icl_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------- filter bank
+
+def _dense(t: torch.Tensor, name: str, dtype=torch.float32) -> int:
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} GPU tensor")
+    return t.data_ptr()
+
+
+def bank_fwd(x: torch.Tensor, w: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    N, H, W = x.shape[0], x.shape[-2], x.shape[-1]
+    F, r = w.shape[0], (w.shape[-1] - 1) // 2
+    if out is None:
+        out = torch.empty((N, F, H, W), dtype=torch.float32, device=x.device)
+    B.check(B.icl_bank_fwd(_dense(x, "x"), _dense(w, "w"), _dense(out, "y"), N, F, H, W, r, _stream()),
+            "icl_bank_fwd")
+    return out
+
+
+def bank_bwd_input(gy: torch.Tensor, w: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    N, F, H, W = gy.shape
+    r = (w.shape[-1] - 1) // 2
+    if out is None:
+        out = torch.empty((N, 1, H, W), dtype=torch.float32, device=gy.device)
+    B.check(B.icl_bank_bwd_input(_dense(gy, "gy"), _dense(w, "w"), _dense(out, "gx"), N, F, H, W, r, _stream()),
+            "icl_bank_bwd_input")
+    return out
+
+
+def bank_bwd_filter(gy: torch.Tensor, x: torch.Tensor, radius: int, out: torch.Tensor | None = None,
+                    workspace: torch.Tensor | None = None) -> torch.Tensor:
+    N, F, H, W = gy.shape
+    k = 2 * radius + 1
+    if out is None:
+        out = torch.empty((F, k, k), dtype=torch.float32, device=gy.device)
+    if workspace is None:
+        _, nb = B.icl_workspace_size(B.ICL_OP_BANK_BWD_FILTER, W, H, N, F, radius)
+        workspace = _workspace(nb, gy.device)
+    B.check(B.icl_bank_bwd_filter(_dense(gy, "gy"), _dense(x, "x"), _dense(out, "gw"), N, F, H, W, radius,
+                                  workspace.data_ptr(), workspace.numel() * 4, _stream()), "icl_bank_bwd_filter")
+    return out
+
+
+def sse_loss(y: torch.Tensor, t: torch.Tensor, grad: bool = True, workspace: torch.Tensor | None = None):
+    """(L, gy): L = sum (y - t)^2 as a 0-d GPU tensor, gy = 2 (y - t) (None if grad is False)."""
+    if y.shape != t.shape:
+        raise ValueError("y and t differ in shape")
+    loss = torch.empty((), dtype=torch.float32, device=y.device)
+    gy = torch.empty_like(y) if grad else None
+    if workspace is None:
+        _, nb = B.icl_workspace_size(B.ICL_OP_SSE_LOSS, y.numel(), 1)
+        workspace = _workspace(nb, y.device)
+    B.check(B.icl_sse_loss(_dense(y, "y"), _dense(t, "t"), gy.data_ptr() if gy is not None else 0, y.numel(),
+                           loss.data_ptr(), workspace.data_ptr(), workspace.numel() * 4, _stream()), "icl_sse_loss")
+    return loss, gy
+
+
+class FilterBankFn(torch.autograd.Function):
+    """y = bank(x, w) with hand-written adjoint kernels for both gradients."""
+
+    @staticmethod
+    def forward(ctx, x, w):
+        ctx.save_for_backward(x, w)
+        return bank_fwd(x.contiguous(), w.contiguous())
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, w = ctx.saved_tensors
+        gy = gy.contiguous()
+        gx = bank_bwd_input(gy, w.contiguous()).view_as(x) if ctx.needs_input_grad[0] else None
+        gw = bank_bwd_filter(gy, x.contiguous(), (w.shape[-1] - 1) // 2) if ctx.needs_input_grad[1] else None
+        return gx, gw
+
+
+def filter_bank(x: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
+    return FilterBankFn.apply(x, w)

@@ -1,0 +1,98 @@
+"""Shared test helpers: device tensors, padded views and the tolerance rules.
+
+Tolerances (stated per result):
+  float32 storage : normwise error |y_gpu - y| / S <= 1e-5, where S is the same
+                    stencil evaluated on absolute values (|taps|, |input|) by the
+                    oracle; S == 0 requires exact equality.
+  float16 storage : normwise error against the FP64 oracle <= 2e-3 (binary16's
+                    half-ulp is 4.9e-4 relative, so the budget covers one output
+                    rounding plus float32 accumulation).
+  bfloat16 storage: the stored value equals the oracle's round-to-nearest-even
+                    bfloat16 of the FP64 result, or one of its two neighbours
+                    (bfloat16's own half-ulp, 3.9e-3, exceeds 2e-3, so "within
+                    1 ulp of the correctly rounded value" is the attainable bar);
+                    the normwise error against FP64 is reported alongside.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+try:
+    import torch
+except Exception:  # pragma: no cover
+    torch = None
+
+from paper_1605_06399_amd import synth
+
+TORCH_DT = {"f32": "float32", "f16": "float16", "bf16": "bfloat16"}
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def storage(img_f32: np.ndarray, dt: str):
+    """(device tensor in the storage dtype, float64 values the oracle must see)."""
+    from oracle import oracle
+    if dt == "f32":
+        t = torch.from_numpy(np.ascontiguousarray(img_f32, dtype=np.float32)).to(dev())
+        return t, img_f32.astype(np.float64)
+    if dt == "f16":
+        bits = synth.to_f16_bits(img_f32)
+        t = torch.from_numpy(bits.view(np.int16).copy()).to(dev()).view(torch.float16)
+        return t, oracle.decode(bits, "f16")
+    bits = synth.to_bf16_bits(img_f32)
+    t = torch.from_numpy(bits.view(np.int16).copy()).to(dev()).view(torch.bfloat16)
+    return t, oracle.decode(bits, "bf16")
+
+
+def padded_view(t, pad_elems: int, offset_elems: int = 0):
+    """Copy of a 2-D tensor inside a larger buffer: row pitch W + pad, start offset."""
+    H, W = t.shape
+    buf = torch.zeros((H + 1) * (W + pad_elems) + offset_elems + 16, dtype=t.dtype, device=t.device)
+    v = buf[offset_elems:offset_elems + H * (W + pad_elems)].view(H, W + pad_elems)[:, :W]
+    v.copy_(t)
+    return v
+
+
+def empty_padded(H, W, dtype, pad_elems: int, offset_elems: int = 0):
+    buf = torch.full(((H + 1) * (W + pad_elems) + offset_elems + 16,), float("nan"), dtype=dtype, device=dev())
+    return buf[offset_elems:offset_elems + H * (W + pad_elems)].view(H, W + pad_elems)[:, :W]
+
+
+def to_host(t) -> np.ndarray:
+    """Device image -> float64 (bf16/f16 decoded by numpy/torch on the host)."""
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+def bits_of(t) -> np.ndarray:
+    return t.detach().contiguous().view(torch.int16).cpu().numpy().view(np.uint16)
+
+
+def normwise(got: np.ndarray, ref: np.ndarray, scale: np.ndarray) -> float:
+    d = np.abs(got - ref)
+    zero = scale == 0
+    if np.any(d[zero] != 0):
+        return float("inf")
+    s = np.where(zero, 1.0, scale)
+    return float(np.max(d / s)) if d.size else 0.0
+
+
+def assert_close(out, ref64: np.ndarray, scale: np.ndarray, dt: str, what: str = ""):
+    """Apply the stated tolerance of the storage type (see module docstring)."""
+    from oracle import oracle
+    got = to_host(out)
+    err = normwise(got, ref64, scale)
+    if dt == "f32":
+        assert err <= 1e-5, f"{what}: float32 normwise error {err:.3e} > 1e-5"
+    elif dt == "f16":
+        assert err <= 2e-3, f"{what}: float16 normwise error {err:.3e} > 2e-3"
+    else:
+        want = oracle.encode(ref64, "bf16").astype(np.int64)
+        have = bits_of(out).astype(np.int64)
+        # distance in representable steps (same sign: monotone integer order of the bit patterns)
+        ord_w = np.where(want & 0x8000, -(want & 0x7FFF), want)
+        ord_h = np.where(have & 0x8000, -(have & 0x7FFF), have)
+        steps = np.abs(ord_w - ord_h)
+        assert steps.max(initial=0) <= 1, f"{what}: bfloat16 off by {steps.max()} ulp (normwise {err:.3e})"
+    return err

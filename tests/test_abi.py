@@ -1,0 +1,172 @@
+"""C-ABI library: loads, exports every declared symbol, and validates arguments on the host.
+
+These tests make no compute call: argument checks run before any device query,
+so each error path returns its status code on a machine without a GPU.  A
+well-formed call returns ICL_OK (empty image), ICL_ERR_NO_DEVICE (no GPU here)
+or launches (GPU machine; not done in this file).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1605_06399_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "icl.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(icl_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libicl.so is not built (run __graft_entry__.build())")
+    return B.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in icl.h but not exported"
+    assert set(names) == set(B.EXPORTED)
+
+
+def test_status_strings_and_version(L):
+    for s in range(0, 11):
+        assert B.status_string(s)
+    assert "gfx950" in B.icl_version()
+
+
+def test_variant_tables(L):
+    for op in range(B.ICL_OP_COUNT):
+        n = B.icl_variant_count(op)
+        assert n >= 1
+        names = B.variant_names(op)
+        assert all(names) and len(set(names)) == n
+        assert B.icl_variant_name(op, n) is None
+    assert B.variant_names(B.ICL_OP_CONV_SEP)[0] == "plain2p"
+    assert B.variant_names(B.ICL_OP_CONV2D)[0] == "plain"
+    assert B.icl_force_variant(B.ICL_OP_CONV2D, 99) == B.ICL_ERR_INVALID_VALUE
+    assert B.icl_force_variant(B.ICL_OP_COUNT, 0) == B.ICL_ERR_INVALID_VALUE
+
+
+def test_workspace_sizes(L):
+    st, nb = B.icl_workspace_size(B.ICL_OP_CONV_SEP, 100, 7)
+    assert st == B.ICL_OK and nb == 100 * 7 * 4
+    st, nb = B.icl_workspace_size(B.ICL_OP_HARRIS, 10, 10)
+    assert st == B.ICL_OK and nb == 2 * 100 * 4
+    st, nb = B.icl_workspace_size(B.ICL_OP_CONV2D, 10, 10)
+    assert st == B.ICL_OK and nb == 0
+    st, nb = B.icl_workspace_size(B.ICL_OP_BANK_BWD_FILTER, 1024, 1024, 32, 16, 4)
+    assert st == B.ICL_OK and nb == 32 * 32 * 16 * 16 * 81 * 4
+    assert B.icl_workspace_size(B.ICL_OP_BANK_BWD_FILTER, 8, 8, 1, 1, 9)[0] == B.ICL_ERR_RADIUS
+    assert B.icl_workspace_size(B.ICL_OP_CONV_SEP, -1, 7)[0] == B.ICL_ERR_INVALID_VALUE
+    assert B.icl_workspace_size(B.ICL_OP_CONV_SEP, 1, 7, dtype=7)[0] == B.ICL_ERR_DTYPE
+    assert B.icl_workspace_size(42, 1, 7)[0] == B.ICL_ERR_INVALID_VALUE
+
+
+# Fake "device" addresses: never dereferenced, because validation fails (or the
+# device check does) before anything is launched.
+SRC, DST, TAPS, WS = 0x10000000, 0x20000000, 0x30000000, 0x40000000
+
+
+def sep(**kw):
+    a = dict(src=SRC, src_pitch=64 * 4, dst=DST, dst_pitch=64 * 4, width=64, height=8, dtype=B.ICL_F32,
+             taps_x=TAPS, taps_y=TAPS, radius=2, workspace=0, workspace_bytes=0)
+    a.update(kw)
+    return B.icl_conv_sep(*a.values())
+
+
+def test_conv_sep_validation(L):
+    assert sep(width=-1) == B.ICL_ERR_INVALID_VALUE
+    assert sep(height=-3) == B.ICL_ERR_INVALID_VALUE
+    assert sep(dtype=5) == B.ICL_ERR_DTYPE
+    assert sep(radius=-1) == B.ICL_ERR_RADIUS
+    assert sep(radius=B.ICL_MAX_RADIUS + 1) == B.ICL_ERR_RADIUS
+    assert sep(width=0) == B.ICL_OK                              # empty image: no-op
+    assert sep(height=0, src=0, dst=0) == B.ICL_OK
+    assert sep(src=0) == B.ICL_ERR_INVALID_VALUE
+    assert sep(taps_y=0) == B.ICL_ERR_INVALID_VALUE
+    assert sep(src_pitch=63 * 4) == B.ICL_ERR_PITCH
+    assert sep(dst_pitch=64 * 4 + 1) == B.ICL_ERR_PITCH
+    assert sep(dtype=B.ICL_F16, src_pitch=129, dst_pitch=128) == B.ICL_ERR_PITCH
+    assert sep(dst=SRC + 7 * 256) == B.ICL_ERR_ALIAS              # last source row overlaps
+    assert sep(dst=SRC + 8 * 256) != B.ICL_ERR_ALIAS
+    assert sep(workspace=DST + 100, workspace_bytes=4096) == B.ICL_ERR_ALIAS
+
+
+def test_conv2d_harris_nms_validation(L):
+    assert B.icl_conv2d(SRC, 256, DST, 256, 64, 8, B.ICL_F32, TAPS, 17) == B.ICL_ERR_RADIUS
+    assert B.icl_conv2d(SRC, 256, DST, 256, 64, 8, B.ICL_F32, 0, 1) == B.ICL_ERR_INVALID_VALUE
+    assert B.icl_conv2d(SRC, 256, SRC, 256, 64, 8, B.ICL_F32, TAPS, 1) == B.ICL_ERR_ALIAS
+    assert B.icl_conv2d(SRC, 256, DST, 256, 0, 8, B.ICL_F32, TAPS, 1) == B.ICL_OK
+    assert B.icl_harris(SRC, 256, DST, 256, 64, 8, TAPS, 8, 0.04) == B.ICL_ERR_RADIUS
+    assert B.icl_harris(SRC, 100, DST, 256, 64, 8, TAPS, 2, 0.04) == B.ICL_ERR_PITCH
+    assert B.icl_harris(SRC, 256, SRC + 4, 256, 64, 8, TAPS, 2, 0.04) == B.ICL_ERR_ALIAS
+    assert B.icl_nms(SRC, 256, DST, 64, 64, 8, 0, 1e-3) == B.ICL_ERR_RADIUS
+    assert B.icl_nms(SRC, 256, DST, 63, 64, 8, 1, 1e-3) == B.ICL_ERR_PITCH
+    assert B.icl_nms(SRC, 256, SRC + 64, 64, 64, 8, 1, 1e-3) == B.ICL_ERR_ALIAS
+    assert B.icl_nms(SRC, 256, DST, 64, -1, 8, 1, 1e-3) == B.ICL_ERR_INVALID_VALUE
+
+
+def test_bank_and_loss_validation(L):
+    assert B.icl_bank_fwd(SRC, TAPS, DST, 2, 16, 8, 8, 5) == B.ICL_ERR_RADIUS
+    assert B.icl_bank_fwd(SRC, TAPS, DST, 2, 0, 8, 8, 4) == B.ICL_ERR_INVALID_VALUE
+    assert B.icl_bank_fwd(SRC, TAPS, DST, 2, 65, 8, 8, 4) == B.ICL_ERR_UNSUPPORTED
+    assert B.icl_bank_fwd(SRC, TAPS, SRC + 4, 2, 4, 8, 8, 4) == B.ICL_ERR_ALIAS
+    assert B.icl_bank_fwd(SRC, TAPS, DST, 0, 4, 8, 8, 4) == B.ICL_OK
+    assert B.icl_bank_bwd_input(0, TAPS, DST, 2, 4, 8, 8, 4) == B.ICL_ERR_INVALID_VALUE
+    assert B.icl_bank_bwd_filter(SRC, DST, WS, 2, 4, 8, 8, 4, 0, 0) == B.ICL_ERR_WORKSPACE
+    assert B.icl_bank_bwd_filter(SRC, DST, WS, 2, 4, 8, 8, 4, 0x50000000, 10) == B.ICL_ERR_WORKSPACE
+    assert B.icl_sse_loss(SRC, DST, 0, -1, WS) == B.ICL_ERR_INVALID_VALUE
+    assert B.icl_sse_loss(SRC, DST, 0, 10, WS, 0, 0) == B.ICL_ERR_WORKSPACE
+    assert B.icl_sse_loss(SRC, DST, SRC + 8, 10, WS, 0x50000000, 1 << 20) == B.ICL_ERR_ALIAS
+
+
+def test_batch_plan_validation(L):
+    d = B.icl_image_desc(SRC, DST, 256, 256, 64, 8, 3, TAPS, TAPS)
+    assert B.icl_batch_plan_create([d], 9)[0] == B.ICL_ERR_DTYPE
+    bad = B.icl_image_desc(SRC, DST, 256, 256, 64, 8, 8, TAPS, TAPS)
+    assert B.icl_batch_plan_create([bad], B.ICL_F16)[0] == B.ICL_ERR_RADIUS
+    bad = B.icl_image_desc(SRC, DST, 100, 256, 64, 8, 1, TAPS, TAPS)
+    assert B.icl_batch_plan_create([bad], B.ICL_F16)[0] == B.ICL_ERR_PITCH
+    bad = B.icl_image_desc(SRC, SRC + 256, 256, 256, 64, 8, 1, TAPS, TAPS)
+    assert B.icl_batch_plan_create([bad], B.ICL_F32)[0] == B.ICL_ERR_ALIAS
+    d2 = B.icl_image_desc(SRC + (1 << 20), DST + 1024, 256, 256, 64, 8, 1, TAPS, TAPS)   # outputs overlap
+    assert B.icl_batch_plan_create([d, d2], B.ICL_F32)[0] == B.ICL_ERR_ALIAS
+    d3 = B.icl_image_desc(DST + 512, DST + (1 << 20), 256, 256, 64, 8, 1, TAPS, TAPS)    # input of 3 = output of 1
+    assert B.icl_batch_plan_create([d, d3], B.ICL_F32)[0] == B.ICL_ERR_ALIAS
+    assert B.lib().icl_conv_sep_batched(None, None) == B.ICL_ERR_INVALID_VALUE
+
+
+def test_no_device_or_launch_path(L):
+    """A valid call either reports that no GPU is visible (CPU container) or succeeds (GPU machine)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present: compute calls are covered by the gpu tests")
+    assert B.icl_init() == B.ICL_ERR_NO_DEVICE
+    assert sep() == B.ICL_ERR_NO_DEVICE
+    assert B.icl_tune(B.ICL_OP_CONV_SEP, B.ICL_F32, 2, 64, 64) == B.ICL_ERR_NO_DEVICE
+
+
+def test_tune_cache_file_roundtrip_and_corruption(L, tmp_path):
+    p = tmp_path / "cache.json"
+    assert B.icl_tune_save(str(p)) == B.ICL_OK
+    assert B.icl_tune_load(str(p)) == B.ICL_OK
+    p.write_text("{not json")
+    assert B.icl_tune_load(str(p)) == B.ICL_ERR_TUNE_CACHE
+    assert B.icl_tune_load(str(tmp_path / "missing.json")) == B.ICL_ERR_TUNE_CACHE
+    # an entry for another device or an unknown variant never selects a kernel
+    p.write_text('{"version": 1, "entries": [\n  {"key": "gfx000|1|conv2d|0|3|20", "variant": "nope", "us": 1.0}\n]}\n')
+    assert B.icl_tune_load(str(p)) == B.ICL_OK
+    st, idx = B.icl_selected_variant(B.ICL_OP_CONV2D, B.ICL_F32, 3, 1024, 1024)
+    assert st == B.ICL_OK and idx == 1      # the default (first LDS variant), not the foreign entry
+    B.icl_tune_clear()

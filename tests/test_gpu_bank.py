@@ -1,0 +1,138 @@
+"""GPU parity: filter bank forward, adjoint kernels, loss and the autograd Function."""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+from oracle import oracle  # noqa: E402
+from paper_1605_06399_amd import synth  # noqa: E402
+
+if gpu_available():
+    import torch
+    from paper_1605_06399_amd import torch_api as T
+
+
+def inputs(N, F, H, W, r, cfg=70):
+    x = synth.uniform01(synth.seed(cfg, 0), N * H * W).reshape(N, 1, H, W)
+    w = synth.normal(synth.seed(cfg, 1), F * (2 * r + 1) ** 2, std=0.1).reshape(F, 2 * r + 1, 2 * r + 1)
+    t = synth.uniform01(synth.seed(cfg, 4), N * F * H * W).reshape(N, F, H, W)
+    return x, w, t
+
+
+def cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel_normwise(got, ref, scale):
+    s = np.where(scale == 0, 1.0, scale)
+    return float(np.max(np.abs(got - ref) / s))
+
+
+SHAPES = [(2, 5, 70, 133, 4), (1, 3, 64, 64, 2), (2, 2, 5, 3, 4), (1, 16, 1, 9, 1), (1, 1, 1, 1, 3), (1, 4, 65, 130, 3)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_bank_forward(shape):
+    N, F, H, W, r = shape
+    x, w, _ = inputs(N, F, H, W, r)
+    y = T.bank_fwd(cu(x), cu(w))
+    torch.cuda.synchronize()
+    ref = oracle.bank_fwd(x, w)
+    scale = oracle.bank_fwd(np.abs(x), np.abs(w))
+    assert rel_normwise(host(y), ref, scale) <= 1e-5
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_bank_input_gradient(shape):
+    """GPU gather (flipped correlation + edge fold) vs the oracle's scatter."""
+    N, F, H, W, r = shape
+    _, w, _ = inputs(N, F, H, W, r)
+    gy = synth.normal(synth.seed(71, 9), N * F * H * W).reshape(N, F, H, W)
+    gx = T.bank_bwd_input(cu(gy), cu(w))
+    torch.cuda.synchronize()
+    ref = oracle.bank_bwd_input(gy, w)
+    scale = oracle.bank_bwd_input(np.abs(gy), np.abs(w))
+    assert rel_normwise(host(gx), ref, scale) <= 1e-5
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_bank_filter_gradient(shape):
+    N, F, H, W, r = shape
+    x, w, _ = inputs(N, F, H, W, r)
+    gy = synth.normal(synth.seed(72, 9), N * F * H * W).reshape(N, F, H, W)
+    gw = T.bank_bwd_filter(cu(gy), cu(x), r)
+    torch.cuda.synchronize()
+    ref = oracle.bank_bwd_filter(gy, x, r)
+    scale = oracle.bank_bwd_filter(np.abs(gy), np.abs(x), r)
+    assert rel_normwise(host(gw), ref, scale) <= 1e-5
+    # deterministic: a second call gives the same bits
+    gw2 = T.bank_bwd_filter(cu(gy), cu(x), r)
+    assert torch.equal(gw, gw2)
+
+
+def test_sse_loss():
+    y = synth.normal(synth.seed(73, 1), 1_000_003).astype(np.float32)
+    t = synth.uniform01(synth.seed(73, 2), 1_000_003)
+    L, gy = T.sse_loss(cu(y), cu(t))
+    Lr, gyr = oracle.sse_loss(y, t)
+    assert abs(L.item() - Lr) <= 1e-5 * Lr
+    assert np.array_equal(host(gy), 2.0 * (y.astype(np.float32) - t).astype(np.float64))
+    L2, none = T.sse_loss(cu(y), cu(t), grad=False)
+    assert none is None and L2.item() == L.item()
+
+
+def test_autograd_function_matches_oracle_chain():
+    """loss.backward() through FilterBankFn vs the oracle's forward -> loss -> adjoints (same x, w, t)."""
+    N, F, H, W, r = 2, 6, 40, 57, 4
+    x, w, t = inputs(N, F, H, W, r, cfg=74)
+    xt = cu(x).requires_grad_(True)
+    wt = cu(w).requires_grad_(True)
+    y = T.filter_bank(xt, wt)
+    L, gy = T.sse_loss(y.detach(), cu(t))
+    y.backward(gy)
+    torch.cuda.synchronize()
+    yr = oracle.bank_fwd(x, w)
+    Lr, gyr = oracle.sse_loss(yr, t)
+    gxr = oracle.bank_bwd_input(gyr, w)
+    gwr = oracle.bank_bwd_filter(gyr, x, r)
+    assert abs(L.item() - Lr) <= 1e-5 * Lr
+    sx = oracle.bank_bwd_input(np.abs(gyr), np.abs(w))
+    sw = oracle.bank_bwd_filter(np.abs(gyr), np.abs(x), r)
+    # gy carries the forward's float32 error (<= 1e-5 normwise), amplified by at most the stencil sums
+    assert rel_normwise(host(xt.grad), gxr, sx + 2 * oracle.bank_bwd_input(oracle.bank_fwd(np.abs(x), np.abs(w)), np.abs(w))) <= 1e-5
+    assert rel_normwise(host(wt.grad), gwr, sw + 2 * oracle.bank_bwd_filter(oracle.bank_fwd(np.abs(x), np.abs(w)), np.abs(x), r)) <= 1e-5
+
+
+def test_gpu_gradient_against_float32_central_differences():
+    """Central differences of the GPU loss (eps 1e-3) on a tiny problem.  The loss is quadratic, so
+    the difference quotient is exact up to float32 cancellation (~ulp(L)/eps), hence rtol 2e-2."""
+    N, F, H, W, r = 1, 2, 9, 7, 2
+    x, w, t = inputs(N, F, H, W, r, cfg=75)
+    xt, wt, tt = cu(x), cu(w), cu(t)
+
+    def loss(xx, ww):
+        return T.sse_loss(T.bank_fwd(xx, ww), tt, grad=False)[0].item()
+
+    y = T.bank_fwd(xt, wt)
+    _, gy = T.sse_loss(y, tt)
+    gx = host(T.bank_bwd_input(gy, wt))
+    gw = host(T.bank_bwd_filter(gy, xt, r))
+    eps = 1e-3
+    for (yy, xx) in [(0, 0), (8, 6), (4, 3), (0, 5)]:
+        xp, xm = xt.clone(), xt.clone()
+        xp[0, 0, yy, xx] += eps
+        xm[0, 0, yy, xx] -= eps
+        fd = (loss(xp, wt) - loss(xm, wt)) / (2 * eps)
+        assert fd == pytest.approx(gx[0, 0, yy, xx], rel=2e-2, abs=2e-2)
+    for idx in [(0, 0, 0), (1, 2, 2), (0, 4, 1)]:
+        wp, wm = wt.clone(), wt.clone()
+        wp[idx] += eps
+        wm[idx] -= eps
+        fd = (loss(xt, wp) - loss(xt, wm)) / (2 * eps)
+        assert fd == pytest.approx(gw[idx], rel=2e-2, abs=2e-2)

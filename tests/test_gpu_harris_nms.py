@@ -1,0 +1,150 @@
+"""GPU parity: Harris response and non-maximum suppression against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+from helpers import normwise, padded_view, storage, to_host
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+from oracle import oracle  # noqa: E402
+from paper_1605_06399_amd import binding as B, synth  # noqa: E402
+
+if gpu_available():
+    import torch
+    from paper_1605_06399_amd import torch_api as T
+
+K = np.float32(0.04)
+TAU = np.float32(1e-3)
+
+
+def g_taps(rg):
+    return synth.gaussian_taps(rg, max(rg, 1) / 2.0 if rg != 2 else 1.0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def harris_ws(H, W):
+    _, nb = B.icl_workspace_size(B.ICL_OP_HARRIS, W, H)
+    return torch.empty(nb // 4 + 1, dtype=torch.float32, device="cuda")
+
+
+@pytest.mark.parametrize("variant", range(4))
+@pytest.mark.parametrize("rg", [0, 1, 2, 3])
+def test_harris_variants(variant, rg):
+    if variant >= B.icl_variant_count(B.ICL_OP_HARRIS):
+        pytest.skip("no such variant")
+    B.check(B.icl_force_variant(B.ICL_OP_HARRIS, variant))
+    try:
+        g = g_taps(rg)
+        for (H, W) in [(389, 517), (1, 1), (2, 3), (5, 4), (1, 90), (90, 1), (64, 64), (17, 130)]:
+            img = synth.image_with_rectangles(49, H, W, count=6) if H > 16 else synth.image_uniform(49, H, W)
+            xd, x64 = storage(img, "f32")
+            R = T.harris(xd, dev(g), float(K), workspace=harris_ws(H, W))
+            torch.cuda.synchronize()
+            Rr, sxx, syy, sxy = oracle.harris(x64, g, float(K), windows=True)
+            err = normwise(to_host(R), Rr, oracle.response_scale(sxx, syy, sxy, float(K)))
+            assert err <= 1e-5, f"harris v{variant} rg{rg} {H}x{W}: normwise {err:.3e}"
+    finally:
+        B.icl_force_variant(B.ICL_OP_HARRIS, -1)
+
+
+def test_harris_large_window_uses_split_path():
+    H, W, rg = 60, 75, 5
+    g = synth.gaussian_taps(rg, 2.5)
+    img = synth.image_uniform(50, H, W)
+    xd, x64 = storage(img, "f32")
+    R = T.harris(xd, dev(g), float(K))
+    torch.cuda.synchronize()
+    Rr, sxx, syy, sxy = oracle.harris(x64, g, float(K), windows=True)
+    assert normwise(to_host(R), Rr, oracle.response_scale(sxx, syy, sxy, float(K))) <= 1e-5
+
+
+@pytest.mark.parametrize("variant", range(4))
+def test_harris_closed_forms_on_gpu(variant):
+    if variant >= B.icl_variant_count(B.ICL_OP_HARRIS):
+        pytest.skip("no such variant")
+    B.check(B.icl_force_variant(B.ICL_OP_HARRIS, variant))
+    try:
+        g = synth.gaussian_taps(2, 1.0)
+        H, W = 70, 90
+        # constant image: every gradient is exactly zero, so R is exactly zero
+        R = T.harris(torch.full((H, W), 0.3, device="cuda"), dev(g), float(K), workspace=harris_ws(H, W))
+        assert torch.count_nonzero(R).item() == 0
+        # linear ramp I = x + 2y (exact in float32): R = -k (64 * 5)^2 * (sum g)^4 away from the edges
+        y, x = np.meshgrid(np.arange(H, dtype=np.float32), np.arange(W, dtype=np.float32), indexing="ij")
+        R = to_host(T.harris(dev(x + 2 * y), dev(g), float(K), workspace=harris_ws(H, W)))
+        s = float(np.sum(g.astype(np.float64)))
+        expect = -float(K) * (64.0 * 5.0 * s * s) ** 2
+        assert np.allclose(R[3:-3, 3:-3], expect, rtol=2e-6)
+    finally:
+        B.icl_force_variant(B.ICL_OP_HARRIS, -1)
+
+
+def quantised_response(H, W, seed):
+    """Synthetic responses with many exact ties, plateaus and values at the threshold."""
+    u = synth.uniform01(synth.seed(seed, 0), H * W).reshape(H, W)
+    q = (np.floor(u * 6) - 1).astype(np.float32) * np.float32(1e-3)   # {-1e-3, 0, 1e-3, .. 4e-3}
+    q[q == np.float32(1e-3)] = TAU                                   # exactly tau: never above threshold
+    return q
+
+
+@pytest.mark.parametrize("variant", range(2))
+@pytest.mark.parametrize("radius", [1, 2])
+def test_nms_bit_exact(variant, radius):
+    if variant >= B.icl_variant_count(B.ICL_OP_NMS):
+        pytest.skip("no such variant")
+    B.check(B.icl_force_variant(B.ICL_OP_NMS, variant))
+    try:
+        for (H, W) in [(257, 389), (1, 1), (1, 9), (9, 1), (4, 4), (63, 65)]:
+            R = quantised_response(H, W, 51)
+            Rd = dev(R)
+            st = B.icl_nms(Rd.data_ptr(), W * 4, 0, 0, W, H, radius, float(TAU), 0)   # null mask is rejected
+            assert st == B.ICL_ERR_INVALID_VALUE
+            if variant == 1 and radius != 1:
+                assert B.icl_selected_variant(B.ICL_OP_NMS, B.ICL_F32, radius, W, H)[1] == 1
+                with pytest.raises(B.IclError):
+                    T.nms(Rd, float(TAU), radius)
+                continue
+            M = T.nms(Rd, float(TAU), radius)
+            torch.cuda.synchronize()
+            ref = oracle.nms(R, float(TAU), radius)
+            assert np.array_equal(M.cpu().numpy(), ref), f"nms v{variant} r{radius} {H}x{W}"
+        # padded / misaligned views take the scalar edges
+        R = quantised_response(70, 133, 52)
+        Rv = padded_view(dev(R), 7, 1)
+        out = torch.zeros((70, 140), dtype=torch.uint8, device="cuda")[:, 3:136]
+        M = T.nms(Rv, float(TAU), radius, out=out)
+        assert np.array_equal(M.cpu().numpy(), oracle.nms(R, float(TAU), radius))
+    finally:
+        B.icl_force_variant(B.ICL_OP_NMS, -1)
+
+
+def test_harris_nms_pipeline_masks_agree_away_from_ties():
+    """Corner masks from GPU responses vs oracle responses.  Where float rounding decides the mask
+    (R within its error bound of tau or of a neighbour) both answers are correct; everywhere else the
+    masks must be identical."""
+    H, W = 600, 500
+    img = synth.image_with_rectangles(3, H, W, count=12)
+    g = synth.gaussian_taps(2, 1.0)
+    xd, x64 = storage(img, "f32")
+    R = T.harris(xd, dev(g), float(K))
+    M = T.nms(R, float(TAU))
+    torch.cuda.synchronize()
+    Rr, sxx, syy, sxy = oracle.harris(x64, g, float(K), windows=True)
+    ref = oracle.nms(Rr, float(TAU))
+    delta = 1e-5 * oracle.response_scale(sxx, syy, sxy, float(K))
+    amb = np.abs(Rr - float(TAU)) <= delta
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if dx == 0 and dy == 0:
+                continue
+            yy = np.clip(np.arange(H)[:, None] + dy, 0, H - 1)
+            xx = np.clip(np.arange(W)[None, :] + dx, 0, W - 1)
+            amb |= np.abs(Rr - Rr[yy, xx]) <= delta + delta[yy, xx]
+    got = M.cpu().numpy()
+    assert ref.sum() > 20
+    assert np.array_equal(got[~amb], ref[~amb]), f"{np.sum(got[~amb] != ref[~amb])} unambiguous mismatches"
+    print(f"pipeline: {ref.sum()} corners, {amb.sum()} ambiguous pixels")
