@@ -1,0 +1,343 @@
+"""Benchmark: the convolution sweep on one MI355X, autotuned vs plain kernels.
+
+Workload (one "step"): a 4096 x 4096 float32 image (U[0,1)) through the
+separable filter and the full 2-D filter of every radius 1, 2, 3, 5, 7
+(N(0,1) taps normalised to sum 1, clamp-to-edge): ten library calls, each
+reading a 64 MiB image and writing a 64 MiB result.  Inputs rotate over eight
+image/output pairs (1 GiB), so the 256 MB Infinity Cache cannot serve them.
+
+value = output Gpixel/s of the autotuned step (10 x 4096^2 pixels per step).
+Alongside: the plain (one pixel per thread) step, per-call Gpixel/s and % of
+the binding roof (HBM 8 TB/s at 8 B/px, or the FP32 FMA rate), the roofline of
+the dominant kernel, the FP64 CPU oracle on a bounded sample of the same
+workload, and (unless --no-extras) the corner pipeline, the uneven half-float
+batch and the filter-bank forward+backward step.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP32_FMA_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, packed FP32 disabled
+FP32_PACKED_PEAK_TFLOPS = 157.3
+METRIC = "Gpixel/s & % HBM peak, autotuned vs plain kernel; fwd+bwd Gpixel/s"
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--side", type=int, default=4096)
+    p.add_argument("--no-extras", action="store_true")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--only", default="", help="comma list of call labels to run (profiling aid)")
+    return p.parse_args()
+
+
+def flops_per_px(kind, r):
+    n = 2 * r + 1
+    return 4 * n if kind == "sep" else 2 * n * n
+
+
+def roof_gpx(kind, r, bytes_px=8.0):
+    hbm = HBM_PEAK_GBS / bytes_px
+    alu = FP32_FMA_PEAK_TFLOPS * 1e3 / flops_per_px(kind, r)
+    return min(hbm, alu), ("hbm" if hbm <= alu else "alu")
+
+
+def source_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1605_06399_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel_key, src_files):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it matches today's source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        e = d.get(kernel_key)
+        if e and e.get("source_hash") == source_hash(*src_files):
+            return e["bytes_per_launch"]
+    except Exception:
+        pass
+    return None
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU design is "
+              "described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1605_06399_amd import binding as B, synth
+    from paper_1605_06399_amd import torch_api as T
+
+    dev = torch.device("cuda:0")
+    side = a.side
+    radii = synth.SWEEP_RADII
+    img = synth.sweep_image(side)
+    NSET = 8
+    src = [torch.from_numpy(img).to(dev) for _ in range(NSET)]
+    dst = [torch.empty_like(src[0]) for _ in range(NSET)]
+    _, wsb = B.icl_workspace_size(B.ICL_OP_CONV_SEP, side, side)
+    ws = torch.empty(wsb // 4, dtype=torch.float32, device=dev)
+    taps = {}
+    for r in radii:
+        h, v = synth.sweep_taps_sep(r)
+        taps[("sep", r)] = (torch.from_numpy(h).to(dev), torch.from_numpy(v).to(dev))
+        taps[("2d", r)] = torch.from_numpy(synth.sweep_taps_2d(r)).to(dev)
+    calls = [(k, r) for r in radii for k in ("sep", "2d")]
+    if a.only:
+        keep = set(a.only.split(","))
+        calls = [c for c in calls if f"{c[0]}{c[1]}" in keep]
+    stream = torch.cuda.current_stream()
+
+    def call(kind, r, k):
+        if kind == "sep":
+            h, v = taps[("sep", r)]
+            T.conv_sep(src[k], h, v, out=dst[k], workspace=ws)
+        else:
+            T.conv2d(src[k], taps[("2d", r)], out=dst[k])
+
+    # autotune every call of the sweep (outside the timed region)
+    t_tune = time.perf_counter()
+    for kind, r in calls:
+        op = B.ICL_OP_CONV_SEP if kind == "sep" else B.ICL_OP_CONV2D
+        B.check(B.icl_tune(op, B.ICL_F32, r, side, side, stream.cuda_stream), "icl_tune")
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t_tune
+    chosen = {}
+    for kind, r in calls:
+        op = B.ICL_OP_CONV_SEP if kind == "sep" else B.ICL_OP_CONV2D
+        chosen[f"{kind}{r}"] = B.icl_variant_name(op, B.icl_selected_variant(op, B.ICL_F32, r, side, side)[1])
+
+    def run(steps, warmup, label):
+        k = 0
+        for _ in range(warmup):
+            for kind, r in calls:
+                call(kind, r, k % NSET)
+                k += 1
+        evs = {c: [] for c in calls}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for c in calls:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                call(c[0], c[1], k % NSET)
+                e1.record(stream)
+                evs[c].append((e0, e1))
+                k += 1
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        per = {c: float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs[c]])) * 1e3 for c in calls}   # us
+        return dt, per
+
+    dt_tuned, per_tuned = run(a.steps, a.warmup, "tuned")
+    print(f"[bench] tuned: {dt_tuned * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+    B.check(B.icl_force_variant(B.ICL_OP_CONV_SEP, 0))
+    B.check(B.icl_force_variant(B.ICL_OP_CONV2D, 0))
+    dt_plain, per_plain = run(max(2, a.steps // 4), max(1, a.warmup // 2), "plain")
+    B.icl_force_variant(B.ICL_OP_CONV_SEP, -1)
+    B.icl_force_variant(B.ICL_OP_CONV2D, -1)
+    print(f"[bench] plain: {dt_plain * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+
+    px = side * side
+    per_op = []
+    for kind, r in calls:
+        us, usp = per_tuned[(kind, r)], per_plain[(kind, r)]
+        gpx = px / (us * 1e-6) / 1e9
+        roof, bound = roof_gpx(kind, r)
+        per_op.append({"call": f"{kind}{r}", "variant": chosen[f"{kind}{r}"], "us": round(us, 2),
+                       "gpx_s": round(gpx, 1), "hbm_frac": round(gpx * 8 / HBM_PEAK_GBS, 3),
+                       "binding_roof": bound, "roof_frac": round(gpx / roof, 3),
+                       "plain_us": round(usp, 2), "speedup_vs_plain": round(usp / us, 2)})
+    dom = max(calls, key=lambda c: per_tuned[c])
+    kind, r = dom
+    us = per_tuned[dom]
+    _, bound = roof_gpx(kind, r)
+    if bound == "alu":
+        achieved = flops_per_px(kind, r) * px / (us * 1e-6) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_FMA_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP32_FMA_PEAK_TFLOPS, 3)}
+        roofline["frac_of_packed_fp32_peak"] = round(achieved / FP32_PACKED_PEAK_TFLOPS, 3)
+    else:
+        achieved = 8.0 * px / (us * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 3)}
+    key = f"{kind}{r}:{chosen[f'{kind}{r}']}"
+    src_files = ["conv_sep.hip", "sep_tile.hpp"] if kind == "sep" else ["conv2d.hip"]
+    roofline["traffic"] = stored_traffic(key, src_files)
+    roofline["kernel"] = key
+    roofline["algorithmic_bytes_per_launch"] = 8 * px
+    roofline["flops_per_launch"] = flops_per_px(kind, r) * px
+    roofline["launch_us"] = round(us, 2)
+
+    value = len(calls) * px / dt_tuned / 1e9
+    plain_value = len(calls) * px / dt_plain / 1e9
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Gpixel/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(dt_tuned * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"convolution sweep {side}x{side} f32: separable + full 2-D filters, "
+                               f"radius {','.join(map(str, radii))}, clamp-to-edge, N(0,1) taps normalised",
+                   "calls_per_step": len(calls), "pixels_per_call": px, "rotating_buffers_GiB": 2 * NSET * px * 4 / 2 ** 30},
+        "plain": {"value": round(plain_value, 2), "ms_per_step": round(dt_plain * 1e3, 4),
+                  "tuned_speedup": round(dt_plain / dt_tuned, 2)},
+        "hbm_frac_step": round(value * 8 / HBM_PEAK_GBS, 3),
+        "tune_seconds": round(t_tune, 2),
+        "per_call": per_op,
+        "roofline": roofline,
+    }
+    del src, dst, ws
+    torch.cuda.empty_cache()
+
+    if not a.no_extras:
+        try:
+            out["extras"] = run_extras(torch, B, T, synth, max(3, a.steps // 2))
+        except Exception as e:  # an extra never hides the sweep's line
+            out["extras"] = {"error": repr(e)}
+
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(synth, radii, side)
+    print(json.dumps(out), flush=True)
+
+
+def _time(torch, fn, steps, warmup=2):
+    for _ in range(warmup):
+        fn(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        fn(s)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def run_extras(torch, B, T, synth, steps):
+    """The other workloads, timed the same way (inputs resident in HBM, events around the whole step)."""
+    dev = torch.device("cuda:0")
+    res = {}
+    # corner pipeline: Harris response + 3x3 NMS on 8192^2 (two calls: 8 + 5 algorithmic B/px)
+    img = synth.corner_image()
+    H, W = img.shape
+    xs = [torch.from_numpy(img).to(dev) for _ in range(2)]
+    Rs = [torch.empty_like(xs[0]) for _ in range(2)]
+    Ms = [torch.empty((H, W), dtype=torch.uint8, device=dev) for _ in range(2)]
+    g = torch.from_numpy(synth.corner_window()).to(dev)
+    st = torch.cuda.current_stream().cuda_stream
+    B.check(B.icl_tune(B.ICL_OP_HARRIS, B.ICL_F32, 2, W, H, st))
+    B.check(B.icl_tune(B.ICL_OP_NMS, B.ICL_F32, 1, W, H, st))
+
+    def corner(s):
+        T.harris(xs[s % 2], g, 0.04, out=Rs[s % 2])
+        T.nms(Rs[s % 2], 1e-3, out=Ms[s % 2])
+
+    dt = _time(torch, corner, steps)
+    gpx = H * W / dt / 1e9
+    res["corner_8192"] = {"ms": round(dt * 1e3, 3), "gpx_s": round(gpx, 1), "bytes_per_px": 13,
+                          "hbm_frac": round(gpx * 13 / HBM_PEAK_GBS, 3),
+                          "harris_variant": B.icl_variant_name(B.ICL_OP_HARRIS, B.icl_selected_variant(
+                              B.ICL_OP_HARRIS, B.ICL_F32, 2, W, H)[1]),
+                          "corners": int(Ms[0].sum().item())}
+    del xs, Rs, Ms
+    torch.cuda.empty_cache()
+
+    # uneven batch: 256 images, one persistent launch replayed from a HIP graph (4 B/px half storage)
+    items = synth.batch_uneven()
+    for name, tdt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+        ims = [torch.from_numpy(it.image).to(dev).to(tdt) for it in items]
+        outs = [torch.empty_like(t) for t in ims]
+        taps = [torch.from_numpy(it.taps).to(dev) for it in items]
+        plan = T.BatchPlan(ims, outs, taps)
+        plan.graph()
+        dt = _time(torch, lambda s: plan.replay(), steps)
+        gpx = plan.pixels / dt / 1e9
+        res[f"batch256_{name}"] = {"ms": round(dt * 1e3, 3), "gpx_s": round(gpx, 1), "pixels": plan.pixels,
+                                   "tiles": plan.tiles, "bytes_per_px": 4,
+                                   "hbm_frac": round(gpx * 4 / HBM_PEAK_GBS, 3)}
+        plan.close()
+        del ims, outs
+    torch.cuda.empty_cache()
+
+    # differentiable filter bank: forward, loss + gradient, input and filter adjoints
+    N, F, Hb, Wb, r = 32, 16, 1024, 1024, 4
+    x, w, t = synth.bank_inputs()
+    xt, wt, tt = torch.from_numpy(x).to(dev), torch.from_numpy(w).to(dev), torch.from_numpy(t).to(dev)
+    del t
+    y = torch.empty((N, F, Hb, Wb), dtype=torch.float32, device=dev)
+    gx = torch.empty_like(xt)
+    gw = torch.empty_like(wt)
+    _, nb = B.icl_workspace_size(B.ICL_OP_BANK_BWD_FILTER, Wb, Hb, N, F, r)
+    wsw = torch.empty(nb // 4 + 1, dtype=torch.float32, device=dev)
+    _, nb = B.icl_workspace_size(B.ICL_OP_SSE_LOSS, 1, 1)
+    wsl = torch.empty(nb // 4 + 1, dtype=torch.float32, device=dev)
+    phase = {}
+
+    def fwd_bwd(s, timed=None):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if timed is not None else None
+        if ev: ev[0].record()
+        T.bank_fwd(xt, wt, out=y)
+        if ev: ev[1].record()
+        L, gy = T.sse_loss(y, tt, workspace=wsl)
+        if ev: ev[2].record()
+        T.bank_bwd_input(gy, wt, out=gx)
+        if ev: ev[3].record()
+        T.bank_bwd_filter(gy, xt, r, out=gw, workspace=wsw)
+        if ev:
+            ev[4].record()
+            timed.append(ev)
+
+    dt = _time(torch, fwd_bwd, steps)
+    evs = []
+    for s in range(3):
+        fwd_bwd(s, evs)
+    torch.cuda.synchronize()
+    for i, name in enumerate(("fwd", "loss", "bwd_input", "bwd_filter")):
+        phase[name] = round(float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])), 3)
+    flops = 3 * 2 * 81 * N * F * Hb * Wb
+    res["filter_bank_fwd_bwd"] = {"ms": round(dt * 1e3, 3), "gpx_s": round(N * Hb * Wb / dt / 1e9, 2),
+                                  "output_gpx_s": round(N * F * Hb * Wb / dt / 1e9, 1),
+                                  "tflops": round(flops / dt / 1e12, 2),
+                                  "alu_frac": round(flops / dt / 1e12 / FP32_FMA_PEAK_TFLOPS, 3),
+                                  "phase_ms": phase}
+    return res
+
+
+def cpu_baseline(synth, radii, side):
+    """The FP64 oracle, as it stands, on a horizontal strip of the same image (all ten calls)."""
+    from oracle import oracle
+    rows = int(os.environ.get("ICL_CPU_SAMPLE_ROWS", "256"))
+    threads = min(os.cpu_count() or 1, 16)
+    img = synth.sweep_image(side)[:rows].astype(np.float64)
+    t0 = time.perf_counter()
+    for r in radii:
+        h, v = synth.sweep_taps_sep(r)
+        oracle.conv_sep(img, h, v, nthreads=threads)
+        oracle.conv2d(img, synth.sweep_taps_2d(r), nthreads=threads)
+    dt = time.perf_counter() - t0
+    px = rows * side * len(radii) * 2
+    return {"value": round(px / dt / 1e9, 5), "unit": "Gpixel/s", "cores": threads, "kind": "oracle",
+            "sample": f"rows 0..{rows - 1} of the {side}x{side} sweep image (a {rows}x{side} strip, clamped at its own "
+                      f"bottom edge), all {2 * len(radii)} calls; {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -195,6 +195,42 @@ EXPORT void orc_harris(const double* X, long W, long H, const double* g, int rg,
         }
 }
 
+/* Magnitude scale of the response for normwise error measures: the same computation
+ * with every term replaced by its absolute value (|Sobel taps| on |X|, non-negative
+ * products, |window taps|), i.e.  Txx Tyy + Txy^2 + k (Txx + Tyy)^2  with
+ * Txx = sum |g| |g| Gx^2, Gx = sum |s d| |X|.  A float32 evaluation of R differs from
+ * the exact R by a small multiple of the unit roundoff times this scale, including
+ * the cancellation inside the Sobel sums.  Not part of the method; test tolerance only. */
+static void sobel_abs_px(const double* X, long W, long H, long x, long y, double* ax, double* ay) {
+    double gx = 0.0, gy = 0.0;
+    for (int j = -1; j <= 1; ++j)
+        for (int i = -1; i <= 1; ++i) {
+            const double p = fabs(at(X, W, H, x + i, y + j));
+            gx += fabs(SOB_S[j + 1] * SOB_D[i + 1]) * p;
+            gy += fabs(SOB_D[j + 1] * SOB_S[i + 1]) * p;
+        }
+    *ax = gx;
+    *ay = gy;
+}
+
+EXPORT void orc_harris_scale_pts(const double* X, long W, long H, const double* g, int rg, double k,
+                                 const long* xs, const long* ys, long npts, double* S, int nthreads) {
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (long p = 0; p < npts; ++p) {
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int j = -rg; j <= rg; ++j)
+            for (int i = -rg; i <= rg; ++i) {
+                double ax, ay;
+                sobel_abs_px(X, W, H, clampi(xs[p] + i, W), clampi(ys[p] + j, H), &ax, &ay);
+                const double wgt = fabs(g[j + rg] * g[i + rg]);
+                a += wgt * ax * ax;
+                b += wgt * ay * ay;
+                c += wgt * ax * ay;
+            }
+        S[p] = a * b + c * c + fabs(k) * (a + b) * (a + b);
+    }
+}
+
 /* Response at single pixels: gradients recomputed at every clamped window position. */
 EXPORT void orc_harris_pts(const double* X, long W, long H, const double* g, int rg, double k,
                            const long* xs, const long* ys, long npts, double* R, double* Sxx,

@@ -24,9 +24,11 @@ def _image(t: torch.Tensor, name: str):
         raise ValueError(f"{name} must be a GPU tensor")
     if t.dim() != 2:
         raise ValueError(f"{name} must be 2-D (H, W)")
+    es = t.element_size()
+    if t.numel() == 0:
+        return 0, t.shape[1] * es, t.shape[1], t.shape[0]
     if t.stride(1) != 1 and t.shape[1] > 1:
         raise ValueError(f"{name} rows must be contiguous (stride(1) == 1)")
-    es = t.element_size()
     pitch = t.stride(0) * es if t.shape[0] > 1 else t.shape[1] * es
     return t.data_ptr(), pitch, t.shape[1], t.shape[0]
 

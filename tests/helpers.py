@@ -7,11 +7,12 @@ Tolerances (stated per result):
   float16 storage : normwise error against the FP64 oracle <= 2e-3 (binary16's
                     half-ulp is 4.9e-4 relative, so the budget covers one output
                     rounding plus float32 accumulation).
-  bfloat16 storage: the stored value equals the oracle's round-to-nearest-even
-                    bfloat16 of the FP64 result, or one of its two neighbours
-                    (bfloat16's own half-ulp, 3.9e-3, exceeds 2e-3, so "within
-                    1 ulp of the correctly rounded value" is the attainable bar);
-                    the normwise error against FP64 is reported alongside.
+  bfloat16 storage: |y_gpu - y| <= ulp_bf16(y) + 1e-5 * S: at most one bfloat16
+                    ulp of output rounding on top of the float32 accumulation
+                    budget.  (bfloat16's own half-ulp, up to 2^-8 = 3.9e-3
+                    relative, exceeds 2e-3, so the 2e-3 figure cannot bind it;
+                    near-zero outputs of cancelling sums need the S term.)  The
+                    normwise error against FP64 is returned alongside.
 """
 from __future__ import annotations
 
@@ -88,11 +89,17 @@ def assert_close(out, ref64: np.ndarray, scale: np.ndarray, dt: str, what: str =
     elif dt == "f16":
         assert err <= 2e-3, f"{what}: float16 normwise error {err:.3e} > 2e-3"
     else:
-        want = oracle.encode(ref64, "bf16").astype(np.int64)
-        have = bits_of(out).astype(np.int64)
-        # distance in representable steps (same sign: monotone integer order of the bit patterns)
-        ord_w = np.where(want & 0x8000, -(want & 0x7FFF), want)
-        ord_h = np.where(have & 0x8000, -(have & 0x7FFF), have)
-        steps = np.abs(ord_w - ord_h)
-        assert steps.max(initial=0) <= 1, f"{what}: bfloat16 off by {steps.max()} ulp (normwise {err:.3e})"
+        bad = bf16_violations(got, ref64, scale)
+        assert bad == 0, f"{what}: {bad} bfloat16 outputs beyond 1 ulp + 1e-5 S (normwise {err:.3e})"
     return err
+
+
+def ulp_bf16(y: np.ndarray) -> np.ndarray:
+    """Spacing of bfloat16 numbers at |y| (8 significant bits; subnormal spacing 2^-133)."""
+    a = np.abs(y)
+    e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+    return np.where(a > 0, np.ldexp(1.0, (np.maximum(e, -126) - 7).astype(np.int64)), 2.0 ** -133)
+
+
+def bf16_violations(got: np.ndarray, ref64: np.ndarray, scale: np.ndarray) -> int:
+    return int(np.sum(np.abs(got - ref64) > ulp_bf16(ref64) + 1e-5 * scale))

@@ -305,6 +305,17 @@ def test_harris_brute_force_tiny(orc):
     assert np.allclose(Rp, R.ravel(), rtol=1e-12, atol=1e-12)
 
 
+def test_harris_scale_bounds_and_homogeneity(orc):
+    """The absolute-value scale used for normwise response errors bounds |R| and the plain
+    |Sxx Syy| + Sxy^2 + k (Sxx+Syy)^2, and is homogeneous of degree 4 in the image."""
+    X = synth.image_with_rectangles(23, 40, 37, count=3).astype(np.float64) - 0.5
+    R, sxx, syy, sxy = orc.harris(X, G5, K, windows=True)
+    S = orc.harris_scale(X, G5, K)
+    assert np.all(S >= np.abs(R) * (1 - 1e-12))
+    assert np.all(S >= orc.response_scale(sxx, syy, sxy, K) * (1 - 1e-12))
+    assert np.allclose(orc.harris_scale(3.0 * X, G5, K), 81.0 * S, rtol=1e-12)
+
+
 def test_harris_transpose(orc):
     X = synth.image_uniform(22, 17, 23).astype(np.float64)
     assert np.allclose(orc.harris(X.T.copy(), G5, K), orc.harris(X, G5, K).T, rtol=1e-12, atol=1e-12)
