@@ -79,6 +79,35 @@ icl_status device_ready() {
     return g_device_state == 1 ? ICL_OK : ICL_ERR_NO_DEVICE;
 }
 
+static std::mutex g_occ_mu;
+static std::vector<std::pair<const void*, int>> g_occ;   // kernel -> resident blocks on the device
+static int g_cus = 0;
+
+int persistent_grid(const void* kernel, int block, int ntiles) {
+    int resident = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_occ_mu);
+        for (const auto& e : g_occ)
+            if (e.first == kernel) resident = e.second;
+        if (resident == 0) {
+            if (g_cus == 0) {
+                int dev = 0;
+                if (hipGetDevice(&dev) != hipSuccess ||
+                    hipDeviceGetAttribute(&g_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+                    g_cus = 1;
+            }
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
+                per_cu = 1;
+            resident = per_cu * g_cus;
+            g_occ.push_back({kernel, resident});
+        }
+    }
+    int g = ntiles < resident ? ntiles : resident;
+    if (g > 8) g -= g % 8;
+    return g < 1 ? 1 : g;
+}
+
 }  // namespace icl
 
 namespace {

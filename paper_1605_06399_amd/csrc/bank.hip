@@ -52,10 +52,10 @@ __device__ __forceinline__ void stage_plane(const float* __restrict__ plane, int
         for (int idx = tid; idx < NR * C4; idx += 256) {
             const int rr = idx / C4, c4 = idx - rr * C4;
             const int yy = y0 - R + rr;
-            float4 v;
-            if (ZERO_PAD && (yy < 0 || yy >= H)) v = make_float4(0.f, 0.f, 0.f, 0.f);
-            else v = *reinterpret_cast<const float4*>(plane + (size_t)clampi(yy, H) * W + (x0 - RA + 4 * c4));
-            *reinterpret_cast<float4*>(&s[rr * LW + 4 * c4]) = v;
+            v4f v;
+            if (ZERO_PAD && (yy < 0 || yy >= H)) v = mk4(0.f, 0.f, 0.f, 0.f);
+            else v = *reinterpret_cast<const v4f*>(plane + (size_t)clampi(yy, H) * W + (x0 - RA + 4 * c4));
+            lds4(&s[rr * LW + 4 * c4], v);
         }
     } else {
         for (int idx = tid; idx < NR * LW; idx += 256) {
@@ -83,7 +83,7 @@ __device__ __forceinline__ void corr_block(const float* __restrict__ s, const fl
         float win[WIN];
 #pragma unroll
         for (int m = 0; m < WIN / 4; ++m) {
-            const float4 v = *reinterpret_cast<const float4*>(base + q * LW + 4 * m);
+            const v4f v = lds4(base + q * LW + 4 * m);
             win[4 * m] = v.x; win[4 * m + 1] = v.y; win[4 * m + 2] = v.z; win[4 * m + 3] = v.w;
         }
 #pragma unroll
@@ -110,7 +110,7 @@ __device__ __forceinline__ void store_block(float* __restrict__ plane, int W, in
         if (y >= H) break;
         float* row = plane + (size_t)y * W;
         if (vec && xb + BPX <= W) {
-            *reinterpret_cast<float4*>(row + xb) = make_float4(acc[py][0], acc[py][1], acc[py][2], acc[py][3]);
+            *reinterpret_cast<v4f*>(row + xb) = mk4(acc[py][0], acc[py][1], acc[py][2], acc[py][3]);
         } else {
 #pragma unroll
             for (int px = 0; px < BPX; ++px)
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void bank_fwd_k(const float* __restrict__ x, c
                                                   float* __restrict__ y, int F, int H, int W, int tiles_x,
                                                   int tiles_img, int vec) {
     using G = BankTile<R>;
-    __shared__ float s[G::NR * G::LW];
+    __shared__ __attribute__((aligned(16))) float s[G::NR * G::LW];
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
     const int n = (int)(t / (unsigned)tiles_img), ti = (int)(t % (unsigned)tiles_img);
     const int x0 = (ti % tiles_x) * BT, y0 = (ti / tiles_x) * BT;
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void bank_bwd_in_k(const float* __restrict__ g
                                                      float* __restrict__ gx, int F, int H, int W, int tiles_x,
                                                      int tiles_img, int vec) {
     using G = BankTile<R>;
-    __shared__ float s[G::NR * G::LW];
+    __shared__ __attribute__((aligned(16))) float s[G::NR * G::LW];
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
     const int n = (int)(t / (unsigned)tiles_img), ti = (int)(t % (unsigned)tiles_img);
     const int x0 = (ti % tiles_x) * BT, y0 = (ti / tiles_x) * BT;
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(64) void bank_bwd_w1_k(const float* __restrict__ gy
                                                     int tiles_img, int ntiles) {
     using G = GwTile<R>;
     constexpr int N = 2 * R + 1, LW = G::LW, NR = G::NR, RA = G::RA;
-    __shared__ float s[NR * LW];
+    __shared__ __attribute__((aligned(16))) float s[NR * LW];
     // block -> (tile, filter); the F blocks of one tile are consecutive logical ids, kept on one XCD
     const unsigned id = xcd_remap(blockIdx.x, gridDim.x);
     const int f = (int)(id % (unsigned)F);
@@ -371,12 +371,12 @@ __global__ __launch_bounds__(256) void sse_k1(const float* __restrict__ y, const
     if (vec) {
         const long long n4 = count / 4;
         for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < n4; q += stride) {
-            const float4 a = reinterpret_cast<const float4*>(y)[q];
-            const float4 b = reinterpret_cast<const float4*>(t)[q];
-            const float4 d = make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+            const v4f a = reinterpret_cast<const v4f*>(y)[q];
+            const v4f b = reinterpret_cast<const v4f*>(t)[q];
+            const v4f d = a - b;
             acc = fmaf(d.x, d.x, acc); acc = fmaf(d.y, d.y, acc);
             acc = fmaf(d.z, d.z, acc); acc = fmaf(d.w, d.w, acc);
-            if (gy) reinterpret_cast<float4*>(gy)[q] = make_float4(2.f * d.x, 2.f * d.y, 2.f * d.z, 2.f * d.w);
+            if (gy) reinterpret_cast<v4f*>(gy)[q] = 2.f * d;
         }
         for (long long q = n4 * 4 + (long long)blockIdx.x * 256 + threadIdx.x; q < count; q += stride) {
             const float d = y[q] - t[q];

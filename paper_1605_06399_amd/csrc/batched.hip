@@ -40,7 +40,7 @@ constexpr int RMAX = 7;
 template <class T>
 __global__ __launch_bounds__(256) void sep_batched_k(const DevImage* __restrict__ imgs,
                                                      const BatchTile* __restrict__ tiles, int ntiles) {
-    __shared__ float lds[SepTile<RMAX, BTH, BCX>::LDS_FLOATS];
+    __shared__ __attribute__((aligned(16))) float lds[SepTile<RMAX, BTH, BCX>::LDS_FLOATS];
     const int start = (int)xcd_remap(blockIdx.x, gridDim.x);
     for (int t = start; t < ntiles; t += gridDim.x) {
         const BatchTile bt = tiles[t];

@@ -22,6 +22,7 @@
 // as float4, taps as scalar operands.
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
+#include "tile_stage.hpp"
 
 namespace icl {
 namespace {
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(256) void conv2d_lds(const void* __restrict__ src, 
     using G = Tile2d<R, PX, PY>;
     constexpr int TW = G::TW, TH = G::TH, RA = G::RA, LW = G::LW, NR = G::NR, WIN = G::WIN;
     constexpr int N = 2 * R + 1;
-    __shared__ float in_s[NR * LW];
+    __shared__ __attribute__((aligned(16))) float in_s[NR * LW];
     const int tid = threadIdx.x;
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
     const int x0 = (int)(t % (unsigned)tiles_x) * TW;
@@ -86,8 +87,7 @@ __global__ __launch_bounds__(256) void conv2d_lds(const void* __restrict__ src, 
         for (int idx = tid; idx < NR * C4; idx += 256) {
             const int rr = idx / C4, c4 = idx - rr * C4;
             const int y = clampi(y0 - R + rr, H);
-            *reinterpret_cast<float4*>(&in_s[rr * LW + 4 * c4]) =
-                load4<T>(src, (size_t)y * sp + (size_t)(x0 - RA + 4 * c4) * T::size);
+            lds4(&in_s[rr * LW + 4 * c4], load4<T>(src, (size_t)y * sp + (size_t)(x0 - RA + 4 * c4) * T::size));
         }
     } else {
         for (int idx = tid; idx < NR * LW; idx += 256) {
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void conv2d_lds(const void* __restrict__ src, 
                 float win[WIN];
 #pragma unroll
                 for (int m = 0; m < WIN / 4; ++m) {
-                    const float4 v = *reinterpret_cast<const float4*>(bj + py * LW + 4 * m);
+                    const v4f v = lds4(bj + py * LW + 4 * m);
                     win[4 * m] = v.x; win[4 * m + 1] = v.y; win[4 * m + 2] = v.z; win[4 * m + 3] = v.w;
                 }
 #pragma unroll
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void conv2d_lds(const void* __restrict__ src, 
             float win[WIN];
 #pragma unroll
             for (int m = 0; m < WIN / 4; ++m) {
-                const float4 v = *reinterpret_cast<const float4*>(base + q * LW + 4 * m);
+                const v4f v = lds4(base + q * LW + 4 * m);
                 win[4 * m] = v.x; win[4 * m + 1] = v.y; win[4 * m + 2] = v.z; win[4 * m + 3] = v.w;
             }
 #pragma unroll
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void conv2d_lds(const void* __restrict__ src, 
 #pragma unroll
             for (int px = 0; px < PX; px += 4)
                 store4<T>(dst, row + (size_t)(xb + px) * T::size,
-                          make_float4(acc[py][px], acc[py][px + 1], acc[py][px + 2], acc[py][px + 3]));
+                          mk4(acc[py][px], acc[py][px + 1], acc[py][px + 2], acc[py][px + 3]));
         } else {
 #pragma unroll
             for (int px = 0; px < PX; ++px)
@@ -213,6 +213,146 @@ hipError_t launch_lds(const Conv2dArgs& a) {
 
 bool supports_lds(const Conv2dArgs& a) { return a.r >= 0 && a.r <= 7; }
 
+// ------------------------------------------------------------------ persistent, prefetching, taps in LDS
+// Each block walks tiles with stride gridDim.x.  While tile t is computed from LDS
+// the global loads of tile t + gridDim.x are in flight in registers, so the HBM
+// latency hides under the FMAs.  The taps live in LDS (read as broadcast float4)
+// rather than SGPRs: a scalar load inside the loop forces a wait on every
+// outstanding LDS read.  Tap rows are the outer loop; the PY input-row windows a
+// lane needs form a rolling register buffer, so each staged row is read once.
+template <class T, int R, int PX, int PY>
+__global__ __launch_bounds__(256) void conv2d_pers(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
+                                                   size_t dp, int W, int H, const float* __restrict__ w, int tiles_x,
+                                                   int ntiles, int vec_ok) {
+    using G = Tile2d<R, PX, PY>;
+    constexpr int TW = G::TW, TH = G::TH, RA = G::RA, LW = G::LW, NR = G::NR, WIN = G::WIN;
+    constexpr int N = 2 * R + 1, NP = (N + 3) & ~3;
+    __shared__ __attribute__((aligned(16))) float s[NR * LW];
+    __shared__ __attribute__((aligned(16))) float wl[N * NP];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < N * NP; i += 256) {
+        const int j = i / NP, c = i - j * NP;
+        wl[i] = c < N ? w[j * N + c] : 0.f;
+    }
+    Stage<T, NR, LW> st;
+    int t = first_tile();
+    int x0, y0;
+    if (t < ntiles) {
+        tile_origin(t, tiles_x, TW, TH, x0, y0);
+        st.load(src, sp, W, H, x0 - RA, y0 - R, vec_ok && x0 - RA >= 0 && x0 + TW + RA <= W);
+    }
+    const int tx = tid & 15, ty = tid >> 4;
+    for (; t < ntiles; t += gridDim.x) {
+        tile_origin(t, tiles_x, TW, TH, x0, y0);
+        st.store(s);
+        __syncthreads();
+        const int tn = t + (int)gridDim.x;
+        if (tn < ntiles) {
+            int nx0, ny0;
+            tile_origin(tn, tiles_x, TW, TH, nx0, ny0);
+            st.load(src, sp, W, H, nx0 - RA, ny0 - R, vec_ok && nx0 - RA >= 0 && nx0 + TW + RA <= W);
+        }
+        float acc[PY][PX];
+#pragma unroll
+        for (int py = 0; py < PY; ++py)
+#pragma unroll
+            for (int px = 0; px < PX; ++px) acc[py][px] = 0.f;
+        const float* base = &s[(ty * PY) * LW + tx * PX];
+        float win[PY][WIN];
+        auto load_win = [&](float* dstw, const float* p) {
+#pragma unroll
+            for (int m = 0; m < WIN / 4; ++m) {
+                const v4f v = lds4(p + 4 * m);
+                dstw[4 * m] = v.x; dstw[4 * m + 1] = v.y; dstw[4 * m + 2] = v.z; dstw[4 * m + 3] = v.w;
+            }
+        };
+#pragma unroll
+        for (int py = 0; py < PY - 1; ++py) load_win(win[py], base + py * LW);
+#pragma unroll 1
+        for (int jb = 0; jb < N; jb += PY) {
+#pragma unroll
+            for (int u = 0; u < PY; ++u) {
+                const int j = jb + u;
+                if (j < N) {
+                    load_win(win[(u + PY - 1) % PY], base + (j + PY - 1) * LW);
+                    float tp[NP];
+#pragma unroll
+                    for (int m = 0; m < NP / 4; ++m) {
+                        const v4f v = lds4(&wl[j * NP + 4 * m]);
+                        tp[4 * m] = v.x; tp[4 * m + 1] = v.y; tp[4 * m + 2] = v.z; tp[4 * m + 3] = v.w;
+                    }
+#pragma unroll
+                    for (int py = 0; py < PY; ++py) {
+                        const float* wv = win[(u + py) % PY];
+#pragma unroll
+                        for (int i = 0; i < N; ++i)
+#pragma unroll
+                            for (int px = 0; px < PX; ++px) acc[py][px] = fmaf(tp[i], wv[RA - R + px + i], acc[py][px]);
+                    }
+                }
+            }
+        }
+        const int xb = x0 + tx * PX;
+#pragma unroll
+        for (int py = 0; py < PY; ++py) {
+            const int y = y0 + ty * PY + py;
+            if (y >= H) break;
+            const size_t row = (size_t)y * dp;
+            if (vec_ok && xb + PX <= W) {
+#pragma unroll
+                for (int px = 0; px < PX; px += 4)
+                    store4<T>(dst, row + (size_t)(xb + px) * T::size,
+                              mk4(acc[py][px], acc[py][px + 1], acc[py][px + 2], acc[py][px + 3]));
+            } else {
+#pragma unroll
+                for (int px = 0; px < PX; ++px)
+                    if (xb + px < W) store_px<T>(dst, row + (size_t)(xb + px) * T::size, acc[py][px]);
+            }
+        }
+        __syncthreads();   // every lane is done with s before the next tile overwrites it
+    }
+}
+
+template <class T, int R, int PX, int PY>
+hipError_t launch_pers_TR(const Conv2dArgs& a) {
+    using G = Tile2d<R, PX, PY>;
+    const int tiles_x = (a.W + G::TW - 1) / G::TW;
+    const int tiles_y = (a.H + G::TH - 1) / G::TH;
+    const int ntiles = tiles_x * tiles_y;
+    const size_t al = 4 * (size_t)T::size;
+    const int vec_ok = ((uintptr_t)a.src % al == 0) && (a.sp % al == 0) && ((uintptr_t)a.dst % al == 0) &&
+                       (a.dp % al == 0);
+    const void* k = reinterpret_cast<const void*>(&conv2d_pers<T, R, PX, PY>);
+    const int grid = persistent_grid(k, 256, ntiles);
+    hipLaunchKernelGGL((conv2d_pers<T, R, PX, PY>), dim3(grid), dim3(256), 0, a.st, a.src, a.sp, a.dst, a.dp, a.W,
+                       a.H, a.taps, tiles_x, ntiles, vec_ok);
+    return hipGetLastError();
+}
+
+template <class T, int PX, int PY>
+hipError_t launch_pers_T(const Conv2dArgs& a) {
+    switch (a.r) {
+        case 0: return launch_pers_TR<T, 0, PX, PY>(a);
+        case 1: return launch_pers_TR<T, 1, PX, PY>(a);
+        case 2: return launch_pers_TR<T, 2, PX, PY>(a);
+        case 3: return launch_pers_TR<T, 3, PX, PY>(a);
+        case 4: return launch_pers_TR<T, 4, PX, PY>(a);
+        case 5: return launch_pers_TR<T, 5, PX, PY>(a);
+        case 6: return launch_pers_TR<T, 6, PX, PY>(a);
+        case 7: return launch_pers_TR<T, 7, PX, PY>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int PX, int PY>
+hipError_t launch_pers(const Conv2dArgs& a) {
+    switch (a.dt) {
+        case ICL_F32: return launch_pers_T<F32, PX, PY>(a);
+        case ICL_F16: return launch_pers_T<F16, PX, PY>(a);
+        default: return launch_pers_T<BF16, PX, PY>(a);
+    }
+}
+
 const Variant<Conv2dArgs> kConv2d[] = {
     {"plain", supports_plain, launch_plain},
     {"lds_p4x4_o0", supports_lds, launch_lds<4, 4, 0>},
@@ -220,6 +360,10 @@ const Variant<Conv2dArgs> kConv2d[] = {
     {"lds_p4x8_o0", supports_lds, launch_lds<4, 8, 0>},
     {"lds_p4x2_o1", supports_lds, launch_lds<4, 2, 1>},
     {"lds_p8x2_o0", supports_lds, launch_lds<8, 2, 0>},
+    {"pers_p4x4", supports_lds, launch_pers<4, 4>},
+    {"pers_p8x2", supports_lds, launch_pers<8, 2>},
+    {"pers_p4x2", supports_lds, launch_pers<4, 2>},
+    {"pers_p8x4", supports_lds, launch_pers<8, 4>},
 };
 
 }  // namespace

@@ -20,6 +20,7 @@
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
 #include "sep_tile.hpp"
+#include "tile_stage.hpp"
 
 namespace icl {
 namespace {
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(256) void sep_fused(const void* __restrict__ src, s
                                                  size_t dp, int W, int H, const float* __restrict__ tx,
                                                  const float* __restrict__ ty, int tiles_x, int vec_ok) {
     using G = SepTile<R, TH, CX>;
-    __shared__ float lds[G::LDS_FLOATS];
+    __shared__ __attribute__((aligned(16))) float lds[G::LDS_FLOATS];
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
     const int x0 = (int)(t % (unsigned)tiles_x) * G::TW;
     const int y0 = (int)(t / (unsigned)tiles_x) * TH;
@@ -126,12 +127,88 @@ hipError_t launch_fused(const SepArgs& a) {
 
 bool supports_fused(const SepArgs& a) { return a.r >= 0 && a.r <= 7; }
 
+// Persistent fused variant: each block walks tiles with stride gridDim.x and keeps the
+// next tile's global loads in flight (registers) while the current tile's row and
+// column passes run from LDS.  Two barriers per tile.
+template <class T, int R, int TH, int CX>
+__global__ __launch_bounds__(256) void sep_pers(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
+                                                size_t dp, int W, int H, const float* __restrict__ tx,
+                                                const float* __restrict__ ty, int tiles_x, int ntiles, int vec_ok) {
+    using G = SepTile<R, TH, CX>;
+    constexpr int TW = G::TW, RA = G::RA, LW = G::LW, NR = G::NR;
+    __shared__ __attribute__((aligned(16))) float lds[G::LDS_FLOATS];
+    float* in_s = lds;
+    float* t_s = lds + NR * LW;
+    Stage<T, NR, LW> st;
+    int t = first_tile();
+    int x0, y0;
+    if (t < ntiles) {
+        tile_origin(t, tiles_x, TW, TH, x0, y0);
+        st.load(src, sp, W, H, x0 - RA, y0 - R, vec_ok && x0 - RA >= 0 && x0 + TW + RA <= W);
+    }
+    for (; t < ntiles; t += gridDim.x) {
+        tile_origin(t, tiles_x, TW, TH, x0, y0);
+        st.store(in_s);
+        __syncthreads();
+        const int tn = t + (int)gridDim.x;
+        if (tn < ntiles) {
+            int nx0, ny0;
+            tile_origin(tn, tiles_x, TW, TH, nx0, ny0);
+            st.load(src, sp, W, H, nx0 - RA, ny0 - R, vec_ok && nx0 - RA >= 0 && nx0 + TW + RA <= W);
+        }
+        sep_row_pass<R, TH, CX>(in_s, t_s, tx);
+        __syncthreads();
+        sep_col_pass<T, R, TH, CX>(t_s, dst, dp, W, H, ty, x0, y0);
+    }
+}
+
+template <class T, int R, int TH, int CX>
+hipError_t launch_pers_TR(const SepArgs& a) {
+    using G = SepTile<R, TH, CX>;
+    const int tiles_x = (a.W + G::TW - 1) / G::TW;
+    const int ntiles = tiles_x * ((a.H + TH - 1) / TH);
+    const size_t al = 4 * (size_t)T::size;
+    const int vec_ok = ((uintptr_t)a.src % al == 0) && (a.sp % al == 0);
+    const void* k = reinterpret_cast<const void*>(&sep_pers<T, R, TH, CX>);
+    hipLaunchKernelGGL((sep_pers<T, R, TH, CX>), dim3(persistent_grid(k, 256, ntiles)), dim3(256), 0, a.st, a.src,
+                       a.sp, a.dst, a.dp, a.W, a.H, a.tx, a.ty, tiles_x, ntiles, vec_ok);
+    return hipGetLastError();
+}
+
+template <class T, int TH, int CX>
+hipError_t launch_pers_T(const SepArgs& a) {
+    switch (a.r) {
+        case 0: return launch_pers_TR<T, 0, TH, CX>(a);
+        case 1: return launch_pers_TR<T, 1, TH, CX>(a);
+        case 2: return launch_pers_TR<T, 2, TH, CX>(a);
+        case 3: return launch_pers_TR<T, 3, TH, CX>(a);
+        case 4: return launch_pers_TR<T, 4, TH, CX>(a);
+        case 5: return launch_pers_TR<T, 5, TH, CX>(a);
+        case 6: return launch_pers_TR<T, 6, TH, CX>(a);
+        case 7: return launch_pers_TR<T, 7, TH, CX>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int TH, int CX>
+hipError_t launch_pers(const SepArgs& a) {
+    switch (a.dt) {
+        case ICL_F32: return launch_pers_T<F32, TH, CX>(a);
+        case ICL_F16: return launch_pers_T<F16, TH, CX>(a);
+        default: return launch_pers_T<BF16, TH, CX>(a);
+    }
+}
+
 const Variant<SepArgs> kSep[] = {
     {"plain2p", supports_plain, launch_plain},
     {"fused_t32_c1", supports_fused, launch_fused<32, 1>},
     {"fused_t64_c1", supports_fused, launch_fused<64, 1>},
     {"fused_t32_c2", supports_fused, launch_fused<32, 2>},
     {"fused_t16_c2", supports_fused, launch_fused<16, 2>},
+    {"pers_t32_c1", supports_fused, launch_pers<32, 1>},
+    {"pers_t16_c2", supports_fused, launch_pers<16, 2>},
+    {"pers_t64_c1", supports_fused, launch_pers<64, 1>},
+    {"pers_t16_c1", supports_fused, launch_pers<16, 1>},
 };
 
 }  // namespace

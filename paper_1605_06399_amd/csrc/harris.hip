@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void harris_fused(const float* __restrict__ sr
     using G = HTile<RG, TH>;
     constexpr int TW = G::TW, HX = G::HX, HXA = G::HXA, IW = G::IW, IR = G::IR, GW = G::GW, GH = G::GH,
                   PY = G::PY;
-    __shared__ float lds[G::LDS_FLOATS];
+    __shared__ __attribute__((aligned(16))) float lds[G::LDS_FLOATS];
     float* img = lds;                      // [IR][IW], dead after the gradient stage
     float* hs = lds;                       // [3][GH][TW] row-pass sums (reuses img)
     float* abc = lds + G::REGION1;         // [3][GH][GW] products Ix^2, Iy^2, Ix*Iy
@@ -118,8 +118,8 @@ __global__ __launch_bounds__(256) void harris_fused(const float* __restrict__ sr
         for (int idx = tid; idx < IR * C4; idx += 256) {
             const int rr = idx / C4, c4 = idx - rr * C4;
             const int y = clampi(y0 - HX + rr, H);
-            *reinterpret_cast<float4*>(&img[rr * IW + 4 * c4]) = *reinterpret_cast<const float4*>(
-                reinterpret_cast<const char*>(src) + (size_t)y * sp + (size_t)(x0 - HXA + 4 * c4) * 4);
+            lds4(&img[rr * IW + 4 * c4], *reinterpret_cast<const v4f*>(
+                reinterpret_cast<const char*>(src) + (size_t)y * sp + (size_t)(x0 - HXA + 4 * c4) * 4));
         }
     } else {
         for (int idx = tid; idx < IR * IW; idx += 256) {

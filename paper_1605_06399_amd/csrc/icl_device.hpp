@@ -6,6 +6,14 @@
 
 namespace icl {
 
+// Native 4 x float32 vector: loads and stores of it lower to single dwordx4 /
+// ds_read_b128 instructions (HIP's float4 struct is copied member by member).
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mk4(float a, float b, float c, float d) { return v4f{a, b, c, d}; }
+__device__ __forceinline__ v4f lds4(const float* p) { return *reinterpret_cast<const v4f*>(p); }
+__device__ __forceinline__ void lds4(float* p, v4f v) { *reinterpret_cast<v4f*>(p) = v; }
+
 // ------------------------------------------------------------------ storage types
 // Pixel storage tags.  Arithmetic is always float32; these convert on load/store.
 struct F32 { using storage = float; static constexpr int size = 4; };
@@ -49,38 +57,37 @@ template <> __device__ __forceinline__ void store_px<BF16>(void* base, size_t of
 }
 
 // Four consecutive pixels starting at a byte offset that is 4*size aligned.
-template <class T> __device__ __forceinline__ float4 load4(const void* base, size_t off);
-template <> __device__ __forceinline__ float4 load4<F32>(const void* base, size_t off) {
-    return *reinterpret_cast<const float4*>(static_cast<const char*>(base) + off);
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+
+template <class T> __device__ __forceinline__ v4f load4(const void* base, size_t off);
+template <> __device__ __forceinline__ v4f load4<F32>(const void* base, size_t off) {
+    return *reinterpret_cast<const v4f*>(static_cast<const char*>(base) + off);
 }
-template <> __device__ __forceinline__ float4 load4<F16>(const void* base, size_t off) {
-    const uint2 u = *reinterpret_cast<const uint2*>(static_cast<const char*>(base) + off);
-    _Float16 h[4];
-    __builtin_memcpy(h, &u, 8);
-    return make_float4(decode(h[0]), decode(h[1]), decode(h[2]), decode(h[3]));
+template <> __device__ __forceinline__ v4f load4<F16>(const void* base, size_t off) {
+    const v4h h = *reinterpret_cast<const v4h*>(static_cast<const char*>(base) + off);
+    return v4f{decode(h.x), decode(h.y), decode(h.z), decode(h.w)};
 }
-template <> __device__ __forceinline__ float4 load4<BF16>(const void* base, size_t off) {
-    const uint2 u = *reinterpret_cast<const uint2*>(static_cast<const char*>(base) + off);
-    return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
-                       __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+template <> __device__ __forceinline__ v4f load4<BF16>(const void* base, size_t off) {
+    const v2u u = *reinterpret_cast<const v2u*>(static_cast<const char*>(base) + off);
+    return v4f{__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u), __uint_as_float(u.y << 16),
+               __uint_as_float(u.y & 0xffff0000u)};
 }
 
-template <class T> __device__ __forceinline__ void store4(void* base, size_t off, float4 v);
-template <> __device__ __forceinline__ void store4<F32>(void* base, size_t off, float4 v) {
-    *reinterpret_cast<float4*>(static_cast<char*>(base) + off) = v;
+template <class T> __device__ __forceinline__ void store4(void* base, size_t off, v4f v);
+template <> __device__ __forceinline__ void store4<F32>(void* base, size_t off, v4f v) {
+    *reinterpret_cast<v4f*>(static_cast<char*>(base) + off) = v;
 }
-template <> __device__ __forceinline__ void store4<F16>(void* base, size_t off, float4 v) {
-    _Float16 h[4] = {static_cast<_Float16>(v.x), static_cast<_Float16>(v.y),
-                     static_cast<_Float16>(v.z), static_cast<_Float16>(v.w)};
-    uint2 u;
-    __builtin_memcpy(&u, h, 8);
-    *reinterpret_cast<uint2*>(static_cast<char*>(base) + off) = u;
+template <> __device__ __forceinline__ void store4<F16>(void* base, size_t off, v4f v) {
+    const v4h h = {static_cast<_Float16>(v.x), static_cast<_Float16>(v.y), static_cast<_Float16>(v.z),
+                   static_cast<_Float16>(v.w)};
+    *reinterpret_cast<v4h*>(static_cast<char*>(base) + off) = h;
 }
-template <> __device__ __forceinline__ void store4<BF16>(void* base, size_t off, float4 v) {
-    uint2 u;
+template <> __device__ __forceinline__ void store4<BF16>(void* base, size_t off, v4f v) {
+    v2u u;
     u.x = static_cast<uint32_t>(encode_bf16(v.x)) | (static_cast<uint32_t>(encode_bf16(v.y)) << 16);
     u.y = static_cast<uint32_t>(encode_bf16(v.z)) | (static_cast<uint32_t>(encode_bf16(v.w)) << 16);
-    *reinterpret_cast<uint2*>(static_cast<char*>(base) + off) = u;
+    *reinterpret_cast<v2u*>(static_cast<char*>(base) + off) = u;
 }
 
 // ------------------------------------------------------------------ indexing

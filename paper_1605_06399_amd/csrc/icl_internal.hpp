@@ -91,6 +91,10 @@ int tune_cache_get(icl_op op, icl_dtype dt, int r, int W, int H);
 icl_status device_ready();
 const char* op_name(icl_op op);
 
+// Grid for a persistent tile loop: resident blocks of `kernel` on the whole device
+// (occupancy x CUs, cached per kernel), at most `ntiles`, rounded down to a multiple of 8.
+int persistent_grid(const void* kernel, int block, int ntiles);
+
 // Zero-fill `n` floats with a kernel (no memset node, so it is safe inside captured graphs).
 hipError_t zero_fill(float* p, size_t n, hipStream_t st);
 

@@ -48,7 +48,7 @@ bool supports_plain(const NmsArgs& a) { return a.r >= 1 && a.r <= ICL_MAX_NMS_RA
 // ------------------------------------------------------------------ four pixels per lane, r = 1
 __device__ __forceinline__ void row6(const float* __restrict__ row, int x, int W, bool interior, float v[6]) {
     if (interior) {
-        const float4 m = *reinterpret_cast<const float4*>(row + x);
+        const v4f m = *reinterpret_cast<const v4f*>(row + x);
         v[0] = row[x - 1]; v[1] = m.x; v[2] = m.y; v[3] = m.z; v[4] = m.w; v[5] = row[x + 4];
     } else {
 #pragma unroll

@@ -97,18 +97,37 @@ __global__ void fill_k(void* dst, size_t pitch, int W, int H, unsigned long long
     store_px<T>(dst, (size_t)y * pitch + (size_t)x * T::size, hash_uniform(i, seed));
 }
 
-// out[0] = max |a - b|, out[1] = max |b| (as float bits; values are non-negative)
+// out[0] = max |a - b|, out[1] = max |b| (as float bits; values are non-negative).
+// Each block reduces in LDS first, so only one pair of atomics per block reaches memory.
 template <class T>
-__global__ void compare_k(const void* a, const void* b, size_t pitch, int W, int H, unsigned* out) {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (size_t)W * H) return;
-    const int y = (int)(i / W), x = (int)(i % W);
-    const size_t off = (size_t)y * pitch + (size_t)x * T::size;
-    const float va = load_px<T>(a, off), vb = load_px<T>(b, off);
-    float d = fabsf(va - vb);
-    if (!(d == d)) d = 3.0e38f;   // NaN counts as a mismatch
-    atomicMax(&out[0], __float_as_uint(d));
-    atomicMax(&out[1], __float_as_uint(fabsf(vb)));
+__global__ __launch_bounds__(256) void compare_k(const void* a, const void* b, size_t pitch, int W, int H,
+                                                 unsigned* out) {
+    __shared__ unsigned red[2][256];
+    const size_t n = (size_t)W * H;
+    unsigned md = 0, mb = 0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const int y = (int)(i / W), x = (int)(i % W);
+        const size_t off = (size_t)y * pitch + (size_t)x * T::size;
+        const float va = load_px<T>(a, off), vb = load_px<T>(b, off);
+        float d = fabsf(va - vb);
+        if (!(d == d)) d = 3.0e38f;   // NaN counts as a mismatch
+        md = max(md, __float_as_uint(d));
+        mb = max(mb, __float_as_uint(fabsf(vb)));
+    }
+    red[0][threadIdx.x] = md;
+    red[1][threadIdx.x] = mb;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] = max(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+            red[1][threadIdx.x] = max(red[1][threadIdx.x], red[1][threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(&out[0], red[0][0]);
+        atomicMax(&out[1], red[1][0]);
+    }
 }
 
 __global__ void compare_u8_k(const uint8_t* a, const uint8_t* b, size_t pitch, int W, int H, unsigned* out) {
@@ -138,7 +157,7 @@ hipError_t fill(icl_dtype dt, void* p, size_t pitch, int W, int H, unsigned long
 bool outputs_agree(icl_dtype dt, const void* a, const void* b, size_t pitch, int W, int H, unsigned* d_stat,
                    hipStream_t st) {
     hipLaunchKernelGGL(zero2_k, dim3(1), dim3(64), 0, st, d_stat);
-    const unsigned nb = blocks_for((size_t)W * H);
+    const unsigned nb = std::min(blocks_for((size_t)W * H), 2048u);
     switch (dt) {
         case ICL_F32: hipLaunchKernelGGL(compare_k<F32>, dim3(nb), dim3(256), 0, st, a, b, pitch, W, H, d_stat); break;
         case ICL_F16: hipLaunchKernelGGL(compare_k<F16>, dim3(nb), dim3(256), 0, st, a, b, pitch, W, H, d_stat); break;
