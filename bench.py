@@ -42,6 +42,11 @@ def parse():
     p.add_argument("--no-extras", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--only", default="", help="comma list of call labels to run (profiling aid)")
+    p.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                   help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter_collection.csv files of a --calib-copy "
+                        "run into profiles/traffic.json and exit")
+    p.add_argument("--calib-copy", action="store_true",
+                   help="also run three 1 GiB device-to-device copies (a known byte count for counter calibration)")
     return p.parse_args()
 
 
@@ -54,6 +59,11 @@ def roof_gpx(kind, r, bytes_px=8.0):
     hbm = HBM_PEAK_GBS / bytes_px
     alu = FP32_FMA_PEAK_TFLOPS * 1e3 / flops_per_px(kind, r)
     return min(hbm, alu), ("hbm" if hbm <= alu else "alu")
+
+
+# kernel source files per call kind: traffic figures are valid only for the source they were taken on
+KERNEL_SOURCES = {"2d": ["conv2d.hip", "tile_stage.hpp", "corr_tile.hpp", "icl_device.hpp"],
+                  "sep": ["conv_sep.hip", "sep_tile.hpp", "tile_stage.hpp", "icl_device.hpp"]}
 
 
 def source_hash(*names):
@@ -78,8 +88,69 @@ def stored_traffic(kernel_key, src_files):
     return None
 
 
+def kernel_variant(name):
+    """(kind, radius, variant name) of a float32 sweep kernel's symbol, else None."""
+    import re
+    pats = [("2d", r"conv2d_pers<icl::F32, (\d+), (\d+), (\d+)>", "pers_p{1}x{2}"),
+            ("2d", r"conv2d_lds<icl::F32, (\d+), (\d+), (\d+), (\d+)>", "lds_p{1}x{2}_o{3}"),
+            ("sep", r"sep_pers<icl::F32, (\d+), (\d+), (\d+)>", "pers_t{1}_c{2}"),
+            ("sep", r"sep_fused<icl::F32, (\d+), (\d+), (\d+)>", "fused_t{1}_c{2}")]
+    for kind, pat, fmt in pats:
+        m = re.search(pat, name)
+        if m:
+            g = m.groups()
+            return kind, int(g[0]), fmt.format(*g)
+    return None
+
+
+def write_traffic(fetch_csv, write_csv, side=4096):
+    """HBM bytes per dispatch: mean FETCH_SIZE / WRITE_SIZE (KiB) per kernel, each scaled so that the
+    counter reads 1 GiB on the run's three 1 GiB device-to-device copies."""
+    import collections
+    import csv
+
+    def load(p):
+        agg = collections.defaultdict(list)
+        for r in csv.DictReader(open(p)):
+            agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return agg
+
+    fe, wr = load(fetch_csv), load(write_csv)
+    cf = sorted(v for k, vs in fe.items() if "copyBuffer" in k for v in vs)[-3:]
+    cw = sorted(v for k, vs in wr.items() if "copyBuffer" in k for v in vs)[-3:]
+    fcal, wcal = (1 << 20) / (sum(cf) / 3), (1 << 20) / (sum(cw) / 3)
+    alg = 8 * side * side
+    out = {"_about": "HBM bytes per dispatch from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per "
+                     "dispatch, mean over dispatches), each scaled by the factor that maps the same counter on a "
+                     "1 GiB device-to-device copy to 1 GiB; source_hash covers the kernel's source files and "
+                     "bench.py reports traffic only while it matches.",
+           "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_fetch -o fetch -- "
+                        "python3 bench.py --only 2d7,sep7 --steps 3 --warmup 1 --no-extras --no-cpu --calib-copy",
+                        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_write -o write -- "
+                        "python3 bench.py --only 2d7,sep7 --steps 3 --warmup 1 --no-extras --no-cpu --calib-copy"],
+           "calibration": {"fetch_factor": round(fcal, 4), "write_factor": round(wcal, 4),
+                           "copy_fetch_kib": [round(v, 1) for v in cf], "copy_write_kib": [round(v, 1) for v in cw]}}
+    for k in fe:
+        v = kernel_variant(k)
+        if not v or k not in wr:
+            continue
+        kind, r, name = v
+        f, w = float(np.mean(fe[k])), float(np.mean(wr[k]))
+        b = (f * fcal + w * wcal) * 1024
+        out[f"{kind}{r}:{name}"] = {"fetch_kib": round(f, 1), "write_kib": round(w, 1), "bytes_per_launch": int(b),
+                                    "algorithmic_bytes": alg, "ratio": round(b / alg, 3),
+                                    "source_hash": source_hash(*KERNEL_SOURCES[kind])}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(f"wrote {path}")
+
+
 def main():
     a = parse()
+    if a.write_traffic:
+        write_traffic(*a.write_traffic, side=a.side)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU design is "
               "described in DESIGN.md but not built.", file=sys.stderr)
@@ -128,36 +199,38 @@ def main():
         chosen[f"{kind}{r}"] = B.icl_variant_name(op, B.icl_selected_variant(op, B.ICL_F32, r, side, side)[1])
 
     def run(steps, warmup, label):
+        """Time `steps` steps.  The calls of the steps run grouped by call (all launches of one
+        call back to back, rotating buffers), so one event pair per call brackets `steps`
+        launches and the per-launch mean carries no per-launch event overhead."""
         k = 0
         for _ in range(warmup):
             for kind, r in calls:
                 call(kind, r, k % NSET)
                 k += 1
-        evs = {c: [] for c in calls}
+        evs = {}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            for c in calls:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
+        for c in calls:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
                 call(c[0], c[1], k % NSET)
-                e1.record(stream)
-                evs[c].append((e0, e1))
                 k += 1
+            e1.record(stream)
+            evs[c] = (e0, e1)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
-        per = {c: float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs[c]])) * 1e3 for c in calls}   # us
+        per = {c: e0.elapsed_time(e1) * 1e3 / steps for c, (e0, e1) in evs.items()}   # us per launch
+        print(f"[bench] {label}: {dt * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
         return dt, per
 
     dt_tuned, per_tuned = run(a.steps, a.warmup, "tuned")
-    print(f"[bench] tuned: {dt_tuned * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
     B.check(B.icl_force_variant(B.ICL_OP_CONV_SEP, 0))
     B.check(B.icl_force_variant(B.ICL_OP_CONV2D, 0))
     dt_plain, per_plain = run(max(2, a.steps // 4), max(1, a.warmup // 2), "plain")
     B.icl_force_variant(B.ICL_OP_CONV_SEP, -1)
     B.icl_force_variant(B.ICL_OP_CONV2D, -1)
-    print(f"[bench] plain: {dt_plain * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
 
     px = side * side
     per_op = []
@@ -183,8 +256,7 @@ def main():
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 3)}
     key = f"{kind}{r}:{chosen[f'{kind}{r}']}"
-    src_files = ["conv_sep.hip", "sep_tile.hpp"] if kind == "sep" else ["conv2d.hip"]
-    roofline["traffic"] = stored_traffic(key, src_files)
+    roofline["traffic"] = stored_traffic(key, KERNEL_SOURCES[kind])
     roofline["kernel"] = key
     roofline["algorithmic_bytes_per_launch"] = 8 * px
     roofline["flops_per_launch"] = flops_per_px(kind, r) * px
@@ -208,6 +280,15 @@ def main():
     }
     del src, dst, ws
     torch.cuda.empty_cache()
+    if a.calib_copy:
+        n = (1 << 30) // 4
+        c_src = torch.ones(n, dtype=torch.float32, device=dev)
+        c_dst = torch.empty_like(c_src)
+        for _ in range(3):
+            c_dst.copy_(c_src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes_each_way"] = 1 << 30
+        del c_src, c_dst
 
     if not a.no_extras:
         try:
@@ -262,9 +343,19 @@ def run_extras(torch, B, T, synth, steps):
 
     # uneven batch: 256 images, one persistent launch replayed from a HIP graph (4 B/px half storage)
     items = synth.batch_uneven()
+
+    def pitched(h, w, tdt):
+        """h x w view with rows padded to a multiple of 256 bytes (the workload's layout)."""
+        pw = -(-w * 2 // 256) * 128
+        return torch.empty((h, pw), dtype=tdt, device=dev)[:, :w]
+
     for name, tdt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
-        ims = [torch.from_numpy(it.image).to(dev).to(tdt) for it in items]
-        outs = [torch.empty_like(t) for t in ims]
+        ims, outs = [], []
+        for it in items:
+            x = pitched(it.height, it.width, tdt)
+            x.copy_(torch.from_numpy(it.image).to(dev).to(tdt))
+            ims.append(x)
+            outs.append(pitched(it.height, it.width, tdt))
         taps = [torch.from_numpy(it.taps).to(dev) for it in items]
         plan = T.BatchPlan(ims, outs, taps)
         plan.graph()
@@ -322,21 +413,27 @@ def run_extras(torch, B, T, synth, steps):
 
 
 def cpu_baseline(synth, radii, side):
-    """The FP64 oracle, as it stands, on a horizontal strip of the same image (all ten calls)."""
+    """The FP64 oracle, as it stands, on the same step: all ten calls over the full image
+    (median of three runs, rows split over the host threads)."""
     from oracle import oracle
-    rows = int(os.environ.get("ICL_CPU_SAMPLE_ROWS", "256"))
+    rows = int(os.environ.get("ICL_CPU_SAMPLE_ROWS", str(side)))
     threads = min(os.cpu_count() or 1, 16)
     img = synth.sweep_image(side)[:rows].astype(np.float64)
-    t0 = time.perf_counter()
-    for r in radii:
-        h, v = synth.sweep_taps_sep(r)
-        oracle.conv_sep(img, h, v, nthreads=threads)
-        oracle.conv2d(img, synth.sweep_taps_2d(r), nthreads=threads)
-    dt = time.perf_counter() - t0
+    taps = [(synth.sweep_taps_sep(r), synth.sweep_taps_2d(r)) for r in radii]
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        for (h, v), w in taps:
+            oracle.conv_sep(img, h, v, nthreads=threads)
+            oracle.conv2d(img, w, nthreads=threads)
+        times.append(time.perf_counter() - t0)
+        print(f"[bench] cpu oracle step {times[-1]:.2f} s", file=sys.stderr, flush=True)
+    dt = sorted(times)[1]
     px = rows * side * len(radii) * 2
+    what = "the full step" if rows == side else f"rows 0..{rows - 1} of every call (a {rows}x{side} strip)"
     return {"value": round(px / dt / 1e9, 5), "unit": "Gpixel/s", "cores": threads, "kind": "oracle",
-            "sample": f"rows 0..{rows - 1} of the {side}x{side} sweep image (a {rows}x{side} strip, clamped at its own "
-                      f"bottom edge), all {2 * len(radii)} calls; {dt:.1f} s"}
+            "sample": f"{what}: {2 * len(radii)} calls on the {side}x{side} sweep image, "
+                      f"median of 3 runs, {dt:.2f} s per step"}
 
 
 if __name__ == "__main__":

@@ -315,7 +315,9 @@ icl_status icl_bank_fwd(const float* x, const float* w, float* y, int n, int f, 
     BankArgs a{x, w, y, n, f, h, wd, radius, nullptr, 0, (hipStream_t)stream};
     int count;
     const Variant<BankArgs>* tab = bank_fwd_variants(&count);
-    return dispatch(ICL_OP_BANK_FWD, tab, count, a, select_variant(ICL_OP_BANK_FWD, ICL_F32, radius, wd, h, 0), 0);
+    const int deflt = bank_fwd_default(a);
+    return dispatch(ICL_OP_BANK_FWD, tab, count, a, select_variant(ICL_OP_BANK_FWD, ICL_F32, radius, wd, h, deflt),
+                    deflt);
 }
 
 icl_status icl_bank_bwd_input(const float* gy, const float* w, float* gx, int n, int f, int h, int wd, int radius,
@@ -332,8 +334,9 @@ icl_status icl_bank_bwd_input(const float* gy, const float* w, float* gx, int n,
     BankArgs a{gy, w, gx, n, f, h, wd, radius, nullptr, 0, (hipStream_t)stream};
     int count;
     const Variant<BankArgs>* tab = bank_bwd_input_variants(&count);
+    const int deflt = bank_bwd_input_default(a);
     return dispatch(ICL_OP_BANK_BWD_INPUT, tab, count, a,
-                    select_variant(ICL_OP_BANK_BWD_INPUT, ICL_F32, radius, wd, h, 0), 0);
+                    select_variant(ICL_OP_BANK_BWD_INPUT, ICL_F32, radius, wd, h, deflt), deflt);
 }
 
 icl_status icl_bank_bwd_filter(const float* gy, const float* x, float* gw, int n, int f, int h, int wd, int radius,
@@ -359,8 +362,9 @@ icl_status icl_bank_bwd_filter(const float* gy, const float* x, float* gw, int n
     BankArgs a{gy, x, gw, n, f, h, wd, radius, workspace, workspace_bytes, (hipStream_t)stream};
     int count;
     const Variant<BankArgs>* tab = bank_bwd_filter_variants(&count);
+    const int deflt = bank_bwd_filter_default(a);
     return dispatch(ICL_OP_BANK_BWD_FILTER, tab, count, a,
-                    select_variant(ICL_OP_BANK_BWD_FILTER, ICL_F32, radius, wd, h, 0), 0);
+                    select_variant(ICL_OP_BANK_BWD_FILTER, ICL_F32, radius, wd, h, deflt), deflt);
 }
 
 icl_status icl_sse_loss(const float* y, const float* t, float* gy, long long count, float* loss, void* workspace,

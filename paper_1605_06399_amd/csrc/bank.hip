@@ -23,8 +23,10 @@
 //                    (column-walk register reuse), reduces across the wave with a
 //                    butterfly, and writes one partial per tap.  Stage 2 sums the
 //                    partials of each (f, tap) in a fixed order: deterministic.
+#include "corr_tile.hpp"
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
+#include "tile_stage.hpp"
 
 namespace icl {
 namespace {
@@ -300,6 +302,205 @@ __global__ __launch_bounds__(256) void bank_bwd_w2_k(const float* __restrict__ p
     if (threadIdx.x == 0) gw[blockIdx.x] = red[0];
 }
 
+// ------------------------------------------------------------------ plain baselines
+// One output per lane, runtime loops, clamped reads straight from global memory.
+__global__ __launch_bounds__(256) void bank_fwd_plain_k(const float* __restrict__ x, const float* __restrict__ w,
+                                                        float* __restrict__ y, int N, int F, int H, int W, int r) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long hw = (long long)H * W;
+    if (i >= (long long)N * F * hw) return;
+    const int n = (int)(i / (F * hw));
+    const int f = (int)((i / hw) % F);
+    const int p = (int)(i % hw), py = p / W, px = p - py * W;
+    const int nk = 2 * r + 1;
+    const float* xp = x + (size_t)n * hw;
+    const float* wf = w + (size_t)f * nk * nk;
+    float acc = 0.f;
+    for (int j = -r; j <= r; ++j)
+        for (int q = -r; q <= r; ++q)
+            acc = fmaf(wf[(j + r) * nk + (q + r)], xp[(size_t)clampi(py + j, H) * W + clampi(px + q, W)], acc);
+    y[i] = acc;
+}
+
+// Input gradient straight from the adjoint's definition: gx[q] = sum over padded u with
+// clamp(u) = q of z[u], z[u] = sum_f sum_k w[f,k] gy0[f, u-k].
+__global__ __launch_bounds__(256) void bank_bwd_in_plain_k(const float* __restrict__ gy, const float* __restrict__ w,
+                                                           float* __restrict__ gx, int N, int F, int H, int W, int r) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long hw = (long long)H * W;
+    if (i >= (long long)N * hw) return;
+    const int n = (int)(i / hw);
+    const int p = (int)(i % hw), qy = p / W, qx = p - qy * W;
+    const int lox = (qx == 0) ? -r : qx, hix = (qx == W - 1) ? W - 1 + r : qx;
+    const int loy = (qy == 0) ? -r : qy, hiy = (qy == H - 1) ? H - 1 + r : qy;
+    const int nk = 2 * r + 1;
+    float acc = 0.f;
+    for (int uy = loy; uy <= hiy; ++uy)
+        for (int ux = lox; ux <= hix; ++ux)
+            for (int f = 0; f < F; ++f) {
+                const float* g = gy + ((size_t)n * F + f) * hw;
+                const float* wf = w + (size_t)f * nk * nk;
+                for (int j = -r; j <= r; ++j) {
+                    const int sy = uy - j;
+                    if (sy < 0 || sy >= H) continue;
+                    for (int q = -r; q <= r; ++q) {
+                        const int sx = ux - q;
+                        if (sx < 0 || sx >= W) continue;
+                        acc = fmaf(wf[(j + r) * nk + (q + r)], g[(size_t)sy * W + sx], acc);
+                    }
+                }
+            }
+    gx[i] = acc;
+}
+
+// ------------------------------------------------------------------ persistent, prefetching, taps in LDS
+constexpr int PERS_FMAX = 16;   // filters whose taps fit the static LDS table
+
+template <int R>
+__global__ __launch_bounds__(256) void bank_fwd_pers_k(const float* __restrict__ x, const float* __restrict__ w,
+                                                       float* __restrict__ y, int F, int H, int W, int tiles_x,
+                                                       int tiles_img, int ntiles, int vec) {
+    using G = BankTile<R>;
+    constexpr int LW = G::LW, NR = G::NR, RA = G::RA, N = 2 * R + 1, NP = (N + 3) & ~3;
+    __shared__ __attribute__((aligned(16))) float s[NR * LW];
+    __shared__ __attribute__((aligned(16))) float wl[PERS_FMAX * N * NP];
+    taps_to_lds<R, false>(w, F, wl);
+    const size_t hw = (size_t)H * W;
+    Stage<F32, NR, LW> st;
+    auto fetch = [&](int t) {
+        const int n = t / tiles_img, ti = t - n * tiles_img;
+        int x0, y0;
+        tile_origin(ti, tiles_x, BT, BT, x0, y0);
+        st.load(x + (size_t)n * hw, (size_t)W * 4, W, H, x0 - RA, y0 - R, vec);
+    };
+    const BandWalk walk(tiles_x, ntiles / tiles_x);   // images stacked vertically
+    int t = walk.tile(0);
+    if (t >= 0) fetch(t);
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int k = 0; t >= 0; t = walk.tile(++k)) {
+        const int n = t / tiles_img, ti = t - n * tiles_img;
+        int x0, y0;
+        tile_origin(ti, tiles_x, BT, BT, x0, y0);
+        st.store(s);
+        __syncthreads();
+        const int tn = walk.tile(k + 1);
+        if (tn >= 0) fetch(tn);
+#pragma unroll 1
+        for (int f = 0; f < F; ++f) {
+            float acc[BPY][BPX] = {};
+            corr_rows<R, BPX, BPY, LW>(&s[(ty * BPY) * LW + tx * BPX], &wl[f * N * NP], acc);
+            store_block(y + ((size_t)n * F + f) * hw, W, H, x0, y0, vec, acc);
+        }
+        __syncthreads();
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void bank_bwd_in_pers_k(const float* __restrict__ gy, const float* __restrict__ w,
+                                                          float* __restrict__ gx, int F, int H, int W, int tiles_x,
+                                                          int tiles_img, int ntiles, int vec) {
+    using G = BankTile<R>;
+    constexpr int LW = G::LW, NR = G::NR, RA = G::RA, N = 2 * R + 1, NP = (N + 3) & ~3;
+    __shared__ __attribute__((aligned(16))) float s[NR * LW];
+    __shared__ __attribute__((aligned(16))) float wl[PERS_FMAX * N * NP];
+    taps_to_lds<R, true>(w, F, wl);
+    const size_t hw = (size_t)H * W;
+    Stage<F32, NR, LW, true> st;   // zero outside the image: gy is extended by zero
+    auto fetch = [&](int t, int f) {
+        const int n = t / tiles_img, ti = t - n * tiles_img;
+        int x0, y0;
+        tile_origin(ti, tiles_x, BT, BT, x0, y0);
+        st.load(gy + ((size_t)n * F + f) * hw, (size_t)W * 4, W, H, x0 - RA, y0 - R, vec);
+    };
+    const BandWalk walk(tiles_x, ntiles / tiles_x);   // images stacked vertically
+    int t = walk.tile(0);
+    if (t >= 0) fetch(t, 0);
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int k = 0; t >= 0; t = walk.tile(++k)) {
+        const int tnext = walk.tile(k + 1);
+        const int n = t / tiles_img, ti = t - n * tiles_img;
+        int x0, y0;
+        tile_origin(ti, tiles_x, BT, BT, x0, y0);
+        float acc[BPY][BPX] = {};
+#pragma unroll 1
+        for (int f = 0; f < F; ++f) {
+            st.store(s);
+            __syncthreads();
+            const int nt = (f + 1 < F) ? t : tnext;
+            if (nt >= 0) fetch(nt, (f + 1 < F) ? f + 1 : 0);
+            corr_rows<R, BPX, BPY, LW, true>(&s[(ty * BPY) * LW + tx * BPX], &wl[f * N * NP], acc);
+            __syncthreads();
+        }
+        store_block(gx + (size_t)n * hw, W, H, x0, y0, vec, acc);
+    }
+}
+
+// Filter gradient, four filters per 256-lane block: the x tile (64x64 pixels plus halo)
+// is staged once and shared by the four waves; wave w accumulates all taps of filter
+// 4*group + w over the tile's 4096 pixels (lane = column, 64 rows), then reduces over
+// the wave and writes one partial per tap.
+constexpr int GW4_T = 64;
+
+template <int R>
+__global__ __launch_bounds__(256) void bank_bwd_w4_k(const float* __restrict__ gy, const float* __restrict__ x,
+                                                     float* __restrict__ part, int F, int H, int W, int tiles_x,
+                                                     int tiles_img, int ntiles, int fgroups) {
+    constexpr int N = 2 * R + 1, RA = (R + 3) & ~3, LW = GW4_T + 2 * RA, NR = GW4_T + 2 * R;
+    __shared__ __attribute__((aligned(16))) float s[NR * LW];
+    const unsigned id = xcd_remap(blockIdx.x, gridDim.x);
+    const int fg = (int)(id % (unsigned)fgroups);
+    const int tile = (int)(id / (unsigned)fgroups);
+    const int n = tile / tiles_img, ti = tile - n * tiles_img;
+    int x0, y0;
+    tile_origin(ti, tiles_x, GW4_T, GW4_T, x0, y0);
+    const size_t hw = (size_t)H * W;
+    const float* xp = x + (size_t)n * hw;
+    for (int idx = threadIdx.x; idx < NR * LW; idx += 256) {
+        const int rr = idx / LW, c = idx - rr * LW;
+        s[idx] = xp[(size_t)clampi(y0 - R + rr, H) * W + clampi(x0 - RA + c, W)];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int f = fg * 4 + wave;
+    if (f >= F) return;
+    const float* g = gy + ((size_t)n * F + f) * hw;
+    const int gxp = x0 + lane;
+    float acc[N][N];
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[j][i] = 0.f;
+#pragma unroll 1
+    for (int r0 = 0; r0 < GW4_T; r0 += GW_CH) {
+        float gv[GW_CH];
+#pragma unroll
+        for (int py = 0; py < GW_CH; ++py) {
+            const int yy = y0 + r0 + py;
+            gv[py] = (gxp < W && yy < H) ? g[(size_t)yy * W + gxp] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            float cv[GW_CH + 2 * R];
+#pragma unroll
+            for (int m = 0; m < GW_CH + 2 * R; ++m) cv[m] = s[(r0 + m) * LW + lane + RA - R + i];
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+#pragma unroll
+                for (int py = 0; py < GW_CH; ++py) acc[j][i] = fmaf(gv[py], cv[py + j], acc[j][i]);
+        }
+    }
+    float* out = part + (size_t)f * N * N * ntiles + tile;
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            float v = acc[j][i];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) out[(size_t)(j * N + i) * ntiles] = v;
+        }
+}
+
 // ------------------------------------------------------------------ launchers
 int bank_vec(const float* a, const float* b, int W) {
     return ((uintptr_t)a % 16 == 0) && ((uintptr_t)b % 16 == 0) && (W % 4 == 0);
@@ -337,6 +538,57 @@ hipError_t bwd_w_R(const BankArgs& a) {
     return hipGetLastError();
 }
 
+hipError_t launch_fwd_plain(const BankArgs& a) {
+    const long long tot = (long long)a.n * a.f * a.h * a.w;
+    hipLaunchKernelGGL(bank_fwd_plain_k, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, a.st, a.a, a.b, a.out, a.n,
+                       a.f, a.h, a.w, a.r);
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_in_plain(const BankArgs& a) {
+    const long long tot = (long long)a.n * a.h * a.w;
+    hipLaunchKernelGGL(bank_bwd_in_plain_k, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, a.st, a.a, a.b, a.out,
+                       a.n, a.f, a.h, a.w, a.r);
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t fwd_pers_R(const BankArgs& a) {
+    const int tx = (a.w + BT - 1) / BT, ty = (a.h + BT - 1) / BT;
+    const int ntiles = a.n * tx * ty;
+    const void* k = reinterpret_cast<const void*>(&bank_fwd_pers_k<R>);
+    hipLaunchKernelGGL(bank_fwd_pers_k<R>, dim3(persistent_grid(k, 256, ntiles)), dim3(256), 0, a.st, a.a, a.b,
+                       a.out, a.f, a.h, a.w, tx, tx * ty, ntiles, bank_vec(a.a, a.out, a.w));
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t bwd_in_pers_R(const BankArgs& a) {
+    const int tx = (a.w + BT - 1) / BT, ty = (a.h + BT - 1) / BT;
+    const int ntiles = a.n * tx * ty;
+    const void* k = reinterpret_cast<const void*>(&bank_bwd_in_pers_k<R>);
+    hipLaunchKernelGGL(bank_bwd_in_pers_k<R>, dim3(persistent_grid(k, 256, ntiles)), dim3(256), 0, a.st, a.a, a.b,
+                       a.out, a.f, a.h, a.w, tx, tx * ty, ntiles, bank_vec(a.a, a.out, a.w));
+    const int per = edge_pixels(a.w, a.h);
+    const long long tot = (long long)a.n * per;
+    hipLaunchKernelGGL(bank_bwd_fold_k, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, a.st, a.a, a.b, a.out, a.n,
+                       a.f, a.h, a.w, a.r, per);
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t bwd_w4_R(const BankArgs& a) {
+    const int tx = (a.w + GW4_T - 1) / GW4_T, ty = (a.h + GW4_T - 1) / GW4_T;
+    const int ntiles = a.n * tx * ty;
+    const int fgroups = (a.f + 3) / 4;
+    float* part = static_cast<float*>(a.ws);
+    hipLaunchKernelGGL(bank_bwd_w4_k<R>, dim3((unsigned)(ntiles * fgroups)), dim3(256), 0, a.st, a.a, a.b, part, a.f,
+                       a.h, a.w, tx, tx * ty, ntiles, fgroups);
+    const int nk = (2 * R + 1) * (2 * R + 1);
+    hipLaunchKernelGGL(bank_bwd_w2_k, dim3((unsigned)(a.f * nk)), dim3(256), 0, a.st, part, a.out, ntiles);
+    return hipGetLastError();
+}
+
 #define ICL_BANK_SWITCH(FN)                   \
     switch (a.r) {                            \
         case 1: return FN<1>(a);              \
@@ -349,15 +601,24 @@ hipError_t bwd_w_R(const BankArgs& a) {
 hipError_t launch_fwd(const BankArgs& a) { ICL_BANK_SWITCH(fwd_R) }
 hipError_t launch_bwd_in(const BankArgs& a) { ICL_BANK_SWITCH(bwd_in_R) }
 hipError_t launch_bwd_w(const BankArgs& a) { ICL_BANK_SWITCH(bwd_w_R) }
+hipError_t launch_fwd_pers(const BankArgs& a) { ICL_BANK_SWITCH(fwd_pers_R) }
+hipError_t launch_bwd_in_pers(const BankArgs& a) { ICL_BANK_SWITCH(bwd_in_pers_R) }
+hipError_t launch_bwd_w4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_w4_R) }
 
 bool supports_bank(const BankArgs& a) { return a.r >= 1 && a.r <= 4 && a.f >= 1 && a.f <= 64; }
+bool supports_pers(const BankArgs& a) { return supports_bank(a) && a.f <= PERS_FMAX; }
 bool supports_bwd_w(const BankArgs& a) {
     return supports_bank(a) && a.ws != nullptr && a.wsb >= bank_bwd_filter_workspace(a.n, a.f, a.h, a.w, a.r);
 }
 
-const Variant<BankArgs> kFwd[] = {{"tile64_p4x4", supports_bank, launch_fwd}};
-const Variant<BankArgs> kBwdIn[] = {{"tile64_p4x4_fold", supports_bank, launch_bwd_in}};
-const Variant<BankArgs> kBwdW[] = {{"wave_t32x64", supports_bwd_w, launch_bwd_w}};
+const Variant<BankArgs> kFwd[] = {{"plain", supports_bank, launch_fwd_plain},
+                                   {"tile64_p4x4", supports_bank, launch_fwd},
+                                   {"pers_p4x4", supports_pers, launch_fwd_pers}};
+const Variant<BankArgs> kBwdIn[] = {{"plain", supports_bank, launch_bwd_in_plain},
+                                    {"tile64_p4x4_fold", supports_bank, launch_bwd_in},
+                                    {"pers_p4x4_fold", supports_pers, launch_bwd_in_pers}};
+const Variant<BankArgs> kBwdW[] = {{"wave_t32x64", supports_bwd_w, launch_bwd_w},
+                                   {"block4_t64", supports_bwd_w, launch_bwd_w4}};
 
 // ------------------------------------------------------------------ sum of squares loss
 constexpr int SSE_BLOCKS = 2048;
@@ -415,9 +676,12 @@ __global__ __launch_bounds__(256) void sse_k2(const float* __restrict__ part, in
 }  // namespace
 
 size_t bank_bwd_filter_workspace(int n, int f, int h, int w, int r) {
+    // partials of the variant with the most tiles (the 32x64 wave tiling)
     const size_t tx = (size_t)(w + GW_TW - 1) / GW_TW, ty = (size_t)(h + GW_TH - 1) / GW_TH;
+    const size_t tx4 = (size_t)(w + GW4_T - 1) / GW4_T, ty4 = (size_t)(h + GW4_T - 1) / GW4_T;
     const size_t nk = (size_t)(2 * r + 1) * (2 * r + 1);
-    return (size_t)n * tx * ty * (size_t)f * nk * sizeof(float);
+    const size_t tiles = tx * ty > tx4 * ty4 ? tx * ty : tx4 * ty4;
+    return (size_t)n * tiles * (size_t)f * nk * sizeof(float);
 }
 
 size_t sse_workspace(long long) { return SSE_BLOCKS * sizeof(float); }
@@ -445,16 +709,20 @@ hipError_t sse_launch(const float* y, const float* t, float* gy, long long count
 }
 
 const Variant<BankArgs>* bank_fwd_variants(int* count) {
-    *count = 1;
+    *count = (int)(sizeof(kFwd) / sizeof(kFwd[0]));
     return kFwd;
 }
 const Variant<BankArgs>* bank_bwd_input_variants(int* count) {
-    *count = 1;
+    *count = (int)(sizeof(kBwdIn) / sizeof(kBwdIn[0]));
     return kBwdIn;
 }
 const Variant<BankArgs>* bank_bwd_filter_variants(int* count) {
-    *count = 1;
+    *count = (int)(sizeof(kBwdW) / sizeof(kBwdW[0]));
     return kBwdW;
 }
+
+int bank_fwd_default(const BankArgs& a) { return supports_pers(a) ? 2 : 1; }
+int bank_bwd_input_default(const BankArgs& a) { return supports_pers(a) ? 2 : 1; }
+int bank_bwd_filter_default(const BankArgs&) { return 1; }
 
 }  // namespace icl

@@ -15,6 +15,7 @@
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
 #include "sep_tile.hpp"
+#include "tile_stage.hpp"
 
 namespace icl {
 
@@ -24,7 +25,7 @@ struct DevImage {
     unsigned long long sp, dp;
     const float* tx;
     const float* ty;
-    int W, H, r, vec_ok;
+    int W, H, r, vec_ok, vec_out, pad;
 };
 
 struct BatchTile {
@@ -37,22 +38,47 @@ constexpr int BTH = 32;    // tile rows
 constexpr int BCX = 1;     // tile columns = 64 * BCX
 constexpr int RMAX = 7;
 
+// Persistent walk over the tile table.  The next tile's descriptor and pixels are
+// fetched into registers while the current tile is computed; the row-pass
+// intermediate lives at a fixed LDS offset past the largest staged tile, so staging
+// the next tile (any radius) never overlaps a column pass still reading.
 template <class T>
 __global__ __launch_bounds__(256) void sep_batched_k(const DevImage* __restrict__ imgs,
                                                      const BatchTile* __restrict__ tiles, int ntiles) {
+    constexpr int TW = 64 * BCX;
+    constexpr int IN_MAX = SepTile<RMAX, BTH, BCX>::NR * SepTile<RMAX, BTH, BCX>::LW;
     __shared__ __attribute__((aligned(16))) float lds[SepTile<RMAX, BTH, BCX>::LDS_FLOATS];
-    const int start = (int)xcd_remap(blockIdx.x, gridDim.x);
-    for (int t = start; t < ntiles; t += gridDim.x) {
-        const BatchTile bt = tiles[t];
-        const DevImage d = imgs[bt.img];
+    float* in_s = lds;
+    float* t_s = lds + IN_MAX;
+    RStage<T, BTH + 2 * RMAX> rs;
+    int t = first_tile();
+    if (t >= ntiles) return;
+    BatchTile bt = tiles[t];
+    DevImage d = imgs[bt.img];
+    auto fetch = [&](const DevImage& im, const BatchTile& b) {
+        const int ra = (im.r + 3) & ~3;
+        rs.load(im.src, im.sp, im.W, im.H, b.x0 - ra, b.y0 - im.r, BTH + 2 * im.r, (TW + 2 * ra) / 4, im.vec_ok);
+    };
+    fetch(d, bt);
+    for (;;) {
+        const int ra = (d.r + 3) & ~3;
+        rs.store(in_s, BTH + 2 * d.r, (TW + 2 * ra) / 4);
+        __syncthreads();
+        const int tn = t + (int)gridDim.x;
+        BatchTile nbt = bt;
+        DevImage nd = d;
+        if (tn < ntiles) {
+            nbt = tiles[tn];
+            nd = imgs[nbt.img];
+            fetch(nd, nbt);
+        }
         switch (d.r) {
-#define ICL_BATCH_CASE(R)                                                                                      \
-    case R: {                                                                                                  \
-        constexpr int RA = SepTile<R, BTH, BCX>::RA;                                                           \
-        const bool vec = d.vec_ok && bt.x0 - RA >= 0 && bt.x0 + 64 * BCX + RA <= d.W;                          \
-        sep_tile_body<T, R, BTH, BCX>(d.src, d.sp, d.dst, d.dp, d.W, d.H, d.tx, d.ty, bt.x0, bt.y0, vec, lds); \
-        break;                                                                                                 \
-    }
+#define ICL_BATCH_CASE(R)                                                                      \
+    case R:                                                                                    \
+        sep_row_pass<R, BTH, BCX>(in_s, t_s, d.tx);                                            \
+        __syncthreads();                                                                       \
+        sep_col_pass<T, R, BTH, BCX>(t_s, d.dst, d.dp, d.W, d.H, d.ty, bt.x0, bt.y0, d.vec_out); \
+        break;
             ICL_BATCH_CASE(0)
             ICL_BATCH_CASE(1)
             ICL_BATCH_CASE(2)
@@ -64,7 +90,10 @@ __global__ __launch_bounds__(256) void sep_batched_k(const DevImage* __restrict_
 #undef ICL_BATCH_CASE
             default: break;
         }
-        __syncthreads();   // LDS is reused by the next tile
+        if (tn >= ntiles) break;
+        t = tn;
+        bt = nbt;
+        d = nd;
     }
 }
 
@@ -132,6 +161,8 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
         di.src = d.src; di.dst = d.dst; di.sp = d.src_pitch; di.dp = d.dst_pitch;
         di.tx = d.taps_x; di.ty = d.taps_y; di.W = d.width; di.H = d.height; di.r = d.radius;
         di.vec_ok = ((uintptr_t)d.src % al == 0) && (d.src_pitch % al == 0);
+        di.vec_out = ((uintptr_t)d.dst % al == 0) && (d.dst_pitch % al == 0);
+        di.pad = 0;
         imgs.push_back(di);
         pixels += (long long)d.width * d.height;
         const int tx = (d.width + 64 * BCX - 1) / (64 * BCX), ty = (d.height + BTH - 1) / BTH;

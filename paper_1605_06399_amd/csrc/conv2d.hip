@@ -23,6 +23,7 @@
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
 #include "tile_stage.hpp"
+#include "corr_tile.hpp"
 
 namespace icl {
 namespace {
@@ -223,75 +224,39 @@ bool supports_lds(const Conv2dArgs& a) { return a.r >= 0 && a.r <= 7; }
 template <class T, int R, int PX, int PY>
 __global__ __launch_bounds__(256) void conv2d_pers(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
                                                    size_t dp, int W, int H, const float* __restrict__ w, int tiles_x,
-                                                   int ntiles, int vec_ok) {
+                                                   int tiles_y, int vec_ok) {
     using G = Tile2d<R, PX, PY>;
-    constexpr int TW = G::TW, TH = G::TH, RA = G::RA, LW = G::LW, NR = G::NR, WIN = G::WIN;
+    constexpr int TW = G::TW, TH = G::TH, RA = G::RA, LW = G::LW, NR = G::NR;
     constexpr int N = 2 * R + 1, NP = (N + 3) & ~3;
     __shared__ __attribute__((aligned(16))) float s[NR * LW];
     __shared__ __attribute__((aligned(16))) float wl[N * NP];
     const int tid = threadIdx.x;
-    for (int i = tid; i < N * NP; i += 256) {
-        const int j = i / NP, c = i - j * NP;
-        wl[i] = c < N ? w[j * N + c] : 0.f;
-    }
+    taps_to_lds<R, false>(w, 1, wl);
     Stage<T, NR, LW> st;
-    int t = first_tile();
+    const BandWalk walk(tiles_x, tiles_y);
+    int t = walk.tile(0);
     int x0, y0;
-    if (t < ntiles) {
+    if (t >= 0) {
         tile_origin(t, tiles_x, TW, TH, x0, y0);
-        st.load(src, sp, W, H, x0 - RA, y0 - R, vec_ok && x0 - RA >= 0 && x0 + TW + RA <= W);
+        st.load(src, sp, W, H, x0 - RA, y0 - R, vec_ok);
     }
     const int tx = tid & 15, ty = tid >> 4;
-    for (; t < ntiles; t += gridDim.x) {
+    for (int k = 0; t >= 0; t = walk.tile(++k)) {
         tile_origin(t, tiles_x, TW, TH, x0, y0);
         st.store(s);
         __syncthreads();
-        const int tn = t + (int)gridDim.x;
-        if (tn < ntiles) {
+        const int tn = walk.tile(k + 1);
+        if (tn >= 0) {
             int nx0, ny0;
             tile_origin(tn, tiles_x, TW, TH, nx0, ny0);
-            st.load(src, sp, W, H, nx0 - RA, ny0 - R, vec_ok && nx0 - RA >= 0 && nx0 + TW + RA <= W);
+            st.load(src, sp, W, H, nx0 - RA, ny0 - R, vec_ok);
         }
         float acc[PY][PX];
 #pragma unroll
         for (int py = 0; py < PY; ++py)
 #pragma unroll
             for (int px = 0; px < PX; ++px) acc[py][px] = 0.f;
-        const float* base = &s[(ty * PY) * LW + tx * PX];
-        float win[PY][WIN];
-        auto load_win = [&](float* dstw, const float* p) {
-#pragma unroll
-            for (int m = 0; m < WIN / 4; ++m) {
-                const v4f v = lds4(p + 4 * m);
-                dstw[4 * m] = v.x; dstw[4 * m + 1] = v.y; dstw[4 * m + 2] = v.z; dstw[4 * m + 3] = v.w;
-            }
-        };
-#pragma unroll
-        for (int py = 0; py < PY - 1; ++py) load_win(win[py], base + py * LW);
-#pragma unroll 1
-        for (int jb = 0; jb < N; jb += PY) {
-#pragma unroll
-            for (int u = 0; u < PY; ++u) {
-                const int j = jb + u;
-                if (j < N) {
-                    load_win(win[(u + PY - 1) % PY], base + (j + PY - 1) * LW);
-                    float tp[NP];
-#pragma unroll
-                    for (int m = 0; m < NP / 4; ++m) {
-                        const v4f v = lds4(&wl[j * NP + 4 * m]);
-                        tp[4 * m] = v.x; tp[4 * m + 1] = v.y; tp[4 * m + 2] = v.z; tp[4 * m + 3] = v.w;
-                    }
-#pragma unroll
-                    for (int py = 0; py < PY; ++py) {
-                        const float* wv = win[(u + py) % PY];
-#pragma unroll
-                        for (int i = 0; i < N; ++i)
-#pragma unroll
-                            for (int px = 0; px < PX; ++px) acc[py][px] = fmaf(tp[i], wv[RA - R + px + i], acc[py][px]);
-                    }
-                }
-            }
-        }
+        corr_rows<R, PX, PY, LW>(&s[(ty * PY) * LW + tx * PX], wl, acc);
         const int xb = x0 + tx * PX;
 #pragma unroll
         for (int py = 0; py < PY; ++py) {
@@ -325,7 +290,7 @@ hipError_t launch_pers_TR(const Conv2dArgs& a) {
     const void* k = reinterpret_cast<const void*>(&conv2d_pers<T, R, PX, PY>);
     const int grid = persistent_grid(k, 256, ntiles);
     hipLaunchKernelGGL((conv2d_pers<T, R, PX, PY>), dim3(grid), dim3(256), 0, a.st, a.src, a.sp, a.dst, a.dp, a.W,
-                       a.H, a.taps, tiles_x, ntiles, vec_ok);
+                       a.H, a.taps, tiles_x, tiles_y, vec_ok);
     return hipGetLastError();
 }
 

@@ -79,14 +79,14 @@ namespace {
 template <class T, int R, int TH, int CX>
 __global__ __launch_bounds__(256) void sep_fused(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
                                                  size_t dp, int W, int H, const float* __restrict__ tx,
-                                                 const float* __restrict__ ty, int tiles_x, int vec_ok) {
+                                                 const float* __restrict__ ty, int tiles_x, int vec_ok, int vec_out) {
     using G = SepTile<R, TH, CX>;
     __shared__ __attribute__((aligned(16))) float lds[G::LDS_FLOATS];
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
     const int x0 = (int)(t % (unsigned)tiles_x) * G::TW;
     const int y0 = (int)(t / (unsigned)tiles_x) * TH;
     const bool vec = vec_ok && x0 - G::RA >= 0 && x0 + G::TW + G::RA <= W;
-    sep_tile_body<T, R, TH, CX>(src, sp, dst, dp, W, H, tx, ty, x0, y0, vec, lds);
+    sep_tile_body<T, R, TH, CX>(src, sp, dst, dp, W, H, tx, ty, x0, y0, vec, vec_out, lds);
 }
 
 template <class T, int R, int TH, int CX>
@@ -96,8 +96,9 @@ hipError_t launch_fused_TR(const SepArgs& a) {
     const int tiles_y = (a.H + TH - 1) / TH;
     const size_t vec_align = 4 * (size_t)T::size;
     const int vec_ok = ((uintptr_t)a.src % vec_align == 0) && (a.sp % vec_align == 0);
+    const int vec_out = ((uintptr_t)a.dst % vec_align == 0) && (a.dp % vec_align == 0);
     hipLaunchKernelGGL((sep_fused<T, R, TH, CX>), dim3(tiles_x * tiles_y), dim3(256), 0, a.st, a.src, a.sp,
-                       a.dst, a.dp, a.W, a.H, a.tx, a.ty, tiles_x, vec_ok);
+                       a.dst, a.dp, a.W, a.H, a.tx, a.ty, tiles_x, vec_ok, vec_out);
     return hipGetLastError();
 }
 
@@ -133,32 +134,34 @@ bool supports_fused(const SepArgs& a) { return a.r >= 0 && a.r <= 7; }
 template <class T, int R, int TH, int CX>
 __global__ __launch_bounds__(256) void sep_pers(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
                                                 size_t dp, int W, int H, const float* __restrict__ tx,
-                                                const float* __restrict__ ty, int tiles_x, int ntiles, int vec_ok) {
+                                                const float* __restrict__ ty, int tiles_x, int tiles_y, int vec_ok,
+                                                int vec_out) {
     using G = SepTile<R, TH, CX>;
     constexpr int TW = G::TW, RA = G::RA, LW = G::LW, NR = G::NR;
     __shared__ __attribute__((aligned(16))) float lds[G::LDS_FLOATS];
     float* in_s = lds;
     float* t_s = lds + NR * LW;
     Stage<T, NR, LW> st;
-    int t = first_tile();
+    const BandWalk walk(tiles_x, tiles_y);
+    int t = walk.tile(0);
     int x0, y0;
-    if (t < ntiles) {
+    if (t >= 0) {
         tile_origin(t, tiles_x, TW, TH, x0, y0);
-        st.load(src, sp, W, H, x0 - RA, y0 - R, vec_ok && x0 - RA >= 0 && x0 + TW + RA <= W);
+        st.load(src, sp, W, H, x0 - RA, y0 - R, vec_ok);
     }
-    for (; t < ntiles; t += gridDim.x) {
+    for (int k = 0; t >= 0; t = walk.tile(++k)) {
         tile_origin(t, tiles_x, TW, TH, x0, y0);
         st.store(in_s);
         __syncthreads();
-        const int tn = t + (int)gridDim.x;
-        if (tn < ntiles) {
+        const int tn = walk.tile(k + 1);
+        if (tn >= 0) {
             int nx0, ny0;
             tile_origin(tn, tiles_x, TW, TH, nx0, ny0);
-            st.load(src, sp, W, H, nx0 - RA, ny0 - R, vec_ok && nx0 - RA >= 0 && nx0 + TW + RA <= W);
+            st.load(src, sp, W, H, nx0 - RA, ny0 - R, vec_ok);
         }
         sep_row_pass<R, TH, CX>(in_s, t_s, tx);
         __syncthreads();
-        sep_col_pass<T, R, TH, CX>(t_s, dst, dp, W, H, ty, x0, y0);
+        sep_col_pass<T, R, TH, CX>(t_s, dst, dp, W, H, ty, x0, y0, vec_out);
     }
 }
 
@@ -166,12 +169,13 @@ template <class T, int R, int TH, int CX>
 hipError_t launch_pers_TR(const SepArgs& a) {
     using G = SepTile<R, TH, CX>;
     const int tiles_x = (a.W + G::TW - 1) / G::TW;
-    const int ntiles = tiles_x * ((a.H + TH - 1) / TH);
+    const int tiles_y = (a.H + TH - 1) / TH;
     const size_t al = 4 * (size_t)T::size;
     const int vec_ok = ((uintptr_t)a.src % al == 0) && (a.sp % al == 0);
+    const int vec_out = ((uintptr_t)a.dst % al == 0) && (a.dp % al == 0);
     const void* k = reinterpret_cast<const void*>(&sep_pers<T, R, TH, CX>);
-    hipLaunchKernelGGL((sep_pers<T, R, TH, CX>), dim3(persistent_grid(k, 256, ntiles)), dim3(256), 0, a.st, a.src,
-                       a.sp, a.dst, a.dp, a.W, a.H, a.tx, a.ty, tiles_x, ntiles, vec_ok);
+    hipLaunchKernelGGL((sep_pers<T, R, TH, CX>), dim3(persistent_grid(k, 256, tiles_x * tiles_y)), dim3(256), 0,
+                       a.st, a.src, a.sp, a.dst, a.dp, a.W, a.H, a.tx, a.ty, tiles_x, tiles_y, vec_ok, vec_out);
     return hipGetLastError();
 }
 

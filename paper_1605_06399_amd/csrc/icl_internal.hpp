@@ -70,6 +70,9 @@ int sep_default(const SepArgs&);
 int conv2d_default(const Conv2dArgs&);
 int harris_default(const HarrisArgs&);
 int nms_default(const NmsArgs&);
+int bank_fwd_default(const BankArgs&);
+int bank_bwd_input_default(const BankArgs&);
+int bank_bwd_filter_default(const BankArgs&);
 
 size_t sep_workspace(int W, int H);
 size_t harris_workspace(int W, int H);

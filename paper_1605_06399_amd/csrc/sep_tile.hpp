@@ -11,7 +11,6 @@ template <int R, int TH, int CX> struct SepTile {
     static constexpr int RA = (R + 3) & ~3;      // column halo rounded up to whole float4s
     static constexpr int LW = TW + 2 * RA;       // staged input row length (floats)
     static constexpr int NR = TH + 2 * R;        // staged input rows
-    static constexpr int PY = TH / 4;            // column-pass rows per lane
     static constexpr int LDS_FLOATS = NR * LW + NR * TW;
 };
 
@@ -40,27 +39,49 @@ __device__ __forceinline__ void sep_row_pass(const float* __restrict__ in_s, flo
     }
 }
 
-// Column pass: lane owns columns lx + 64c, rows ly*PY .. ly*PY+PY-1 of the tile at (x0, y0).
+// Column pass: lane owns 4 adjacent columns (group g of TW/4) and PYC consecutive rows;
+// the t_s rows it needs are read as float4, and the 4 outputs of a row are stored as one
+// vector when the destination rows are 4-pixel aligned (vec_out).
 template <class T, int R, int TH, int CX>
 __device__ __forceinline__ void sep_col_pass(const float* __restrict__ t_s, void* __restrict__ dst, size_t dp, int W,
-                                             int H, const float* __restrict__ ty, int x0, int y0) {
+                                             int H, const float* __restrict__ ty, int x0, int y0, bool vec_out) {
     using G = SepTile<R, TH, CX>;
-    constexpr int TW = G::TW, PY = G::PY;
-    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    constexpr int TW = G::TW, G4 = TW / 4, RPI = 256 / G4, PYC = TH / RPI;
+    static_assert(PYC * RPI == TH, "tile rows must split evenly over the row groups");
+    const int g = threadIdx.x % G4, rg = threadIdx.x / G4;
+    const float* col = t_s + (rg * PYC) * TW + 4 * g;
+    // each staged row is read once and added into every output row it feeds
+    v4f acc[PYC];
 #pragma unroll
-    for (int c = 0; c < CX; ++c) {
-        const int col = lx + 64 * c;
-        float v[PY + 2 * R];
+    for (int py = 0; py < PYC; ++py) acc[py] = mk4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int m = 0; m < PY + 2 * R; ++m) v[m] = t_s[(ly * PY + m) * TW + col];
-        const int x = x0 + col;
+    for (int m = 0; m < PYC + 2 * R; ++m) {
+        const v4f v = lds4(col + m * TW);
 #pragma unroll
-        for (int py = 0; py < PY; ++py) {
-            float acc = 0.f;
+        for (int py = 0; py < PYC; ++py) {
+            const int j = m - py;
+            if (j < 0 || j > 2 * R) continue;
+            const float c = ty[j];
+            acc[py].x = fmaf(c, v.x, acc[py].x);
+            acc[py].y = fmaf(c, v.y, acc[py].y);
+            acc[py].z = fmaf(c, v.z, acc[py].z);
+            acc[py].w = fmaf(c, v.w, acc[py].w);
+        }
+    }
+    const int x = x0 + 4 * g;
 #pragma unroll
-            for (int j = 0; j <= 2 * R; ++j) acc = fmaf(ty[j], v[py + j], acc);
-            const int y = y0 + ly * PY + py;
-            if (x < W && y < H) store_px<T>(dst, (size_t)y * dp + (size_t)x * T::size, acc);
+    for (int py = 0; py < PYC; ++py) {
+        const int y = y0 + rg * PYC + py;
+        if (y >= H) break;
+        const size_t row = (size_t)y * dp;
+        const v4f a = acc[py];
+        if (vec_out && x + 4 <= W) {
+            store4<T>(dst, row + (size_t)x * T::size, a);
+        } else {
+            if (x < W) store_px<T>(dst, row + (size_t)x * T::size, a.x);
+            if (x + 1 < W) store_px<T>(dst, row + (size_t)(x + 1) * T::size, a.y);
+            if (x + 2 < W) store_px<T>(dst, row + (size_t)(x + 2) * T::size, a.z);
+            if (x + 3 < W) store_px<T>(dst, row + (size_t)(x + 3) * T::size, a.w);
         }
     }
 }
@@ -71,7 +92,7 @@ __device__ __forceinline__ void sep_col_pass(const float* __restrict__ t_s, void
 template <class T, int R, int TH, int CX>
 __device__ __forceinline__ void sep_tile_body(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
                                               size_t dp, int W, int H, const float* __restrict__ tx,
-                                              const float* __restrict__ ty, int x0, int y0, bool vec,
+                                              const float* __restrict__ ty, int x0, int y0, bool vec, bool vec_out,
                                               float* __restrict__ lds) {
     using G = SepTile<R, TH, CX>;
     constexpr int TW = G::TW, RA = G::RA, LW = G::LW, NR = G::NR;
@@ -96,7 +117,7 @@ __device__ __forceinline__ void sep_tile_body(const void* __restrict__ src, size
     __syncthreads();
     sep_row_pass<R, TH, CX>(in_s, t_s, tx);
     __syncthreads();
-    sep_col_pass<T, R, TH, CX>(t_s, dst, dp, W, H, ty, x0, y0);
+    sep_col_pass<T, R, TH, CX>(t_s, dst, dp, W, H, ty, x0, y0, vec_out);
 }
 
 }  // namespace icl

@@ -17,33 +17,41 @@ struct Stage {
     static constexpr int N = (NR * C4 + 255) / 256;
     v4f v[N];
 
-    // vec: every column of the tile is inside the image and rows start 4-pixel aligned
+    // One float4 chunk of staged row data starting at pixel x of a row.  With `aligned`
+    // rows (4-pixel aligned base and pitch, x a multiple of 4) a chunk is either fully
+    // inside the row (one vector load), fully outside (zeros, or the clamped edge pixel
+    // broadcast), or straddles the right edge (per element; only when W % 4 != 0).
+    __device__ __forceinline__ static v4f chunk(const void* __restrict__ src, size_t row, int W, int x, bool aligned) {
+        if (aligned && x >= 0 && x + 4 <= W) return load4<T>(src, row + (size_t)x * T::size);
+        if (aligned && (x + 4 <= 0 || x >= W)) {
+            if (ZERO_PAD) return mk4(0.f, 0.f, 0.f, 0.f);
+            const float e = load_px<T>(src, row + (size_t)clampi(x, W) * T::size);
+            return mk4(e, e, e, e);
+        }
+        float e[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int xx = x + q;
+            e[q] = (ZERO_PAD && (xx < 0 || xx >= W)) ? 0.f : load_px<T>(src, row + (size_t)clampi(xx, W) * T::size);
+        }
+        return mk4(e[0], e[1], e[2], e[3]);
+    }
+
+    // Load the tile with top-left pixel (gx0, gy0); gx0 must be a multiple of 4 when
+    // `aligned` (rows 4-pixel aligned in memory).
     __device__ __forceinline__ void load(const void* __restrict__ src, size_t sp, int W, int H, int gx0, int gy0,
-                                         bool vec) {
+                                         bool aligned) {
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             const int idx = (int)threadIdx.x + 256 * k;
             if (N * 256 != NR * C4 && idx >= NR * C4) break;
             const int rr = idx / C4, c4 = idx - rr * C4;
             const int yy = gy0 + rr;
-            const int x = gx0 + 4 * c4;
             if (ZERO_PAD && (yy < 0 || yy >= H)) {
                 v[k] = mk4(0.f, 0.f, 0.f, 0.f);
                 continue;
             }
-            const size_t row = (size_t)clampi(yy, H) * sp;
-            if (vec) {
-                v[k] = load4<T>(src, row + (size_t)x * T::size);
-            } else {
-                float e[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int xx = x + q;
-                    e[q] = (ZERO_PAD && (xx < 0 || xx >= W)) ? 0.f
-                                                             : load_px<T>(src, row + (size_t)clampi(xx, W) * T::size);
-                }
-                v[k] = mk4(e[0], e[1], e[2], e[3]);
-            }
+            v[k] = chunk(src, (size_t)clampi(yy, H) * sp, W, gx0 + 4 * c4, aligned);
         }
     }
 
@@ -69,5 +77,72 @@ __device__ __forceinline__ void tile_origin(int t, int tiles_x, int tw, int th, 
 // is a multiple of 8, consecutive tiles of each round go to one XCD, so tiles sharing
 // halo rows meet in the same L2.
 __device__ __forceinline__ int first_tile() { return (int)xcd_remap(blockIdx.x, gridDim.x); }
+
+// Persistent schedule over a tiles_x x tiles_y grid (tiles numbered row-major) that keeps
+// halo reuse inside one L2: the grid is cut into 8 column bands, one per XCD (gfx950
+// places work-group b on XCD b % 8), and the blocks of an XCD walk their band row by
+// row.  A tile's upper neighbour was therefore processed on the same XCD shortly before,
+// and the halo rows they share are served from that XCD's L2 rather than HBM.
+struct BandWalk {
+    int tiles_x, bx0, bw, nband, slot, nslots;
+    __device__ __forceinline__ BandWalk(int tx, int ty) : tiles_x(tx) {
+        const int g = (int)gridDim.x;
+        // one band per XCD; fewer when the grid or the tile row is too small, so every
+        // band owns at least one block and one column (every tile is covered exactly once)
+        int nb = g < 8 ? g : 8;
+        nb = nb < tx ? nb : tx;
+        const int x = (int)blockIdx.x % nb;
+        slot = (int)blockIdx.x / nb;
+        nslots = g / nb + (x < g % nb ? 1 : 0);
+        bx0 = x * tx / nb;
+        bw = (x + 1) * tx / nb - bx0;
+        nband = bw * ty;
+    }
+    // k-th tile of this block, or -1 when its band is exhausted
+    __device__ __forceinline__ int tile(int k) const {
+        const int j = k * nslots + slot;
+        if (j >= nband) return -1;
+        const int row = j / bw;
+        return row * tiles_x + bx0 + (j - row * bw);
+    }
+};
+
+}  // namespace icl
+
+namespace icl {
+
+// Staged tile whose shape is known only at run time (NR <= NRMAX rows, LW = 4*C4 <= 128
+// columns), as in a batch whose images have different radii.  The 256 lanes form 8 rows
+// x 32 float4 columns, so no division by the runtime row length is needed.
+template <class T, int NRMAX>
+struct RStage {
+    static constexpr int K = (NRMAX + 7) / 8;
+    v4f v[K];
+
+    // vec: rows 4-pixel aligned in memory (gx0 a multiple of 4)
+    __device__ __forceinline__ void load(const void* __restrict__ src, size_t sp, int W, int H, int gx0, int gy0,
+                                         int NR, int C4, bool vec) {
+        const int c4 = threadIdx.x & 31, ry = threadIdx.x >> 5;
+        if (c4 >= C4) return;
+        const int x = gx0 + 4 * c4;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int rr = ry + 8 * k;
+            if (rr >= NR) break;
+            v[k] = Stage<T, 1, 4>::chunk(src, (size_t)clampi(gy0 + rr, H) * sp, W, x, vec);
+        }
+    }
+
+    __device__ __forceinline__ void store(float* __restrict__ s, int NR, int C4) const {
+        const int c4 = threadIdx.x & 31, ry = threadIdx.x >> 5;
+        if (c4 >= C4) return;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int rr = ry + 8 * k;
+            if (rr >= NR) break;
+            lds4(&s[rr * 4 * C4 + 4 * c4], v[k]);
+        }
+    }
+};
 
 }  // namespace icl

@@ -182,25 +182,29 @@ bool masks_agree(const uint8_t* a, const uint8_t* b, size_t pitch, int W, int H,
     return h == 0;
 }
 
-// Median event time (us) of `iters` launches after `warm`, rotating over `sets` buffer sets.
+// Per-launch time (us): after `warm` launches, `reps` event-bracketed batches of `per`
+// back-to-back launches (rotating over `sets` buffer sets); the median batch mean wins.
+// Batches amortise the dispatch gap that a per-launch event pair would add.
 template <class F>
-double time_launches(F&& launch, int sets, int warm, int iters, hipStream_t st, bool* ok) {
-    std::vector<hipEvent_t> ev(2 * iters);
+double time_launches(F&& launch, int sets, int warm, int reps, int per, hipStream_t st, bool* ok) {
+    std::vector<hipEvent_t> ev(2 * reps);
     for (auto& e : ev) hipEventCreate(&e);
     *ok = true;
+    int k = 0;
     for (int i = 0; i < warm; ++i)
-        if (launch(i % sets) != hipSuccess) *ok = false;
-    for (int i = 0; i < iters; ++i) {
+        if (launch(k++ % sets) != hipSuccess) *ok = false;
+    for (int i = 0; i < reps; ++i) {
         hipEventRecord(ev[2 * i], st);
-        if (launch((warm + i) % sets) != hipSuccess) *ok = false;
+        for (int j = 0; j < per; ++j)
+            if (launch(k++ % sets) != hipSuccess) *ok = false;
         hipEventRecord(ev[2 * i + 1], st);
     }
     hipStreamSynchronize(st);
     std::vector<double> t;
-    for (int i = 0; i < iters; ++i) {
+    for (int i = 0; i < reps; ++i) {
         float ms = 0.f;
         hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
-        t.push_back(ms * 1000.0);
+        t.push_back(ms * 1000.0 / per);
     }
     for (auto& e : ev) hipEventDestroy(e);
     std::sort(t.begin(), t.end());
@@ -249,7 +253,7 @@ icl_status search(icl_op op, const Variant<A>* tab, int count, icl_dtype dt, int
             continue;
         }
         bool ok = true;
-        const double us = time_launches([&](int s) { return tab[i].launch(make(s, i)); }, sets, 3, 15, st, &ok);
+        const double us = time_launches([&](int s) { return tab[i].launch(make(s, i)); }, sets, 3, 5, 8, st, &ok);
         if (!ok) continue;
         if (log_on()) std::fprintf(stderr, "icl tune: %s/%s %.2f us\n", op_name(op), tab[i].name, us);
         if (us < best) {

@@ -7,7 +7,7 @@ from conftest import gpu_available
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
 from oracle import oracle  # noqa: E402
-from paper_1605_06399_amd import synth  # noqa: E402
+from paper_1605_06399_amd import binding as B, synth  # noqa: E402
 
 if gpu_available():
     import torch
@@ -37,15 +37,26 @@ def rel_normwise(got, ref, scale):
 SHAPES = [(2, 5, 70, 133, 4), (1, 3, 64, 64, 2), (2, 2, 5, 3, 4), (1, 16, 1, 9, 1), (1, 1, 1, 1, 3), (1, 4, 65, 130, 3)]
 
 
+def each_variant(op):
+    """Run the body once per variant of `op` (forced), restoring automatic selection after."""
+    for v in range(B.icl_variant_count(op)):
+        B.check(B.icl_force_variant(op, v))
+        try:
+            yield v
+        finally:
+            B.icl_force_variant(op, -1)
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 def test_bank_forward(shape):
     N, F, H, W, r = shape
     x, w, _ = inputs(N, F, H, W, r)
-    y = T.bank_fwd(cu(x), cu(w))
-    torch.cuda.synchronize()
     ref = oracle.bank_fwd(x, w)
     scale = oracle.bank_fwd(np.abs(x), np.abs(w))
-    assert rel_normwise(host(y), ref, scale) <= 1e-5
+    for v in each_variant(B.ICL_OP_BANK_FWD):
+        y = T.bank_fwd(cu(x), cu(w))
+        torch.cuda.synchronize()
+        assert rel_normwise(host(y), ref, scale) <= 1e-5, f"variant {v}"
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -54,11 +65,12 @@ def test_bank_input_gradient(shape):
     N, F, H, W, r = shape
     _, w, _ = inputs(N, F, H, W, r)
     gy = synth.normal(synth.seed(71, 9), N * F * H * W).reshape(N, F, H, W)
-    gx = T.bank_bwd_input(cu(gy), cu(w))
-    torch.cuda.synchronize()
     ref = oracle.bank_bwd_input(gy, w)
     scale = oracle.bank_bwd_input(np.abs(gy), np.abs(w))
-    assert rel_normwise(host(gx), ref, scale) <= 1e-5
+    for v in each_variant(B.ICL_OP_BANK_BWD_INPUT):
+        gx = T.bank_bwd_input(cu(gy), cu(w))
+        torch.cuda.synchronize()
+        assert rel_normwise(host(gx), ref, scale) <= 1e-5, f"variant {v}"
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -66,14 +78,24 @@ def test_bank_filter_gradient(shape):
     N, F, H, W, r = shape
     x, w, _ = inputs(N, F, H, W, r)
     gy = synth.normal(synth.seed(72, 9), N * F * H * W).reshape(N, F, H, W)
-    gw = T.bank_bwd_filter(cu(gy), cu(x), r)
-    torch.cuda.synchronize()
     ref = oracle.bank_bwd_filter(gy, x, r)
     scale = oracle.bank_bwd_filter(np.abs(gy), np.abs(x), r)
-    assert rel_normwise(host(gw), ref, scale) <= 1e-5
-    # deterministic: a second call gives the same bits
-    gw2 = T.bank_bwd_filter(cu(gy), cu(x), r)
-    assert torch.equal(gw, gw2)
+    for v in each_variant(B.ICL_OP_BANK_BWD_FILTER):
+        gw = T.bank_bwd_filter(cu(gy), cu(x), r)
+        torch.cuda.synchronize()
+        assert rel_normwise(host(gw), ref, scale) <= 1e-5, f"variant {v}"
+        # deterministic: a second call gives the same bits
+        gw2 = T.bank_bwd_filter(cu(gy), cu(x), r)
+        assert torch.equal(gw, gw2)
+
+
+def test_bank_many_filters_falls_back():
+    """More filters than the persistent kernels' tap table holds: the tiled kernels take over."""
+    N, F, H, W, r = 1, 20, 33, 70, 2
+    x, w, _ = inputs(N, F, H, W, r, cfg=76)
+    y = T.bank_fwd(cu(x), cu(w))
+    torch.cuda.synchronize()
+    assert rel_normwise(host(y), oracle.bank_fwd(x, w), oracle.bank_fwd(np.abs(x), np.abs(w))) <= 1e-5
 
 
 def test_sse_loss():
