@@ -333,7 +333,16 @@ def run_extras(torch, B, T, synth, steps):
 
     dt = _time(torch, corner, steps)
     gpx = H * W / dt / 1e9
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    T.harris(xs[0], g, 0.04, out=Rs[0])
+    ev[1].record()
+    T.nms(Rs[0], 1e-3, out=Ms[0])
+    ev[2].record()
+    torch.cuda.synchronize()
     res["corner_8192"] = {"ms": round(dt * 1e3, 3), "gpx_s": round(gpx, 1), "bytes_per_px": 13,
+                          "phase_ms": {"harris": round(ev[0].elapsed_time(ev[1]), 3),
+                                       "nms": round(ev[1].elapsed_time(ev[2]), 3)},
                           "hbm_frac": round(gpx * 13 / HBM_PEAK_GBS, 3),
                           "harris_variant": B.icl_variant_name(B.ICL_OP_HARRIS, B.icl_selected_variant(
                               B.ICL_OP_HARRIS, B.ICL_F32, 2, W, H)[1]),

@@ -362,7 +362,8 @@ __global__ __launch_bounds__(256) void bank_fwd_pers_k(const float* __restrict__
                                                        int tiles_img, int ntiles, int vec) {
     using G = BankTile<R>;
     constexpr int LW = G::LW, NR = G::NR, RA = G::RA, N = 2 * R + 1, NP = (N + 3) & ~3;
-    __shared__ __attribute__((aligned(16))) float s[NR * LW];
+    // two x tiles: the next tile is staged into the idle one while all F filters run on the other
+    __shared__ __attribute__((aligned(16))) float s[2][NR * LW];
     __shared__ __attribute__((aligned(16))) float wl[PERS_FMAX * N * NP];
     taps_to_lds<R, false>(w, F, wl);
     const size_t hw = (size_t)H * W;
@@ -375,23 +376,30 @@ __global__ __launch_bounds__(256) void bank_fwd_pers_k(const float* __restrict__
     };
     const BandWalk walk(tiles_x, ntiles / tiles_x);   // images stacked vertically
     int t = walk.tile(0);
-    if (t >= 0) fetch(t);
+    if (t < 0) return;
+    fetch(t);
+    st.store(s[0]);
+    __syncthreads();
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    for (int k = 0; t >= 0; t = walk.tile(++k)) {
+    int cur = 0;
+    for (int k = 0; t >= 0; ++k) {
         const int n = t / tiles_img, ti = t - n * tiles_img;
         int x0, y0;
         tile_origin(ti, tiles_x, BT, BT, x0, y0);
-        st.store(s);
-        __syncthreads();
         const int tn = walk.tile(k + 1);
         if (tn >= 0) fetch(tn);
 #pragma unroll 1
         for (int f = 0; f < F; ++f) {
             float acc[BPY][BPX] = {};
-            corr_rows<R, BPX, BPY, LW>(&s[(ty * BPY) * LW + tx * BPX], &wl[f * N * NP], acc);
+            corr_rows<R, BPX, BPY, LW>(&s[cur][(ty * BPY) * LW + tx * BPX], &wl[f * N * NP], acc);
+            // stage the next tile before this tile's first output store: the wait on the
+            // prefetch loads then never includes stores
+            if (f == 0 && tn >= 0) st.store(s[cur ^ 1]);
             store_block(y + ((size_t)n * F + f) * hw, W, H, x0, y0, vec, acc);
         }
         __syncthreads();
+        cur ^= 1;
+        t = tn;
     }
 }
 

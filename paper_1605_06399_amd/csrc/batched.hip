@@ -1,5 +1,5 @@
 // Batched separable convolution over images of uneven size and radius in one
-// persistent launch.  The host turns the batch into a table of 64x32 output
+// persistent launch.  The host turns the batch into a table of 64x64 output
 // tiles, each naming its image; a grid sized to the device's resident capacity
 // walks the table with a fixed stride, and each tile runs the same fused
 // single-pass body as icl_conv_sep (row pass into LDS, column pass from LDS),
@@ -34,7 +34,7 @@ struct BatchTile {
 
 namespace {
 
-constexpr int BTH = 32;    // tile rows
+constexpr int BTH = 64;    // tile rows
 constexpr int BCX = 1;     // tile columns = 64 * BCX
 constexpr int RMAX = 7;
 
@@ -60,10 +60,11 @@ __global__ __launch_bounds__(256) void sep_batched_k(const DevImage* __restrict_
         rs.load(im.src, im.sp, im.W, im.H, b.x0 - ra, b.y0 - im.r, BTH + 2 * im.r, (TW + 2 * ra) / 4, im.vec_ok);
     };
     fetch(d, bt);
+    rs.store(in_s, BTH + 2 * d.r, (TW + 2 * ((d.r + 3) & ~3)) / 4);
+    __syncthreads();
+    // Per tile: issue the next tile's loads, row pass, barrier, move the prefetched
+    // registers into in_s before this tile's output stores are issued, column pass, barrier.
     for (;;) {
-        const int ra = (d.r + 3) & ~3;
-        rs.store(in_s, BTH + 2 * d.r, (TW + 2 * ra) / 4);
-        __syncthreads();
         const int tn = t + (int)gridDim.x;
         BatchTile nbt = bt;
         DevImage nd = d;
@@ -73,10 +74,11 @@ __global__ __launch_bounds__(256) void sep_batched_k(const DevImage* __restrict_
             fetch(nd, nbt);
         }
         switch (d.r) {
-#define ICL_BATCH_CASE(R)                                                                      \
-    case R:                                                                                    \
-        sep_row_pass<R, BTH, BCX>(in_s, t_s, d.tx);                                            \
-        __syncthreads();                                                                       \
+#define ICL_BATCH_CASE(R)                                                                        \
+    case R:                                                                                      \
+        sep_row_pass<R, BTH, BCX>(in_s, t_s, d.tx);                                              \
+        __syncthreads();                                                                         \
+        if (tn < ntiles) rs.store(in_s, BTH + 2 * nd.r, (TW + 2 * ((nd.r + 3) & ~3)) / 4);       \
         sep_col_pass<T, R, BTH, BCX>(t_s, d.dst, d.dp, d.W, d.H, d.ty, bt.x0, bt.y0, d.vec_out); \
         break;
             ICL_BATCH_CASE(0)
@@ -90,6 +92,7 @@ __global__ __launch_bounds__(256) void sep_batched_k(const DevImage* __restrict_
 #undef ICL_BATCH_CASE
             default: break;
         }
+        __syncthreads();
         if (tn >= ntiles) break;
         t = tn;
         bt = nbt;

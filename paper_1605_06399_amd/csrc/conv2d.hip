@@ -235,16 +235,14 @@ __global__ __launch_bounds__(256) void conv2d_pers(const void* __restrict__ src,
     Stage<T, NR, LW> st;
     const BandWalk walk(tiles_x, tiles_y);
     int t = walk.tile(0);
+    if (t < 0) return;
     int x0, y0;
-    if (t >= 0) {
-        tile_origin(t, tiles_x, TW, TH, x0, y0);
-        st.load(src, sp, W, H, x0 - RA, y0 - R, vec_ok);
-    }
+    tile_origin(t, tiles_x, TW, TH, x0, y0);
+    st.load(src, sp, W, H, x0 - RA, y0 - R, vec_ok);
+    st.store(s);
+    __syncthreads();
     const int tx = tid & 15, ty = tid >> 4;
-    for (int k = 0; t >= 0; t = walk.tile(++k)) {
-        tile_origin(t, tiles_x, TW, TH, x0, y0);
-        st.store(s);
-        __syncthreads();
+    for (int k = 0; t >= 0; ++k) {
         const int tn = walk.tile(k + 1);
         if (tn >= 0) {
             int nx0, ny0;
@@ -257,6 +255,8 @@ __global__ __launch_bounds__(256) void conv2d_pers(const void* __restrict__ src,
 #pragma unroll
             for (int px = 0; px < PX; ++px) acc[py][px] = 0.f;
         corr_rows<R, PX, PY, LW>(&s[(ty * PY) * LW + tx * PX], wl, acc);
+        __syncthreads();                 // every lane is done reading s
+        if (tn >= 0) st.store(s);        // waits on the prefetch loads only: no output store issued yet
         const int xb = x0 + tx * PX;
 #pragma unroll
         for (int py = 0; py < PY; ++py) {
@@ -274,7 +274,9 @@ __global__ __launch_bounds__(256) void conv2d_pers(const void* __restrict__ src,
                     if (xb + px < W) store_px<T>(dst, row + (size_t)(xb + px) * T::size, acc[py][px]);
             }
         }
-        __syncthreads();   // every lane is done with s before the next tile overwrites it
+        __syncthreads();                 // s holds the next tile
+        t = tn;
+        if (t >= 0) tile_origin(t, tiles_x, TW, TH, x0, y0);
     }
 }
 

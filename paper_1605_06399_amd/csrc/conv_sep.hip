@@ -144,15 +144,16 @@ __global__ __launch_bounds__(256) void sep_pers(const void* __restrict__ src, si
     Stage<T, NR, LW> st;
     const BandWalk walk(tiles_x, tiles_y);
     int t = walk.tile(0);
+    if (t < 0) return;
     int x0, y0;
-    if (t >= 0) {
-        tile_origin(t, tiles_x, TW, TH, x0, y0);
-        st.load(src, sp, W, H, x0 - RA, y0 - R, vec_ok);
-    }
-    for (int k = 0; t >= 0; t = walk.tile(++k)) {
-        tile_origin(t, tiles_x, TW, TH, x0, y0);
-        st.store(in_s);
-        __syncthreads();
+    tile_origin(t, tiles_x, TW, TH, x0, y0);
+    st.load(src, sp, W, H, x0 - RA, y0 - R, vec_ok);
+    st.store(in_s);
+    __syncthreads();
+    // Pipeline per tile: issue the next tile's loads, run the row pass, then (after the
+    // barrier that frees in_s) move the prefetched registers into in_s BEFORE this tile's
+    // output stores are issued, so the wait on the loads never waits on stores too.
+    for (int k = 0; t >= 0; ++k) {
         const int tn = walk.tile(k + 1);
         if (tn >= 0) {
             int nx0, ny0;
@@ -161,7 +162,11 @@ __global__ __launch_bounds__(256) void sep_pers(const void* __restrict__ src, si
         }
         sep_row_pass<R, TH, CX>(in_s, t_s, tx);
         __syncthreads();
+        if (tn >= 0) st.store(in_s);
         sep_col_pass<T, R, TH, CX>(t_s, dst, dp, W, H, ty, x0, y0, vec_out);
+        __syncthreads();
+        t = tn;
+        if (t >= 0) tile_origin(t, tiles_x, TW, TH, x0, y0);
     }
 }
 

@@ -44,7 +44,8 @@ def test_batched_matches_oracle_per_image(dt):
 
 
 def test_batched_equals_per_image_calls():
-    """The persistent kernel and icl_conv_sep (fused variant, same tile body) agree bit for bit."""
+    """The persistent kernel and icl_conv_sep (fused variant) agree bit for bit: every variant sums each
+    output in the same tap order, whatever its tile shape."""
     items, xs, _, outs, taps = make_batch("f16", count=9, seed=61)
     plan = T.BatchPlan(xs, outs, taps)
     plan.launch()
