@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP32_FMA_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, packed FP32 disabled
 FP32_PACKED_PEAK_TFLOPS = 157.3
+EXTRAS = ("corner", "batch", "bank")
 METRIC = "Gpixel/s & % HBM peak, autotuned vs plain kernel; fwd+bwd Gpixel/s"
 
 
@@ -41,7 +42,8 @@ def parse():
     p.add_argument("--side", type=int, default=4096)
     p.add_argument("--no-extras", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--only", default="", help="comma list of call labels to run (profiling aid)")
+    p.add_argument("--only", default="", help="comma list of sweep call labels (sep1 ... 2d7) and extra "
+                   "workloads (corner, batch, bank) to run; a profiling aid")
     p.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter_collection.csv files of a --calib-copy "
                         "run into profiles/traffic.json and exit")
@@ -174,9 +176,16 @@ def main():
         taps[("sep", r)] = (torch.from_numpy(h).to(dev), torch.from_numpy(v).to(dev))
         taps[("2d", r)] = torch.from_numpy(synth.sweep_taps_2d(r)).to(dev)
     calls = [(k, r) for r in radii for k in ("sep", "2d")]
+    extras = EXTRAS
     if a.only:
         keep = set(a.only.split(","))
         calls = [c for c in calls if f"{c[0]}{c[1]}" in keep]
+        extras = tuple(e for e in EXTRAS if e in keep)
+    if not calls:
+        # profiling aid: the extra workloads alone, no sweep line
+        del src, dst, ws
+        print(json.dumps({"extras": run_extras(torch, B, T, synth, max(3, a.steps // 2), extras)}), flush=True)
+        return
     stream = torch.cuda.current_stream()
 
     def call(kind, r, k):
@@ -292,7 +301,7 @@ def main():
 
     if not a.no_extras:
         try:
-            out["extras"] = run_extras(torch, B, T, synth, max(3, a.steps // 2))
+            out["extras"] = run_extras(torch, B, T, synth, max(3, a.steps // 2), extras)
         except Exception as e:  # an extra never hides the sweep's line
             out["extras"] = {"error": repr(e)}
 
@@ -312,8 +321,19 @@ def _time(torch, fn, steps, warmup=2):
     return (time.perf_counter() - t0) / steps
 
 
-def run_extras(torch, B, T, synth, steps):
+def run_extras(torch, B, T, synth, steps, which=EXTRAS):
     """The other workloads, timed the same way (inputs resident in HBM, events around the whole step)."""
+    res = {}
+    if "corner" in which:
+        res.update(extra_corner(torch, B, T, synth, steps))
+    if "batch" in which:
+        res.update(extra_batch(torch, B, T, synth, steps))
+    if "bank" in which:
+        res.update(extra_bank(torch, B, T, synth, steps))
+    return res
+
+
+def extra_corner(torch, B, T, synth, steps):
     dev = torch.device("cuda:0")
     res = {}
     # corner pipeline: Harris response + 3x3 NMS on 8192^2 (two calls: 8 + 5 algorithmic B/px)
@@ -349,7 +369,12 @@ def run_extras(torch, B, T, synth, steps):
                           "corners": int(Ms[0].sum().item())}
     del xs, Rs, Ms
     torch.cuda.empty_cache()
+    return res
 
+
+def extra_batch(torch, B, T, synth, steps):
+    dev = torch.device("cuda:0")
+    res = {}
     # uneven batch: 256 images, one persistent launch replayed from a HIP graph (4 B/px half storage)
     items = synth.batch_uneven()
 
@@ -376,7 +401,12 @@ def run_extras(torch, B, T, synth, steps):
         plan.close()
         del ims, outs
     torch.cuda.empty_cache()
+    return res
 
+
+def extra_bank(torch, B, T, synth, steps):
+    dev = torch.device("cuda:0")
+    res = {}
     # differentiable filter bank: forward, loss + gradient, input and filter adjoints
     N, F, Hb, Wb, r = 32, 16, 1024, 1024, 4
     x, w, t = synth.bank_inputs()

@@ -16,8 +16,9 @@
 //   bank_bwd_in    : same tiling; for each filter the gy tile (zero outside the image)
 //                    is staged and correlated with the flipped filter; the F sums
 //                    accumulate in registers and are stored once.
-//   bank_bwd_fold  : one lane per edge pixel q adds z at the padded positions u != q
-//                    that clamp onto q (up to (r+1)^2 - 1 of them at a corner).
+//   bank_bwd_edge  : recomputes the border pixels, where the clamp folds padded positions
+//                    onto q, as a correlation of gy with box sums of the taps; one
+//                    work-group per 256-pixel border segment, gy strip staged in LDS.
 //   bank_bwd_w1/w2 : filter gradient.  Stage 1: one wave per (image, 32x64 tile,
 //                    filter) accumulates all (2r+1)^2 taps over its 2048 pixels
 //                    (column-walk register reuse), reduces across the wave with a
@@ -164,55 +165,113 @@ __global__ __launch_bounds__(256) void bank_bwd_in_k(const float* __restrict__ g
     store_block(gx + (size_t)n * hw, W, H, x0, y0, vec, acc);
 }
 
-// Edge fold: gx[q] += sum of z[u] over padded u != q with clamp(u) = q.
-__global__ __launch_bounds__(256) void bank_bwd_fold_k(const float* __restrict__ gy, const float* __restrict__ w,
-                                                       float* __restrict__ gx, int N, int F, int H, int W, int r,
-                                                       int per_img) {
-    const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (gid >= (long long)N * per_img) return;
-    const int n = (int)(gid / per_img);
-    int e = (int)(gid % per_img);
-    // enumerate the edge pixels: top row, bottom row, then the left and right columns between them
-    int qx, qy;
-    if (e < W) { qx = e; qy = 0; }
-    else if (H > 1 && e < 2 * W) { qx = e - W; qy = H - 1; }
-    else {
-        e -= (H > 1 ? 2 * W : W);
-        const int rows = H - 2;
-        if (e < rows) { qx = 0; qy = 1 + e; }
-        else { qx = W - 1; qy = 1 + (e - rows); }
-    }
-    const int lox = (qx == 0) ? -r : qx, hix = (qx == W - 1) ? W - 1 + r : qx;
-    const int loy = (qy == 0) ? -r : qy, hiy = (qy == H - 1) ? H - 1 + r : qy;
-    const int nk = 2 * r + 1;
-    const size_t hw = (size_t)H * W;
-    float extra = 0.f;
-    for (int uy = loy; uy <= hiy; ++uy)
-        for (int ux = lox; ux <= hix; ++ux) {
-            if (ux == qx && uy == qy) continue;
-            float z = 0.f;
-            for (int f = 0; f < F; ++f) {
-                const float* g = gy + ((size_t)n * F + f) * hw;
-                const float* wf = w + (size_t)f * nk * nk;
-                for (int j = -r; j <= r; ++j) {
-                    const int py = uy - j;
-                    if (py < 0 || py >= H) continue;
-                    for (int i = -r; i <= r; ++i) {
-                        const int px = ux - i;
-                        if (px < 0 || px >= W) continue;
-                        z = fmaf(wf[(j + r) * nk + (i + r)], g[(size_t)py * W + px], z);
-                    }
-                }
-            }
-            extra += z;
-        }
-    gx[(size_t)n * hw + (size_t)qy * W + qx] += extra;
+// Border pixels.  For a pixel q on the image border the clamp maps the whole interval
+// S_x(q) x S_y(q) of padded positions onto q (S_x = [-r, 0] on the left edge, [W-1, W-1+r]
+// on the right, {qx} elsewhere; the same for y), so
+//   gx[n,q] = sum_f sum_p gy[n,f,p] * B_f(q,p),   B_f(q,p) = sum_{k in (S(q) - p), |k| <= r} w[f,k],
+// a correlation of gy with box sums of the taps.  Each box sum is taken directly over its
+// own taps (no differences of prefix sums), so its rounding is bounded by the box's own
+// magnitude.  The value replaces what the interior kernel wrote at q.
+//
+// One work-group per (image, side, 256-pixel segment): top and bottom rows (corners
+// included), then the left and right columns without their end rows.  For each filter the
+// r+1 deep strip of gy along the segment (plus r on each end, zero outside the image) is
+// staged in LDS, row-major along the edge so that the loads stay contiguous.
+constexpr int EDGE_SEG = 256;
+
+struct EdgeSegments {
+    int top, bottom, left, right;
+    int per_image() const { return top + bottom + left + right; }
+};
+
+EdgeSegments edge_segments(int W, int H) {
+    EdgeSegments e;
+    e.top = (W + EDGE_SEG - 1) / EDGE_SEG;
+    e.bottom = H > 1 ? e.top : 0;                                   // H == 1: the top row is the bottom row
+    e.left = H > 2 ? (H - 2 + EDGE_SEG - 1) / EDGE_SEG : 0;
+    e.right = (H > 2 && W > 1) ? e.left : 0;                        // W == 1: the left column is the right one
+    return e;
 }
 
-int edge_pixels(int W, int H) {
-    if (H == 1) return W;
-    if (W == 1) return H;
-    return 2 * W + 2 * (H - 2);
+template <int R>
+__global__ __launch_bounds__(256) void bank_bwd_edge_k(const float* __restrict__ gy, const float* __restrict__ w,
+                                                       float* __restrict__ gx, int F, int H, int W, int top,
+                                                       int bottom, int left, int per_img) {
+    constexpr int N = 2 * R + 1, L = EDGE_SEG + 2 * R;
+    __shared__ float wl[64 * N * N];
+    __shared__ float strip[L * (R + 1)];
+    for (int i = threadIdx.x; i < F * N * N; i += 256) wl[i] = w[i];
+    const int n = blockIdx.x / per_img;
+    int s = blockIdx.x - n * per_img, side, a0;
+    if (s < top) { side = 0; a0 = s * EDGE_SEG; }
+    else if ((s -= top) < bottom) { side = 1; a0 = s * EDGE_SEG; }
+    else if ((s -= bottom) < left) { side = 2; a0 = 1 + s * EDGE_SEG; }
+    else { s -= left; side = 3; a0 = 1 + s * EDGE_SEG; }
+    const int along = side < 2 ? W : H;
+    const int D = min(R + 1, side < 2 ? H : W);                      // strip depth
+    const int a = a0 + (int)threadIdx.x;
+    const bool active = a < (side < 2 ? W : H - 1);
+    // (along, depth) -> pixel
+    auto pixel = [&](int aa, int d, int& x, int& y) {
+        switch (side) {
+            case 0: x = aa; y = d; break;
+            case 1: x = aa; y = H - 1 - d; break;
+            case 2: x = d; y = aa; break;
+            default: x = W - 1 - d; y = aa; break;
+        }
+    };
+    int qx, qy;
+    pixel(a, 0, qx, qy);
+    const int sxl = qx == 0 ? -R : qx, sxh = qx == W - 1 ? W - 1 + R : qx;
+    const int syl = qy == 0 ? -R : qy, syh = qy == H - 1 ? H - 1 + R : qy;
+    const int pxl = max(sxl - R, 0), pxh = min(sxh + R, W - 1);
+    const int pyl = max(syl - R, 0), pyh = min(syh + R, H - 1);
+    const size_t hw = (size_t)H * W;
+    float acc = 0.f;
+    for (int f = 0; f < F; ++f) {
+        const float* g = gy + ((size_t)n * F + f) * hw;
+        __syncthreads();   // taps staged; previous strip consumed
+        for (int idx = threadIdx.x; idx < L * D; idx += 256) {
+            const int ai = idx / D, d = idx - ai * D, aa = a0 - R + ai;
+            float v = 0.f;
+            if (aa >= 0 && aa < along) {
+                int x, y;
+                pixel(aa, d, x, y);
+                v = g[(size_t)y * W + x];
+            }
+            strip[idx] = v;
+        }
+        __syncthreads();
+        if (!active) continue;
+        const float* wf = wl + f * N * N;
+        for (int py = pyl; py <= pyh; ++py) {
+            const int kyl = max(syl - py, -R), kyh = min(syh - py, R);
+            for (int px = pxl; px <= pxh; ++px) {
+                const int kxl = max(sxl - px, -R), kxh = min(sxh - px, R);
+                float b = 0.f;
+                for (int ky = kyl; ky <= kyh; ++ky)
+                    for (int kx = kxl; kx <= kxh; ++kx) b += wf[(ky + R) * N + kx + R];
+                int ai, d;
+                switch (side) {
+                    case 0: ai = px - a0 + R; d = py; break;
+                    case 1: ai = px - a0 + R; d = H - 1 - py; break;
+                    case 2: ai = py - a0 + R; d = px; break;
+                    default: ai = py - a0 + R; d = W - 1 - px; break;
+                }
+                acc = fmaf(strip[ai * D + d], b, acc);
+            }
+        }
+    }
+    if (active) gx[(size_t)n * hw + (size_t)qy * W + qx] = acc;
+}
+
+template <int R>
+hipError_t launch_edge(const BankArgs& a) {
+    const EdgeSegments e = edge_segments(a.w, a.h);
+    const int per = e.per_image();
+    hipLaunchKernelGGL(bank_bwd_edge_k<R>, dim3((unsigned)(a.n * per)), dim3(256), 0, a.st, a.a, a.b, a.out, a.f,
+                       a.h, a.w, e.top, e.bottom, e.left, per);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ filter gradient
@@ -527,11 +586,7 @@ hipError_t bwd_in_R(const BankArgs& a) {
     const int tx = (a.w + BT - 1) / BT, ty = (a.h + BT - 1) / BT;
     hipLaunchKernelGGL(bank_bwd_in_k<R>, dim3((unsigned)(a.n * tx * ty)), dim3(256), 0, a.st, a.a, a.b, a.out, a.f,
                        a.h, a.w, tx, tx * ty, bank_vec(a.a, a.out, a.w));
-    const int per = edge_pixels(a.w, a.h);
-    const long long tot = (long long)a.n * per;
-    hipLaunchKernelGGL(bank_bwd_fold_k, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, a.st, a.a, a.b, a.out, a.n,
-                       a.f, a.h, a.w, a.r, per);
-    return hipGetLastError();
+    return launch_edge<R>(a);
 }
 
 template <int R>
@@ -577,11 +632,7 @@ hipError_t bwd_in_pers_R(const BankArgs& a) {
     const void* k = reinterpret_cast<const void*>(&bank_bwd_in_pers_k<R>);
     hipLaunchKernelGGL(bank_bwd_in_pers_k<R>, dim3(persistent_grid(k, 256, ntiles)), dim3(256), 0, a.st, a.a, a.b,
                        a.out, a.f, a.h, a.w, tx, tx * ty, ntiles, bank_vec(a.a, a.out, a.w));
-    const int per = edge_pixels(a.w, a.h);
-    const long long tot = (long long)a.n * per;
-    hipLaunchKernelGGL(bank_bwd_fold_k, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, a.st, a.a, a.b, a.out, a.n,
-                       a.f, a.h, a.w, a.r, per);
-    return hipGetLastError();
+    return launch_edge<R>(a);
 }
 
 template <int R>

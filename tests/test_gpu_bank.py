@@ -34,7 +34,10 @@ def rel_normwise(got, ref, scale):
     return float(np.max(np.abs(got - ref) / s))
 
 
-SHAPES = [(2, 5, 70, 133, 4), (1, 3, 64, 64, 2), (2, 2, 5, 3, 4), (1, 16, 1, 9, 1), (1, 1, 1, 1, 3), (1, 4, 65, 130, 3)]
+# several tiles with ragged tails, images narrower or shorter than the stencil, one row, one
+# column, 1x1, and borders long enough to span several 256-pixel border segments
+SHAPES = [(2, 5, 70, 133, 4), (1, 3, 64, 64, 2), (2, 2, 5, 3, 4), (1, 16, 1, 9, 1), (1, 1, 1, 1, 3), (1, 4, 65, 130, 3),
+          (1, 3, 40, 1, 2), (1, 2, 2, 300, 3), (2, 2, 600, 3, 4), (1, 2, 530, 517, 1)]
 
 
 def each_variant(op):
