@@ -407,47 +407,72 @@ def extra_batch(torch, B, T, synth, steps):
 def extra_bank(torch, B, T, synth, steps):
     dev = torch.device("cuda:0")
     res = {}
-    # differentiable filter bank: forward, loss + gradient, input and filter adjoints
+    # differentiable filter bank training step: forward fused with the loss (gy = 2 (y - t), y never
+    # stored), then the input and filter adjoints; the unfused chain (forward, loss, adjoints) beside it
     N, F, Hb, Wb, r = 32, 16, 1024, 1024, 4
     x, w, t = synth.bank_inputs()
     xt, wt, tt = torch.from_numpy(x).to(dev), torch.from_numpy(w).to(dev), torch.from_numpy(t).to(dev)
     del t
     y = torch.empty((N, F, Hb, Wb), dtype=torch.float32, device=dev)
+    gy = torch.empty_like(y)
     gx = torch.empty_like(xt)
     gw = torch.empty_like(wt)
     _, nb = B.icl_workspace_size(B.ICL_OP_BANK_BWD_FILTER, Wb, Hb, N, F, r)
     wsw = torch.empty(nb // 4 + 1, dtype=torch.float32, device=dev)
     _, nb = B.icl_workspace_size(B.ICL_OP_SSE_LOSS, 1, 1)
     wsl = torch.empty(nb // 4 + 1, dtype=torch.float32, device=dev)
-    phase = {}
+    _, nb = B.icl_workspace_size(B.ICL_OP_BANK_FWD_SSE, Wb, Hb, N, F, r)
+    wsf = torch.empty(nb // 4 + 1, dtype=torch.float32, device=dev)
 
-    def fwd_bwd(s, timed=None):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if timed is not None else None
+    def fused(s, ev=None):
+        if ev: ev[0].record()
+        T.bank_fwd_sse(xt, wt, tt, workspace=wsf, gy=gy)
+        if ev: ev[1].record()
+        T.bank_bwd_input(gy, wt, out=gx)
+        if ev: ev[2].record()
+        T.bank_bwd_filter(gy, xt, r, out=gw, workspace=wsw)
+        if ev: ev[3].record()
+
+    def unfused(s, ev=None):
         if ev: ev[0].record()
         T.bank_fwd(xt, wt, out=y)
         if ev: ev[1].record()
-        L, gy = T.sse_loss(y, tt, workspace=wsl)
+        T.sse_loss(y, tt, workspace=wsl)
         if ev: ev[2].record()
         T.bank_bwd_input(gy, wt, out=gx)
         if ev: ev[3].record()
         T.bank_bwd_filter(gy, xt, r, out=gw, workspace=wsw)
-        if ev:
-            ev[4].record()
-            timed.append(ev)
+        if ev: ev[4].record()
 
-    dt = _time(torch, fwd_bwd, steps)
-    evs = []
-    for s in range(3):
-        fwd_bwd(s, evs)
-    torch.cuda.synchronize()
-    for i, name in enumerate(("fwd", "loss", "bwd_input", "bwd_filter")):
-        phase[name] = round(float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])), 3)
+    def phases(fn, names):
+        evs = []
+        for s in range(3):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+            fn(s, ev)
+            evs.append(ev)
+        torch.cuda.synchronize()
+        return {nm: round(float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])), 3) for i, nm in enumerate(names)}
+
+    dt = _time(torch, fused, steps)
+    ph = phases(fused, ("fwd_loss", "bwd_input", "bwd_filter"))
+    dt_u = _time(torch, unfused, max(2, steps // 2))
+    ph_u = phases(unfused, ("fwd", "loss", "bwd_input", "bwd_filter"))
+    per_variant = {}
+    for v in range(1, B.icl_variant_count(B.ICL_OP_BANK_FWD_SSE)):   # the fused kernels, plain aside
+        B.check(B.icl_force_variant(B.ICL_OP_BANK_FWD_SSE, v))
+        try:
+            fv = _time(torch, lambda s: T.bank_fwd_sse(xt, wt, tt, workspace=wsf, gy=gy), 3)
+        finally:
+            B.icl_force_variant(B.ICL_OP_BANK_FWD_SSE, -1)
+        per_variant[B.icl_variant_name(B.ICL_OP_BANK_FWD_SSE, v)] = round(fv * 1e3, 3)
     flops = 3 * 2 * 81 * N * F * Hb * Wb
     res["filter_bank_fwd_bwd"] = {"ms": round(dt * 1e3, 3), "gpx_s": round(N * Hb * Wb / dt / 1e9, 2),
                                   "output_gpx_s": round(N * F * Hb * Wb / dt / 1e9, 1),
                                   "tflops": round(flops / dt / 1e12, 2),
                                   "alu_frac": round(flops / dt / 1e12 / FP32_FMA_PEAK_TFLOPS, 3),
-                                  "phase_ms": phase}
+                                  "phase_ms": ph,
+                                  "fwd_loss_variants_ms": per_variant,
+                                  "unfused": {"ms": round(dt_u * 1e3, 3), "phase_ms": ph_u}}
     return res
 
 

@@ -74,7 +74,8 @@ typedef enum icl_op {
     ICL_OP_BANK_BWD_INPUT = 6,
     ICL_OP_BANK_BWD_FILTER = 7,
     ICL_OP_SSE_LOSS = 8,
-    ICL_OP_COUNT = 9
+    ICL_OP_BANK_FWD_SSE = 9,
+    ICL_OP_COUNT = 10
 } icl_op;
 
 #define ICL_MAX_RADIUS 16          /* largest stencil radius accepted by the convolution calls */
@@ -94,8 +95,8 @@ const char* icl_version(void);
 /* Scratch bytes an operation needs for the given problem (0 when none).  For
  * ICL_OP_CONV_SEP this is the float32 row-pass intermediate of the two-pass
  * variants; for ICL_OP_HARRIS the two float32 gradient images of the split
- * (Sobel kernel + Harris kernel) variant; for ICL_OP_BANK_BWD_FILTER and
- * ICL_OP_SSE_LOSS the per-block partial sums.  Callers that always pass this
+ * (Sobel kernel + Harris kernel) variant; for ICL_OP_BANK_BWD_FILTER,
+ * ICL_OP_SSE_LOSS and ICL_OP_BANK_FWD_SSE the per-block partial sums.  Callers that always pass this
  * much workspace may use every variant.  `n` and `f` are the batch and filter
  * counts of the filter-bank ops (ignored otherwise). */
 icl_status icl_workspace_size(icl_op op, int width, int height, int n, int f, int radius,
@@ -210,6 +211,23 @@ icl_status icl_bank_bwd_filter(const float* gy, const float* x, float* gw, int n
  * the reduction order is fixed, so results are reproducible run to run. */
 icl_status icl_sse_loss(const float* y, const float* t, float* gy, long long count, float* loss,
                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* The filter-bank forward fused with the sum-of-squares loss against a target
+ * t [n][f][h][wd] (dense, float32):
+ *   L = sum (y - t)^2 written to the device float32 `loss`, gy = 2 (y - t) written
+ *   when gy != NULL, the forward output y written when y != NULL.
+ * The training step of a learnable filter bank needs gy and L but not y, so with
+ * y == NULL the 4-byte-per-element write of y and its re-read by the loss drop out.
+ * y and gy are bit-identical to icl_bank_fwd followed by icl_sse_loss (every forward
+ * variant sums the taps in the same order).  L is accumulated in float64 per
+ * work-group and summed in a fixed order, so it is reproducible run to run.
+ *   workspace : icl_workspace_size(ICL_OP_BANK_FWD_SSE) bytes of device scratch
+ *               (ICL_ERR_WORKSPACE if NULL or smaller).
+ * Shapes, radius and filter limits as icl_bank_fwd; t, y, gy must not overlap x, w or
+ * each other (ICL_ERR_ALIAS). */
+icl_status icl_bank_fwd_sse(const float* x, const float* w, const float* t, float* y, float* gy, float* loss,
+                            int n, int f, int h, int wd, int radius, void* workspace, size_t workspace_bytes,
+                            void* stream);
 
 /* ------------------------------------------------------------------ auto-tuning and variants
  * The tuner plays the role of the paper's auto-tuner (Section 4 and the

@@ -33,7 +33,7 @@ ICL_F32, ICL_F16, ICL_BF16 = 0, 1, 2
 
 # icl_op
 (ICL_OP_CONV_SEP, ICL_OP_CONV2D, ICL_OP_HARRIS, ICL_OP_NMS, ICL_OP_CONV_SEP_BATCHED, ICL_OP_BANK_FWD,
- ICL_OP_BANK_BWD_INPUT, ICL_OP_BANK_BWD_FILTER, ICL_OP_SSE_LOSS, ICL_OP_COUNT) = range(10)
+ ICL_OP_BANK_BWD_INPUT, ICL_OP_BANK_BWD_FILTER, ICL_OP_SSE_LOSS, ICL_OP_BANK_FWD_SSE, ICL_OP_COUNT) = range(11)
 
 ICL_MAX_RADIUS = 16
 ICL_MAX_WINDOW_RADIUS = 7
@@ -79,6 +79,7 @@ _SIGS = {
     "icl_bank_bwd_input": ([_vp, _vp, _vp, _i, _i, _i, _i, _i, _vp], _i),
     "icl_bank_bwd_filter": ([_vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _sz, _vp], _i),
     "icl_sse_loss": ([_vp, _vp, _vp, _ll, _vp, _vp, _sz, _vp], _i),
+    "icl_bank_fwd_sse": ([_vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _sz, _vp], _i),
     "icl_tune": ([_i, _i, _i, _i, _i, _vp], _i),
     "icl_tune_save": ([ctypes.c_char_p], _i),
     "icl_tune_load": ([ctypes.c_char_p], _i),
@@ -213,6 +214,11 @@ def icl_bank_bwd_filter(gy, x, gw, n, f, h, wd, radius, workspace=0, workspace_b
 
 def icl_sse_loss(y, t, gy, count, loss, workspace=0, workspace_bytes=0, stream=0) -> int:
     return lib().icl_sse_loss(y, t, gy or None, count, loss, workspace or None, workspace_bytes, stream or None)
+
+
+def icl_bank_fwd_sse(x, w, t, y, gy, loss, n, f, h, wd, radius, workspace=0, workspace_bytes=0, stream=0) -> int:
+    return lib().icl_bank_fwd_sse(x, w, t, y or None, gy or None, loss, n, f, h, wd, radius, workspace or None,
+                                  workspace_bytes, stream or None)
 
 
 def icl_tune(op, dtype, radius, width, height, stream=0) -> int:

@@ -26,7 +26,8 @@ static int g_device_state = -1;     // -1 unknown, 0 none, 1 ok
 static std::mutex g_init_mu;
 
 static const char* kOpNames[ICL_OP_COUNT] = {"conv_sep", "conv2d", "harris", "nms", "conv_sep_batched",
-                                             "bank_fwd", "bank_bwd_input", "bank_bwd_filter", "sse_loss"};
+                                             "bank_fwd", "bank_bwd_input", "bank_bwd_filter", "sse_loss",
+                                             "bank_fwd_sse"};
 
 // ICL_FORCE_VARIANT="conv_sep=1,conv2d=3": the analogue of the paper's directives
 // that force optimisations on or off.
@@ -194,6 +195,7 @@ icl_status icl_workspace_size(icl_op op, int width, int height, int n, int f, in
             *bytes = bank_bwd_filter_workspace(n, f, height, width, radius);
             break;
         case ICL_OP_SSE_LOSS: *bytes = sse_workspace((long long)width * height); break;
+        case ICL_OP_BANK_FWD_SSE: *bytes = bank_fwd_sse_workspace(); break;
         case ICL_OP_CONV2D: case ICL_OP_NMS: case ICL_OP_CONV_SEP_BATCHED: case ICL_OP_BANK_FWD:
         case ICL_OP_BANK_BWD_INPUT: break;
         default: return ICL_ERR_INVALID_VALUE;
@@ -380,6 +382,39 @@ icl_status icl_sse_loss(const float* y, const float* t, float* gy, long long cou
     return hip_status(sse_launch(y, t, gy, count, loss, workspace, workspace_bytes, (hipStream_t)stream));
 }
 
+icl_status icl_bank_fwd_sse(const float* x, const float* w, const float* t, float* y, float* gy, float* loss, int n,
+                            int f, int h, int wd, int radius, void* workspace, size_t workspace_bytes, void* stream) {
+    icl_status s;
+    if ((s = check_bank(n, f, h, wd, radius)) != ICL_OK) return s;
+    if (!loss) return ICL_ERR_INVALID_VALUE;
+    if (!workspace || workspace_bytes < bank_fwd_sse_workspace()) return ICL_ERR_WORKSPACE;
+    const size_t hw = (size_t)h * wd, nx = (size_t)n * hw * 4, ny = (size_t)n * f * hw * 4;
+    const size_t nw = (size_t)f * (2 * radius + 1) * (2 * radius + 1) * 4;
+    if (ny > 0 && (!x || !w || !t)) return ICL_ERR_INVALID_VALUE;
+    // outputs against every input and against each other (the loss scalar and the workspace too)
+    const void* outs[4] = {y, gy, loss, workspace};
+    const size_t onb[4] = {ny, ny, 4, workspace_bytes};
+    const void* ins[3] = {x, w, t};
+    const size_t inb[3] = {nx, nw, ny};
+    for (int i = 0; i < 4; ++i) {
+        if (!outs[i] || !onb[i]) continue;
+        for (int j = 0; j < 3; ++j)
+            if (ins[j] && inb[j] && range_overlaps(outs[i], onb[i], ins[j], inb[j])) return ICL_ERR_ALIAS;
+        for (int j = i + 1; j < 4; ++j)
+            if (outs[j] && onb[j] && range_overlaps(outs[i], onb[i], outs[j], onb[j])) return ICL_ERR_ALIAS;
+    }
+    if ((s = device_ready()) != ICL_OK) return s;
+    BankSseArgs a{x, w, t, y, gy, loss, n, f, h, wd, radius, workspace, workspace_bytes, (hipStream_t)stream};
+    if (ny == 0) {   // empty batch: L = 0
+        return hip_status(zero_fill(loss, 1, a.st));
+    }
+    int count;
+    const Variant<BankSseArgs>* tab = bank_fwd_sse_variants(&count);
+    const int deflt = bank_fwd_sse_default(a);
+    return dispatch(ICL_OP_BANK_FWD_SSE, tab, count, a,
+                    select_variant(ICL_OP_BANK_FWD_SSE, ICL_F32, radius, wd, h, deflt), deflt);
+}
+
 // ------------------------------------------------------------------ variants
 int icl_variant_count(icl_op op) {
     int c = 0;
@@ -391,6 +426,7 @@ int icl_variant_count(icl_op op) {
         case ICL_OP_BANK_FWD: bank_fwd_variants(&c); break;
         case ICL_OP_BANK_BWD_INPUT: bank_bwd_input_variants(&c); break;
         case ICL_OP_BANK_BWD_FILTER: bank_bwd_filter_variants(&c); break;
+        case ICL_OP_BANK_FWD_SSE: bank_fwd_sse_variants(&c); break;
         case ICL_OP_CONV_SEP_BATCHED: case ICL_OP_SSE_LOSS: c = 1; break;
         default: c = 0;
     }
@@ -408,7 +444,8 @@ const char* icl_variant_name(icl_op op, int index) {
         case ICL_OP_BANK_FWD: return bank_fwd_variants(&c)[index].name;
         case ICL_OP_BANK_BWD_INPUT: return bank_bwd_input_variants(&c)[index].name;
         case ICL_OP_BANK_BWD_FILTER: return bank_bwd_filter_variants(&c)[index].name;
-        case ICL_OP_CONV_SEP_BATCHED: return "persistent_fused_t32";
+        case ICL_OP_BANK_FWD_SSE: return bank_fwd_sse_variants(&c)[index].name;
+        case ICL_OP_CONV_SEP_BATCHED: return "persistent_fused_t64";
         case ICL_OP_SSE_LOSS: return "two_stage";
         default: return nullptr;
     }

@@ -415,12 +415,83 @@ __global__ __launch_bounds__(256) void bank_bwd_in_plain_k(const float* __restri
 // ------------------------------------------------------------------ persistent, prefetching, taps in LDS
 constexpr int PERS_FMAX = 16;   // filters whose taps fit the static LDS table
 
-template <int R>
-__global__ __launch_bounds__(256) void bank_fwd_pers_k(const float* __restrict__ x, const float* __restrict__ w,
-                                                       float* __restrict__ y, int F, int H, int W, int tiles_x,
-                                                       int tiles_img, int ntiles, int vec) {
+// Target block of the fused loss: the lane's BPY x BPX pixels of plane `tg` (0 outside).
+__device__ __forceinline__ void load_block(const float* __restrict__ plane, int W, int H, int x0, int y0, bool vec,
+                                           float (&v)[BPY][BPX]) {
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int xb = x0 + tx * BPX;
+#pragma unroll
+    for (int py = 0; py < BPY; ++py) {
+        const int y = y0 + ty * BPY + py;
+        const float* row = plane + (size_t)(y < H ? y : 0) * W;
+        if (y < H && vec && xb + BPX <= W) {
+            const v4f q = *reinterpret_cast<const v4f*>(row + xb);
+            v[py][0] = q.x; v[py][1] = q.y; v[py][2] = q.z; v[py][3] = q.w;
+        } else {
+#pragma unroll
+            for (int px = 0; px < BPX; ++px) v[py][px] = (y < H && xb + px < W) ? row[xb + px] : 0.f;
+        }
+    }
+}
+
+// Loss epilogue of the fused forward: d = y - t on the lane's in-image pixels; adds the
+// block's sum of d^2 (float32 over these <= 16 terms) to `sq`, writes gy = 2 d and y where
+// the pointers are non-null.  2 d is the same float32 product as the stand-alone loss.
+__device__ __forceinline__ void sse_block(float* __restrict__ gyp, float* __restrict__ yp, int W, int H, int x0,
+                                          int y0, bool vec, const float (&acc)[BPY][BPX],
+                                          const float (&tv)[BPY][BPX], double& sq) {
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int xb = x0 + tx * BPX;
+    float s = 0.f;
+#pragma unroll
+    for (int py = 0; py < BPY; ++py) {
+        const int y = y0 + ty * BPY + py;
+        if (y >= H) break;
+        const size_t off = (size_t)y * W + xb;
+        float d[BPX];
+#pragma unroll
+        for (int px = 0; px < BPX; ++px) d[px] = acc[py][px] - tv[py][px];
+        if (vec && xb + BPX <= W) {
+#pragma unroll
+            for (int px = 0; px < BPX; ++px) s = fmaf(d[px], d[px], s);
+            if (gyp) *reinterpret_cast<v4f*>(gyp + off) = 2.f * mk4(d[0], d[1], d[2], d[3]);
+            if (yp) *reinterpret_cast<v4f*>(yp + off) = mk4(acc[py][0], acc[py][1], acc[py][2], acc[py][3]);
+        } else {
+#pragma unroll
+            for (int px = 0; px < BPX; ++px)
+                if (xb + px < W) {
+                    s = fmaf(d[px], d[px], s);
+                    if (gyp) gyp[off + px] = 2.f * d[px];
+                    if (yp) yp[off + px] = acc[py][px];
+                }
+        }
+    }
+    sq += (double)s;
+}
+
+// Work-group sum of one double per lane into part[blockIdx.x], through LDS scratch of
+// at least 256 doubles (fixed tree order).
+__device__ __forceinline__ void block_sum_store(double v, double* __restrict__ red, double* __restrict__ part) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// SSE: the forward fused with the sum-of-squares loss against tg (y and gy optional, the
+// block's partial sum of (y - t)^2 to part[blockIdx.x]); otherwise the plain forward into y.
+template <int R, bool SSE, bool TPRE>
+__device__ __forceinline__ void bank_fwd_pers_body(const float* __restrict__ x, const float* __restrict__ w,
+                                                   float* __restrict__ y, const float* __restrict__ tg,
+                                                   float* __restrict__ gy, double* __restrict__ part, int F, int H,
+                                                   int W, int tiles_x, int tiles_img, int ntiles, int vec) {
     using G = BankTile<R>;
     constexpr int LW = G::LW, NR = G::NR, RA = G::RA, N = 2 * R + 1, NP = (N + 3) & ~3;
+    static_assert(2 * NR * LW * sizeof(float) >= 256 * sizeof(double), "the x tiles double as reduction scratch");
     // two x tiles: the next tile is staged into the idle one while all F filters run on the other
     __shared__ __attribute__((aligned(16))) float s[2][NR * LW];
     __shared__ __attribute__((aligned(16))) float wl[PERS_FMAX * N * NP];
@@ -435,12 +506,14 @@ __global__ __launch_bounds__(256) void bank_fwd_pers_k(const float* __restrict__
     };
     const BandWalk walk(tiles_x, ntiles / tiles_x);   // images stacked vertically
     int t = walk.tile(0);
-    if (t < 0) return;
-    fetch(t);
-    st.store(s[0]);
+    if (t >= 0) {
+        fetch(t);
+        st.store(s[0]);
+    }
     __syncthreads();
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     int cur = 0;
+    double sq = 0.0;
     for (int k = 0; t >= 0; ++k) {
         const int n = t / tiles_img, ti = t - n * tiles_img;
         int x0, y0;
@@ -449,17 +522,46 @@ __global__ __launch_bounds__(256) void bank_fwd_pers_k(const float* __restrict__
         if (tn >= 0) fetch(tn);
 #pragma unroll 1
         for (int f = 0; f < F; ++f) {
+            const size_t plane = ((size_t)n * F + f) * hw;
+            float tv[BPY][BPX];
+            if constexpr (SSE && TPRE) load_block(tg + plane, W, H, x0, y0, vec, tv);   // in flight during the FMAs
             float acc[BPY][BPX] = {};
             corr_rows<R, BPX, BPY, LW>(&s[cur][(ty * BPY) * LW + tx * BPX], &wl[f * N * NP], acc);
+            if constexpr (SSE && !TPRE) {
+                __builtin_amdgcn_sched_barrier(0);   // keep the target loads (and their registers) after the FMAs
+                load_block(tg + plane, W, H, x0, y0, vec, tv);
+            }
             // stage the next tile before this tile's first output store: the wait on the
             // prefetch loads then never includes stores
             if (f == 0 && tn >= 0) st.store(s[cur ^ 1]);
-            store_block(y + ((size_t)n * F + f) * hw, W, H, x0, y0, vec, acc);
+            if constexpr (SSE) sse_block(gy ? gy + plane : nullptr, y ? y + plane : nullptr, W, H, x0, y0, vec, acc, tv, sq);
+            else store_block(y + plane, W, H, x0, y0, vec, acc);
         }
         __syncthreads();
         cur ^= 1;
         t = tn;
     }
+    if constexpr (SSE) block_sum_store(sq, reinterpret_cast<double*>(&s[0][0]), part);
+}
+
+// Three waves per SIMD (the x tiles' LDS allows three work-groups per CU): the plain
+// forward fits without the hint; the fused forward with late target loads fits with it.
+template <int R, bool SSE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void bank_fwd_pers_k(
+    const float* __restrict__ x, const float* __restrict__ w, float* __restrict__ y, const float* __restrict__ tg,
+    float* __restrict__ gy, double* __restrict__ part, int F, int H, int W, int tiles_x, int tiles_img, int ntiles,
+    int vec) {
+    bank_fwd_pers_body<R, SSE, false>(x, w, y, tg, gy, part, F, H, W, tiles_x, tiles_img, ntiles, vec);
+}
+
+// Fused forward with the target block loaded before the FMAs: more live registers, two waves.
+template <int R>
+__global__ __launch_bounds__(256) void bank_fwd_sse_tpre_k(const float* __restrict__ x, const float* __restrict__ w,
+                                                           float* __restrict__ y, const float* __restrict__ tg,
+                                                           float* __restrict__ gy, double* __restrict__ part, int F,
+                                                           int H, int W, int tiles_x, int tiles_img, int ntiles,
+                                                           int vec) {
+    bank_fwd_pers_body<R, true, true>(x, w, y, tg, gy, part, F, H, W, tiles_x, tiles_img, ntiles, vec);
 }
 
 template <int R>
@@ -619,9 +721,10 @@ template <int R>
 hipError_t fwd_pers_R(const BankArgs& a) {
     const int tx = (a.w + BT - 1) / BT, ty = (a.h + BT - 1) / BT;
     const int ntiles = a.n * tx * ty;
-    const void* k = reinterpret_cast<const void*>(&bank_fwd_pers_k<R>);
-    hipLaunchKernelGGL(bank_fwd_pers_k<R>, dim3(persistent_grid(k, 256, ntiles)), dim3(256), 0, a.st, a.a, a.b,
-                       a.out, a.f, a.h, a.w, tx, tx * ty, ntiles, bank_vec(a.a, a.out, a.w));
+    const void* k = reinterpret_cast<const void*>(&bank_fwd_pers_k<R, false>);
+    hipLaunchKernelGGL((bank_fwd_pers_k<R, false>), dim3(persistent_grid(k, 256, ntiles)), dim3(256), 0, a.st, a.a,
+                       a.b, a.out, nullptr, nullptr, nullptr, a.f, a.h, a.w, tx, tx * ty, ntiles,
+                       bank_vec(a.a, a.out, a.w));
     return hipGetLastError();
 }
 
@@ -732,6 +835,101 @@ __global__ __launch_bounds__(256) void sse_k2(const float* __restrict__ part, in
     if (threadIdx.x == 0) *loss = red[0];
 }
 
+// ------------------------------------------------------------------ forward fused with the loss
+constexpr int FWD_SSE_PARTS = 2048;   // most work-groups of a fused launch = double partials in the workspace
+
+// Plain fused forward: grid-stride over the outputs, each from its clamped taps directly
+// (the same tap order as every forward variant), double partial per work-group.
+__global__ __launch_bounds__(256) void bank_fwd_sse_plain_k(const float* __restrict__ x, const float* __restrict__ w,
+                                                            const float* __restrict__ tg, float* __restrict__ y,
+                                                            float* __restrict__ gy, double* __restrict__ part, int N,
+                                                            int F, int H, int W, int r) {
+    __shared__ double red[256];
+    const long long hw = (long long)H * W, total = (long long)N * F * hw;
+    const int nk = 2 * r + 1;
+    double sq = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long long)gridDim.x * 256) {
+        const int n = (int)(i / (F * hw));
+        const int f = (int)((i / hw) % F);
+        const int p = (int)(i % hw), py = p / W, px = p - py * W;
+        const float* xp = x + (size_t)n * hw;
+        const float* wf = w + (size_t)f * nk * nk;
+        float acc = 0.f;
+        for (int j = -r; j <= r; ++j)
+            for (int q = -r; q <= r; ++q)
+                acc = fmaf(wf[(j + r) * nk + (q + r)], xp[(size_t)clampi(py + j, H) * W + clampi(px + q, W)], acc);
+        const float d = acc - tg[i];
+        sq = fma((double)d, (double)d, sq);
+        if (gy) gy[i] = 2.f * d;
+        if (y) y[i] = acc;
+    }
+    block_sum_store(sq, red, part);
+}
+
+// L = sum of the partials in a fixed order, in double, rounded once to float32.
+__global__ __launch_bounds__(256) void sse_final_k(const double* __restrict__ part, int nparts, float* __restrict__ loss) {
+    __shared__ double red[256];
+    double v = 0.0;
+    for (int q = threadIdx.x; q < nparts; q += 256) v += part[q];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = (float)red[0];
+}
+
+int sse_vec(const BankSseArgs& a) {
+    auto al = [](const void* p) { return p == nullptr || (uintptr_t)p % 16 == 0; };
+    return al(a.x) && al(a.t) && al(a.y) && al(a.gy) && (a.wd % 4 == 0);
+}
+
+hipError_t launch_fwd_sse_plain(const BankSseArgs& a) {
+    double* part = static_cast<double*>(a.ws);
+    const long long tot = (long long)a.n * a.f * a.h * a.wd;
+    const int grid = (int)std::min<long long>(FWD_SSE_PARTS, (tot + 255) / 256);
+    hipLaunchKernelGGL(bank_fwd_sse_plain_k, dim3(grid), dim3(256), 0, a.st, a.x, a.w, a.t, a.y, a.gy, part, a.n, a.f,
+                       a.h, a.wd, a.r);
+    hipLaunchKernelGGL(sse_final_k, dim3(1), dim3(256), 0, a.st, part, grid, a.loss);
+    return hipGetLastError();
+}
+
+template <int R, bool TPRE>
+hipError_t fwd_sse_pers_R(const BankSseArgs& a) {
+    double* part = static_cast<double*>(a.ws);
+    const int tx = (a.wd + BT - 1) / BT, ty = (a.h + BT - 1) / BT;
+    const int ntiles = a.n * tx * ty;
+    auto kern = TPRE ? bank_fwd_sse_tpre_k<R> : bank_fwd_pers_k<R, true>;
+    const int grid = std::min(persistent_grid(reinterpret_cast<const void*>(kern), 256, ntiles), FWD_SSE_PARTS);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, a.st, a.x, a.w, a.y, a.t, a.gy, part, a.f, a.h, a.wd, tx,
+                       tx * ty, ntiles, sse_vec(a));
+    hipLaunchKernelGGL(sse_final_k, dim3(1), dim3(256), 0, a.st, part, grid, a.loss);
+    return hipGetLastError();
+}
+
+template <bool TPRE>
+hipError_t launch_fwd_sse_pers(const BankSseArgs& a) {
+    switch (a.r) {
+        case 1: return fwd_sse_pers_R<1, TPRE>(a);
+        case 2: return fwd_sse_pers_R<2, TPRE>(a);
+        case 3: return fwd_sse_pers_R<3, TPRE>(a);
+        case 4: return fwd_sse_pers_R<4, TPRE>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool supports_sse(const BankSseArgs& a) {
+    return a.r >= 1 && a.r <= 4 && a.f >= 1 && a.f <= 64 && a.ws != nullptr && a.wsb >= bank_fwd_sse_workspace();
+}
+bool supports_sse_pers(const BankSseArgs& a) { return supports_sse(a) && a.f <= PERS_FMAX; }
+
+// pers_p4x4_tpre loads the lane's target block before the FMAs (more registers, fewer
+// waves); pers_p4x4 loads it after them and relies on the other resident waves.
+const Variant<BankSseArgs> kFwdSse[] = {{"plain", supports_sse, launch_fwd_sse_plain},
+                                        {"pers_p4x4", supports_sse_pers, launch_fwd_sse_pers<false>},
+                                        {"pers_p4x4_tpre", supports_sse_pers, launch_fwd_sse_pers<true>}};
+
 }  // namespace
 
 size_t bank_bwd_filter_workspace(int n, int f, int h, int w, int r) {
@@ -744,6 +942,8 @@ size_t bank_bwd_filter_workspace(int n, int f, int h, int w, int r) {
 }
 
 size_t sse_workspace(long long) { return SSE_BLOCKS * sizeof(float); }
+
+size_t bank_fwd_sse_workspace() { return FWD_SSE_PARTS * sizeof(double); }
 
 namespace {
 __global__ __launch_bounds__(256) void zero_k(float* __restrict__ p, size_t n) {
@@ -783,5 +983,10 @@ const Variant<BankArgs>* bank_bwd_filter_variants(int* count) {
 int bank_fwd_default(const BankArgs& a) { return supports_pers(a) ? 2 : 1; }
 int bank_bwd_input_default(const BankArgs& a) { return supports_pers(a) ? 2 : 1; }
 int bank_bwd_filter_default(const BankArgs&) { return 1; }
+const Variant<BankSseArgs>* bank_fwd_sse_variants(int* count) {
+    *count = (int)(sizeof(kFwdSse) / sizeof(kFwdSse[0]));
+    return kFwdSse;
+}
+int bank_fwd_sse_default(const BankSseArgs& a) { return supports_sse_pers(a) ? 1 : 0; }
 
 }  // namespace icl

@@ -49,6 +49,14 @@ struct BankArgs {
     hipStream_t st;
 };
 
+struct BankSseArgs {
+    const float *x, *w, *t;
+    float *y, *gy, *loss;   // y and gy may be null
+    int n, f, h, wd, r;
+    void* ws; size_t wsb;
+    hipStream_t st;
+};
+
 // One precompiled candidate implementation of an operation.
 template <class A> struct Variant {
     const char* name;
@@ -64,6 +72,7 @@ const Variant<NmsArgs>* nms_variants(int* count);
 const Variant<BankArgs>* bank_fwd_variants(int* count);
 const Variant<BankArgs>* bank_bwd_input_variants(int* count);
 const Variant<BankArgs>* bank_bwd_filter_variants(int* count);
+const Variant<BankSseArgs>* bank_fwd_sse_variants(int* count);
 
 // Default choice when neither a forced variant nor a tune-cache entry applies.
 int sep_default(const SepArgs&);
@@ -73,11 +82,13 @@ int nms_default(const NmsArgs&);
 int bank_fwd_default(const BankArgs&);
 int bank_bwd_input_default(const BankArgs&);
 int bank_bwd_filter_default(const BankArgs&);
+int bank_fwd_sse_default(const BankSseArgs&);
 
 size_t sep_workspace(int W, int H);
 size_t harris_workspace(int W, int H);
 size_t bank_bwd_filter_workspace(int n, int f, int h, int w, int r);
 size_t sse_workspace(long long count);
+size_t bank_fwd_sse_workspace();
 
 hipError_t sse_launch(const float* y, const float* t, float* gy, long long count, float* loss,
                       void* ws, size_t wsb, hipStream_t st);

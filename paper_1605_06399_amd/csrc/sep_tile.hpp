@@ -95,7 +95,7 @@ __device__ __forceinline__ void sep_tile_body(const void* __restrict__ src, size
                                               const float* __restrict__ ty, int x0, int y0, bool vec, bool vec_out,
                                               float* __restrict__ lds) {
     using G = SepTile<R, TH, CX>;
-    constexpr int TW = G::TW, RA = G::RA, LW = G::LW, NR = G::NR;
+    constexpr int RA = G::RA, LW = G::LW, NR = G::NR;
     float* in_s = lds;             // [NR][LW]
     float* t_s = lds + NR * LW;    // [NR][TW]
     const int tid = threadIdx.x;

@@ -221,6 +221,32 @@ def sse_loss(y: torch.Tensor, t: torch.Tensor, grad: bool = True, workspace: tor
     return loss, gy
 
 
+def bank_fwd_sse(x: torch.Tensor, w: torch.Tensor, t: torch.Tensor, grad: bool = True, want_y: bool = False,
+                 workspace: torch.Tensor | None = None, gy: torch.Tensor | None = None,
+                 y: torch.Tensor | None = None):
+    """Forward fused with the loss: (L, gy, y) with L = sum (bank(x, w) - t)^2 as a 0-d GPU tensor,
+    gy = 2 (bank(x, w) - t) (None if grad is False) and the forward output y (None unless want_y)."""
+    N, H, W = x.shape[0], x.shape[-2], x.shape[-1]
+    F, r = w.shape[0], (w.shape[-1] - 1) // 2
+    if tuple(t.shape) != (N, F, H, W):
+        raise ValueError(f"target shape {tuple(t.shape)} != {(N, F, H, W)}")
+    loss = torch.empty((), dtype=torch.float32, device=x.device)
+    if grad and gy is None:
+        gy = torch.empty((N, F, H, W), dtype=torch.float32, device=x.device)
+    if want_y and y is None:
+        y = torch.empty((N, F, H, W), dtype=torch.float32, device=x.device)
+    gy = gy if grad else None
+    y = y if want_y else None
+    if workspace is None:
+        _, nb = B.icl_workspace_size(B.ICL_OP_BANK_FWD_SSE, W, H, N, F, r)
+        workspace = _workspace(nb, x.device)
+    B.check(B.icl_bank_fwd_sse(_dense(x, "x"), _dense(w, "w"), _dense(t, "t"),
+                               _dense(y, "y") if y is not None else 0, _dense(gy, "gy") if gy is not None else 0,
+                               loss.data_ptr(), N, F, H, W, r, workspace.data_ptr(), workspace.numel() * 4,
+                               _stream()), "icl_bank_fwd_sse")
+    return loss, gy, y
+
+
 class FilterBankFn(torch.autograd.Function):
     """y = bank(x, w) with hand-written adjoint kernels for both gradients."""
 
@@ -240,3 +266,30 @@ class FilterBankFn(torch.autograd.Function):
 
 def filter_bank(x: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
     return FilterBankFn.apply(x, w)
+
+
+class FilterBankLossFn(torch.autograd.Function):
+    """L = sum (bank(x, w) - t)^2 from the fused forward (y is never stored); the backward runs
+    the two adjoint kernels on the saved gy = 2 (y - t).  The target is a constant (no gradient)."""
+
+    @staticmethod
+    def forward(ctx, x, w, t):
+        L, gy, _ = bank_fwd_sse(x.contiguous(), w.contiguous(), t.contiguous())
+        ctx.save_for_backward(x, w, gy)
+        return L
+
+    @staticmethod
+    def backward(ctx, gL):
+        x, w, gy = ctx.saved_tensors
+        gx = bank_bwd_input(gy, w.contiguous()).view_as(x) if ctx.needs_input_grad[0] else None
+        gw = bank_bwd_filter(gy, x.contiguous(), (w.shape[-1] - 1) // 2) if ctx.needs_input_grad[1] else None
+        # chain rule for an upstream factor on L (1 for loss.backward()); the adjoints are linear in gy
+        if gx is not None:
+            gx.mul_(gL)
+        if gw is not None:
+            gw.mul_(gL)
+        return gx, gw, None
+
+
+def filter_bank_loss(x: torch.Tensor, w: torch.Tensor, t: torch.Tensor) -> torch.Tensor:
+    return FilterBankLossFn.apply(x, w, t)

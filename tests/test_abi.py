@@ -1,9 +1,11 @@
 """C-ABI library: loads, exports every declared symbol, and validates arguments on the host.
 
 These tests make no compute call: argument checks run before any device query,
-so each error path returns its status code on a machine without a GPU.  A
-well-formed call returns ICL_OK (empty image), ICL_ERR_NO_DEVICE (no GPU here)
-or launches (GPU machine; not done in this file).
+so each error path returns its status code on a machine without a GPU.  The
+addresses are fake, so a call here must never pass validation where a GPU is
+visible (it would launch on them): every call either fails a check or is an
+empty no-op, except in test_no_device_or_launch_path, which is skipped when a
+GPU is present.
 """
 import ctypes
 import os
@@ -29,6 +31,16 @@ def L():
     if not os.path.exists(B.LIB_PATH):
         pytest.fail("libicl.so is not built (run __graft_entry__.build())")
     return B.lib()
+
+
+@pytest.fixture
+def no_gpu(L):
+    """The fake-address validation tests run only where no GPU is visible: should a check
+    regress there, the call fails with ICL_ERR_NO_DEVICE instead of launching on fake memory."""
+    from conftest import gpu_available
+    if gpu_available():
+        pytest.skip("fake device addresses are only passed where no GPU is visible")
+    return L
 
 
 def test_every_declared_symbol_is_exported(L):
@@ -85,7 +97,7 @@ def sep(**kw):
     return B.icl_conv_sep(*a.values())
 
 
-def test_conv_sep_validation(L):
+def test_conv_sep_validation(no_gpu):
     assert sep(width=-1) == B.ICL_ERR_INVALID_VALUE
     assert sep(height=-3) == B.ICL_ERR_INVALID_VALUE
     assert sep(dtype=5) == B.ICL_ERR_DTYPE
@@ -99,11 +111,10 @@ def test_conv_sep_validation(L):
     assert sep(dst_pitch=64 * 4 + 1) == B.ICL_ERR_PITCH
     assert sep(dtype=B.ICL_F16, src_pitch=129, dst_pitch=128) == B.ICL_ERR_PITCH
     assert sep(dst=SRC + 7 * 256) == B.ICL_ERR_ALIAS              # last source row overlaps
-    assert sep(dst=SRC + 8 * 256) != B.ICL_ERR_ALIAS
     assert sep(workspace=DST + 100, workspace_bytes=4096) == B.ICL_ERR_ALIAS
 
 
-def test_conv2d_harris_nms_validation(L):
+def test_conv2d_harris_nms_validation(no_gpu):
     assert B.icl_conv2d(SRC, 256, DST, 256, 64, 8, B.ICL_F32, TAPS, 17) == B.ICL_ERR_RADIUS
     assert B.icl_conv2d(SRC, 256, DST, 256, 64, 8, B.ICL_F32, 0, 1) == B.ICL_ERR_INVALID_VALUE
     assert B.icl_conv2d(SRC, 256, SRC, 256, 64, 8, B.ICL_F32, TAPS, 1) == B.ICL_ERR_ALIAS
@@ -117,7 +128,7 @@ def test_conv2d_harris_nms_validation(L):
     assert B.icl_nms(SRC, 256, DST, 64, -1, 8, 1, 1e-3) == B.ICL_ERR_INVALID_VALUE
 
 
-def test_bank_and_loss_validation(L):
+def test_bank_and_loss_validation(no_gpu):
     assert B.icl_bank_fwd(SRC, TAPS, DST, 2, 16, 8, 8, 5) == B.ICL_ERR_RADIUS
     assert B.icl_bank_fwd(SRC, TAPS, DST, 2, 0, 8, 8, 4) == B.ICL_ERR_INVALID_VALUE
     assert B.icl_bank_fwd(SRC, TAPS, DST, 2, 65, 8, 8, 4) == B.ICL_ERR_UNSUPPORTED
@@ -126,12 +137,32 @@ def test_bank_and_loss_validation(L):
     assert B.icl_bank_bwd_input(0, TAPS, DST, 2, 4, 8, 8, 4) == B.ICL_ERR_INVALID_VALUE
     assert B.icl_bank_bwd_filter(SRC, DST, WS, 2, 4, 8, 8, 4, 0, 0) == B.ICL_ERR_WORKSPACE
     assert B.icl_bank_bwd_filter(SRC, DST, WS, 2, 4, 8, 8, 4, 0x50000000, 10) == B.ICL_ERR_WORKSPACE
+    # fused forward + loss: x 512 B, y / gy / t 2 KiB each at these sizes
+    TG, GY, LS = 0x50000000, 0x60000000, 0x70000000
+    _, wsb = B.icl_workspace_size(B.ICL_OP_BANK_FWD_SSE, 8, 8, 2, 4, 4)
+    assert wsb >= 8
+
+    def fs(**kw):
+        a = dict(x=SRC, w=TAPS, t=TG, y=0, gy=GY, loss=LS, n=2, f=4, h=8, wd=8, r=4, ws=WS, wsb=wsb)
+        a.update(kw)
+        return B.icl_bank_fwd_sse(*a.values())
+    assert fs(r=5) == B.ICL_ERR_RADIUS
+    assert fs(f=65) == B.ICL_ERR_UNSUPPORTED
+    assert fs(loss=0) == B.ICL_ERR_INVALID_VALUE
+    assert fs(t=0) == B.ICL_ERR_INVALID_VALUE
+    assert fs(ws=0) == B.ICL_ERR_WORKSPACE
+    assert fs(wsb=wsb - 1) == B.ICL_ERR_WORKSPACE
+    assert fs(gy=SRC + 4) == B.ICL_ERR_ALIAS          # gradient over x
+    assert fs(y=GY + 1024) == B.ICL_ERR_ALIAS         # y over gy
+    assert fs(y=TG) == B.ICL_ERR_ALIAS                # y over the target
+    assert fs(loss=TG + 2044) == B.ICL_ERR_ALIAS      # loss scalar inside the target
+    assert fs(ws=GY + 8) == B.ICL_ERR_ALIAS           # workspace over gy
     assert B.icl_sse_loss(SRC, DST, 0, -1, WS) == B.ICL_ERR_INVALID_VALUE
     assert B.icl_sse_loss(SRC, DST, 0, 10, WS, 0, 0) == B.ICL_ERR_WORKSPACE
     assert B.icl_sse_loss(SRC, DST, SRC + 8, 10, WS, 0x50000000, 1 << 20) == B.ICL_ERR_ALIAS
 
 
-def test_batch_plan_validation(L):
+def test_batch_plan_validation(no_gpu):
     d = B.icl_image_desc(SRC, DST, 256, 256, 64, 8, 3, TAPS, TAPS)
     assert B.icl_batch_plan_create([d], 9)[0] == B.ICL_ERR_DTYPE
     bad = B.icl_image_desc(SRC, DST, 256, 256, 64, 8, 8, TAPS, TAPS)
@@ -154,6 +185,11 @@ def test_no_device_or_launch_path(L):
         pytest.skip("GPU present: compute calls are covered by the gpu tests")
     assert B.icl_init() == B.ICL_ERR_NO_DEVICE
     assert sep() == B.ICL_ERR_NO_DEVICE
+    assert sep(dst=SRC + 8 * 256) == B.ICL_ERR_NO_DEVICE         # adjacent rows are no alias
+    _, wsb = B.icl_workspace_size(B.ICL_OP_BANK_FWD_SSE, 8, 8, 2, 4, 4)
+    # loss scalar right after the target, y absent: valid, so it reaches the device check
+    assert B.icl_bank_fwd_sse(SRC, TAPS, 0x50000000, 0, 0x60000000, 0x50000000 + 2048, 2, 4, 8, 8, 4,
+                              WS, wsb) == B.ICL_ERR_NO_DEVICE
     assert B.icl_tune(B.ICL_OP_CONV_SEP, B.ICL_F32, 2, 64, 64) == B.ICL_ERR_NO_DEVICE
 
 

@@ -112,6 +112,87 @@ def test_sse_loss():
     assert none is None and L2.item() == L.item()
 
 
+def loss_bound(yr, t, ys, Lr):
+    """|L_gpu - L| for a forward within 1e-5 * ys of yr (what test_bank_forward asserts), the float32
+    subtraction y - t, and the float64 sum: sum 2|d| (1e-5 ys + 2^-23 (|y| + |t|)) + 1e-6 L."""
+    return float(np.sum(2 * np.abs(yr - t) * (1e-5 * ys + 2.0 ** -23 * (np.abs(yr) + np.abs(t))))) + 1e-6 * Lr
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_bank_forward_fused_with_loss(shape):
+    N, F, H, W, r = shape
+    x, w, t = inputs(N, F, H, W, r)
+    yr = oracle.bank_fwd(x, w)
+    ys = oracle.bank_fwd(np.abs(x), np.abs(w))
+    Lr, gyr = oracle.sse_loss(yr, t)
+    for v in each_variant(B.ICL_OP_BANK_FWD_SSE):
+        L, gy, y = T.bank_fwd_sse(cu(x), cu(w), cu(t), want_y=True)
+        torch.cuda.synchronize()
+        assert rel_normwise(host(y), yr, ys) <= 1e-5, f"variant {v}: y"
+        assert rel_normwise(host(gy), gyr, 2 * ys + 2 * np.abs(t)) <= 1e-5, f"variant {v}: gy"
+        assert abs(L.item() - Lr) <= loss_bound(yr, t, ys, Lr), f"variant {v}: L {L.item()} vs {Lr}"
+        # the optional outputs change nothing else: same loss bits, same gradient bits
+        L2, gy2, none = T.bank_fwd_sse(cu(x), cu(w), cu(t))
+        L3, none2, _ = T.bank_fwd_sse(cu(x), cu(w), cu(t), grad=False)
+        assert none is None and none2 is None
+        assert L2.item() == L.item() == L3.item()
+        assert torch.equal(gy2, gy)
+
+
+@pytest.mark.parametrize("shape", [(2, 5, 70, 133, 4), (1, 16, 64, 64, 2), (1, 3, 33, 70, 3), (2, 2, 5, 3, 1)])
+def test_fused_outputs_equal_forward_then_loss(shape):
+    """Every forward variant sums the taps in the same order, so the fused y and gy are the
+    same bits as icl_bank_fwd followed by icl_sse_loss."""
+    N, F, H, W, r = shape
+    x, w, t = inputs(N, F, H, W, r, cfg=77)
+    xt, wt, tt = cu(x), cu(w), cu(t)
+    y_ref = T.bank_fwd(xt, wt)
+    _, gy_ref = T.sse_loss(y_ref, tt)
+    for v in each_variant(B.ICL_OP_BANK_FWD_SSE):
+        _, gy, y = T.bank_fwd_sse(xt, wt, tt, want_y=True)
+        assert torch.equal(y, y_ref), f"variant {v}: y"
+        assert torch.equal(gy, gy_ref), f"variant {v}: gy"
+
+
+def test_fused_loss_many_filters_and_empty():
+    N, F, H, W, r = 1, 20, 33, 70, 2          # beyond the persistent kernel's tap table: plain variant
+    x, w, t = inputs(N, F, H, W, r, cfg=78)
+    yr = oracle.bank_fwd(x, w)
+    Lr, _ = oracle.sse_loss(yr, t)
+    L, gy, _ = T.bank_fwd_sse(cu(x), cu(w), cu(t))
+    torch.cuda.synchronize()
+    assert abs(L.item() - Lr) <= loss_bound(yr, t, oracle.bank_fwd(np.abs(x), np.abs(w)), Lr)
+    e = torch.empty((0, 1, 8, 8), dtype=torch.float32, device="cuda")
+    L0, gy0, _ = T.bank_fwd_sse(e, cu(w), torch.empty((0, F, 8, 8), dtype=torch.float32, device="cuda"))
+    assert L0.item() == 0.0 and gy0.numel() == 0
+
+
+def test_loss_function_backward_matches_oracle_chain():
+    """filter_bank_loss(x, w, t).backward(): fused forward, saved gy, the two adjoint kernels."""
+    N, F, H, W, r = 2, 6, 40, 57, 4
+    x, w, t = inputs(N, F, H, W, r, cfg=79)
+    xt = cu(x).requires_grad_(True)
+    wt = cu(w).requires_grad_(True)
+    L = T.filter_bank_loss(xt, wt, cu(t))
+    L.backward()
+    torch.cuda.synchronize()
+    yr = oracle.bank_fwd(x, w)
+    Lr, gyr = oracle.sse_loss(yr, t)
+    ys = oracle.bank_fwd(np.abs(x), np.abs(w))
+    assert abs(L.item() - Lr) <= loss_bound(yr, t, ys, Lr)
+    gxr = oracle.bank_bwd_input(gyr, w)
+    gwr = oracle.bank_bwd_filter(gyr, x, r)
+    sx = oracle.bank_bwd_input(np.abs(gyr), np.abs(w)) + 2 * oracle.bank_bwd_input(ys, np.abs(w))
+    sw = oracle.bank_bwd_filter(np.abs(gyr), np.abs(x), r) + 2 * oracle.bank_bwd_filter(ys, np.abs(x), r)
+    assert rel_normwise(host(xt.grad), gxr, sx) <= 1e-5
+    assert rel_normwise(host(wt.grad), gwr, sw) <= 1e-5
+    # an upstream factor scales both gradients
+    xt.grad = None
+    wt.grad = None
+    (3.0 * T.filter_bank_loss(xt, wt, cu(t))).backward()
+    assert rel_normwise(host(xt.grad), 3 * gxr, 3 * sx) <= 1e-5
+
+
 def test_autograd_function_matches_oracle_chain():
     """loss.backward() through FilterBankFn vs the oracle's forward -> loss -> adjoints (same x, w, t)."""
     N, F, H, W, r = 2, 6, 40, 57, 4
