@@ -367,7 +367,20 @@ def extra_corner(torch, B, T, synth, steps):
                           "harris_variant": B.icl_variant_name(B.ICL_OP_HARRIS, B.icl_selected_variant(
                               B.ICL_OP_HARRIS, B.ICL_F32, 2, W, H)[1]),
                           "corners": int(Ms[0].sum().item())}
-    del xs, Rs, Ms
+    # every Harris variant on the same input (forced), for the record
+    per_variant = {}
+    ws_h = torch.empty(B.icl_workspace_size(B.ICL_OP_HARRIS, W, H)[1] // 4 + 1, dtype=torch.float32, device=dev)
+    for v in range(B.icl_variant_count(B.ICL_OP_HARRIS)):
+        B.check(B.icl_force_variant(B.ICL_OP_HARRIS, v))
+        try:
+            dv = _time(torch, lambda s: T.harris(xs[s % 2], g, 0.04, out=Rs[s % 2], workspace=ws_h), 5)
+            per_variant[B.icl_variant_name(B.ICL_OP_HARRIS, v)] = round(dv * 1e3, 3)
+        except Exception as e:   # a variant that does not take this input
+            per_variant[B.icl_variant_name(B.ICL_OP_HARRIS, v)] = repr(e)[:60]
+        finally:
+            B.icl_force_variant(B.ICL_OP_HARRIS, -1)
+    res["corner_8192"]["harris_variants_ms"] = per_variant
+    del xs, Rs, Ms, ws_h
     torch.cuda.empty_cache()
     return res
 

@@ -17,6 +17,11 @@
 //                   exactly "window reads clamp on the gradient image"), their
 //                   products go to LDS, and the separable window runs as a row pass
 //                   into LDS and a column pass in registers.  8 B/px of HBM.
+//   stream_t{TH}  : one wave per 248-column strip and TH rows, walking down the rows
+//                   with everything in registers (one float4 image load per lane and
+//                   row, neighbour columns by lane shuffles, rings of prefetched image
+//                   rows and of pending output rows); the 64-column left band and the
+//                   right remainder run through the tile kernel.  16-byte aligned rows.
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
 
@@ -96,10 +101,13 @@ template <int RG, int TH> struct HTile {
     static constexpr int LDS_FLOATS = REGION1 + 3 * GH * GW;
 };
 
+// Tile columns come in two bands: the first n0 start at 0 (step TW) and write columns
+// below xl; the rest start at xr (step TW) and write columns below W.  The full image is
+// n0 = tiles_x, xl = W.
 template <int RG, int TH>
 __global__ __launch_bounds__(256) void harris_fused(const float* __restrict__ src, size_t sp, float* __restrict__ resp,
                                                     size_t rp, int W, int H, const float* __restrict__ g, float k,
-                                                    int tiles_x, int vec_ok) {
+                                                    int tiles_x, int n0, int xl, int xr, int vec_ok) {
     using G = HTile<RG, TH>;
     constexpr int TW = G::TW, HX = G::HX, HXA = G::HXA, IW = G::IW, IR = G::IR, GW = G::GW, GH = G::GH,
                   PY = G::PY;
@@ -109,7 +117,9 @@ __global__ __launch_bounds__(256) void harris_fused(const float* __restrict__ sr
     float* abc = lds + G::REGION1;         // [3][GH][GW] products Ix^2, Iy^2, Ix*Iy
     const int tid = threadIdx.x;
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
-    const int x0 = (int)(t % (unsigned)tiles_x) * TW;
+    const int tx = (int)(t % (unsigned)tiles_x);
+    const int x0 = tx < n0 ? tx * TW : xr + (tx - n0) * TW;
+    const int xe = tx < n0 ? xl : W;       // columns this tile may write
     const int y0 = (int)(t / (unsigned)tiles_x) * TH;
 
     // 1. stage image rows y0-HX .. y0+TH+HX-1, columns x0-HXA .. x0+TW+HXA-1 (clamped)
@@ -188,20 +198,201 @@ __global__ __launch_bounds__(256) void harris_fused(const float* __restrict__ sr
             sc = fmaf(w, vc[py + j], sc);
         }
         const int y = y0 + ly * PY + py;
-        if (x < W && y < H)
+        if (x < xe && y < H)
             reinterpret_cast<float*>(reinterpret_cast<char*>(resp) + (size_t)y * rp)[x] = harris_response(sa, sb, sc, k);
     }
 }
 
+// Tile kernel over the bands [0, xl) and [xr, W) (xl = W: the whole image).
 template <int RG, int TH>
-hipError_t launch_fused_R(const HarrisArgs& a) {
+hipError_t launch_fused_bands(const HarrisArgs& a, int xl, int xr) {
     using G = HTile<RG, TH>;
-    const int tiles_x = (a.W + G::TW - 1) / G::TW;
+    const int n0 = (xl + G::TW - 1) / G::TW;
+    const int n1 = xl >= a.W ? 0 : (a.W - xr + G::TW - 1) / G::TW;
+    const int tiles_x = n0 + n1;
     const int tiles_y = (a.H + TH - 1) / TH;
     const int vec_ok = ((uintptr_t)a.src % 16 == 0) && (a.sp % 16 == 0);
     hipLaunchKernelGGL((harris_fused<RG, TH>), dim3(tiles_x * tiles_y), dim3(256), 0, a.st, a.src, a.sp, a.resp, a.rp,
-                       a.W, a.H, a.g, a.k, tiles_x, vec_ok);
+                       a.W, a.H, a.g, a.k, tiles_x, n0, xl, xr, vec_ok);
     return hipGetLastError();
+}
+
+template <int RG, int TH>
+hipError_t launch_fused_R(const HarrisArgs& a) {
+    return launch_fused_bands<RG, TH>(a, a.W, a.W);
+}
+
+// ------------------------------------------------------------------ streaming strips
+// One wave per strip of HS_COLS output columns and TH rows.  Lane l holds the four image
+// columns xs-4+4l .. xs-1+4l; lanes 1..62 own the strip's outputs, lanes 0 and 63 only
+// supply the left and right halo (3 columns suffice: Sobel 1 + window radius <= 3 = 4),
+// so every read of the strip is inside the image and nothing is clamped in x.  The wave
+// walks down the clamped window rows: per row it loads one float4 of the image per lane
+// (prefetched D rows ahead), forms the vertical Sobel parts from the last three image
+// rows, gets the neighbouring columns by lane shuffles, forms the three products and
+// their horizontal window sum, and adds that row into a ring of D = 2r+1 pending output
+// rows; the oldest completes and is written each step.  No LDS tile, no barrier.
+constexpr int HS_COLS = 248;   // output columns per strip (62 lanes x 4)
+constexpr int HS_XL = 64;      // left border band, done by the tile kernel
+
+template <int RG>
+__device__ __forceinline__ v4f hwin(v4f p, const float (&gw)[2 * RG + 1]) {
+    float e[4 + 2 * RG];
+#pragma unroll
+    for (int i = 0; i < RG; ++i) e[i] = __shfl_up(p[4 - RG + i], 1);
+    e[RG] = p.x; e[RG + 1] = p.y; e[RG + 2] = p.z; e[RG + 3] = p.w;
+#pragma unroll
+    for (int i = 0; i < RG; ++i) e[RG + 4 + i] = __shfl_down(p[i], 1);
+    float o[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t <= 2 * RG; ++t) acc = fmaf(gw[t], e[q + t], acc);
+        o[q] = acc;
+    }
+    return mk4(o[0], o[1], o[2], o[3]);
+}
+
+// Products of one window row: Sobel from image rows ra (above), rb, rc (below), neighbour
+// columns by lane shuffles, then the horizontal window of each product.
+template <int RG>
+__device__ __forceinline__ void window_row(const v4f ra, const v4f rb, const v4f rc, const float (&gw)[2 * RG + 1],
+                                           v4f& qa, v4f& qb, v4f& qc) {
+    const v4f vs = ra + 2.f * rb + rc;   // vertical smoothing (for Ix)
+    const v4f vd = rc - ra;              // vertical difference (for Iy)
+    const float vsl = __shfl_up(vs.w, 1), vsr = __shfl_down(vs.x, 1);
+    const float vdl = __shfl_up(vd.w, 1), vdr = __shfl_down(vd.x, 1);
+    const v4f ix = mk4(vs.y - vsl, vs.z - vs.x, vs.w - vs.y, vsr - vs.z);
+    const v4f iy = mk4(vdl + 2.f * vd.x + vd.y, vd.x + 2.f * vd.y + vd.z, vd.y + 2.f * vd.z + vd.w,
+                       vd.z + 2.f * vd.w + vdr);
+    qa = hwin<RG>(ix * ix, gw);
+    qb = hwin<RG>(iy * iy, gw);
+    qc = hwin<RG>(ix * iy, gw);
+}
+
+constexpr int hs_gcd(int a, int b) { return b == 0 ? a : hs_gcd(b, a % b); }
+
+template <int RG, int TH>
+__global__ __launch_bounds__(64) void harris_stream(const float* __restrict__ src, size_t sp, float* __restrict__ resp,
+                                                    size_t rp, int H, const float* __restrict__ g, float k,
+                                                    int nstrips) {
+    constexpr int NW = 2 * RG + 1;   // window taps = length of the ring of pending output rows
+    constexpr int K = TH + 2 * RG;   // window rows walked per strip
+    constexpr int D = NW;
+    const int lane = threadIdx.x;
+    const int strip = (int)(blockIdx.x % (unsigned)nstrips);
+    const int y0 = (int)(blockIdx.x / (unsigned)nstrips) * TH;
+    const int c = HS_XL + strip * HS_COLS - 4 + 4 * lane;
+    const char* col = reinterpret_cast<const char*>(src) + (size_t)c * 4;
+    auto image_row = [&](int y) { return *reinterpret_cast<const v4f*>(col + (size_t)y * sp); };
+    float gw[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) gw[j] = g[j];
+    v4f acc[D][3];
+#pragma unroll
+    for (int u = 0; u < D; ++u) acc[u][0] = acc[u][1] = acc[u][2] = mk4(0.f, 0.f, 0.f, 0.f);
+    const bool writer = lane >= 1 && lane <= 62;
+    char* out_col = reinterpret_cast<char*>(resp) + (size_t)c * 4;
+
+    // window row kk (phase u = kk mod D of the ring) feeds output rows kk - j; output row
+    // kk - 2r is then complete and is written
+    auto accumulate_emit = [&](int kk, auto u_c, v4f qa, v4f qb, v4f qc) {
+        constexpr int u = decltype(u_c)::value;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const int m = kk - j;
+            if (m < 0 || m >= TH) continue;
+            const int slot = ((u - j) % D + D) % D;
+            acc[slot][0] += gw[j] * qa;
+            acc[slot][1] += gw[j] * qb;
+            acc[slot][2] += gw[j] * qc;
+        }
+        if (kk >= 2 * RG) {
+            constexpr int slot = ((u - 2 * RG) % D + D) % D;
+            const int y = y0 + kk - 2 * RG;
+            const v4f sa = acc[slot][0], sb = acc[slot][1], sc = acc[slot][2];
+            if (writer && y < H)
+                *reinterpret_cast<v4f*>(out_col + (size_t)y * rp) =
+                    mk4(harris_response(sa.x, sb.x, sc.x, k), harris_response(sa.y, sb.y, sc.y, k),
+                        harris_response(sa.z, sb.z, sc.z, k), harris_response(sa.w, sb.w, sc.w, k));
+            acc[slot][0] = acc[slot][1] = acc[slot][2] = mk4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+
+    if (y0 - RG - 1 >= 0 && y0 + TH + RG <= H - 1) {
+        // interior row block: window row kk is gradient row y0 - r + kk, whose Sobel reads
+        // image rows y0 - r - 1 + kk + {0, 1, 2}; those come from a ring of M image rows
+        // (image row i of the block in slot i mod M), each loaded M - 2 steps before use
+        constexpr int M = D >= 5 ? D : (D == 3 ? 6 : 5);
+        constexpr int U = D * M / hs_gcd(D, M);   // unroll: both rings' slots are constants
+        const int ybase = y0 - RG - 1;
+        v4f img[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) img[i] = image_row(ybase + i);
+        for (int kb = 0; kb < K; kb += U) {
+            static_for<U>([&](auto u_c) {
+                constexpr int u = decltype(u_c)::value;
+                const int kk = kb + u;
+                if (kk >= K) return;
+                v4f qa, qb, qc;
+                window_row<RG>(img[u % M], img[(u + 1) % M], img[(u + 2) % M], gw, qa, qb, qc);
+                if (kk + M <= K + 1) img[u % M] = image_row(ybase + kk + M);
+                accumulate_emit(kk, std::integral_constant<int, u % D>{}, qa, qb, qc);
+            });
+        }
+        return;
+    }
+
+    // row block at the top or bottom edge: window rows clamp to the gradient image, so a
+    // repeated gradient row reuses the last products and the image rows around gradient row
+    // g are clamp(g - 1), g, clamp(g + 1)
+    auto wrow = [&](int kk) { return clampi(y0 - RG + kk, H); };
+    const int g0 = wrow(0);
+    v4f ra = image_row(clampi(g0 - 1, H)), rb = image_row(g0), rc = image_row(clampi(g0 + 1, H));
+    v4f qa, qb, qc;
+    window_row<RG>(ra, rb, rc, gw, qa, qb, qc);
+    for (int kb = 0; kb < K; kb += D) {
+        static_for<D>([&](auto u_c) {
+            constexpr int u = decltype(u_c)::value;
+            const int kk = kb + u;
+            if (kk >= K) return;
+            if (kk > 0 && wrow(kk) != wrow(kk - 1)) {
+                ra = rb;
+                rb = rc;
+                rc = image_row(clampi(wrow(kk) + 1, H));
+                window_row<RG>(ra, rb, rc, gw, qa, qb, qc);
+            }
+            accumulate_emit(kk, u_c, qa, qb, qc);
+        });
+    }
+}
+
+bool supports_stream(const HarrisArgs& a) {
+    return a.rg >= 0 && a.rg <= 3 && a.W >= HS_XL + HS_COLS + 4 && (uintptr_t)a.src % 16 == 0 && a.sp % 16 == 0 &&
+           (uintptr_t)a.resp % 16 == 0 && a.rp % 16 == 0;
+}
+
+template <int RG, int TH>
+hipError_t launch_stream_R(const HarrisArgs& a) {
+    const int nstrips = (a.W - HS_XL - 4) / HS_COLS;
+    const int xr = HS_XL + nstrips * HS_COLS;
+    const int rows = (a.H + TH - 1) / TH;
+    hipLaunchKernelGGL((harris_stream<RG, TH>), dim3((unsigned)(nstrips * rows)), dim3(64), 0, a.st, a.src, a.sp,
+                       a.resp, a.rp, a.H, a.g, a.k, nstrips);
+    // the two border bands with the tile kernel
+    return launch_fused_bands<RG, 16>(a, HS_XL, xr);
+}
+
+template <int TH>
+hipError_t launch_stream(const HarrisArgs& a) {
+    switch (a.rg) {
+        case 0: return launch_stream_R<0, TH>(a);
+        case 1: return launch_stream_R<1, TH>(a);
+        case 2: return launch_stream_R<2, TH>(a);
+        case 3: return launch_stream_R<3, TH>(a);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int TH>
@@ -222,6 +413,9 @@ const Variant<HarrisArgs> kHarris[] = {
     {"fused_t16", supports_fused, launch_fused<16>},
     {"fused_t32", supports_fused, launch_fused<32>},
     {"fused_t8", supports_fused, launch_fused<8>},
+    {"stream_t64", supports_stream, launch_stream<64>},
+    {"stream_t32", supports_stream, launch_stream<32>},
+    {"stream_t128", supports_stream, launch_stream<128>},
 };
 
 }  // namespace
@@ -233,6 +427,7 @@ const Variant<HarrisArgs>* harris_variants(int* count) {
     return kHarris;
 }
 
-int harris_default(const HarrisArgs& a) { return supports_fused(a) ? 1 : 0; }
+// strip variant with 32-row blocks where the rows allow it, else the 64 x 16 tile kernel
+int harris_default(const HarrisArgs& a) { return supports_stream(a) ? 5 : supports_fused(a) ? 1 : 0; }
 
 }  // namespace icl

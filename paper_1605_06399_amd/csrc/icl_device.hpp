@@ -1,10 +1,23 @@
 // Device-side helpers shared by the gfx950 stencil kernels: storage decode /
 // encode, clamped indexing and work-group ordering.
 #pragma once
+#include <type_traits>
+#include <utility>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace icl {
+
+// Calls f(std::integral_constant<int, 0>{}) ... f(integral_constant<int, N-1>{}): a loop whose
+// index is a compile-time constant in the body (static register-ring slots).
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 // Native 4 x float32 vector: loads and stores of it lower to single dwordx4 /
 // ds_read_b128 instructions (HIP's float4 struct is copied member by member).

@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 from conftest import gpu_available
-from helpers import normwise, padded_view, storage, to_host
+from helpers import empty_padded, normwise, padded_view, storage, to_host
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
@@ -31,7 +31,31 @@ def harris_ws(H, W):
     return torch.empty(nb // 4 + 1, dtype=torch.float32, device="cuda")
 
 
-@pytest.mark.parametrize("variant", range(4))
+def _nvariants(op, default):
+    try:
+        return B.icl_variant_count(op)
+    except Exception:
+        return default
+
+
+N_HARRIS = _nvariants(B.ICL_OP_HARRIS, 7)
+STREAM_MIN_W = 64 + 248 + 4     # the strip variants need one strip between the two border bands
+
+
+def runs(variant, W):
+    """Whether a forced variant accepts a dense W-wide image: the strip variants need
+    W >= STREAM_MIN_W and 16-byte aligned rows (W a multiple of 4 here)."""
+    return not B.icl_variant_name(B.ICL_OP_HARRIS, variant).startswith("stream") or (
+        W >= STREAM_MIN_W and W % 4 == 0)
+
+
+# small and degenerate images, several strips with a ragged right band and ragged row
+# blocks, fewer rows than a row block, one row, and the narrowest width the strips take
+HARRIS_SHAPES = [(389, 517), (1, 1), (2, 3), (5, 4), (1, 90), (90, 1), (64, 64), (17, 130),
+                 (133, 1100), (5, 700), (1, 640), (300, STREAM_MIN_W), (70, STREAM_MIN_W + 4)]
+
+
+@pytest.mark.parametrize("variant", range(N_HARRIS))
 @pytest.mark.parametrize("rg", [0, 1, 2, 3])
 def test_harris_variants(variant, rg):
     if variant >= B.icl_variant_count(B.ICL_OP_HARRIS):
@@ -39,7 +63,9 @@ def test_harris_variants(variant, rg):
     B.check(B.icl_force_variant(B.ICL_OP_HARRIS, variant))
     try:
         g = g_taps(rg)
-        for (H, W) in [(389, 517), (1, 1), (2, 3), (5, 4), (1, 90), (90, 1), (64, 64), (17, 130)]:
+        for (H, W) in HARRIS_SHAPES:
+            if not runs(variant, W):
+                continue
             img = synth.image_with_rectangles(49, H, W, count=6) if H > 16 else synth.image_uniform(49, H, W)
             xd, x64 = storage(img, "f32")
             R = T.harris(xd, dev(g), float(K), workspace=harris_ws(H, W))
@@ -62,14 +88,14 @@ def test_harris_large_window_uses_split_path():
     assert normwise(to_host(R), Rr, oracle.harris_scale(x64, g, float(K))) <= 1e-5
 
 
-@pytest.mark.parametrize("variant", range(4))
+@pytest.mark.parametrize("variant", range(N_HARRIS))
 def test_harris_closed_forms_on_gpu(variant):
     if variant >= B.icl_variant_count(B.ICL_OP_HARRIS):
         pytest.skip("no such variant")
     B.check(B.icl_force_variant(B.ICL_OP_HARRIS, variant))
     try:
         g = synth.gaussian_taps(2, 1.0)
-        H, W = 70, 90
+        H, W = 70, 90 if runs(variant, 90) else STREAM_MIN_W + 12
         # constant image: every gradient is exactly zero, so R is exactly zero
         R = T.harris(torch.full((H, W), 0.3, device="cuda"), dev(g), float(K), workspace=harris_ws(H, W))
         assert torch.count_nonzero(R).item() == 0
@@ -81,6 +107,45 @@ def test_harris_closed_forms_on_gpu(variant):
         assert np.allclose(R[3:-3, 3:-3], expect, rtol=2e-6)
     finally:
         B.icl_force_variant(B.ICL_OP_HARRIS, -1)
+
+
+def test_harris_strip_variants_refuse_unaligned_rows():
+    """A forced strip variant needs 16-byte aligned rows; automatic selection falls back."""
+    H, W = 40, 600
+    img = synth.image_uniform(53, H, W)
+    xd, x64 = storage(img, "f32")
+    xv = padded_view(xd, 3, 1)
+    g = synth.gaussian_taps(2, 1.0)
+    ref = oracle.harris(x64, g, float(K))
+    for v in range(B.icl_variant_count(B.ICL_OP_HARRIS)):
+        if not B.icl_variant_name(B.ICL_OP_HARRIS, v).startswith("stream"):
+            continue
+        B.check(B.icl_force_variant(B.ICL_OP_HARRIS, v))
+        try:
+            with pytest.raises(B.IclError):
+                T.harris(xv, dev(g), float(K))
+        finally:
+            B.icl_force_variant(B.ICL_OP_HARRIS, -1)
+    R = T.harris(xv, dev(g), float(K))
+    torch.cuda.synchronize()
+    assert normwise(to_host(R), ref, oracle.harris_scale(x64, g, float(K))) <= 1e-5
+    # an odd width in rows padded to a 16-byte pitch: the strips take it
+    H, W = 45, 517
+    img = synth.image_with_rectangles(54, H, W, count=5)
+    xd, x64 = storage(img, "f32")
+    xv = padded_view(xd, 3, 0)
+    out = empty_padded(H, W, torch.float32, 7, 0)
+    ref, sc = oracle.harris(x64, g, float(K)), oracle.harris_scale(x64, g, float(K))
+    for v in range(B.icl_variant_count(B.ICL_OP_HARRIS)):
+        if not B.icl_variant_name(B.ICL_OP_HARRIS, v).startswith("stream"):
+            continue
+        B.check(B.icl_force_variant(B.ICL_OP_HARRIS, v))
+        try:
+            R = T.harris(xv, dev(g), float(K), out=out)
+            torch.cuda.synchronize()
+            assert normwise(to_host(R), ref, sc) <= 1e-5, f"variant {v} padded pitch"
+        finally:
+            B.icl_force_variant(B.ICL_OP_HARRIS, -1)
 
 
 def quantised_response(H, W, seed):
