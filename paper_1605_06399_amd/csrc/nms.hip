@@ -15,6 +15,9 @@
 //   row4       : one lane per 4 consecutive pixels of a row (r = 1): three aligned
 //                float4 row loads plus the two flanking pixels, one 32-bit store of
 //                four mask bytes; clamps only on edge lanes.
+//   stream_t{TH}: one wave per 248-column strip and TH rows (r = 1): every response row
+//                loaded once, the 3 x 3 neighbourhood from registers and lane shuffles;
+//                the border bands run through row4.  16-byte aligned response rows.
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
 
@@ -56,11 +59,16 @@ __device__ __forceinline__ void row6(const float* __restrict__ row, int x, int W
     }
 }
 
+// Column groups come in two bands: the first n0 groups start at column 0 and write columns
+// below xl, the rest start at xr and write columns below W (the whole image: n0 = all, xl = W).
 __global__ __launch_bounds__(256) void nms_row4(const float* __restrict__ R, size_t rp, uint8_t* __restrict__ M,
-                                                size_t mp, int W, int H, float tau, int groups_x, int vec_ok) {
+                                                size_t mp, int W, int H, float tau, int groups_x, int n0, int xl,
+                                                int xr, int vec_ok) {
     const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
     const int y = (int)(gid / groups_x);
-    const int x = (int)(gid - (long long)y * groups_x) * 4;
+    const int gx = (int)(gid - (long long)y * groups_x);
+    const int x = gx < n0 ? 4 * gx : xr + 4 * (gx - n0);
+    const int xe = gx < n0 ? xl : W;
     if (y >= H) return;
     const bool interior = vec_ok && x >= 1 && x + 5 <= W;
     float a[6], b[6], c[6];
@@ -77,27 +85,118 @@ __global__ __launch_bounds__(256) void nms_row4(const float* __restrict__ R, siz
         bits |= (keep ? 1u : 0u) << (8 * p);
     }
     uint8_t* out = M + (size_t)y * mp + x;
-    if (vec_ok && x + 4 <= W) {
+    if (vec_ok && x + 4 <= xe) {
         *reinterpret_cast<uint32_t*>(out) = bits;
     } else {
-        for (int p = 0; p < 4 && x + p < W; ++p) out[p] = (uint8_t)((bits >> (8 * p)) & 1u);
+        for (int p = 0; p < 4 && x + p < xe; ++p) out[p] = (uint8_t)((bits >> (8 * p)) & 1u);
     }
 }
 
-hipError_t launch_row4(const NmsArgs& a) {
-    const int groups_x = (a.W + 3) / 4;
+// Row kernel over the bands [0, xl) and [xr, W) (xl = W: the whole image).
+hipError_t launch_row4_bands(const NmsArgs& a, int xl, int xr) {
+    const int n0 = (xl + 3) / 4;
+    const int n1 = xl >= a.W ? 0 : (a.W - xr + 3) / 4;
+    const int groups_x = n0 + n1;
     const long long n = (long long)groups_x * a.H;
     const int vec_ok = ((uintptr_t)a.R % 16 == 0) && (a.rp % 16 == 0) && ((uintptr_t)a.M % 4 == 0) && (a.mp % 4 == 0);
     hipLaunchKernelGGL(nms_row4, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, a.st, a.R, a.rp, a.M, a.mp, a.W, a.H,
-                       a.tau, groups_x, vec_ok);
+                       a.tau, groups_x, n0, xl, xr, vec_ok);
     return hipGetLastError();
 }
 
+hipError_t launch_row4(const NmsArgs& a) { return launch_row4_bands(a, a.W, a.W); }
+
 bool supports_row4(const NmsArgs& a) { return a.r == 1; }
+
+// ------------------------------------------------------------------ strips, r = 1
+// One wave per strip of NS_COLS columns and TH rows: lane l holds the four columns
+// xs-4+4l .. xs-1+4l of the response rows, lanes 1..62 own the outputs and lanes 0 and 63
+// only supply the neighbouring column, so no read of a strip is clamped in x.  The wave
+// walks down the rows holding the rows above, at and below the output row in registers
+// (each row loaded once, prefetched through a ring), gets the left and right neighbours by
+// lane shuffles and writes the four mask bytes of a lane as one 32-bit store.  The left
+// 64 columns and the right remainder run through the row kernel.
+constexpr int NS_COLS = 248;
+constexpr int NS_XL = 64;
+
+__device__ __forceinline__ uint32_t nms_bits(v4f a, v4f b, v4f c, float tau) {
+    const float al = __shfl_up(a.w, 1), ar = __shfl_down(a.x, 1);
+    const float bl = __shfl_up(b.w, 1), br = __shfl_down(b.x, 1);
+    const float cl = __shfl_up(c.w, 1), cr = __shfl_down(c.x, 1);
+    const float ea[6] = {al, a.x, a.y, a.z, a.w, ar};
+    const float eb[6] = {bl, b.x, b.y, b.z, b.w, br};
+    const float ec[6] = {cl, c.x, c.y, c.z, c.w, cr};
+    uint32_t bits = 0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const float v = eb[p + 1];
+        const bool keep = v > tau && v >= ea[p] && v >= ea[p + 1] && v >= ea[p + 2] && v >= eb[p] && v >= eb[p + 2] &&
+                          v >= ec[p] && v >= ec[p + 1] && v >= ec[p + 2];
+        bits |= (keep ? 1u : 0u) << (8 * p);
+    }
+    return bits;
+}
+
+template <int TH>
+__global__ __launch_bounds__(64) void nms_stream(const float* __restrict__ R, size_t rp, uint8_t* __restrict__ M,
+                                                 size_t mp, int H, float tau, int nstrips) {
+    const int lane = threadIdx.x;
+    const int strip = (int)(blockIdx.x % (unsigned)nstrips);
+    const int y0 = (int)(blockIdx.x / (unsigned)nstrips) * TH;
+    const int c = NS_XL + strip * NS_COLS - 4 + 4 * lane;
+    const char* col = reinterpret_cast<const char*>(R) + (size_t)c * 4;
+    auto row = [&](int y) { return *reinterpret_cast<const v4f*>(col + (size_t)y * rp); };
+    const bool writer = lane >= 1 && lane <= 62;
+    uint8_t* out_col = M + c;
+    if (y0 >= 1 && y0 + TH <= H - 1) {
+        // interior: output row m reads rows y0 - 1 + m + {0, 1, 2}, from a ring of RING rows
+        // (row i of the block in slot i mod RING), each loaded RING - 2 rows before use
+        constexpr int RING = 8;
+        const int ybase = y0 - 1;
+        v4f ring[RING];
+#pragma unroll
+        for (int i = 0; i < RING; ++i) ring[i] = row(ybase + i);
+        for (int mb = 0; mb < TH; mb += RING) {
+            static_for<RING>([&](auto u_c) {
+                constexpr int u = decltype(u_c)::value;
+                const int m = mb + u;
+                if (m >= TH) return;
+                const uint32_t bits = nms_bits(ring[u], ring[(u + 1) % RING], ring[(u + 2) % RING], tau);
+                if (m + RING <= TH + 1) ring[u] = row(ybase + m + RING);
+                if (writer) *reinterpret_cast<uint32_t*>(out_col + (size_t)(y0 + m) * mp) = bits;
+            });
+        }
+        return;
+    }
+    // top or bottom block: rows clamp at the image edge
+    for (int m = 0; m < TH; ++m) {
+        const int y = y0 + m;
+        if (y >= H) break;
+        const uint32_t bits = nms_bits(row(clampi(y - 1, H)), row(y), row(clampi(y + 1, H)), tau);
+        if (writer) *reinterpret_cast<uint32_t*>(out_col + (size_t)y * mp) = bits;
+    }
+}
+
+bool supports_stream(const NmsArgs& a) {
+    return a.r == 1 && a.W >= NS_XL + NS_COLS + 4 && (uintptr_t)a.R % 16 == 0 && a.rp % 16 == 0 &&
+           (uintptr_t)a.M % 4 == 0 && a.mp % 4 == 0;
+}
+
+template <int TH>
+hipError_t launch_stream(const NmsArgs& a) {
+    const int nstrips = (a.W - NS_XL - 4) / NS_COLS;
+    const int xr = NS_XL + nstrips * NS_COLS;
+    const int rows = (a.H + TH - 1) / TH;
+    hipLaunchKernelGGL(nms_stream<TH>, dim3((unsigned)(nstrips * rows)), dim3(64), 0, a.st, a.R, a.rp, a.M, a.mp, a.H,
+                       a.tau, nstrips);
+    return launch_row4_bands(a, NS_XL, xr);
+}
 
 const Variant<NmsArgs> kNms[] = {
     {"plain", supports_plain, launch_plain},
     {"row4", supports_row4, launch_row4},
+    {"stream_t64", supports_stream, launch_stream<64>},
+    {"stream_t128", supports_stream, launch_stream<128>},
 };
 
 }  // namespace
@@ -107,6 +206,6 @@ const Variant<NmsArgs>* nms_variants(int* count) {
     return kNms;
 }
 
-int nms_default(const NmsArgs& a) { return supports_row4(a) ? 1 : 0; }
+int nms_default(const NmsArgs& a) { return supports_stream(a) ? 2 : supports_row4(a) ? 1 : 0; }
 
 }  // namespace icl

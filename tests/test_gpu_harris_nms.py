@@ -156,35 +156,57 @@ def quantised_response(H, W, seed):
     return q
 
 
-@pytest.mark.parametrize("variant", range(2))
+N_NMS = _nvariants(B.ICL_OP_NMS, 4)
+
+
+def nms_runs(variant, radius, W, aligned=True):
+    """Whether a forced NMS variant takes the input: row4 needs r = 1; the strip variants need
+    r = 1, W >= STREAM_MIN_W and 16-byte aligned response rows (dense: W a multiple of 4)."""
+    name = B.icl_variant_name(B.ICL_OP_NMS, variant)
+    if name == "row4":
+        return radius == 1
+    if name.startswith("stream"):
+        return radius == 1 and W >= STREAM_MIN_W and aligned
+    return True
+
+
+NMS_SHAPES = [(257, 389), (1, 1), (1, 9), (9, 1), (4, 4), (63, 65),
+              (133, 1100), (5, 700), (1, 640), (300, STREAM_MIN_W), (70, STREAM_MIN_W + 4), (129, 2000)]
+
+
+@pytest.mark.parametrize("variant", range(N_NMS))
 @pytest.mark.parametrize("radius", [1, 2])
 def test_nms_bit_exact(variant, radius):
     if variant >= B.icl_variant_count(B.ICL_OP_NMS):
         pytest.skip("no such variant")
     B.check(B.icl_force_variant(B.ICL_OP_NMS, variant))
     try:
-        for (H, W) in [(257, 389), (1, 1), (1, 9), (9, 1), (4, 4), (63, 65)]:
+        for (H, W) in NMS_SHAPES:
             R = quantised_response(H, W, 51)
             Rd = dev(R)
             st = B.icl_nms(Rd.data_ptr(), W * 4, 0, 0, W, H, radius, float(TAU), 0)   # null mask is rejected
             assert st == B.ICL_ERR_INVALID_VALUE
-            if variant == 1 and radius != 1:
-                assert B.icl_selected_variant(B.ICL_OP_NMS, B.ICL_F32, radius, W, H)[1] == 1
-                with pytest.raises(B.IclError):
+            if not nms_runs(variant, radius, W, W % 4 == 0):
+                with pytest.raises(B.IclError):      # a forced variant never falls back silently
                     T.nms(Rd, float(TAU), radius)
                 continue
             M = T.nms(Rd, float(TAU), radius)
             torch.cuda.synchronize()
             ref = oracle.nms(R, float(TAU), radius)
             assert np.array_equal(M.cpu().numpy(), ref), f"nms v{variant} r{radius} {H}x{W}"
-        if variant == 1 and radius != 1:
-            return
-        # padded / misaligned views take the scalar edges
-        R = quantised_response(70, 133, 52)
-        Rv = padded_view(dev(R), 7, 1)
-        out = torch.zeros((70, 140), dtype=torch.uint8, device="cuda")[:, 3:136]
-        M = T.nms(Rv, float(TAU), radius, out=out)
-        assert np.array_equal(M.cpu().numpy(), oracle.nms(R, float(TAU), radius))
+        # padded / misaligned views take the scalar edges (the strips refuse misaligned rows)
+        for (H, W, pad, off, mpad, moff) in [(70, 133, 7, 1, 7, 3), (90, 517, 3, 0, 3, 0)]:
+            R = quantised_response(H, W, 52)
+            Rv = padded_view(dev(R), pad, off)
+            buf = torch.zeros((H + 1) * (W + mpad) + moff + 8, dtype=torch.uint8, device="cuda")
+            out = buf[moff:moff + H * (W + mpad)].view(H, W + mpad)[:, :W]
+            aligned = (W + pad) % 4 == 0 and off % 4 == 0 and (W + mpad) % 4 == 0 and moff % 4 == 0
+            if not nms_runs(variant, radius, W, aligned):
+                with pytest.raises(B.IclError):
+                    T.nms(Rv, float(TAU), radius, out=out)
+                continue
+            M = T.nms(Rv, float(TAU), radius, out=out)
+            assert np.array_equal(M.cpu().numpy(), oracle.nms(R, float(TAU), radius)), f"padded {H}x{W}"
     finally:
         B.icl_force_variant(B.ICL_OP_NMS, -1)
 
