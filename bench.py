@@ -405,12 +405,23 @@ def extra_batch(torch, B, T, synth, steps):
             outs.append(pitched(it.height, it.width, tdt))
         taps = [torch.from_numpy(it.taps).to(dev) for it in items]
         plan = T.BatchPlan(ims, outs, taps)
-        plan.graph()
+        per_variant = {}
+        for v in range(B.icl_variant_count(B.ICL_OP_CONV_SEP_BATCHED)):   # plain launches, forced
+            B.check(B.icl_force_variant(B.ICL_OP_CONV_SEP_BATCHED, v))
+            try:
+                per_variant[B.icl_variant_name(B.ICL_OP_CONV_SEP_BATCHED, v)] = round(
+                    _time(torch, lambda s: plan.launch(), steps) * 1e3, 3)
+            finally:
+                B.icl_force_variant(B.ICL_OP_CONV_SEP_BATCHED, -1)
+        plan.graph()   # the default variant, captured once and replayed
         dt = _time(torch, lambda s: plan.replay(), steps)
         gpx = plan.pixels / dt / 1e9
         res[f"batch256_{name}"] = {"ms": round(dt * 1e3, 3), "gpx_s": round(gpx, 1), "pixels": plan.pixels,
                                    "tiles": plan.tiles, "bytes_per_px": 4,
-                                   "hbm_frac": round(gpx * 4 / HBM_PEAK_GBS, 3)}
+                                   "hbm_frac": round(gpx * 4 / HBM_PEAK_GBS, 3),
+                                   "variant": B.icl_variant_name(B.ICL_OP_CONV_SEP_BATCHED, B.icl_selected_variant(
+                                       B.ICL_OP_CONV_SEP_BATCHED, B.ICL_F16, 0, 0, 0)[1]),
+                                   "variants_ms": per_variant}
         plan.close()
         del ims, outs
     torch.cuda.empty_cache()
@@ -489,28 +500,30 @@ def extra_bank(torch, B, T, synth, steps):
     return res
 
 
-def cpu_baseline(synth, radii, side):
-    """The FP64 oracle, as it stands, on the same step: all ten calls over the full image
-    (median of three runs, rows split over the host threads)."""
+def cpu_baseline(synth, radii, side, min_seconds=10.0):
+    """The FP64 oracle, as it stands, on the same step: all ten calls over the full image, rows
+    split over the host threads, repeated until at least `min_seconds` (and 3 steps) have run."""
     from oracle import oracle
     rows = int(os.environ.get("ICL_CPU_SAMPLE_ROWS", str(side)))
     threads = min(os.cpu_count() or 1, 16)
     img = synth.sweep_image(side)[:rows].astype(np.float64)
     taps = [(synth.sweep_taps_sep(r), synth.sweep_taps_2d(r)) for r in radii]
     times = []
-    for _ in range(3):
+    while len(times) < 3 or sum(times) < min_seconds:
         t0 = time.perf_counter()
         for (h, v), w in taps:
             oracle.conv_sep(img, h, v, nthreads=threads)
             oracle.conv2d(img, w, nthreads=threads)
         times.append(time.perf_counter() - t0)
-        print(f"[bench] cpu oracle step {times[-1]:.2f} s", file=sys.stderr, flush=True)
-    dt = sorted(times)[1]
+        if len(times) % 5 == 1:
+            print(f"[bench] cpu oracle step {len(times)}: {times[-1]:.2f} s", file=sys.stderr, flush=True)
+    total = sum(times)
     px = rows * side * len(radii) * 2
     what = "the full step" if rows == side else f"rows 0..{rows - 1} of every call (a {rows}x{side} strip)"
-    return {"value": round(px / dt / 1e9, 5), "unit": "Gpixel/s", "cores": threads, "kind": "oracle",
-            "sample": f"{what}: {2 * len(radii)} calls on the {side}x{side} sweep image, "
-                      f"median of 3 runs, {dt:.2f} s per step"}
+    return {"value": round(len(times) * px / total / 1e9, 5), "unit": "Gpixel/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{what}: {2 * len(radii)} calls on the {side}x{side} sweep image, {len(times)} steps "
+                      f"in {total:.1f} s ({sorted(times)[len(times) // 2]:.2f} s median per step)"}
 
 
 if __name__ == "__main__":

@@ -6,6 +6,14 @@
 // instantiated per radius and picked by a wave-uniform branch on the image's
 // radius.  Launch arguments are only the two tables, so the launch captures into
 // a HIP graph as one kernel node and replays re-read images and taps.
+//
+// Variants
+//   persistent_fused_t64 : the tile walk above (64x64 output tiles, LDS passes).
+//   persistent_strip_t32 : a persistent grid of single waves walking a table of
+//                          (image, strip, 32-row block) items with the register-
+//                          streaming body of the per-image strip variant; the items
+//                          are sorted by radius, so the waves resident at a time mostly
+//                          run the same radius body.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +22,7 @@
 
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
+#include "sep_strip.hpp"
 #include "sep_tile.hpp"
 #include "tile_stage.hpp"
 
@@ -30,6 +39,10 @@ struct DevImage {
 
 struct BatchTile {
     int img, x0, y0, pad;
+};
+
+struct StripItem {
+    int img, xs, y0, r;
 };
 
 namespace {
@@ -100,6 +113,51 @@ __global__ __launch_bounds__(256) void sep_batched_k(const DevImage* __restrict_
     }
 }
 
+constexpr int STH = 32;   // rows per strip item
+
+// Persistent strip walk: wave i takes items i, i + grid, ...
+template <class T>
+__global__ __launch_bounds__(64) void sep_batched_strip_k(const DevImage* __restrict__ imgs,
+                                                          const StripItem* __restrict__ items, int nitems) {
+    for (int i = (int)blockIdx.x; i < nitems; i += (int)gridDim.x) {
+        const StripItem it = items[i];
+        const DevImage d = imgs[it.img];
+        switch (it.r) {
+#define ICL_STRIP_CASE(R)                                                                                   \
+    case R:                                                                                                 \
+        sep_strip_body<T, R, STH>(d.src, d.sp, d.dst, d.dp, d.W, d.H, d.tx, d.ty, it.xs, it.y0, d.vec_ok != 0, \
+                                  d.vec_out != 0);                                                          \
+        break;
+            ICL_STRIP_CASE(0)
+            ICL_STRIP_CASE(1)
+            ICL_STRIP_CASE(2)
+            ICL_STRIP_CASE(3)
+            ICL_STRIP_CASE(4)
+            ICL_STRIP_CASE(5)
+            ICL_STRIP_CASE(6)
+            ICL_STRIP_CASE(7)
+#undef ICL_STRIP_CASE
+            default: break;
+        }
+    }
+}
+
+}  // namespace
+
+// the tile walk: on the 256-image workload the strip walk's waves hold too many registers
+// (two waves per SIMD) and it runs at about half the tile walk's rate
+int batched_default() { return 0; }
+
+namespace {
+
+int strip_width(int r) {
+    switch (r) {
+        case 0: return StripGeom<0>::SW;
+        case 1: case 2: case 3: case 4: return StripGeom<4>::SW;
+        default: return StripGeom<7>::SW;
+    }
+}
+
 }  // namespace
 }  // namespace icl
 
@@ -109,8 +167,11 @@ struct icl_batch_plan {
     icl_dtype dt;
     DevImage* d_imgs;
     BatchTile* d_tiles;
+    StripItem* d_items;
     int ntiles;
     int grid;
+    int nitems;
+    int strip_grid;
     long long pixels;
 };
 
@@ -129,6 +190,14 @@ const void* kernel_for(icl_dtype dt) {
     }
 }
 
+const void* strip_kernel_for(icl_dtype dt) {
+    switch (dt) {
+        case ICL_F32: return reinterpret_cast<const void*>(&sep_batched_strip_k<F32>);
+        case ICL_F16: return reinterpret_cast<const void*>(&sep_batched_strip_k<F16>);
+        default: return reinterpret_cast<const void*>(&sep_batched_strip_k<BF16>);
+    }
+}
+
 bool ranges_overlap(uintptr_t a0, uintptr_t a1, uintptr_t b0, uintptr_t b1) { return a0 < b1 && b0 < a1; }
 
 }  // namespace
@@ -143,6 +212,7 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
     const int es = elem_size(dtype);
     std::vector<DevImage> imgs;
     std::vector<BatchTile> tiles;
+    std::vector<StripItem> items;
     long long pixels = 0;
     const size_t al = 4 * (size_t)es;
     for (int i = 0; i < count; ++i) {
@@ -171,7 +241,14 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
         const int tx = (d.width + 64 * BCX - 1) / (64 * BCX), ty = (d.height + BTH - 1) / BTH;
         for (int y = 0; y < ty; ++y)
             for (int x = 0; x < tx; ++x) tiles.push_back(BatchTile{i, x * 64 * BCX, y * BTH, 0});
+        const int sw = strip_width(d.radius);
+        const int sx = (d.width + sw - 1) / sw, sy = (d.height + STH - 1) / STH;
+        for (int y = 0; y < sy; ++y)
+            for (int x = 0; x < sx; ++x) items.push_back(StripItem{i, x * sw, y * STH, d.radius});
     }
+    // largest radius first (longest items first), then image, row, strip
+    std::stable_sort(items.begin(), items.end(),
+                     [](const StripItem& a, const StripItem& b) { return a.r > b.r; });
     // outputs of different images must not overlap each other or any input
     {
         std::vector<std::pair<uintptr_t, uintptr_t>> outs, ins;
@@ -198,21 +275,28 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
     if (!p) return ICL_ERR_INVALID_VALUE;
     p->dt = dtype;
     p->ntiles = (int)tiles.size();
+    p->nitems = (int)items.size();
     p->pixels = pixels;
     hipError_t e = hipSuccess;
     if (!imgs.empty()) e = hipMalloc(&p->d_imgs, imgs.size() * sizeof(DevImage));
     if (e == hipSuccess && !tiles.empty()) e = hipMalloc(&p->d_tiles, tiles.size() * sizeof(BatchTile));
+    if (e == hipSuccess && !items.empty()) e = hipMalloc(&p->d_items, items.size() * sizeof(StripItem));
     if (e == hipSuccess && !imgs.empty())
         e = hipMemcpy(p->d_imgs, imgs.data(), imgs.size() * sizeof(DevImage), hipMemcpyHostToDevice);
     if (e == hipSuccess && !tiles.empty())
         e = hipMemcpy(p->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
-    int per_cu = 0, dev = 0, cus = 0;
+    if (e == hipSuccess && !items.empty())
+        e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(StripItem), hipMemcpyHostToDevice);
+    int per_cu = 0, per_cu_strip = 0, dev = 0, cus = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(dtype), 256, 0);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_strip, strip_kernel_for(dtype), 64, 0);
     if (e != hipSuccess) {
         hipFree(p->d_imgs);
         hipFree(p->d_tiles);
+        hipFree(p->d_items);
         delete p;
         return hip_status(e);
     }
@@ -220,6 +304,8 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
     p->grid = (int)std::min<long long>(resident, std::max(p->ntiles, 1));
     // a multiple of 8 keeps the XCD-aware remap a permutation of the grid
     if (p->grid > 8) p->grid -= p->grid % 8;
+    const long long resident_strip = (long long)std::max(per_cu_strip, 1) * std::max(cus, 1);
+    p->strip_grid = (int)std::min<long long>(resident_strip, std::max(p->nitems, 1));
     *plan = p;
     return ICL_OK;
 }
@@ -228,6 +314,24 @@ icl_status icl_conv_sep_batched(const icl_batch_plan* plan, void* stream) {
     if (!plan) return ICL_ERR_INVALID_VALUE;
     if (plan->ntiles == 0) return ICL_OK;
     hipStream_t st = (hipStream_t)stream;
+    const int v = select_variant(ICL_OP_CONV_SEP_BATCHED, plan->dt, 0, 0, 0, batched_default());
+    if (v == 1) {
+        switch (plan->dt) {
+            case ICL_F32:
+                hipLaunchKernelGGL(sep_batched_strip_k<F32>, dim3(plan->strip_grid), dim3(64), 0, st, plan->d_imgs,
+                                   plan->d_items, plan->nitems);
+                break;
+            case ICL_F16:
+                hipLaunchKernelGGL(sep_batched_strip_k<F16>, dim3(plan->strip_grid), dim3(64), 0, st, plan->d_imgs,
+                                   plan->d_items, plan->nitems);
+                break;
+            default:
+                hipLaunchKernelGGL(sep_batched_strip_k<BF16>, dim3(plan->strip_grid), dim3(64), 0, st, plan->d_imgs,
+                                   plan->d_items, plan->nitems);
+                break;
+        }
+        return hip_status(hipGetLastError());
+    }
     switch (plan->dt) {
         case ICL_F32:
             hipLaunchKernelGGL(sep_batched_k<F32>, dim3(plan->grid), dim3(256), 0, st, plan->d_imgs, plan->d_tiles,
@@ -256,6 +360,7 @@ void icl_batch_plan_destroy(icl_batch_plan* plan) {
     if (!plan) return;
     hipFree(plan->d_imgs);
     hipFree(plan->d_tiles);
+    hipFree(plan->d_items);
     delete plan;
 }
 

@@ -17,8 +17,17 @@
 //                       discussion credits for Halide's win).  CX = 2 gives each
 //                       lane two columns 64 apart (interleaved within the
 //                       work-group, Fig. 4c), keeping stores coalesced.
+//   pers_t{TH}_c{CX}  : the fused tile body in a persistent grid that prefetches the
+//                       next tile into registers while computing the current one.
+//   strip_t{TH}       : one wave per strip of 256 - 8*ceil(r/4) output columns and TH
+//                       rows, walking down the rows with both passes in registers:
+//                       horizontal neighbours by DPP lane shifts, a ring of 2r+1
+//                       pending output rows for the vertical pass, prefetched input
+//                       rows.  No LDS, no barrier; the same float32 expression per
+//                       output as the tile variants.
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
+#include "sep_strip.hpp"
 #include "sep_tile.hpp"
 #include "tile_stage.hpp"
 
@@ -208,6 +217,53 @@ hipError_t launch_pers(const SepArgs& a) {
     }
 }
 
+// ------------------------------------------------------------------ register strips
+template <class T, int R, int TH>
+__global__ __launch_bounds__(64) void sep_strip(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
+                                                size_t dp, int W, int H, const float* __restrict__ tx,
+                                                const float* __restrict__ ty, int nstrips, int vec_in, int vec_out) {
+    const int strip = (int)(blockIdx.x % (unsigned)nstrips);
+    const int y0 = (int)(blockIdx.x / (unsigned)nstrips) * TH;
+    sep_strip_body<T, R, TH>(src, sp, dst, dp, W, H, tx, ty, strip * StripGeom<R>::SW, y0, vec_in != 0,
+                             vec_out != 0);
+}
+
+template <class T, int R, int TH>
+hipError_t launch_strip_TR(const SepArgs& a) {
+    const int nstrips = (a.W + StripGeom<R>::SW - 1) / StripGeom<R>::SW;
+    const int rows = (a.H + TH - 1) / TH;
+    const size_t al = 4 * (size_t)T::size;
+    const int vec_in = ((uintptr_t)a.src % al == 0) && (a.sp % al == 0);
+    const int vec_out = ((uintptr_t)a.dst % al == 0) && (a.dp % al == 0);
+    hipLaunchKernelGGL((sep_strip<T, R, TH>), dim3((unsigned)(nstrips * rows)), dim3(64), 0, a.st, a.src, a.sp, a.dst,
+                       a.dp, a.W, a.H, a.tx, a.ty, nstrips, vec_in, vec_out);
+    return hipGetLastError();
+}
+
+template <class T, int TH>
+hipError_t launch_strip_T(const SepArgs& a) {
+    switch (a.r) {
+        case 0: return launch_strip_TR<T, 0, TH>(a);
+        case 1: return launch_strip_TR<T, 1, TH>(a);
+        case 2: return launch_strip_TR<T, 2, TH>(a);
+        case 3: return launch_strip_TR<T, 3, TH>(a);
+        case 4: return launch_strip_TR<T, 4, TH>(a);
+        case 5: return launch_strip_TR<T, 5, TH>(a);
+        case 6: return launch_strip_TR<T, 6, TH>(a);
+        case 7: return launch_strip_TR<T, 7, TH>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int TH>
+hipError_t launch_strip(const SepArgs& a) {
+    switch (a.dt) {
+        case ICL_F32: return launch_strip_T<F32, TH>(a);
+        case ICL_F16: return launch_strip_T<F16, TH>(a);
+        default: return launch_strip_T<BF16, TH>(a);
+    }
+}
+
 const Variant<SepArgs> kSep[] = {
     {"plain2p", supports_plain, launch_plain},
     {"fused_t32_c1", supports_fused, launch_fused<32, 1>},
@@ -218,6 +274,9 @@ const Variant<SepArgs> kSep[] = {
     {"pers_t16_c2", supports_fused, launch_pers<16, 2>},
     {"pers_t64_c1", supports_fused, launch_pers<64, 1>},
     {"pers_t16_c1", supports_fused, launch_pers<16, 1>},
+    {"strip_t32", supports_fused, launch_strip<32>},
+    {"strip_t16", supports_fused, launch_strip<16>},
+    {"strip_t64", supports_fused, launch_strip<64>},
 };
 
 }  // namespace

@@ -19,8 +19,8 @@
 //                   into LDS and a column pass in registers.  8 B/px of HBM.
 //   stream_t{TH}  : one wave per 248-column strip and TH rows, walking down the rows
 //                   with everything in registers (one float4 image load per lane and
-//                   row, neighbour columns by lane shuffles, rings of prefetched image
-//                   rows and of pending output rows); the 64-column left band and the
+//                   row, neighbour columns by DPP lane shifts, rings of prefetched image
+//                   rows and of pending output rows); the 4-column left band and the
 //                   right remainder run through the tile kernel.  16-byte aligned rows.
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
@@ -229,20 +229,20 @@ hipError_t launch_fused_R(const HarrisArgs& a) {
 // so every read of the strip is inside the image and nothing is clamped in x.  The wave
 // walks down the clamped window rows: per row it loads one float4 of the image per lane
 // (prefetched D rows ahead), forms the vertical Sobel parts from the last three image
-// rows, gets the neighbouring columns by lane shuffles, forms the three products and
+// rows, gets the neighbouring columns by DPP lane shifts, forms the three products and
 // their horizontal window sum, and adds that row into a ring of D = 2r+1 pending output
 // rows; the oldest completes and is written each step.  No LDS tile, no barrier.
 constexpr int HS_COLS = 248;   // output columns per strip (62 lanes x 4)
-constexpr int HS_XL = 64;      // left border band, done by the tile kernel
+constexpr int HS_XL = 4;       // left border band (the strips start here), done by the tile kernel
 
 template <int RG>
 __device__ __forceinline__ v4f hwin(v4f p, const float (&gw)[2 * RG + 1]) {
     float e[4 + 2 * RG];
 #pragma unroll
-    for (int i = 0; i < RG; ++i) e[i] = __shfl_up(p[4 - RG + i], 1);
+    for (int i = 0; i < RG; ++i) e[i] = lane_from_left(p[4 - RG + i]);
     e[RG] = p.x; e[RG + 1] = p.y; e[RG + 2] = p.z; e[RG + 3] = p.w;
 #pragma unroll
-    for (int i = 0; i < RG; ++i) e[RG + 4 + i] = __shfl_down(p[i], 1);
+    for (int i = 0; i < RG; ++i) e[RG + 4 + i] = lane_from_right(p[i]);
     float o[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -255,14 +255,14 @@ __device__ __forceinline__ v4f hwin(v4f p, const float (&gw)[2 * RG + 1]) {
 }
 
 // Products of one window row: Sobel from image rows ra (above), rb, rc (below), neighbour
-// columns by lane shuffles, then the horizontal window of each product.
+// columns by DPP lane shifts, then the horizontal window of each product.
 template <int RG>
 __device__ __forceinline__ void window_row(const v4f ra, const v4f rb, const v4f rc, const float (&gw)[2 * RG + 1],
                                            v4f& qa, v4f& qb, v4f& qc) {
     const v4f vs = ra + 2.f * rb + rc;   // vertical smoothing (for Ix)
     const v4f vd = rc - ra;              // vertical difference (for Iy)
-    const float vsl = __shfl_up(vs.w, 1), vsr = __shfl_down(vs.x, 1);
-    const float vdl = __shfl_up(vd.w, 1), vdr = __shfl_down(vd.x, 1);
+    const float vsl = lane_from_left(vs.w), vsr = lane_from_right(vs.x);
+    const float vdl = lane_from_left(vd.w), vdr = lane_from_right(vd.x);
     const v4f ix = mk4(vs.y - vsl, vs.z - vs.x, vs.w - vs.y, vsr - vs.z);
     const v4f iy = mk4(vdl + 2.f * vd.x + vd.y, vd.x + 2.f * vd.y + vd.z, vd.y + 2.f * vd.z + vd.w,
                        vd.z + 2.f * vd.w + vdr);
@@ -271,8 +271,8 @@ __device__ __forceinline__ void window_row(const v4f ra, const v4f rb, const v4f
     qc = hwin<RG>(ix * iy, gw);
 }
 
-constexpr int hs_gcd(int a, int b) { return b == 0 ? a : hs_gcd(b, a % b); }
-
+// One wave per work-group (the register allocation of a 64-lane launch bound keeps the
+// working set at four waves per SIMD without spills).
 template <int RG, int TH>
 __global__ __launch_bounds__(64) void harris_stream(const float* __restrict__ src, size_t sp, float* __restrict__ resp,
                                                     size_t rp, int H, const float* __restrict__ g, float k,
@@ -324,23 +324,20 @@ __global__ __launch_bounds__(64) void harris_stream(const float* __restrict__ sr
         // interior row block: window row kk is gradient row y0 - r + kk, whose Sobel reads
         // image rows y0 - r - 1 + kk + {0, 1, 2}; those come from a ring of M image rows
         // (image row i of the block in slot i mod M), each loaded M - 2 steps before use
+        // The walk is unrolled completely (TH is small), so every ring slot, row range and
+        // prefetch bound is a constant and the steady state has no branch.
         constexpr int M = D >= 5 ? D : (D == 3 ? 6 : 5);
-        constexpr int U = D * M / hs_gcd(D, M);   // unroll: both rings' slots are constants
         const int ybase = y0 - RG - 1;
         v4f img[M];
 #pragma unroll
         for (int i = 0; i < M; ++i) img[i] = image_row(ybase + i);
-        for (int kb = 0; kb < K; kb += U) {
-            static_for<U>([&](auto u_c) {
-                constexpr int u = decltype(u_c)::value;
-                const int kk = kb + u;
-                if (kk >= K) return;
-                v4f qa, qb, qc;
-                window_row<RG>(img[u % M], img[(u + 1) % M], img[(u + 2) % M], gw, qa, qb, qc);
-                if (kk + M <= K + 1) img[u % M] = image_row(ybase + kk + M);
-                accumulate_emit(kk, std::integral_constant<int, u % D>{}, qa, qb, qc);
-            });
-        }
+        static_for<K>([&](auto k_c) {
+            constexpr int kk = decltype(k_c)::value;
+            v4f qa, qb, qc;
+            window_row<RG>(img[kk % M], img[(kk + 1) % M], img[(kk + 2) % M], gw, qa, qb, qc);
+            if constexpr (kk + M <= K + 1) img[kk % M] = image_row(ybase + kk + M);
+            accumulate_emit(kk, std::integral_constant<int, kk % D>{}, qa, qb, qc);
+        });
         return;
     }
 
@@ -415,7 +412,7 @@ const Variant<HarrisArgs> kHarris[] = {
     {"fused_t8", supports_fused, launch_fused<8>},
     {"stream_t64", supports_stream, launch_stream<64>},
     {"stream_t32", supports_stream, launch_stream<32>},
-    {"stream_t128", supports_stream, launch_stream<128>},
+    {"stream_t16", supports_stream, launch_stream<16>},
 };
 
 }  // namespace

@@ -19,6 +19,16 @@ __device__ __forceinline__ void static_for(F&& f) {
     static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
+// Neighbour-lane moves within a wave as DPP wave shifts (a VALU operand modifier, no LDS
+// round trip): lane i receives v of lane i-1 (from_left) or of lane i+1 (from_right); the
+// end lane with no such neighbour receives 0.
+__device__ __forceinline__ float lane_from_left(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138 /* wave_shr:1 */, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_from_right(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130 /* wave_shl:1 */, 0xf, 0xf, true));
+}
+
 // Native 4 x float32 vector: loads and stores of it lower to single dwordx4 /
 // ds_read_b128 instructions (HIP's float4 struct is copied member by member).
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -62,8 +72,17 @@ template <class T> __device__ __forceinline__ void store_px(void* base, size_t o
 template <> __device__ __forceinline__ void store_px<F32>(void* base, size_t off, float v) {
     *reinterpret_cast<float*>(static_cast<char*>(base) + off) = v;
 }
+// float32 -> float16, round to nearest even, from a float32 value that is final: the
+// empty asm keeps the compiler from merging the conversion with the FMA that produced v
+// (a mixed-precision FMA would round once, straight to float16, and differ from the
+// float32-then-float16 rounding of every other kernel in rare cases).
+__device__ __forceinline__ _Float16 encode_f16(float v) {
+    asm volatile("" : "+v"(v));
+    return static_cast<_Float16>(v);
+}
+
 template <> __device__ __forceinline__ void store_px<F16>(void* base, size_t off, float v) {
-    *reinterpret_cast<_Float16*>(static_cast<char*>(base) + off) = static_cast<_Float16>(v);
+    *reinterpret_cast<_Float16*>(static_cast<char*>(base) + off) = encode_f16(v);
 }
 template <> __device__ __forceinline__ void store_px<BF16>(void* base, size_t off, float v) {
     *reinterpret_cast<uint16_t*>(static_cast<char*>(base) + off) = encode_bf16(v);
@@ -92,8 +111,7 @@ template <> __device__ __forceinline__ void store4<F32>(void* base, size_t off, 
     *reinterpret_cast<v4f*>(static_cast<char*>(base) + off) = v;
 }
 template <> __device__ __forceinline__ void store4<F16>(void* base, size_t off, v4f v) {
-    const v4h h = {static_cast<_Float16>(v.x), static_cast<_Float16>(v.y), static_cast<_Float16>(v.z),
-                   static_cast<_Float16>(v.w)};
+    const v4h h = {encode_f16(v.x), encode_f16(v.y), encode_f16(v.z), encode_f16(v.w)};
     *reinterpret_cast<v4h*>(static_cast<char*>(base) + off) = h;
 }
 template <> __device__ __forceinline__ void store4<BF16>(void* base, size_t off, v4f v) {

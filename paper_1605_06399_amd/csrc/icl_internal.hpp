@@ -83,6 +83,7 @@ int bank_fwd_default(const BankArgs&);
 int bank_bwd_input_default(const BankArgs&);
 int bank_bwd_filter_default(const BankArgs&);
 int bank_fwd_sse_default(const BankSseArgs&);
+int batched_default();
 
 size_t sep_workspace(int W, int H);
 size_t harris_workspace(int W, int H);

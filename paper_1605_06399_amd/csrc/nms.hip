@@ -16,7 +16,7 @@
 //                float4 row loads plus the two flanking pixels, one 32-bit store of
 //                four mask bytes; clamps only on edge lanes.
 //   stream_t{TH}: one wave per 248-column strip and TH rows (r = 1): every response row
-//                loaded once, the 3 x 3 neighbourhood from registers and lane shuffles;
+//                loaded once, the 3 x 3 neighbourhood from registers and DPP lane shifts;
 //                the border bands run through row4.  16-byte aligned response rows.
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
@@ -80,8 +80,8 @@ __global__ __launch_bounds__(256) void nms_row4(const float* __restrict__ R, siz
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const float v = b[p + 1];
-        const bool keep = v > tau && v >= a[p] && v >= a[p + 1] && v >= a[p + 2] && v >= b[p] && v >= b[p + 2] &&
-                          v >= c[p] && v >= c[p + 1] && v >= c[p + 2];
+        const bool keep = (v > tau) & (v >= a[p]) & (v >= a[p + 1]) & (v >= a[p + 2]) & (v >= b[p]) & (v >= b[p + 2]) &
+                          (v >= c[p]) & (v >= c[p + 1]) & (v >= c[p + 2]);
         bits |= (keep ? 1u : 0u) << (8 * p);
     }
     uint8_t* out = M + (size_t)y * mp + x;
@@ -114,15 +114,15 @@ bool supports_row4(const NmsArgs& a) { return a.r == 1; }
 // only supply the neighbouring column, so no read of a strip is clamped in x.  The wave
 // walks down the rows holding the rows above, at and below the output row in registers
 // (each row loaded once, prefetched through a ring), gets the left and right neighbours by
-// lane shuffles and writes the four mask bytes of a lane as one 32-bit store.  The left
-// 64 columns and the right remainder run through the row kernel.
+// DPP lane shifts and writes the four mask bytes of a lane as one 32-bit store.  The left
+// 4 columns and the right remainder (under 252 columns) run through the row kernel.
 constexpr int NS_COLS = 248;
-constexpr int NS_XL = 64;
+constexpr int NS_XL = 4;
 
 __device__ __forceinline__ uint32_t nms_bits(v4f a, v4f b, v4f c, float tau) {
-    const float al = __shfl_up(a.w, 1), ar = __shfl_down(a.x, 1);
-    const float bl = __shfl_up(b.w, 1), br = __shfl_down(b.x, 1);
-    const float cl = __shfl_up(c.w, 1), cr = __shfl_down(c.x, 1);
+    const float al = lane_from_left(a.w), ar = lane_from_right(a.x);
+    const float bl = lane_from_left(b.w), br = lane_from_right(b.x);
+    const float cl = lane_from_left(c.w), cr = lane_from_right(c.x);
     const float ea[6] = {al, a.x, a.y, a.z, a.w, ar};
     const float eb[6] = {bl, b.x, b.y, b.z, b.w, br};
     const float ec[6] = {cl, c.x, c.y, c.z, c.w, cr};
@@ -130,19 +130,23 @@ __device__ __forceinline__ uint32_t nms_bits(v4f a, v4f b, v4f c, float tau) {
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const float v = eb[p + 1];
-        const bool keep = v > tau && v >= ea[p] && v >= ea[p + 1] && v >= ea[p + 2] && v >= eb[p] && v >= eb[p + 2] &&
-                          v >= ec[p] && v >= ec[p + 1] && v >= ec[p + 2];
+        // bitwise & (no short circuit): nine compares, no branches
+        const bool keep = (v > tau) & (v >= ea[p]) & (v >= ea[p + 1]) & (v >= ea[p + 2]) & (v >= eb[p]) &
+                          (v >= eb[p + 2]) & (v >= ec[p]) & (v >= ec[p + 1]) & (v >= ec[p + 2]);
         bits |= (keep ? 1u : 0u) << (8 * p);
     }
     return bits;
 }
 
+// Four independent strip waves per work-group (wave w of group b is strip wave 4b + w).
 template <int TH>
-__global__ __launch_bounds__(64) void nms_stream(const float* __restrict__ R, size_t rp, uint8_t* __restrict__ M,
-                                                 size_t mp, int H, float tau, int nstrips) {
-    const int lane = threadIdx.x;
-    const int strip = (int)(blockIdx.x % (unsigned)nstrips);
-    const int y0 = (int)(blockIdx.x / (unsigned)nstrips) * TH;
+__global__ __launch_bounds__(256) void nms_stream(const float* __restrict__ R, size_t rp, uint8_t* __restrict__ M,
+                                                  size_t mp, int H, float tau, int nstrips, int nwaves) {
+    const int lane = threadIdx.x & 63;
+    const int wv = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (wv >= nwaves) return;   // no barrier in this kernel: a wave may leave early
+    const int strip = wv % nstrips;
+    const int y0 = (wv / nstrips) * TH;
     const int c = NS_XL + strip * NS_COLS - 4 + 4 * lane;
     const char* col = reinterpret_cast<const char*>(R) + (size_t)c * 4;
     auto row = [&](int y) { return *reinterpret_cast<const v4f*>(col + (size_t)y * rp); };
@@ -151,21 +155,18 @@ __global__ __launch_bounds__(64) void nms_stream(const float* __restrict__ R, si
     if (y0 >= 1 && y0 + TH <= H - 1) {
         // interior: output row m reads rows y0 - 1 + m + {0, 1, 2}, from a ring of RING rows
         // (row i of the block in slot i mod RING), each loaded RING - 2 rows before use
+        // completely unrolled (TH is small): constant ring slots and bounds, no branch
         constexpr int RING = 8;
         const int ybase = y0 - 1;
         v4f ring[RING];
 #pragma unroll
         for (int i = 0; i < RING; ++i) ring[i] = row(ybase + i);
-        for (int mb = 0; mb < TH; mb += RING) {
-            static_for<RING>([&](auto u_c) {
-                constexpr int u = decltype(u_c)::value;
-                const int m = mb + u;
-                if (m >= TH) return;
-                const uint32_t bits = nms_bits(ring[u], ring[(u + 1) % RING], ring[(u + 2) % RING], tau);
-                if (m + RING <= TH + 1) ring[u] = row(ybase + m + RING);
-                if (writer) *reinterpret_cast<uint32_t*>(out_col + (size_t)(y0 + m) * mp) = bits;
-            });
-        }
+        static_for<TH>([&](auto m_c) {
+            constexpr int m = decltype(m_c)::value;
+            const uint32_t bits = nms_bits(ring[m % RING], ring[(m + 1) % RING], ring[(m + 2) % RING], tau);
+            if constexpr (m + RING <= TH + 1) ring[m % RING] = row(ybase + m + RING);
+            if (writer) *reinterpret_cast<uint32_t*>(out_col + (size_t)(y0 + m) * mp) = bits;
+        });
         return;
     }
     // top or bottom block: rows clamp at the image edge
@@ -187,8 +188,9 @@ hipError_t launch_stream(const NmsArgs& a) {
     const int nstrips = (a.W - NS_XL - 4) / NS_COLS;
     const int xr = NS_XL + nstrips * NS_COLS;
     const int rows = (a.H + TH - 1) / TH;
-    hipLaunchKernelGGL(nms_stream<TH>, dim3((unsigned)(nstrips * rows)), dim3(64), 0, a.st, a.R, a.rp, a.M, a.mp, a.H,
-                       a.tau, nstrips);
+    const int nwaves = nstrips * rows;
+    hipLaunchKernelGGL(nms_stream<TH>, dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, a.st, a.R, a.rp, a.M, a.mp,
+                       a.H, a.tau, nstrips, nwaves);
     return launch_row4_bands(a, NS_XL, xr);
 }
 
@@ -196,7 +198,7 @@ const Variant<NmsArgs> kNms[] = {
     {"plain", supports_plain, launch_plain},
     {"row4", supports_row4, launch_row4},
     {"stream_t64", supports_stream, launch_stream<64>},
-    {"stream_t128", supports_stream, launch_stream<128>},
+    {"stream_t32", supports_stream, launch_stream<32>},
 };
 
 }  // namespace

@@ -29,8 +29,20 @@ def make_batch(dt, count=14, lo=1, hi=300, seed=60):
     return items, xs, x64s, outs, taps
 
 
+N_BATCHED = 2   # persistent tile walk, persistent strip walk
+
+
+@pytest.fixture(params=range(N_BATCHED), ids=["tiles", "strips"])
+def batched_variant(request):
+    if request.param >= B.icl_variant_count(B.ICL_OP_CONV_SEP_BATCHED):
+        pytest.skip("no such variant")
+    B.check(B.icl_force_variant(B.ICL_OP_CONV_SEP_BATCHED, request.param))
+    yield request.param
+    B.icl_force_variant(B.ICL_OP_CONV_SEP_BATCHED, -1)
+
+
 @pytest.mark.parametrize("dt", ["f32", "f16", "bf16"])
-def test_batched_matches_oracle_per_image(dt):
+def test_batched_matches_oracle_per_image(dt, batched_variant):
     items, xs, x64s, outs, taps = make_batch(dt)
     plan = T.BatchPlan(xs, outs, taps)
     assert plan.pixels == sum(i.width * i.height for i in items)
@@ -43,9 +55,9 @@ def test_batched_matches_oracle_per_image(dt):
     plan.close()
 
 
-def test_batched_equals_per_image_calls():
-    """The persistent kernel and icl_conv_sep (fused variant) agree bit for bit: every variant sums each
-    output in the same tap order, whatever its tile shape."""
+def test_batched_equals_per_image_calls(batched_variant):
+    """The persistent kernels and icl_conv_sep (fused variant) agree bit for bit: every variant sums each
+    output in the same tap order, whatever its tile or strip shape."""
     items, xs, _, outs, taps = make_batch("f16", count=9, seed=61)
     plan = T.BatchPlan(xs, outs, taps)
     plan.launch()
@@ -59,7 +71,7 @@ def test_batched_equals_per_image_calls():
     plan.close()
 
 
-def test_graph_replay_is_bit_identical_and_sees_new_data():
+def test_graph_replay_is_bit_identical_and_sees_new_data(batched_variant):
     items, xs, x64s, outs, taps = make_batch("bf16", count=11, seed=62)
     plan = T.BatchPlan(xs, outs, taps)
     plan.launch()
@@ -87,7 +99,7 @@ def test_graph_replay_is_bit_identical_and_sees_new_data():
     plan.close()
 
 
-def test_batch_with_empty_and_tiny_images():
+def test_batch_with_empty_and_tiny_images(batched_variant):
     shapes = [(0, 5), (1, 1), (3, 1), (1, 7), (70, 0), (2, 2)]
     xs, outs, taps, refs = [], [], [], []
     for k, (H, W) in enumerate(shapes):

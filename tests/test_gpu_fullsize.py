@@ -148,22 +148,33 @@ def test_uneven_batch_256(dt):
         taps.append(torch.from_numpy(it.taps).cuda())
     plan = T.BatchPlan(xs_d, outs, taps)
     assert plan.pixels == sum(it.width * it.height for it in items)
-    plan.replay()
-    torch.cuda.synchronize()
-    worst = 0.0
-    for k, (it, x64, out) in enumerate(zip(items, x64s, outs)):
+    refs = []
+    for k, (it, x64) in enumerate(zip(items, x64s)):
         g = it.taps.astype(np.float64)
         xs, ys = sample_points(it.height, it.width, 40, 1000 + k)
-        ref = oracle.conv_sep_pts(x64, g, g, xs, ys)
-        scale = oracle.conv_sep_pts(np.abs(x64), g, g, xs, ys)
-        got = out[torch.from_numpy(ys).cuda(), torch.from_numpy(xs).cuda()].float().cpu().numpy().astype(np.float64)
-        err = normwise(got, ref, scale)
-        worst = max(worst, err)
-        if dt == "f16":
-            assert err <= 2e-3, f"image {k}: {err:.3e}"
-        else:
-            assert bf16_violations(got, ref, scale) == 0, f"image {k}: bf16 beyond 1 ulp + 1e-5 S"
-    print(f"{dt}: worst normwise error vs FP64 {worst:.3e}")
+        refs.append((xs, ys, oracle.conv_sep_pts(x64, g, g, xs, ys), oracle.conv_sep_pts(np.abs(x64), g, g, xs, ys)))
+    for variant in range(B.icl_variant_count(B.ICL_OP_CONV_SEP_BATCHED)):   # tile walk, strip walk
+        B.check(B.icl_force_variant(B.ICL_OP_CONV_SEP_BATCHED, variant))
+        try:
+            for o in outs:
+                o.fill_(float("nan"))
+            plan.launch()
+            torch.cuda.synchronize()
+        finally:
+            B.icl_force_variant(B.ICL_OP_CONV_SEP_BATCHED, -1)
+        worst = 0.0
+        for k, (out, (xs, ys, ref, scale)) in enumerate(zip(outs, refs)):
+            got = out[torch.from_numpy(ys).cuda(), torch.from_numpy(xs).cuda()].float().cpu().numpy()
+            got = got.astype(np.float64)
+            err = normwise(got, ref, scale)
+            worst = max(worst, err)
+            if dt == "f16":
+                assert err <= 2e-3, f"variant {variant} image {k}: {err:.3e}"
+            else:
+                assert bf16_violations(got, ref, scale) == 0, f"variant {variant} image {k}: beyond 1 ulp + 1e-5 S"
+        print(f"{dt} variant {variant}: worst normwise error vs FP64 {worst:.3e}")
+    plan.replay()   # the captured graph (default variant)
+    torch.cuda.synchronize()
     plan.close()
 
 

@@ -39,7 +39,7 @@ def _nvariants(op, default):
 
 
 N_HARRIS = _nvariants(B.ICL_OP_HARRIS, 7)
-STREAM_MIN_W = 64 + 248 + 4     # the strip variants need one strip between the two border bands
+STREAM_MIN_W = 4 + 248 + 4     # the strip variants need one strip between the two border bands
 
 
 def runs(variant, W):
@@ -52,7 +52,7 @@ def runs(variant, W):
 # small and degenerate images, several strips with a ragged right band and ragged row
 # blocks, fewer rows than a row block, one row, and the narrowest width the strips take
 HARRIS_SHAPES = [(389, 517), (1, 1), (2, 3), (5, 4), (1, 90), (90, 1), (64, 64), (17, 130),
-                 (133, 1100), (5, 700), (1, 640), (300, STREAM_MIN_W), (70, STREAM_MIN_W + 4)]
+                 (133, 1100), (5, 700), (1, 640), (300, STREAM_MIN_W), (70, STREAM_MIN_W + 4), (37, 752)]
 
 
 @pytest.mark.parametrize("variant", range(N_HARRIS))
@@ -171,7 +171,7 @@ def nms_runs(variant, radius, W, aligned=True):
 
 
 NMS_SHAPES = [(257, 389), (1, 1), (1, 9), (9, 1), (4, 4), (63, 65),
-              (133, 1100), (5, 700), (1, 640), (300, STREAM_MIN_W), (70, STREAM_MIN_W + 4), (129, 2000)]
+              (133, 1100), (5, 700), (1, 640), (300, STREAM_MIN_W), (70, STREAM_MIN_W + 4), (129, 2000), (37, 752)]
 
 
 @pytest.mark.parametrize("variant", range(N_NMS))
