@@ -65,7 +65,7 @@ def roof_gpx(kind, r, bytes_px=8.0):
 
 # kernel source files per call kind: traffic figures are valid only for the source they were taken on
 KERNEL_SOURCES = {"2d": ["conv2d.hip", "tile_stage.hpp", "corr_tile.hpp", "icl_device.hpp"],
-                  "sep": ["conv_sep.hip", "sep_tile.hpp", "tile_stage.hpp", "icl_device.hpp"]}
+                  "sep": ["conv_sep.hip", "sep_tile.hpp", "sep_strip.hpp", "tile_stage.hpp", "icl_device.hpp"]}
 
 
 def source_hash(*names):

@@ -427,7 +427,7 @@ int icl_variant_count(icl_op op) {
         case ICL_OP_BANK_BWD_INPUT: bank_bwd_input_variants(&c); break;
         case ICL_OP_BANK_BWD_FILTER: bank_bwd_filter_variants(&c); break;
         case ICL_OP_BANK_FWD_SSE: bank_fwd_sse_variants(&c); break;
-        case ICL_OP_CONV_SEP_BATCHED: c = 2; break;
+        case ICL_OP_CONV_SEP_BATCHED: c = 4; break;
         case ICL_OP_SSE_LOSS: c = 1; break;
         default: c = 0;
     }
@@ -446,7 +446,11 @@ const char* icl_variant_name(icl_op op, int index) {
         case ICL_OP_BANK_BWD_INPUT: return bank_bwd_input_variants(&c)[index].name;
         case ICL_OP_BANK_BWD_FILTER: return bank_bwd_filter_variants(&c)[index].name;
         case ICL_OP_BANK_FWD_SSE: return bank_fwd_sse_variants(&c)[index].name;
-        case ICL_OP_CONV_SEP_BATCHED: return index == 0 ? "persistent_fused_t64" : "persistent_strip_t32";
+        case ICL_OP_CONV_SEP_BATCHED: {
+            static const char* names[] = {"persistent_fused_t64", "persistent_strip_t32",
+                                          "persistent_fused_t64_rsort", "persistent_fused_t32_rsort"};
+            return names[index];
+        }
         case ICL_OP_SSE_LOSS: return "two_stage";
         default: return nullptr;
     }

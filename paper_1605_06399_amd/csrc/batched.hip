@@ -9,6 +9,8 @@
 //
 // Variants
 //   persistent_fused_t64 : the tile walk above (64x64 output tiles, LDS passes).
+//   persistent_fused_t64_rsort, persistent_fused_t32_rsort : the same walk over 64- or
+//                          32-row tiles ordered by decreasing radius.
 //   persistent_strip_t32 : a persistent grid of single waves walking a table of
 //                          (image, strip, 32-row block) items with the register-
 //                          streaming body of the per-image strip variant; the items
@@ -38,7 +40,7 @@ struct DevImage {
 };
 
 struct BatchTile {
-    int img, x0, y0, pad;
+    int img, x0, y0, r;   // r: the image's radius (orders the tiles on the host)
 };
 
 struct StripItem {
@@ -47,7 +49,6 @@ struct StripItem {
 
 namespace {
 
-constexpr int BTH = 64;    // tile rows
 constexpr int BCX = 1;     // tile columns = 64 * BCX
 constexpr int RMAX = 7;
 
@@ -55,7 +56,7 @@ constexpr int RMAX = 7;
 // fetched into registers while the current tile is computed; the row-pass
 // intermediate lives at a fixed LDS offset past the largest staged tile, so staging
 // the next tile (any radius) never overlaps a column pass still reading.
-template <class T>
+template <class T, int BTH>
 __global__ __launch_bounds__(256) void sep_batched_k(const DevImage* __restrict__ imgs,
                                                      const BatchTile* __restrict__ tiles, int ntiles) {
     constexpr int TW = 64 * BCX;
@@ -163,13 +164,17 @@ int strip_width(int r) {
 
 using namespace icl;
 
+// Tile tables of the tile-walk variants: 64-row tiles in image order, 64-row tiles with
+// the largest radius first, 32-row tiles with the largest radius first.
+constexpr int NWALKS = 3;
+
 struct icl_batch_plan {
     icl_dtype dt;
     DevImage* d_imgs;
-    BatchTile* d_tiles;
+    BatchTile* d_tiles[NWALKS];
+    int ntiles[NWALKS];
+    int grid[NWALKS];
     StripItem* d_items;
-    int ntiles;
-    int grid;
     int nitems;
     int strip_grid;
     long long pixels;
@@ -177,17 +182,30 @@ struct icl_batch_plan {
 
 namespace {
 
+constexpr int walk_rows(int w) { return w == 2 ? 32 : 64; }
+
 template <class T>
-const void* batched_kernel() {
-    return reinterpret_cast<const void*>(&sep_batched_k<T>);
+const void* batched_kernel(int walk) {
+    return walk == 2 ? reinterpret_cast<const void*>(&sep_batched_k<T, 32>)
+                     : reinterpret_cast<const void*>(&sep_batched_k<T, 64>);
 }
 
-const void* kernel_for(icl_dtype dt) {
+const void* kernel_for(icl_dtype dt, int walk) {
     switch (dt) {
-        case ICL_F32: return batched_kernel<F32>();
-        case ICL_F16: return batched_kernel<F16>();
-        default: return batched_kernel<BF16>();
+        case ICL_F32: return batched_kernel<F32>(walk);
+        case ICL_F16: return batched_kernel<F16>(walk);
+        default: return batched_kernel<BF16>(walk);
     }
+}
+
+template <class T>
+void launch_walk(const icl_batch_plan* p, int w, hipStream_t st) {
+    if (w == 2)
+        hipLaunchKernelGGL((sep_batched_k<T, 32>), dim3(p->grid[w]), dim3(256), 0, st, p->d_imgs, p->d_tiles[w],
+                           p->ntiles[w]);
+    else
+        hipLaunchKernelGGL((sep_batched_k<T, 64>), dim3(p->grid[w]), dim3(256), 0, st, p->d_imgs, p->d_tiles[w],
+                           p->ntiles[w]);
 }
 
 const void* strip_kernel_for(icl_dtype dt) {
@@ -211,7 +229,7 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
     if (dtype != ICL_F32 && dtype != ICL_F16 && dtype != ICL_BF16) return ICL_ERR_DTYPE;
     const int es = elem_size(dtype);
     std::vector<DevImage> imgs;
-    std::vector<BatchTile> tiles;
+    std::vector<BatchTile> tiles[NWALKS];
     std::vector<StripItem> items;
     long long pixels = 0;
     const size_t al = 4 * (size_t)es;
@@ -238,17 +256,26 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
         di.pad = 0;
         imgs.push_back(di);
         pixels += (long long)d.width * d.height;
-        const int tx = (d.width + 64 * BCX - 1) / (64 * BCX), ty = (d.height + BTH - 1) / BTH;
-        for (int y = 0; y < ty; ++y)
-            for (int x = 0; x < tx; ++x) tiles.push_back(BatchTile{i, x * 64 * BCX, y * BTH, 0});
+        const int tx = (d.width + 64 * BCX - 1) / (64 * BCX);
+        for (int w = 0; w < NWALKS; w += 1) {
+            if (w == 1) continue;   // the sorted copy of walk 0 is made below
+            const int th = walk_rows(w), ty = (d.height + th - 1) / th;
+            for (int y = 0; y < ty; ++y)
+                for (int x = 0; x < tx; ++x) tiles[w].push_back(BatchTile{i, x * 64 * BCX, y * th, d.radius});
+        }
         const int sw = strip_width(d.radius);
         const int sx = (d.width + sw - 1) / sw, sy = (d.height + STH - 1) / STH;
         for (int y = 0; y < sy; ++y)
             for (int x = 0; x < sx; ++x) items.push_back(StripItem{i, x * sw, y * STH, d.radius});
     }
-    // largest radius first (longest items first), then image, row, strip
+    // largest radius first (the longest work first, and the resident waves mostly run one
+    // radius body at a time), then image, row, column
     std::stable_sort(items.begin(), items.end(),
                      [](const StripItem& a, const StripItem& b) { return a.r > b.r; });
+    tiles[1] = tiles[0];
+    auto by_radius = [](const BatchTile& a, const BatchTile& b) { return a.r > b.r; };
+    std::stable_sort(tiles[1].begin(), tiles[1].end(), by_radius);
+    std::stable_sort(tiles[2].begin(), tiles[2].end(), by_radius);
     // outputs of different images must not overlap each other or any input
     {
         std::vector<std::pair<uintptr_t, uintptr_t>> outs, ins;
@@ -274,36 +301,41 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
     icl_batch_plan* p = new (std::nothrow) icl_batch_plan{};
     if (!p) return ICL_ERR_INVALID_VALUE;
     p->dt = dtype;
-    p->ntiles = (int)tiles.size();
     p->nitems = (int)items.size();
     p->pixels = pixels;
     hipError_t e = hipSuccess;
     if (!imgs.empty()) e = hipMalloc(&p->d_imgs, imgs.size() * sizeof(DevImage));
-    if (e == hipSuccess && !tiles.empty()) e = hipMalloc(&p->d_tiles, tiles.size() * sizeof(BatchTile));
+    for (int w = 0; w < NWALKS; ++w) {
+        p->ntiles[w] = (int)tiles[w].size();
+        if (e == hipSuccess && !tiles[w].empty()) e = hipMalloc(&p->d_tiles[w], tiles[w].size() * sizeof(BatchTile));
+        if (e == hipSuccess && !tiles[w].empty())
+            e = hipMemcpy(p->d_tiles[w], tiles[w].data(), tiles[w].size() * sizeof(BatchTile), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess && !items.empty()) e = hipMalloc(&p->d_items, items.size() * sizeof(StripItem));
     if (e == hipSuccess && !imgs.empty())
         e = hipMemcpy(p->d_imgs, imgs.data(), imgs.size() * sizeof(DevImage), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !tiles.empty())
-        e = hipMemcpy(p->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
     if (e == hipSuccess && !items.empty())
         e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(StripItem), hipMemcpyHostToDevice);
-    int per_cu = 0, per_cu_strip = 0, dev = 0, cus = 0;
+    int per_cu[NWALKS] = {}, per_cu_strip = 0, dev = 0, cus = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(dtype), 256, 0);
+    for (int w = 0; w < NWALKS && e == hipSuccess; ++w)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[w], kernel_for(dtype, w), 256, 0);
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_strip, strip_kernel_for(dtype), 64, 0);
     if (e != hipSuccess) {
         hipFree(p->d_imgs);
-        hipFree(p->d_tiles);
+        for (int w = 0; w < NWALKS; ++w) hipFree(p->d_tiles[w]);
         hipFree(p->d_items);
         delete p;
         return hip_status(e);
     }
-    const long long resident = (long long)std::max(per_cu, 1) * std::max(cus, 1);
-    p->grid = (int)std::min<long long>(resident, std::max(p->ntiles, 1));
-    // a multiple of 8 keeps the XCD-aware remap a permutation of the grid
-    if (p->grid > 8) p->grid -= p->grid % 8;
+    for (int w = 0; w < NWALKS; ++w) {
+        const long long resident = (long long)std::max(per_cu[w], 1) * std::max(cus, 1);
+        p->grid[w] = (int)std::min<long long>(resident, std::max(p->ntiles[w], 1));
+        // a multiple of 8 keeps the XCD-aware remap a permutation of the grid
+        if (p->grid[w] > 8) p->grid[w] -= p->grid[w] % 8;
+    }
     const long long resident_strip = (long long)std::max(per_cu_strip, 1) * std::max(cus, 1);
     p->strip_grid = (int)std::min<long long>(resident_strip, std::max(p->nitems, 1));
     *plan = p;
@@ -312,7 +344,7 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
 
 icl_status icl_conv_sep_batched(const icl_batch_plan* plan, void* stream) {
     if (!plan) return ICL_ERR_INVALID_VALUE;
-    if (plan->ntiles == 0) return ICL_OK;
+    if (plan->ntiles[0] == 0) return ICL_OK;
     hipStream_t st = (hipStream_t)stream;
     const int v = select_variant(ICL_OP_CONV_SEP_BATCHED, plan->dt, 0, 0, 0, batched_default());
     if (v == 1) {
@@ -332,26 +364,18 @@ icl_status icl_conv_sep_batched(const icl_batch_plan* plan, void* stream) {
         }
         return hip_status(hipGetLastError());
     }
+    const int w = v == 0 ? 0 : v - 1;   // variants 0, 2, 3 are tile walks 0, 1, 2
     switch (plan->dt) {
-        case ICL_F32:
-            hipLaunchKernelGGL(sep_batched_k<F32>, dim3(plan->grid), dim3(256), 0, st, plan->d_imgs, plan->d_tiles,
-                               plan->ntiles);
-            break;
-        case ICL_F16:
-            hipLaunchKernelGGL(sep_batched_k<F16>, dim3(plan->grid), dim3(256), 0, st, plan->d_imgs, plan->d_tiles,
-                               plan->ntiles);
-            break;
-        default:
-            hipLaunchKernelGGL(sep_batched_k<BF16>, dim3(plan->grid), dim3(256), 0, st, plan->d_imgs, plan->d_tiles,
-                               plan->ntiles);
-            break;
+        case ICL_F32: launch_walk<F32>(plan, w, st); break;
+        case ICL_F16: launch_walk<F16>(plan, w, st); break;
+        default: launch_walk<BF16>(plan, w, st); break;
     }
     return hip_status(hipGetLastError());
 }
 
 icl_status icl_batch_plan_info(const icl_batch_plan* plan, long long* tiles, long long* pixels) {
     if (!plan) return ICL_ERR_INVALID_VALUE;
-    if (tiles) *tiles = plan->ntiles;
+    if (tiles) *tiles = plan->ntiles[0];
     if (pixels) *pixels = plan->pixels;
     return ICL_OK;
 }
@@ -359,7 +383,7 @@ icl_status icl_batch_plan_info(const icl_batch_plan* plan, long long* tiles, lon
 void icl_batch_plan_destroy(icl_batch_plan* plan) {
     if (!plan) return;
     hipFree(plan->d_imgs);
-    hipFree(plan->d_tiles);
+    for (int w = 0; w < NWALKS; ++w) hipFree(plan->d_tiles[w]);
     hipFree(plan->d_items);
     delete plan;
 }

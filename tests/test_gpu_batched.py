@@ -29,10 +29,17 @@ def make_batch(dt, count=14, lo=1, hi=300, seed=60):
     return items, xs, x64s, outs, taps
 
 
-N_BATCHED = 2   # persistent tile walk, persistent strip walk
+def _nvariants(default):
+    try:
+        return B.icl_variant_count(B.ICL_OP_CONV_SEP_BATCHED)
+    except Exception:
+        return default
 
 
-@pytest.fixture(params=range(N_BATCHED), ids=["tiles", "strips"])
+N_BATCHED = _nvariants(4)   # tile walks (image order, by radius, 32-row by radius) and the strip walk
+
+
+@pytest.fixture(params=range(N_BATCHED))
 def batched_variant(request):
     if request.param >= B.icl_variant_count(B.ICL_OP_CONV_SEP_BATCHED):
         pytest.skip("no such variant")
