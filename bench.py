@@ -96,7 +96,8 @@ def kernel_variant(name):
     pats = [("2d", r"conv2d_pers<icl::F32, (\d+), (\d+), (\d+)>", "pers_p{1}x{2}"),
             ("2d", r"conv2d_lds<icl::F32, (\d+), (\d+), (\d+), (\d+)>", "lds_p{1}x{2}_o{3}"),
             ("sep", r"sep_pers<icl::F32, (\d+), (\d+), (\d+)>", "pers_t{1}_c{2}"),
-            ("sep", r"sep_fused<icl::F32, (\d+), (\d+), (\d+)>", "fused_t{1}_c{2}")]
+            ("sep", r"sep_fused<icl::F32, (\d+), (\d+), (\d+)>", "fused_t{1}_c{2}"),
+            ("sep", r"sep_strip<icl::F32, (\d+), (\d+)>", "strip_t{1}")]
     for kind, pat, fmt in pats:
         m = re.search(pat, name)
         if m:

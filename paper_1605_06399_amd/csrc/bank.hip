@@ -200,6 +200,8 @@ __global__ __launch_bounds__(256) void bank_bwd_edge_k(const float* __restrict__
     constexpr int N = 2 * R + 1, L = EDGE_SEG + 2 * R;
     __shared__ float wl[64 * N * N];
     __shared__ float strip[L * (R + 1)];
+    __shared__ float tab[(R + 1) * N];   // this side's one-axis box sums of the current filter
+    __shared__ float ctab[2][(R + 1) * (R + 1)];   // 2-D box sums of the left / right corner
     for (int i = threadIdx.x; i < F * N * N; i += 256) wl[i] = w[i];
     const int n = blockIdx.x / per_img;
     int s = blockIdx.x - n * per_img, side, a0;
@@ -226,24 +228,89 @@ __global__ __launch_bounds__(256) void bank_bwd_edge_k(const float* __restrict__
     const int syl = qy == 0 ? -R : qy, syh = qy == H - 1 ? H - 1 + R : qy;
     const int pxl = max(sxl - R, 0), pxh = min(sxh + R, W - 1);
     const int pyl = max(syl - R, 0), pyh = min(syh + R, H - 1);
+    // Fast path: a pixel that is on exactly one edge of an image at least two pixels across
+    // that edge.  Its box is then a one-axis interval at depth d from the edge times a
+    // single tap across it, so B_f(q, p) = tab[d][r - e] with e the offset of p along the
+    // edge; tab is summed once per filter.  Corners use a table of 2-D boxes; only one-row
+    // and one-column images take the general loop.
+    const bool fast = side < 2 ? (H > 1 && qx != 0 && qx != W - 1) : W > 1;
+    // corner pixels of an image at least two pixels in each direction: B_f(q, p) is a box
+    // at depth (dy, dx) from both edges, ctab[c][dy][dx] (c = 0 left, 1 right corner)
+    const bool corner = side < 2 && H > 1 && W > 1 && (qx == 0 || qx == W - 1);
+    const bool has_left = side < 2 && H > 1 && W > 1 && a0 == 0;
+    const bool has_right = side < 2 && H > 1 && W > 1 && W - 1 - a0 < EDGE_SEG;
+    const int Dx = min(R + 1, W);
+    const int t = (int)threadIdx.x;
     const size_t hw = (size_t)H * W;
-    float acc = 0.f;
-    for (int f = 0; f < F; ++f) {
+    // The strip of filter f+1 is loaded into registers while filter f is computed (thread
+    // t holds strip entries t, t + 256, ...), so the global loads of the whole walk overlap.
+    constexpr int NPRE = (L * (R + 1) + 255) / 256;
+    float pre[NPRE];
+    auto fetch = [&](int f) {
         const float* g = gy + ((size_t)n * F + f) * hw;
-        __syncthreads();   // taps staged; previous strip consumed
-        for (int idx = threadIdx.x; idx < L * D; idx += 256) {
+#pragma unroll
+        for (int u = 0; u < NPRE; ++u) {
+            const int idx = t + 256 * u;
             const int ai = idx / D, d = idx - ai * D, aa = a0 - R + ai;
             float v = 0.f;
-            if (aa >= 0 && aa < along) {
+            if (idx < L * D && aa >= 0 && aa < along) {
                 int x, y;
                 pixel(aa, d, x, y);
                 v = g[(size_t)y * W + x];
             }
-            strip[idx] = v;
+            pre[u] = v;
+        }
+    };
+    fetch(0);
+    float acc = 0.f;
+    for (int f = 0; f < F; ++f) {
+        __syncthreads();   // taps staged; previous strip and table consumed
+#pragma unroll
+        for (int u = 0; u < NPRE; ++u)
+            if (t + 256 * u < L * D) strip[t + 256 * u] = pre[u];
+        if (f + 1 < F) fetch(f + 1);
+        const float* wf = wl + f * N * N;
+        if (t < (R + 1) * N) {
+            // top: sum over rows ky = -r .. -d; bottom: ky = d .. r; left / right: the same
+            // over columns.  Each box is summed directly, in ascending tap order.
+            const int d = t / N, k = t - d * N;
+            const int lo = side == 0 || side == 2 ? 0 : R + d, hi = side == 0 || side == 2 ? R - d : 2 * R;
+            float b = 0.f;
+            for (int m = lo; m <= hi; ++m) b += side < 2 ? wf[m * N + k] : wf[k * N + m];
+            tab[t] = b;
+        }
+        {
+            // corner boxes: rows -r .. -dy (top) or dy .. r (bottom), columns -r .. -dx
+            // (left corner) or dx .. r (right corner), summed directly
+            const int u = t - 64, c = u / ((R + 1) * (R + 1)), e = u - c * (R + 1) * (R + 1);
+            if (u >= 0 && c < 2 && (c == 0 ? has_left : has_right)) {
+                const int dy = e / (R + 1), dx = e - dy * (R + 1);
+                const int rlo = side == 0 ? 0 : R + dy, rhi = side == 0 ? R - dy : 2 * R;
+                const int clo = c == 0 ? 0 : R + dx, chi = c == 0 ? R - dx : 2 * R;
+                float b = 0.f;
+                for (int m = rlo; m <= rhi; ++m)
+                    for (int l = clo; l <= chi; ++l) b += wf[m * N + l];
+                ctab[c][e] = b;
+            }
         }
         __syncthreads();
         if (!active) continue;
-        const float* wf = wl + f * N * N;
+        if (fast) {
+            for (int d = 0; d < D; ++d) {
+#pragma unroll
+                for (int e = -R; e <= R; ++e) acc = fmaf(strip[(t + e + R) * D + d], tab[d * N + R - e], acc);
+            }
+            continue;
+        }
+        if (corner) {
+            const int c = qx == 0 ? 0 : 1;
+            for (int dy = 0; dy < D; ++dy)
+                for (int dx = 0; dx < Dx; ++dx) {
+                    const int px = c == 0 ? dx : W - 1 - dx;
+                    acc = fmaf(strip[(px - a0 + R) * D + dy], ctab[c][dy * (R + 1) + dx], acc);
+                }
+            continue;
+        }
         for (int py = pyl; py <= pyh; ++py) {
             const int kyl = max(syl - py, -R), kyh = min(syh - py, R);
             for (int px = pxl; px <= pxh; ++px) {
