@@ -490,6 +490,14 @@ def extra_bank(torch, B, T, synth, steps):
         finally:
             B.icl_force_variant(B.ICL_OP_BANK_FWD_SSE, -1)
         per_variant[B.icl_variant_name(B.ICL_OP_BANK_FWD_SSE, v)] = round(fv * 1e3, 3)
+    per_variant_w = {}
+    for v in range(B.icl_variant_count(B.ICL_OP_BANK_BWD_FILTER)):
+        B.check(B.icl_force_variant(B.ICL_OP_BANK_BWD_FILTER, v))
+        try:
+            fv = _time(torch, lambda s: T.bank_bwd_filter(gy, xt, r, out=gw, workspace=wsw), 3)
+        finally:
+            B.icl_force_variant(B.ICL_OP_BANK_BWD_FILTER, -1)
+        per_variant_w[B.icl_variant_name(B.ICL_OP_BANK_BWD_FILTER, v)] = round(fv * 1e3, 3)
     flops = 3 * 2 * 81 * N * F * Hb * Wb
     res["filter_bank_fwd_bwd"] = {"ms": round(dt * 1e3, 3), "gpx_s": round(N * Hb * Wb / dt / 1e9, 2),
                                   "output_gpx_s": round(N * F * Hb * Wb / dt / 1e9, 1),
@@ -497,6 +505,7 @@ def extra_bank(torch, B, T, synth, steps):
                                   "alu_frac": round(flops / dt / 1e12 / FP32_FMA_PEAK_TFLOPS, 3),
                                   "phase_ms": ph,
                                   "fwd_loss_variants_ms": per_variant,
+                                  "bwd_filter_variants_ms": per_variant_w,
                                   "unfused": {"ms": round(dt_u * 1e3, 3), "phase_ms": ph_u}}
     return res
 

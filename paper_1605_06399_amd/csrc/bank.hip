@@ -24,6 +24,9 @@
 //                    (column-walk register reuse), reduces across the wave with a
 //                    butterfly, and writes one partial per tap.  Stage 2 sums the
 //                    partials of each (f, tap) in a fixed order: deterministic.
+//   bank_bwd_w4    : stage 1 with four filters per work-group sharing one staged x
+//                    tile (one wave each), over 64 x 64 or 64 x 256 pixels (four
+//                    staged 64-row sub-tiles before the single cross-lane reduction).
 #include "corr_tile.hpp"
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
@@ -677,7 +680,9 @@ __global__ __launch_bounds__(256) void bank_bwd_in_pers_k(const float* __restric
 // the wave and writes one partial per tap.
 constexpr int GW4_T = 64;
 
-template <int R>
+// TY 64-row sub-tiles per work-group: the wave's (2r+1)^2 accumulators run over all of them
+// before the one cross-lane reduction, so TY > 1 divides that reduction and the partials.
+template <int R, int TY, int CH = GW_CH>
 __global__ __launch_bounds__(256) void bank_bwd_w4_k(const float* __restrict__ gy, const float* __restrict__ x,
                                                      float* __restrict__ part, int F, int H, int W, int tiles_x,
                                                      int tiles_img, int ntiles, int fgroups) {
@@ -688,43 +693,50 @@ __global__ __launch_bounds__(256) void bank_bwd_w4_k(const float* __restrict__ g
     const int tile = (int)(id / (unsigned)fgroups);
     const int n = tile / tiles_img, ti = tile - n * tiles_img;
     int x0, y0;
-    tile_origin(ti, tiles_x, GW4_T, GW4_T, x0, y0);
+    tile_origin(ti, tiles_x, GW4_T, GW4_T * TY, x0, y0);
     const size_t hw = (size_t)H * W;
     const float* xp = x + (size_t)n * hw;
-    for (int idx = threadIdx.x; idx < NR * LW; idx += 256) {
-        const int rr = idx / LW, c = idx - rr * LW;
-        s[idx] = xp[(size_t)clampi(y0 - R + rr, H) * W + clampi(x0 - RA + c, W)];
-    }
-    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int f = fg * 4 + wave;
-    if (f >= F) return;
-    const float* g = gy + ((size_t)n * F + f) * hw;
+    const bool live = f < F;   // a wave past the last filter still joins the barriers
+    const float* g = gy + ((size_t)n * F + (live ? f : 0)) * hw;
     const int gxp = x0 + lane;
     float acc[N][N];
 #pragma unroll
     for (int j = 0; j < N; ++j)
 #pragma unroll
         for (int i = 0; i < N; ++i) acc[j][i] = 0.f;
-#pragma unroll 1
-    for (int r0 = 0; r0 < GW4_T; r0 += GW_CH) {
-        float gv[GW_CH];
-#pragma unroll
-        for (int py = 0; py < GW_CH; ++py) {
-            const int yy = y0 + r0 + py;
-            gv[py] = (gxp < W && yy < H) ? g[(size_t)yy * W + gxp] : 0.f;
+    for (int sub = 0; sub < TY; ++sub) {
+        const int ys = y0 + sub * GW4_T;
+        if (ys >= H) break;   // uniform over the work-group
+        if (sub) __syncthreads();   // the previous sub-tile is consumed
+        for (int idx = threadIdx.x; idx < NR * LW; idx += 256) {
+            const int rr = idx / LW, c = idx - rr * LW;
+            s[idx] = xp[(size_t)clampi(ys - R + rr, H) * W + clampi(x0 - RA + c, W)];
         }
+        __syncthreads();
+        if (!live) continue;
+#pragma unroll 1
+        for (int r0 = 0; r0 < GW4_T; r0 += CH) {
+            float gv[CH];
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            float cv[GW_CH + 2 * R];
+            for (int py = 0; py < CH; ++py) {
+                const int yy = ys + r0 + py;
+                gv[py] = (gxp < W && yy < H) ? g[(size_t)yy * W + gxp] : 0.f;
+            }
 #pragma unroll
-            for (int m = 0; m < GW_CH + 2 * R; ++m) cv[m] = s[(r0 + m) * LW + lane + RA - R + i];
+            for (int i = 0; i < N; ++i) {
+                float cv[CH + 2 * R];
 #pragma unroll
-            for (int j = 0; j < N; ++j)
+                for (int m = 0; m < CH + 2 * R; ++m) cv[m] = s[(r0 + m) * LW + lane + RA - R + i];
 #pragma unroll
-                for (int py = 0; py < GW_CH; ++py) acc[j][i] = fmaf(gv[py], cv[py + j], acc[j][i]);
+                for (int j = 0; j < N; ++j)
+#pragma unroll
+                    for (int py = 0; py < CH; ++py) acc[j][i] = fmaf(gv[py], cv[py + j], acc[j][i]);
+            }
         }
     }
+    if (!live) return;
     float* out = part + (size_t)f * N * N * ntiles + tile;
 #pragma unroll
     for (int j = 0; j < N; ++j)
@@ -805,14 +817,14 @@ hipError_t bwd_in_pers_R(const BankArgs& a) {
     return launch_edge<R>(a);
 }
 
-template <int R>
-hipError_t bwd_w4_R(const BankArgs& a) {
-    const int tx = (a.w + GW4_T - 1) / GW4_T, ty = (a.h + GW4_T - 1) / GW4_T;
+template <int R, int TY, int CH = GW_CH>
+hipError_t bwd_w4_RT(const BankArgs& a) {
+    const int tx = (a.w + GW4_T - 1) / GW4_T, ty = (a.h + GW4_T * TY - 1) / (GW4_T * TY);
     const int ntiles = a.n * tx * ty;
     const int fgroups = (a.f + 3) / 4;
     float* part = static_cast<float*>(a.ws);
-    hipLaunchKernelGGL(bank_bwd_w4_k<R>, dim3((unsigned)(ntiles * fgroups)), dim3(256), 0, a.st, a.a, a.b, part, a.f,
-                       a.h, a.w, tx, tx * ty, ntiles, fgroups);
+    hipLaunchKernelGGL((bank_bwd_w4_k<R, TY, CH>), dim3((unsigned)(ntiles * fgroups)), dim3(256), 0, a.st, a.a, a.b,
+                       part, a.f, a.h, a.w, tx, tx * ty, ntiles, fgroups);
     const int nk = (2 * R + 1) * (2 * R + 1);
     hipLaunchKernelGGL(bank_bwd_w2_k, dim3((unsigned)(a.f * nk)), dim3(256), 0, a.st, part, a.out, ntiles);
     return hipGetLastError();
@@ -832,7 +844,14 @@ hipError_t launch_bwd_in(const BankArgs& a) { ICL_BANK_SWITCH(bwd_in_R) }
 hipError_t launch_bwd_w(const BankArgs& a) { ICL_BANK_SWITCH(bwd_w_R) }
 hipError_t launch_fwd_pers(const BankArgs& a) { ICL_BANK_SWITCH(fwd_pers_R) }
 hipError_t launch_bwd_in_pers(const BankArgs& a) { ICL_BANK_SWITCH(bwd_in_pers_R) }
+template <int R>
+hipError_t bwd_w4_R(const BankArgs& a) { return bwd_w4_RT<R, 1>(a); }
+template <int R>
+hipError_t bwd_w4x4_R(const BankArgs& a) { return bwd_w4_RT<R, 4>(a); }
+
 hipError_t launch_bwd_w4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_w4_R) }
+hipError_t launch_bwd_w4x4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_w4x4_R) }
+
 
 bool supports_bank(const BankArgs& a) { return a.r >= 1 && a.r <= 4 && a.f >= 1 && a.f <= 64; }
 bool supports_pers(const BankArgs& a) { return supports_bank(a) && a.f <= PERS_FMAX; }
@@ -847,7 +866,8 @@ const Variant<BankArgs> kBwdIn[] = {{"plain", supports_bank, launch_bwd_in_plain
                                     {"tile64_p4x4_fold", supports_bank, launch_bwd_in},
                                     {"pers_p4x4_fold", supports_pers, launch_bwd_in_pers}};
 const Variant<BankArgs> kBwdW[] = {{"wave_t32x64", supports_bwd_w, launch_bwd_w},
-                                   {"block4_t64", supports_bwd_w, launch_bwd_w4}};
+                                   {"block4_t64", supports_bwd_w, launch_bwd_w4},
+                                   {"block4_t64x256", supports_bwd_w, launch_bwd_w4x4}};
 
 // ------------------------------------------------------------------ sum of squares loss
 constexpr int SSE_BLOCKS = 2048;
@@ -1049,7 +1069,7 @@ const Variant<BankArgs>* bank_bwd_filter_variants(int* count) {
 
 int bank_fwd_default(const BankArgs& a) { return supports_pers(a) ? 2 : 1; }
 int bank_bwd_input_default(const BankArgs& a) { return supports_pers(a) ? 2 : 1; }
-int bank_bwd_filter_default(const BankArgs&) { return 1; }
+int bank_bwd_filter_default(const BankArgs&) { return 2; }   // block4_t64x256
 const Variant<BankSseArgs>* bank_fwd_sse_variants(int* count) {
     *count = (int)(sizeof(kFwdSse) / sizeof(kFwdSse[0]));
     return kFwdSse;
