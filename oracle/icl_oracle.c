@@ -15,7 +15,8 @@
  * Boundary handling is the clamped condition of Section 5 / Fig. 3(a): a read
  * outside the image returns the closest pixel inside it.  Per axis that is
  * min(max(i, 0), n-1), and the per-axis clamp is the closest pixel in the
- * Euclidean sense too (corners included).
+ * Euclidean sense too (corners included).  The convolutions also take the
+ * constant condition of Fig. 3(b): a read outside the image returns a constant.
  *
  * Parity pins (all checked by the CPU test-suite, none by re-typing a formula):
  *   conv2d / conv_sep : delta filter reproduces the input bit-exactly; a shifted
@@ -25,7 +26,14 @@
  *                       the separable pair equals the brute-force outer-product
  *                       2-D filter; 1x1 images give X * sum(w); the 3x3 box
  *                       filter of Listing 1 on integer images is exact;
- *                       linearity and transposition.
+ *                       linearity and transposition.  Constant boundary: equal
+ *                       to a correlation of the constant-padded image computed
+ *                       by numpy slicing; hand-worked 3x3 box sums; a constant
+ *                       image equal to the constant gives c * sum(w).
+ *   conv2d_u8         : exact integer sums against numpy int64 slicing of the
+ *                       padded image; delta taps reproduce the input; rounding
+ *                       ties and saturation worked by hand; agreement with the
+ *                       float oracle followed by the rounding rule.
  *   harris            : constant image gives R = 0 exactly; the linear ramp
  *                       a*x + b*y gives R = -k (64 (a^2+b^2))^2 away from the
  *                       edges; transposition; brute force on tiny images.
@@ -53,69 +61,149 @@ static inline double at(const double* X, long W, long H, long x, long y) {
     return X[clampi(y, H) * W + clampi(x, W)];
 }
 
+/* The two boundary conditions of Section 5 (Fig. 3): ORC_CLAMP reads the closest pixel
+ * inside the image, ORC_CONSTANT returns the constant c for every read outside it. */
+enum { ORC_CLAMP = 0, ORC_CONSTANT = 1 };
+
+static inline int outside(long W, long H, long x, long y) { return x < 0 || x >= W || y < 0 || y >= H; }
+
+static inline double at_b(const double* X, long W, long H, long x, long y, int border, double c) {
+    if (border == ORC_CONSTANT && outside(W, H, x, y)) return c;
+    return at(X, W, H, x, y);
+}
+
 /* ---------------------------------------------------------------- 2-D correlation
  * Y(x,y) = sum_{j=-r..r} sum_{i=-r..r} w[(j+r)(2r+1) + (i+r)] * X(x+i, y+j)
- * (non-separable convolution benchmark, Section 6; taps known at run time). */
-static double conv2d_px(const double* X, long W, long H, const double* w, int r, long x, long y) {
+ * (non-separable convolution benchmark, Section 6; taps known at run time),
+ * every read through the boundary condition. */
+static double conv2d_px(const double* X, long W, long H, const double* w, int r, int border, double c,
+                        long x, long y) {
     const int n = 2 * r + 1;
     double acc = 0.0;
     for (int j = -r; j <= r; ++j)
         for (int i = -r; i <= r; ++i)
-            acc += w[(j + r) * n + (i + r)] * at(X, W, H, x + i, y + j);
+            acc += w[(j + r) * n + (i + r)] * at_b(X, W, H, x + i, y + j, border, c);
     return acc;
 }
 
-EXPORT void orc_conv2d(const double* X, long W, long H, const double* w, int r, double* Y, int nthreads) {
+EXPORT void orc_conv2d(const double* X, long W, long H, const double* w, int r, int border, double c,
+                       double* Y, int nthreads) {
 #pragma omp parallel for num_threads(nthreads) schedule(static)
     for (long y = 0; y < H; ++y)
         for (long x = 0; x < W; ++x)
-            Y[y * W + x] = conv2d_px(X, W, H, w, r, x, y);
+            Y[y * W + x] = conv2d_px(X, W, H, w, r, border, c, x, y);
 }
 
-EXPORT void orc_conv2d_pts(const double* X, long W, long H, const double* w, int r,
+EXPORT void orc_conv2d_pts(const double* X, long W, long H, const double* w, int r, int border, double c,
                            const long* xs, const long* ys, long npts, double* out, int nthreads) {
 #pragma omp parallel for num_threads(nthreads) schedule(static)
-    for (long p = 0; p < npts; ++p) out[p] = conv2d_px(X, W, H, w, r, xs[p], ys[p]);
+    for (long p = 0; p < npts; ++p) out[p] = conv2d_px(X, W, H, w, r, border, c, xs[p], ys[p]);
 }
 
 /* ---------------------------------------------------------------- separable convolution
  * Row (R) kernel then column (C) kernel, as the paper's separable benchmark
  * splits it (Section 6, Table 2):
  *   T(x,y) = sum_i h[i+r] X(x+i, y)        Y(x,y) = sum_j v[j+r] T(x, y+j)
- * with both reads clamped.  The intermediate T is kept in double. */
+ * The intermediate T is kept in double.  The pair is the 2-D filter v (x) h on the
+ * image extended by the boundary condition, so T is defined for every row the column
+ * pass reads: under the clamped condition row y + j outside the image is row
+ * clamp(y + j) (the closest pixel of the extended image); under the constant
+ * condition every pixel of such a row is c, so T there is sum_i h[i+r] c. */
+static double row_pass_px(const double* X, long W, long H, const double* h, int r, int border, double c,
+                          long x, long y) {
+    double acc = 0.0;
+    for (int i = -r; i <= r; ++i) acc += h[i + r] * at_b(X, W, H, x + i, y, border, c);
+    return acc;
+}
+
+static double row_pass_outside(const double* h, int r, double c) {
+    double acc = 0.0;
+    for (int i = -r; i <= r; ++i) acc += h[i + r] * c;
+    return acc;
+}
+
 EXPORT void orc_conv_sep(const double* X, long W, long H, const double* h, const double* v, int r,
-                         double* T, double* Y, int nthreads) {
+                         int border, double c, double* T, double* Y, int nthreads) {
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) T[y * W + x] = row_pass_px(X, W, H, h, r, border, c, x, y);
+    const double t_out = row_pass_outside(h, r, c);
 #pragma omp parallel for num_threads(nthreads) schedule(static)
     for (long y = 0; y < H; ++y)
         for (long x = 0; x < W; ++x) {
             double acc = 0.0;
-            for (int i = -r; i <= r; ++i) acc += h[i + r] * at(X, W, H, x + i, y);
-            T[y * W + x] = acc;
-        }
-#pragma omp parallel for num_threads(nthreads) schedule(static)
-    for (long y = 0; y < H; ++y)
-        for (long x = 0; x < W; ++x) {
-            double acc = 0.0;
-            for (int j = -r; j <= r; ++j) acc += v[j + r] * at(T, W, H, x, y + j);
+            for (int j = -r; j <= r; ++j) {
+                const long yy = y + j;
+                const double t = (border == ORC_CONSTANT && (yy < 0 || yy >= H)) ? t_out : at(T, W, H, x, yy);
+                acc += v[j + r] * t;
+            }
             Y[y * W + x] = acc;
         }
 }
 
 /* the same two passes evaluated at single output pixels (row pass recomputed per column tap) */
 EXPORT void orc_conv_sep_pts(const double* X, long W, long H, const double* h, const double* v, int r,
-                             const long* xs, const long* ys, long npts, double* out, int nthreads) {
+                             int border, double c, const long* xs, const long* ys, long npts, double* out,
+                             int nthreads) {
+    const double t_out = row_pass_outside(h, r, c);
 #pragma omp parallel for num_threads(nthreads) schedule(static)
     for (long p = 0; p < npts; ++p) {
         const long x = xs[p], y = ys[p];
         double acc = 0.0;
         for (int j = -r; j <= r; ++j) {
-            const long yy = clampi(y + j, H);
-            double t = 0.0;
-            for (int i = -r; i <= r; ++i) t += h[i + r] * at(X, W, H, x + i, yy);
+            const long yy = y + j;
+            const double t = (border == ORC_CONSTANT && (yy < 0 || yy >= H))
+                                 ? t_out
+                                 : row_pass_px(X, W, H, h, r, border, c, x, clampi(yy, H));
             acc += v[j + r] * t;
         }
         out[p] = acc;
     }
+}
+
+/* ---------------------------------------------------------------- 8-bit 2-D correlation
+ * The non-separable benchmark of Section 6 runs on unsigned char pixels.  Taps are
+ * signed 16-bit integers and the sum is exact integer arithmetic (here in 64 bits):
+ *   S(x,y) = sum_{j,i} w[(j+r)(2r+1) + (i+r)] * X(x+i, y+j)
+ *   Y(x,y) = min(max(floor((S + b) / 2^shift), 0), 255),  b = 2^(shift-1) (0 if shift = 0)
+ * i.e. the fixed-point sum rounded to nearest with ties upward, then saturated to
+ * 0..255.  Reads go through the boundary condition (constant c in 0..255). */
+static inline long long floor_div_pow2(long long a, int shift) {
+    const long long d = 1LL << shift;
+    long long q = a / d;                       /* C division truncates toward zero */
+    if (a % d != 0 && a < 0) q -= 1;
+    return q;
+}
+
+static unsigned char conv2d_u8_px(const unsigned char* X, long W, long H, const int16_t* w, int r, int shift,
+                                  int border, int c, long x, long y) {
+    const int n = 2 * r + 1;
+    long long acc = 0;
+    for (int j = -r; j <= r; ++j)
+        for (int i = -r; i <= r; ++i) {
+            const long xx = x + i, yy = y + j;
+            const long long p = (border == ORC_CONSTANT && outside(W, H, xx, yy))
+                                    ? (long long)c
+                                    : (long long)X[clampi(yy, H) * W + clampi(xx, W)];
+            acc += (long long)w[(j + r) * n + (i + r)] * p;
+        }
+    const long long b = shift > 0 ? (1LL << (shift - 1)) : 0;
+    const long long q = floor_div_pow2(acc + b, shift);
+    return (unsigned char)(q < 0 ? 0 : (q > 255 ? 255 : q));
+}
+
+EXPORT void orc_conv2d_u8(const unsigned char* X, long W, long H, const int16_t* w, int r, int shift,
+                          int border, int c, unsigned char* Y, int nthreads) {
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) Y[y * W + x] = conv2d_u8_px(X, W, H, w, r, shift, border, c, x, y);
+}
+
+EXPORT void orc_conv2d_u8_pts(const unsigned char* X, long W, long H, const int16_t* w, int r, int shift,
+                              int border, int c, const long* xs, const long* ys, long npts, unsigned char* out,
+                              int nthreads) {
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (long p = 0; p < npts; ++p) out[p] = conv2d_u8_px(X, W, H, w, r, shift, border, c, xs[p], ys[p]);
 }
 
 /* ---------------------------------------------------------------- Harris corner response
@@ -286,7 +374,7 @@ EXPORT void orc_bank_fwd(const double* x, const double* w, long N, long F, long 
     const long hw = H * W, nk = (2 * r + 1) * (2 * r + 1);
     for (long n = 0; n < N; ++n)
         for (long f = 0; f < F; ++f)
-            orc_conv2d(x + n * hw, W, H, w + f * nk, r, y + (n * F + f) * hw, nthreads);
+            orc_conv2d(x + n * hw, W, H, w + f * nk, r, ORC_CLAMP, 0.0, y + (n * F + f) * hw, nthreads);
 }
 
 EXPORT double orc_sse_loss(const double* y, const double* t, long count, double* gy) {

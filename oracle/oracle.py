@@ -25,6 +25,10 @@ _D = ctypes.POINTER(ctypes.c_double)
 _L = ctypes.POINTER(ctypes.c_long)
 _U16 = ctypes.POINTER(ctypes.c_uint16)
 _U8 = ctypes.POINTER(ctypes.c_uint8)
+_I16 = ctypes.POINTER(ctypes.c_int16)
+
+# boundary conditions (Section 5, Fig. 3)
+BORDERS = {"clamp": 0, "constant": 1}
 
 
 def build(force: bool = True) -> str:
@@ -45,10 +49,14 @@ def lib():
             build()
         L = ctypes.CDLL(_LIB)
         c_long, c_int, c_double = ctypes.c_long, ctypes.c_int, ctypes.c_double
-        L.orc_conv2d.argtypes = [_D, c_long, c_long, _D, c_int, _D, c_int]
-        L.orc_conv2d_pts.argtypes = [_D, c_long, c_long, _D, c_int, _L, _L, c_long, _D, c_int]
-        L.orc_conv_sep.argtypes = [_D, c_long, c_long, _D, _D, c_int, _D, _D, c_int]
-        L.orc_conv_sep_pts.argtypes = [_D, c_long, c_long, _D, _D, c_int, _L, _L, c_long, _D, c_int]
+        L.orc_conv2d.argtypes = [_D, c_long, c_long, _D, c_int, c_int, c_double, _D, c_int]
+        L.orc_conv2d_pts.argtypes = [_D, c_long, c_long, _D, c_int, c_int, c_double, _L, _L, c_long, _D, c_int]
+        L.orc_conv_sep.argtypes = [_D, c_long, c_long, _D, _D, c_int, c_int, c_double, _D, _D, c_int]
+        L.orc_conv_sep_pts.argtypes = [_D, c_long, c_long, _D, _D, c_int, c_int, c_double, _L, _L, c_long, _D,
+                                       c_int]
+        L.orc_conv2d_u8.argtypes = [_U8, c_long, c_long, _I16, c_int, c_int, c_int, c_int, _U8, c_int]
+        L.orc_conv2d_u8_pts.argtypes = [_U8, c_long, c_long, _I16, c_int, c_int, c_int, c_int, _L, _L, c_long,
+                                        _U8, c_int]
         L.orc_harris.argtypes = [_D, c_long, c_long, _D, c_int, c_double, _D, _D, _D, _D, _D, c_int]
         L.orc_harris_pts.argtypes = [_D, c_long, c_long, _D, c_int, c_double, _L, _L, c_long,
                                      _D, _D, _D, _D, c_int]
@@ -113,30 +121,33 @@ def encode(values: np.ndarray, dtype: str) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------- stencils
+# border: "clamp" (closest pixel inside, Fig. 3a) or "constant" (reads outside return
+# `constant`, Fig. 3b).
 
-def conv2d(X, w, nthreads=None):
+def conv2d(X, w, nthreads=None, border="clamp", constant=0.0):
     X = _f64(X)
     w = _f64(w)
     H, W = X.shape
     r = (w.shape[-1] - 1) // 2
     assert w.size == (2 * r + 1) ** 2
     Y = np.empty_like(X)
-    lib().orc_conv2d(_p(X), W, H, _p(w), r, _p(Y), _threads(nthreads))
+    lib().orc_conv2d(_p(X), W, H, _p(w), r, BORDERS[border], float(constant), _p(Y), _threads(nthreads))
     return Y
 
 
-def conv2d_pts(X, w, xs, ys, nthreads=None):
+def conv2d_pts(X, w, xs, ys, nthreads=None, border="clamp", constant=0.0):
     X = _f64(X)
     w = _f64(w)
     H, W = X.shape
     r = (w.shape[-1] - 1) // 2
     xs, ys = _pts(xs, ys)
     out = np.empty(xs.shape, dtype=np.float64)
-    lib().orc_conv2d_pts(_p(X), W, H, _p(w), r, _p(xs, _L), _p(ys, _L), xs.size, _p(out), _threads(nthreads))
+    lib().orc_conv2d_pts(_p(X), W, H, _p(w), r, BORDERS[border], float(constant), _p(xs, _L), _p(ys, _L),
+                         xs.size, _p(out), _threads(nthreads))
     return out
 
 
-def conv_sep(X, h, v, nthreads=None, return_intermediate=False):
+def conv_sep(X, h, v, nthreads=None, return_intermediate=False, border="clamp", constant=0.0):
     X = _f64(X)
     h = _f64(h)
     v = _f64(v)
@@ -145,11 +156,12 @@ def conv_sep(X, h, v, nthreads=None, return_intermediate=False):
     assert h.size == v.size == 2 * r + 1
     T = np.empty_like(X)
     Y = np.empty_like(X)
-    lib().orc_conv_sep(_p(X), W, H, _p(h), _p(v), r, _p(T), _p(Y), _threads(nthreads))
+    lib().orc_conv_sep(_p(X), W, H, _p(h), _p(v), r, BORDERS[border], float(constant), _p(T), _p(Y),
+                       _threads(nthreads))
     return (Y, T) if return_intermediate else Y
 
 
-def conv_sep_pts(X, h, v, xs, ys, nthreads=None):
+def conv_sep_pts(X, h, v, xs, ys, nthreads=None, border="clamp", constant=0.0):
     X = _f64(X)
     h = _f64(h)
     v = _f64(v)
@@ -157,8 +169,37 @@ def conv_sep_pts(X, h, v, xs, ys, nthreads=None):
     r = (h.size - 1) // 2
     xs, ys = _pts(xs, ys)
     out = np.empty(xs.shape, dtype=np.float64)
-    lib().orc_conv_sep_pts(_p(X), W, H, _p(h), _p(v), r, _p(xs, _L), _p(ys, _L), xs.size, _p(out),
-                           _threads(nthreads))
+    lib().orc_conv_sep_pts(_p(X), W, H, _p(h), _p(v), r, BORDERS[border], float(constant), _p(xs, _L),
+                           _p(ys, _L), xs.size, _p(out), _threads(nthreads))
+    return out
+
+
+def _u8_args(X, w, shift, constant):
+    X = np.ascontiguousarray(X, dtype=np.uint8)
+    w = np.ascontiguousarray(w, dtype=np.int16)
+    r = (w.shape[-1] - 1) // 2
+    assert w.size == (2 * r + 1) ** 2
+    assert 0 <= int(shift) <= 16 and 0 <= int(constant) <= 255
+    return X, w, r
+
+
+def conv2d_u8(X, w, shift, nthreads=None, border="clamp", constant=0):
+    """Integer correlation of an unsigned char image: exact sum, round (ties up), saturate."""
+    X, w, r = _u8_args(X, w, shift, constant)
+    H, W = X.shape
+    Y = np.empty_like(X)
+    lib().orc_conv2d_u8(_p(X, _U8), W, H, _p(w, _I16), r, int(shift), BORDERS[border], int(constant),
+                        _p(Y, _U8), _threads(nthreads))
+    return Y
+
+
+def conv2d_u8_pts(X, w, shift, xs, ys, nthreads=None, border="clamp", constant=0):
+    X, w, r = _u8_args(X, w, shift, constant)
+    H, W = X.shape
+    xs, ys = _pts(xs, ys)
+    out = np.empty(xs.shape, dtype=np.uint8)
+    lib().orc_conv2d_u8_pts(_p(X, _U8), W, H, _p(w, _I16), r, int(shift), BORDERS[border], int(constant),
+                            _p(xs, _L), _p(ys, _L), xs.size, _p(out, _U8), _threads(nthreads))
     return out
 
 
@@ -279,13 +320,14 @@ def bank_bwd_filter(gy, x, radius, fk_range=None, nthreads=None):
 
 # ----------------------------------------------------------------------------- tolerance helpers
 
-def normwise_scale_conv2d(X, w, nthreads=None):
+def normwise_scale_conv2d(X, w, nthreads=None, border="clamp", constant=0.0):
     """S(p) = sum_k |w_k| |X(p+k)|: the same stencil on absolute values."""
-    return conv2d(np.abs(_f64(X)), np.abs(_f64(w)), nthreads)
+    return conv2d(np.abs(_f64(X)), np.abs(_f64(w)), nthreads, border=border, constant=abs(constant))
 
 
-def normwise_scale_sep(X, h, v, nthreads=None):
-    return conv_sep(np.abs(_f64(X)), np.abs(_f64(h)), np.abs(_f64(v)), nthreads)
+def normwise_scale_sep(X, h, v, nthreads=None, border="clamp", constant=0.0):
+    return conv_sep(np.abs(_f64(X)), np.abs(_f64(h)), np.abs(_f64(v)), nthreads, border=border,
+                    constant=abs(constant))
 
 
 def response_scale(sxx, syy, sxy, k):

@@ -104,6 +104,11 @@ def integer_image(config: int, height: int, width: int, hi: int = 255) -> np.nda
     return randint(seed(config, PIXELS), height * width, 0, hi).reshape(height, width).astype(np.float32)
 
 
+def u8_image(config: int, height: int, width: int) -> np.ndarray:
+    """unsigned char image, bytes uniform on 0..255."""
+    return randint(seed(config, PIXELS), height * width, 0, 255).reshape(height, width).astype(np.uint8)
+
+
 # ----------------------------------------------------------------------------- taps
 
 def gaussian_taps(radius: int, sigma: float) -> np.ndarray:
@@ -204,6 +209,27 @@ def sweep_taps_sep(r: int):
 def sweep_taps_2d(r: int) -> np.ndarray:
     n = 2 * r + 1
     return normal_taps_normalised(2, n * n, stream=10 * r + 2).reshape(n, n)
+
+
+def u8_taps(config: int, radius: int, shift: int) -> np.ndarray:
+    """Signed 16-bit fixed-point taps with `shift` fraction bits: a sampled Gaussian
+    (sigma = r/2, or 1 for r <= 2) scaled by 2^shift and rounded, plus seeded integer
+    noise of up to 2^(shift-4) per tap, so the filter is non-separable and has negative
+    taps while its sum stays near 2^shift."""
+    n = 2 * radius + 1
+    g = gaussian_taps(radius, max(1.0, radius / 2.0)).astype(np.float64) if radius else np.ones(1)
+    base = np.rint(np.outer(g, g) * (1 << shift)).astype(np.int64)
+    amp = max(1, 1 << max(shift - 4, 0))
+    noise = randint(seed(config, TAPS), n * n, -amp, amp).reshape(n, n)
+    return np.clip(base + noise, -32768, 32767).astype(np.int16)
+
+
+U8_SHIFT = 12
+
+
+def paper_u8_image(side: int = 8192) -> np.ndarray:
+    """Non-separable convolution workload of Section 6: side x side unsigned char."""
+    return u8_image(6, side, side)
 
 
 def corner_image(side: int = 8192) -> np.ndarray:

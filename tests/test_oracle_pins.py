@@ -239,6 +239,174 @@ def test_points_match_full_image(orc):
     assert np.allclose(orc.conv_sep_pts(X, h, v, xs, ys), orc.conv_sep(X, h, v).ravel(), rtol=0, atol=1e-13)
 
 
+# ----------------------------------------------------------------------------- constant boundary
+
+def padded_correlation(X, w, mode, c=0.0):
+    """Correlation of the padded image by whole-array slicing: Xp = pad(X, r) and
+    Y = sum_{j,i} w[j, i] Xp[j:j+H, i:i+W] (a formulation with no per-pixel boundary test)."""
+    H, W = X.shape
+    r = (w.shape[0] - 1) // 2
+    if mode == "constant":
+        Xp = np.pad(np.asarray(X, dtype=np.float64), r, mode="constant", constant_values=c)
+    else:
+        Xp = np.pad(np.asarray(X, dtype=np.float64), r, mode="edge")
+    Y = np.zeros((H, W))
+    for j in range(2 * r + 1):
+        for i in range(2 * r + 1):
+            Y += float(w[j, i]) * Xp[j:j + H, i:i + W]
+    return Y
+
+
+def test_constant_border_box_hand_worked(orc):
+    g = _golden("box3x3_constant.json")
+    X = np.array(g["image"], dtype=np.float64)
+    for c, key in ((0.0, "expected_constant_0"), (float(g["constant"]), "expected_constant_10")):
+        exp = np.array(g[key], dtype=np.float64)
+        assert np.array_equal(orc.conv2d(X, np.ones((3, 3)), border="constant", constant=c), exp)
+        assert np.array_equal(orc.conv_sep(X, np.ones(3), np.ones(3), border="constant", constant=c), exp)
+
+
+@pytest.mark.parametrize("r,H,W,c", [(1, 7, 9, 0.0), (2, 8, 5, 0.37), (3, 6, 11, -1.5), (4, 3, 5, 2.0)])
+def test_constant_border_matches_padded_slicing(orc, r, H, W, c):
+    n = 2 * r + 1
+    X = synth.image_uniform(40 + r, H, W).astype(np.float64)
+    w = synth.normal(synth.seed(40 + r, 1), n * n).astype(np.float64).reshape(n, n)
+    assert np.allclose(orc.conv2d(X, w, border="constant", constant=c), padded_correlation(X, w, "constant", c),
+                       rtol=0, atol=1e-12)
+    # the separable pair is the 2-D filter v (x) h on the constant-extended image, c != 0 included
+    h = synth.normal(synth.seed(40 + r, 2), n).astype(np.float64)
+    v = synth.normal(synth.seed(40 + r, 3), n).astype(np.float64)
+    ref = padded_correlation(X, np.outer(v, h), "constant", c)
+    assert np.allclose(orc.conv_sep(X, h, v, border="constant", constant=c), ref, rtol=0, atol=1e-12)
+    # and the clamped condition is numpy's edge padding
+    assert np.allclose(orc.conv2d(X, w), padded_correlation(X, w, "edge"), rtol=0, atol=1e-12)
+
+
+def test_constant_border_shifted_delta(orc):
+    """A single tap at (a, b): inside pixels read X(x+a, y+b), the others read exactly c."""
+    r, H, W, c = 2, 5, 6, 0.8125
+    X = synth.image_uniform(44, H, W).astype(np.float64)
+    for a, b in ((2, -1), (-2, 2), (0, 1)):
+        w = np.zeros((2 * r + 1, 2 * r + 1))
+        w[b + r, a + r] = 1.0
+        Y = orc.conv2d(X, w, border="constant", constant=c)
+        for y in range(H):
+            for x in range(W):
+                inside = 0 <= x + a < W and 0 <= y + b < H
+                assert Y[y, x] == (X[y + b, x + a] if inside else c)
+
+
+def test_constant_border_zero_image_counts_outside_taps(orc):
+    """X = 0 with constant 1 and integer taps: each output is the sum of the taps whose
+    read falls outside the image, counted directly."""
+    r, H, W = 2, 4, 7
+    n = 2 * r + 1
+    w = np.arange(1, n * n + 1, dtype=np.float64).reshape(n, n)
+    Y = orc.conv2d(np.zeros((H, W)), w, border="constant", constant=1.0)
+    for y in range(H):
+        for x in range(W):
+            exp = sum(w[j + r, i + r] for j in range(-r, r + 1) for i in range(-r, r + 1)
+                      if not (0 <= x + i < W and 0 <= y + j < H))
+            assert Y[y, x] == exp
+
+
+def test_constant_border_points_match_full(orc):
+    r, H, W, c = 3, 19, 23, 0.25
+    n = 2 * r + 1
+    X = synth.image_uniform(45, H, W).astype(np.float64)
+    w = synth.normal(synth.seed(45, 1), n * n).astype(np.float64).reshape(n, n)
+    h = synth.normal(synth.seed(45, 2), n).astype(np.float64)
+    v = synth.normal(synth.seed(45, 3), n).astype(np.float64)
+    ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    xs, ys = xs.ravel(), ys.ravel()
+    kw = dict(border="constant", constant=c)
+    assert np.allclose(orc.conv2d_pts(X, w, xs, ys, **kw), orc.conv2d(X, w, **kw).ravel(), rtol=0, atol=1e-13)
+    assert np.allclose(orc.conv_sep_pts(X, h, v, xs, ys, **kw), orc.conv_sep(X, h, v, **kw).ravel(),
+                       rtol=0, atol=1e-13)
+
+
+# ----------------------------------------------------------------------------- unsigned char, integer taps
+
+def u8_reference(X, w, shift, mode, c=0):
+    """Exact sum by int64 slicing of the padded image, then the rounding rule written with
+    numpy's arithmetic shift (floor) and a clip."""
+    H, W = X.shape
+    r = (w.shape[0] - 1) // 2
+    if mode == "constant":
+        Xp = np.pad(X.astype(np.int64), r, mode="constant", constant_values=c)
+    else:
+        Xp = np.pad(X.astype(np.int64), r, mode="edge")
+    S = np.zeros((H, W), dtype=np.int64)
+    for j in range(2 * r + 1):
+        for i in range(2 * r + 1):
+            S += int(w[j, i]) * Xp[j:j + H, i:i + W]
+    b = (1 << (shift - 1)) if shift > 0 else 0
+    return np.clip((S + b) >> shift, 0, 255).astype(np.uint8)
+
+
+@pytest.mark.parametrize("r,shift,mode,c", [(0, 0, "clamp", 0), (1, 7, "constant", 200), (2, 12, "clamp", 0),
+                                            (2, 12, "constant", 0), (3, 16, "constant", 17), (7, 12, "clamp", 0)])
+def test_u8_matches_int64_slicing(orc, r, shift, mode, c):
+    n = 2 * r + 1
+    X = synth.u8_image(50 + r, 13, 17)
+    w = synth.randint(synth.seed(50 + r, 1), n * n, -32768, 32767).reshape(n, n).astype(np.int16)
+    assert np.array_equal(orc.conv2d_u8(X, w, shift, border=mode, constant=c), u8_reference(X, w, shift, mode, c))
+    w2 = synth.u8_taps(50 + r, r, shift) if shift >= 4 else w
+    assert np.array_equal(orc.conv2d_u8(X, w2, shift, border=mode, constant=c),
+                          u8_reference(X, w2, shift, mode, c))
+
+
+@pytest.mark.parametrize("shift", [0, 5, 14])
+def test_u8_delta_reproduces_input(orc, shift):
+    X = synth.u8_image(55, 9, 10)
+    w = np.zeros((5, 5), dtype=np.int16)
+    w[2, 2] = 1 << shift
+    assert np.array_equal(orc.conv2d_u8(X, w, shift), X)
+    assert np.array_equal(orc.conv2d_u8(X, w, shift, border="constant", constant=99), X)
+
+
+def test_u8_rounding_ties_and_saturation_hand_worked(orc):
+    # (X(x-1) + X(x+1) + 1) >> 1 on [1, 2, 3] with clamped reads: sums 3, 4, 5 -> 2, 2, 3
+    X = np.array([[1, 2, 3]], dtype=np.uint8)
+    w = np.zeros((3, 3), dtype=np.int16)
+    w[1, 0] = w[1, 2] = 1
+    assert orc.conv2d_u8(X, w, 1).tolist() == [[2, 2, 3]]
+    # constant 0 instead: sums 2, 4, 2 -> 1, 2, 1
+    assert orc.conv2d_u8(X, w, 1, border="constant", constant=0).tolist() == [[1, 2, 1]]
+    c = np.zeros((1, 1), dtype=np.int16)
+    c[0, 0] = 300
+    assert orc.conv2d_u8(X, c, 0).tolist() == [[255, 255, 255]]
+    c[0, 0] = -1
+    assert orc.conv2d_u8(X, c, 0).tolist() == [[0, 0, 0]]
+    # 3 * 5 = 15 with shift 2: 15 / 4 = 3.75 -> 4;  1 * 6 = 6: 1.5 -> 2 (tie upward)
+    c[0, 0] = 5
+    assert orc.conv2d_u8(np.array([[3]], dtype=np.uint8), c, 2).tolist() == [[4]]
+    c[0, 0] = 6
+    assert orc.conv2d_u8(np.array([[1]], dtype=np.uint8), c, 2).tolist() == [[2]]
+
+
+def test_u8_agrees_with_float_oracle(orc):
+    """Integer sums below 2^53 are exact in double: the u8 result is the float oracle's
+    correlation followed by the rounding rule."""
+    r, shift = 2, 12
+    X = synth.u8_image(56, 21, 33)
+    w = synth.u8_taps(56, r, shift)
+    for mode, c in (("clamp", 0), ("constant", 128)):
+        S = orc.conv2d(X.astype(np.float64), w.astype(np.float64), border=mode, constant=float(c))
+        exp = np.clip(np.floor((S + 2.0 ** (shift - 1)) / 2.0 ** shift), 0, 255).astype(np.uint8)
+        assert np.array_equal(orc.conv2d_u8(X, w, shift, border=mode, constant=c), exp)
+
+
+def test_u8_points_match_full(orc):
+    X = synth.u8_image(57, 15, 26)
+    w = synth.u8_taps(57, 3, 12)
+    ys, xs = np.meshgrid(np.arange(15), np.arange(26), indexing="ij")
+    xs, ys = xs.ravel(), ys.ravel()
+    for mode in ("clamp", "constant"):
+        assert np.array_equal(orc.conv2d_u8_pts(X, w, 12, xs, ys, border=mode, constant=7),
+                              orc.conv2d_u8(X, w, 12, border=mode, constant=7).ravel())
+
+
 # ----------------------------------------------------------------------------- Harris
 
 G5 = synth.gaussian_taps(2, 1.0).astype(np.float64)
