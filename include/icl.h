@@ -16,6 +16,8 @@
  *    must satisfy pitch >= width * elem_size and pitch % elem_size == 0.
  *  - Boundary: clamped (Section 5, Fig. 3a): a read outside the image returns
  *    the closest pixel inside, i.e. x -> min(max(x, 0), width-1), same for y.
+ *    The convolution calls with an icl_border argument also take the constant
+ *    condition (Fig. 3b): every read outside the image returns a given constant.
  *  - Image, tap and workspace pointers are DEVICE pointers unless stated.
  *    Filter taps are float32 in device memory and are read at run time, so taps
  *    updated in place are seen by later calls and by graph replays.
@@ -61,7 +63,14 @@ typedef enum icl_status {
     ICL_ERR_TUNE_CACHE = 10    /* tune cache unreadable or written for another device */
 } icl_status;
 
-typedef enum icl_dtype { ICL_F32 = 0, ICL_F16 = 1, ICL_BF16 = 2 } icl_dtype;
+/* pixel storage types; ICL_U8 (unsigned char) only for icl_conv2d_u8 */
+typedef enum icl_dtype { ICL_F32 = 0, ICL_F16 = 1, ICL_BF16 = 2, ICL_U8 = 3 } icl_dtype;
+
+/* boundary conditions (Section 5, Fig. 3) */
+typedef enum icl_border {
+    ICL_BORDER_CLAMP = 0,     /* a read outside returns the closest pixel inside */
+    ICL_BORDER_CONSTANT = 1   /* a read outside returns the given constant */
+} icl_border;
 
 /* operations, for icl_workspace_size / icl_tune / variant control */
 typedef enum icl_op {
@@ -75,12 +84,15 @@ typedef enum icl_op {
     ICL_OP_BANK_BWD_FILTER = 7,
     ICL_OP_SSE_LOSS = 8,
     ICL_OP_BANK_FWD_SSE = 9,
-    ICL_OP_COUNT = 10
+    ICL_OP_CONV2D_U8 = 10,
+    ICL_OP_COUNT = 11
 } icl_op;
 
 #define ICL_MAX_RADIUS 16          /* largest stencil radius accepted by the convolution calls */
 #define ICL_MAX_WINDOW_RADIUS 7    /* largest Harris window radius */
 #define ICL_MAX_NMS_RADIUS 7
+#define ICL_MAX_U8_RADIUS 7        /* largest radius of icl_conv2d_u8 (keeps its int32 sum exact) */
+#define ICL_MAX_U8_SHIFT 16
 
 /* ------------------------------------------------------------------ library */
 
@@ -119,6 +131,19 @@ icl_status icl_conv_sep(const void* src, size_t src_pitch, void* dst, size_t dst
                         const float* taps_x, const float* taps_y, int radius,
                         void* workspace, size_t workspace_bytes, void* stream);
 
+/* icl_conv_sep under a chosen boundary condition (Section 5, Fig. 3; the paper's
+ * separable benchmark uses the constant one).  With ICL_BORDER_CONSTANT the filter
+ * is the 2-D correlation with taps taps_y (x) taps_x of the image extended by
+ * `constant`: a row of T outside the image is sum_i taps_x[i] * constant (summed
+ * in tap order), not the constant itself.  With ICL_BORDER_CLAMP (`constant`
+ * ignored) this is exactly icl_conv_sep.  ICL_ERR_INVALID_VALUE for another
+ * `border`; every other argument as in icl_conv_sep. */
+icl_status icl_conv_sep_border(const void* src, size_t src_pitch, void* dst, size_t dst_pitch,
+                               int width, int height, icl_dtype dtype,
+                               const float* taps_x, const float* taps_y, int radius,
+                               icl_border border, float constant,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
 /* ------------------------------------------------------------------ 2-D correlation
  * Paper: Section 6, non-separable convolution benchmark (Table 3): a full
  * (2r+1)^2 filter whose taps are known only at run time.
@@ -127,6 +152,32 @@ icl_status icl_conv_sep(const void* src, size_t src_pitch, void* dst, size_t dst
 icl_status icl_conv2d(const void* src, size_t src_pitch, void* dst, size_t dst_pitch,
                       int width, int height, icl_dtype dtype,
                       const float* taps, int radius, void* stream);
+
+/* icl_conv2d under a chosen boundary condition: with ICL_BORDER_CONSTANT every
+ * read outside the image is `constant` (Section 5, Fig. 3b).  With
+ * ICL_BORDER_CLAMP (`constant` ignored) this is exactly icl_conv2d. */
+icl_status icl_conv2d_border(const void* src, size_t src_pitch, void* dst, size_t dst_pitch,
+                             int width, int height, icl_dtype dtype,
+                             const float* taps, int radius, icl_border border, float constant,
+                             void* stream);
+
+/* ------------------------------------------------------------------ 8-bit 2-D correlation
+ * Paper: Section 6, non-separable convolution benchmark, run on unsigned char
+ * pixels with a 5x5 filter known at run time and the clamped boundary.  Integer
+ * arithmetic, exact:
+ *   S(x,y)   = sum_{j,i=-r..r} taps[(j+r)(2r+1) + (i+r)] * src(x+i, y+j)
+ *   dst(x,y) = min(max((S + b) >> shift, 0), 255),  b = 2^(shift-1), or 0 if shift = 0
+ * (>> is the arithmetic shift, i.e. floor division: round to nearest, ties up,
+ * then saturate).  The sum is exact in 32-bit integers for every input.
+ *   src, dst : device unsigned char images, pitches in bytes (any alignment)
+ *   taps     : device int16, (2r+1)^2 values, row (j) major; r in [0, ICL_MAX_U8_RADIUS]
+ *   shift    : 0 .. ICL_MAX_U8_SHIFT, else ICL_ERR_INVALID_VALUE
+ *   border   : ICL_BORDER_CLAMP, or ICL_BORDER_CONSTANT with `constant` in 0..255
+ *              (the value of every read outside the image; else ICL_ERR_INVALID_VALUE).
+ * Every variant returns the same bytes. */
+icl_status icl_conv2d_u8(const uint8_t* src, size_t src_pitch, uint8_t* dst, size_t dst_pitch,
+                         int width, int height, const int16_t* taps, int radius, int shift,
+                         icl_border border, int constant, void* stream);
 
 /* ------------------------------------------------------------------ Harris corner response
  * Paper: Section 6, Harris corner detection, run there as a Sobel kernel

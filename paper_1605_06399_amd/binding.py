@@ -29,15 +29,21 @@ ICL_ERR_UNSUPPORTED = 9
 ICL_ERR_TUNE_CACHE = 10
 
 # icl_dtype
-ICL_F32, ICL_F16, ICL_BF16 = 0, 1, 2
+ICL_F32, ICL_F16, ICL_BF16, ICL_U8 = 0, 1, 2, 3
+
+# icl_border
+ICL_BORDER_CLAMP, ICL_BORDER_CONSTANT = 0, 1
 
 # icl_op
 (ICL_OP_CONV_SEP, ICL_OP_CONV2D, ICL_OP_HARRIS, ICL_OP_NMS, ICL_OP_CONV_SEP_BATCHED, ICL_OP_BANK_FWD,
- ICL_OP_BANK_BWD_INPUT, ICL_OP_BANK_BWD_FILTER, ICL_OP_SSE_LOSS, ICL_OP_BANK_FWD_SSE, ICL_OP_COUNT) = range(11)
+ ICL_OP_BANK_BWD_INPUT, ICL_OP_BANK_BWD_FILTER, ICL_OP_SSE_LOSS, ICL_OP_BANK_FWD_SSE, ICL_OP_CONV2D_U8,
+ ICL_OP_COUNT) = range(12)
 
 ICL_MAX_RADIUS = 16
 ICL_MAX_WINDOW_RADIUS = 7
 ICL_MAX_NMS_RADIUS = 7
+ICL_MAX_U8_RADIUS = 7
+ICL_MAX_U8_SHIFT = 16
 
 _vp = ctypes.c_void_p
 _sz = ctypes.c_size_t
@@ -65,7 +71,10 @@ _SIGS = {
     "icl_version": ([], ctypes.c_char_p),
     "icl_workspace_size": ([_i, _i, _i, _i, _i, _i, _i, ctypes.POINTER(_sz)], _i),
     "icl_conv_sep": ([_vp, _sz, _vp, _sz, _i, _i, _i, _vp, _vp, _i, _vp, _sz, _vp], _i),
+    "icl_conv_sep_border": ([_vp, _sz, _vp, _sz, _i, _i, _i, _vp, _vp, _i, _i, _f, _vp, _sz, _vp], _i),
     "icl_conv2d": ([_vp, _sz, _vp, _sz, _i, _i, _i, _vp, _i, _vp], _i),
+    "icl_conv2d_border": ([_vp, _sz, _vp, _sz, _i, _i, _i, _vp, _i, _i, _f, _vp], _i),
+    "icl_conv2d_u8": ([_vp, _sz, _vp, _sz, _i, _i, _vp, _i, _i, _i, _i, _vp], _i),
     "icl_harris": ([_vp, _sz, _vp, _sz, _i, _i, _vp, _i, _f, _vp, _sz, _vp], _i),
     "icl_nms": ([_vp, _sz, _vp, _sz, _i, _i, _i, _f, _vp], _i),
     "icl_batch_plan_create": ([ctypes.POINTER(icl_image_desc), _i, _i, ctypes.POINTER(_vp)], _i),
@@ -149,8 +158,26 @@ def icl_conv_sep(src, src_pitch, dst, dst_pitch, width, height, dtype, taps_x, t
                               workspace or None, workspace_bytes, stream or None)
 
 
+def icl_conv_sep_border(src, src_pitch, dst, dst_pitch, width, height, dtype, taps_x, taps_y, radius, border,
+                        constant, workspace=0, workspace_bytes=0, stream=0) -> int:
+    return lib().icl_conv_sep_border(src, src_pitch, dst, dst_pitch, width, height, dtype, taps_x, taps_y, radius,
+                                     border, constant, workspace or None, workspace_bytes, stream or None)
+
+
 def icl_conv2d(src, src_pitch, dst, dst_pitch, width, height, dtype, taps, radius, stream=0) -> int:
     return lib().icl_conv2d(src, src_pitch, dst, dst_pitch, width, height, dtype, taps, radius, stream or None)
+
+
+def icl_conv2d_border(src, src_pitch, dst, dst_pitch, width, height, dtype, taps, radius, border, constant,
+                      stream=0) -> int:
+    return lib().icl_conv2d_border(src, src_pitch, dst, dst_pitch, width, height, dtype, taps, radius, border,
+                                   constant, stream or None)
+
+
+def icl_conv2d_u8(src, src_pitch, dst, dst_pitch, width, height, taps, radius, shift, border=ICL_BORDER_CLAMP,
+                  constant=0, stream=0) -> int:
+    return lib().icl_conv2d_u8(src, src_pitch, dst, dst_pitch, width, height, taps, radius, shift, border, constant,
+                               stream or None)
 
 
 def icl_harris(src, src_pitch, resp, resp_pitch, width, height, window_taps, window_radius, k,

@@ -27,7 +27,7 @@ static std::mutex g_init_mu;
 
 static const char* kOpNames[ICL_OP_COUNT] = {"conv_sep", "conv2d", "harris", "nms", "conv_sep_batched",
                                              "bank_fwd", "bank_bwd_input", "bank_bwd_filter", "sse_loss",
-                                             "bank_fwd_sse"};
+                                             "bank_fwd_sse", "conv2d_u8"};
 
 // ICL_FORCE_VARIANT="conv_sep=1,conv2d=3": the analogue of the paper's directives
 // that force optimisations on or off.
@@ -115,6 +115,13 @@ namespace {
 
 bool dtype_ok(icl_dtype d) { return d == ICL_F32 || d == ICL_F16 || d == ICL_BF16; }
 
+icl::Border border_of(icl_border b, float value) {
+    icl::Border bd;
+    bd.constant = b == ICL_BORDER_CONSTANT ? 1 : 0;
+    bd.value = bd.constant ? value : 0.f;
+    return bd;
+}
+
 // Image checks shared by the entry points (sizes already known to be >= 1).
 icl_status check_image(const void* p, size_t pitch, int W, int es) {
     if (!p) return ICL_ERR_INVALID_VALUE;
@@ -185,7 +192,7 @@ icl_status icl_workspace_size(icl_op op, int width, int height, int n, int f, in
                               size_t* bytes) {
     if (!bytes) return ICL_ERR_INVALID_VALUE;
     if (width < 0 || height < 0 || n < 0 || f < 0) return ICL_ERR_INVALID_VALUE;
-    if (!dtype_ok(dtype)) return ICL_ERR_DTYPE;
+    if (op == ICL_OP_CONV2D_U8 ? dtype != ICL_U8 : !dtype_ok(dtype)) return ICL_ERR_DTYPE;
     *bytes = 0;
     switch (op) {
         case ICL_OP_CONV_SEP: *bytes = sep_workspace(width, height); break;
@@ -197,7 +204,7 @@ icl_status icl_workspace_size(icl_op op, int width, int height, int n, int f, in
         case ICL_OP_SSE_LOSS: *bytes = sse_workspace((long long)width * height); break;
         case ICL_OP_BANK_FWD_SSE: *bytes = bank_fwd_sse_workspace(); break;
         case ICL_OP_CONV2D: case ICL_OP_NMS: case ICL_OP_CONV_SEP_BATCHED: case ICL_OP_BANK_FWD:
-        case ICL_OP_BANK_BWD_INPUT: break;
+        case ICL_OP_BANK_BWD_INPUT: case ICL_OP_CONV2D_U8: break;
         default: return ICL_ERR_INVALID_VALUE;
     }
     return ICL_OK;
@@ -206,7 +213,16 @@ icl_status icl_workspace_size(icl_op op, int width, int height, int n, int f, in
 icl_status icl_conv_sep(const void* src, size_t src_pitch, void* dst, size_t dst_pitch, int width, int height,
                         icl_dtype dtype, const float* taps_x, const float* taps_y, int radius, void* workspace,
                         size_t workspace_bytes, void* stream) {
+    return icl_conv_sep_border(src, src_pitch, dst, dst_pitch, width, height, dtype, taps_x, taps_y, radius,
+                               ICL_BORDER_CLAMP, 0.f, workspace, workspace_bytes, stream);
+}
+
+icl_status icl_conv_sep_border(const void* src, size_t src_pitch, void* dst, size_t dst_pitch, int width,
+                               int height, icl_dtype dtype, const float* taps_x, const float* taps_y, int radius,
+                               icl_border border, float constant, void* workspace, size_t workspace_bytes,
+                               void* stream) {
     if (width < 0 || height < 0) return ICL_ERR_INVALID_VALUE;
+    if (border != ICL_BORDER_CLAMP && border != ICL_BORDER_CONSTANT) return ICL_ERR_INVALID_VALUE;
     if (!dtype_ok(dtype)) return ICL_ERR_DTYPE;
     if (radius < 0 || radius > ICL_MAX_RADIUS) return ICL_ERR_RADIUS;
     if (width == 0 || height == 0) return ICL_OK;
@@ -223,7 +239,7 @@ icl_status icl_conv_sep(const void* src, size_t src_pitch, void* dst, size_t dst
         return ICL_ERR_ALIAS;
     if ((s = device_ready()) != ICL_OK) return s;
     SepArgs a{src, src_pitch, dst, dst_pitch, width, height, dtype, taps_x, taps_y, radius,
-              workspace, workspace_bytes, (hipStream_t)stream};
+              workspace, workspace_bytes, (hipStream_t)stream, border_of(border, constant)};
     int count;
     const Variant<SepArgs>* tab = sep_variants(&count);
     const int deflt = sep_default(a);
@@ -236,7 +252,15 @@ icl_status icl_conv_sep(const void* src, size_t src_pitch, void* dst, size_t dst
 
 icl_status icl_conv2d(const void* src, size_t src_pitch, void* dst, size_t dst_pitch, int width, int height,
                       icl_dtype dtype, const float* taps, int radius, void* stream) {
+    return icl_conv2d_border(src, src_pitch, dst, dst_pitch, width, height, dtype, taps, radius, ICL_BORDER_CLAMP,
+                             0.f, stream);
+}
+
+icl_status icl_conv2d_border(const void* src, size_t src_pitch, void* dst, size_t dst_pitch, int width, int height,
+                             icl_dtype dtype, const float* taps, int radius, icl_border border, float constant,
+                             void* stream) {
     if (width < 0 || height < 0) return ICL_ERR_INVALID_VALUE;
+    if (border != ICL_BORDER_CLAMP && border != ICL_BORDER_CONSTANT) return ICL_ERR_INVALID_VALUE;
     if (!dtype_ok(dtype)) return ICL_ERR_DTYPE;
     if (radius < 0 || radius > ICL_MAX_RADIUS) return ICL_ERR_RADIUS;
     if (width == 0 || height == 0) return ICL_OK;
@@ -247,12 +271,38 @@ icl_status icl_conv2d(const void* src, size_t src_pitch, void* dst, size_t dst_p
     if (!taps) return ICL_ERR_INVALID_VALUE;
     if (overlaps(src, src_pitch, es, dst, dst_pitch, es, width, height)) return ICL_ERR_ALIAS;
     if ((s = device_ready()) != ICL_OK) return s;
-    Conv2dArgs a{src, src_pitch, dst, dst_pitch, width, height, dtype, taps, radius, (hipStream_t)stream};
+    Conv2dArgs a{src, src_pitch, dst, dst_pitch, width, height, dtype, taps, radius, (hipStream_t)stream,
+                 border_of(border, constant)};
     int count;
     const Variant<Conv2dArgs>* tab = conv2d_variants(&count);
     const int deflt = conv2d_default(a);
     return dispatch(ICL_OP_CONV2D, tab, count, a, select_variant(ICL_OP_CONV2D, dtype, radius, width, height, deflt),
                     deflt);
+}
+
+icl_status icl_conv2d_u8(const uint8_t* src, size_t src_pitch, uint8_t* dst, size_t dst_pitch, int width,
+                         int height, const int16_t* taps, int radius, int shift, icl_border border, int constant,
+                         void* stream) {
+    if (width < 0 || height < 0) return ICL_ERR_INVALID_VALUE;
+    if (radius < 0 || radius > ICL_MAX_U8_RADIUS) return ICL_ERR_RADIUS;
+    if (shift < 0 || shift > ICL_MAX_U8_SHIFT) return ICL_ERR_INVALID_VALUE;
+    if (border != ICL_BORDER_CLAMP && border != ICL_BORDER_CONSTANT) return ICL_ERR_INVALID_VALUE;
+    if (border == ICL_BORDER_CONSTANT && (constant < 0 || constant > 255)) return ICL_ERR_INVALID_VALUE;
+    if (width == 0 || height == 0) return ICL_OK;
+    icl_status s;
+    if ((s = check_image(src, src_pitch, width, 1)) != ICL_OK) return s;
+    if ((s = check_image(dst, dst_pitch, width, 1)) != ICL_OK) return s;
+    if (!taps) return ICL_ERR_INVALID_VALUE;
+    if (overlaps(src, src_pitch, 1, dst, dst_pitch, 1, width, height)) return ICL_ERR_ALIAS;
+    if ((s = device_ready()) != ICL_OK) return s;
+    const int cmode = border == ICL_BORDER_CONSTANT ? 1 : 0;
+    U8Args a{src, src_pitch, dst, dst_pitch, width, height, taps, radius, shift, cmode, cmode ? constant : 0,
+             (hipStream_t)stream};
+    int count;
+    const Variant<U8Args>* tab = conv2d_u8_variants(&count);
+    const int deflt = conv2d_u8_default(a);
+    return dispatch(ICL_OP_CONV2D_U8, tab, count, a,
+                    select_variant(ICL_OP_CONV2D_U8, ICL_U8, radius, width, height, deflt), deflt);
 }
 
 icl_status icl_harris(const float* src, size_t src_pitch, float* resp, size_t resp_pitch, int width, int height,
@@ -421,6 +471,7 @@ int icl_variant_count(icl_op op) {
     switch (op) {
         case ICL_OP_CONV_SEP: sep_variants(&c); break;
         case ICL_OP_CONV2D: conv2d_variants(&c); break;
+        case ICL_OP_CONV2D_U8: conv2d_u8_variants(&c); break;
         case ICL_OP_HARRIS: harris_variants(&c); break;
         case ICL_OP_NMS: nms_variants(&c); break;
         case ICL_OP_BANK_FWD: bank_fwd_variants(&c); break;
@@ -440,6 +491,7 @@ const char* icl_variant_name(icl_op op, int index) {
     switch (op) {
         case ICL_OP_CONV_SEP: return sep_variants(&c)[index].name;
         case ICL_OP_CONV2D: return conv2d_variants(&c)[index].name;
+        case ICL_OP_CONV2D_U8: return conv2d_u8_variants(&c)[index].name;
         case ICL_OP_HARRIS: return harris_variants(&c)[index].name;
         case ICL_OP_NMS: return nms_variants(&c)[index].name;
         case ICL_OP_BANK_FWD: return bank_fwd_variants(&c)[index].name;
@@ -493,6 +545,12 @@ icl_status icl_selected_variant(icl_op op, icl_dtype dtype, int radius, int widt
             break;
         }
         case ICL_OP_CONV_SEP_BATCHED: deflt = batched_default(); break;
+        case ICL_OP_CONV2D_U8: {
+            U8Args a{};
+            a.r = radius;
+            deflt = conv2d_u8_default(a);
+            break;
+        }
         default: break;
     }
     *index = select_variant(op, dtype, radius, width, height, deflt);

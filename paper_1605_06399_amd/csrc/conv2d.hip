@@ -30,16 +30,21 @@ namespace {
 
 template <class T>
 __global__ __launch_bounds__(256) void conv2d_plain(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
-                                                    size_t dp, int W, int H, const float* __restrict__ w, int r) {
+                                                    size_t dp, int W, int H, const float* __restrict__ w, int r,
+                                                    Border bd) {
     const int x = blockIdx.x * 16 + threadIdx.x % 16;
     const int y = blockIdx.y * 16 + threadIdx.x / 16;
     if (x >= W || y >= H) return;
     const int n = 2 * r + 1;
     float acc = 0.f;
     for (int j = -r; j <= r; ++j) {
+        const bool yout = y + j < 0 || y + j >= H;
         const size_t row = (size_t)clampi(y + j, H) * sp;
-        for (int i = -r; i <= r; ++i)
-            acc += w[(j + r) * n + (i + r)] * load_px<T>(src, row + (size_t)clampi(x + i, W) * T::size);
+        for (int i = -r; i <= r; ++i) {
+            const bool out = bd.constant && (yout || x + i < 0 || x + i >= W);
+            acc += w[(j + r) * n + (i + r)] *
+                   (out ? bd.value : load_px<T>(src, row + (size_t)clampi(x + i, W) * T::size));
+        }
     }
     store_px<T>(dst, (size_t)y * dp + (size_t)x * T::size, acc);
 }
@@ -47,7 +52,8 @@ __global__ __launch_bounds__(256) void conv2d_plain(const void* __restrict__ src
 template <class T>
 hipError_t launch_plain_T(const Conv2dArgs& a) {
     dim3 grid((a.W + 15) / 16, (a.H + 15) / 16);
-    hipLaunchKernelGGL(conv2d_plain<T>, grid, dim3(256), 0, a.st, a.src, a.sp, a.dst, a.dp, a.W, a.H, a.taps, a.r);
+    hipLaunchKernelGGL(conv2d_plain<T>, grid, dim3(256), 0, a.st, a.src, a.sp, a.dst, a.dp, a.W, a.H, a.taps, a.r,
+                       a.bd);
     return hipGetLastError();
 }
 
@@ -73,7 +79,7 @@ template <int R, int PX, int PY> struct Tile2d {
 template <class T, int R, int PX, int PY, int ORD>
 __global__ __launch_bounds__(256) void conv2d_lds(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
                                                   size_t dp, int W, int H, const float* __restrict__ w,
-                                                  int tiles_x, int vec_ok) {
+                                                  int tiles_x, int vec_ok, Border bd) {
     using G = Tile2d<R, PX, PY>;
     constexpr int TW = G::TW, TH = G::TH, RA = G::RA, LW = G::LW, NR = G::NR, WIN = G::WIN;
     constexpr int N = 2 * R + 1;
@@ -87,15 +93,19 @@ __global__ __launch_bounds__(256) void conv2d_lds(const void* __restrict__ src, 
         constexpr int C4 = LW / 4;
         for (int idx = tid; idx < NR * C4; idx += 256) {
             const int rr = idx / C4, c4 = idx - rr * C4;
-            const int y = clampi(y0 - R + rr, H);
-            lds4(&in_s[rr * LW + 4 * c4], load4<T>(src, (size_t)y * sp + (size_t)(x0 - RA + 4 * c4) * T::size));
+            const int yy = y0 - R + rr;
+            const v4f v = (bd.constant && (yy < 0 || yy >= H))
+                              ? mk4(bd.value, bd.value, bd.value, bd.value)
+                              : load4<T>(src, (size_t)clampi(yy, H) * sp + (size_t)(x0 - RA + 4 * c4) * T::size);
+            lds4(&in_s[rr * LW + 4 * c4], v);
         }
     } else {
         for (int idx = tid; idx < NR * LW; idx += 256) {
             const int rr = idx / LW, c = idx - rr * LW;
-            const int y = clampi(y0 - R + rr, H);
-            const int x = clampi(x0 - RA + c, W);
-            in_s[rr * LW + c] = load_px<T>(src, (size_t)y * sp + (size_t)x * T::size);
+            const int yy = y0 - R + rr, xx = x0 - RA + c;
+            in_s[rr * LW + c] = (bd.constant && (yy < 0 || yy >= H || xx < 0 || xx >= W))
+                                    ? bd.value
+                                    : load_px<T>(src, (size_t)clampi(yy, H) * sp + (size_t)clampi(xx, W) * T::size);
         }
     }
     __syncthreads();
@@ -184,7 +194,7 @@ hipError_t launch_lds_TR(const Conv2dArgs& a) {
     const int vec_ok = ((uintptr_t)a.src % al == 0) && (a.sp % al == 0) && ((uintptr_t)a.dst % al == 0) &&
                        (a.dp % al == 0);
     hipLaunchKernelGGL((conv2d_lds<T, R, PX, PY, ORD>), dim3(tiles_x * tiles_y), dim3(256), 0, a.st, a.src, a.sp,
-                       a.dst, a.dp, a.W, a.H, a.taps, tiles_x, vec_ok);
+                       a.dst, a.dp, a.W, a.H, a.taps, tiles_x, vec_ok, a.bd);
     return hipGetLastError();
 }
 
@@ -224,7 +234,7 @@ bool supports_lds(const Conv2dArgs& a) { return a.r >= 0 && a.r <= 7; }
 template <class T, int R, int PX, int PY>
 __global__ __launch_bounds__(256) void conv2d_pers(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
                                                    size_t dp, int W, int H, const float* __restrict__ w, int tiles_x,
-                                                   int tiles_y, int vec_ok) {
+                                                   int tiles_y, int vec_ok, Border bd) {
     using G = Tile2d<R, PX, PY>;
     constexpr int TW = G::TW, TH = G::TH, RA = G::RA, LW = G::LW, NR = G::NR;
     constexpr int N = 2 * R + 1, NP = (N + 3) & ~3;
@@ -238,7 +248,7 @@ __global__ __launch_bounds__(256) void conv2d_pers(const void* __restrict__ src,
     if (t < 0) return;
     int x0, y0;
     tile_origin(t, tiles_x, TW, TH, x0, y0);
-    st.load(src, sp, W, H, x0 - RA, y0 - R, vec_ok);
+    st.load(src, sp, W, H, x0 - RA, y0 - R, vec_ok, bd);
     st.store(s);
     __syncthreads();
     const int tx = tid & 15, ty = tid >> 4;
@@ -247,7 +257,7 @@ __global__ __launch_bounds__(256) void conv2d_pers(const void* __restrict__ src,
         if (tn >= 0) {
             int nx0, ny0;
             tile_origin(tn, tiles_x, TW, TH, nx0, ny0);
-            st.load(src, sp, W, H, nx0 - RA, ny0 - R, vec_ok);
+            st.load(src, sp, W, H, nx0 - RA, ny0 - R, vec_ok, bd);
         }
         float acc[PY][PX];
 #pragma unroll
@@ -292,7 +302,7 @@ hipError_t launch_pers_TR(const Conv2dArgs& a) {
     const void* k = reinterpret_cast<const void*>(&conv2d_pers<T, R, PX, PY>);
     const int grid = persistent_grid(k, 256, ntiles);
     hipLaunchKernelGGL((conv2d_pers<T, R, PX, PY>), dim3(grid), dim3(256), 0, a.st, a.src, a.sp, a.dst, a.dp, a.W,
-                       a.H, a.taps, tiles_x, tiles_y, vec_ok);
+                       a.H, a.taps, tiles_x, tiles_y, vec_ok, a.bd);
     return hipGetLastError();
 }
 

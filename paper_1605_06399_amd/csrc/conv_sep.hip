@@ -38,25 +38,39 @@ namespace {
 template <class T>
 __global__ __launch_bounds__(256) void sep_row_plain(const void* __restrict__ src, size_t sp,
                                                      float* __restrict__ tmp, int W, int H,
-                                                     const float* __restrict__ tx, int r) {
+                                                     const float* __restrict__ tx, int r, Border bd) {
     const int x = blockIdx.x * 16 + threadIdx.x % 16;
     const int y = blockIdx.y * 16 + threadIdx.x / 16;
     if (x >= W || y >= H) return;
     float acc = 0.f;
-    for (int i = -r; i <= r; ++i)
-        acc += tx[i + r] * load_px<T>(src, (size_t)y * sp + (size_t)clampi(x + i, W) * T::size);
+    for (int i = -r; i <= r; ++i) {
+        const int xx = x + i;
+        const float v = (bd.constant && (xx < 0 || xx >= W))
+                            ? bd.value
+                            : load_px<T>(src, (size_t)y * sp + (size_t)clampi(xx, W) * T::size);
+        acc += tx[i + r] * v;
+    }
     tmp[(size_t)y * W + x] = acc;
 }
 
+// With a constant boundary a row outside the image is the constant everywhere, so its row
+// pass is sum_i tx[i] * c (summed in the row pass's order).
 template <class T>
 __global__ __launch_bounds__(256) void sep_col_plain(const float* __restrict__ tmp, void* __restrict__ dst,
-                                                     size_t dp, int W, int H,
-                                                     const float* __restrict__ ty, int r) {
+                                                     size_t dp, int W, int H, const float* __restrict__ tx,
+                                                     const float* __restrict__ ty, int r, Border bd) {
     const int x = blockIdx.x * 16 + threadIdx.x % 16;
     const int y = blockIdx.y * 16 + threadIdx.x / 16;
     if (x >= W || y >= H) return;
+    float outside = 0.f;
+    if (bd.constant)
+        for (int i = -r; i <= r; ++i) outside = fmaf(tx[i + r], bd.value, outside);
     float acc = 0.f;
-    for (int j = -r; j <= r; ++j) acc += ty[j + r] * tmp[(size_t)clampi(y + j, H) * W + x];
+    for (int j = -r; j <= r; ++j) {
+        const int yy = y + j;
+        const float v = (bd.constant && (yy < 0 || yy >= H)) ? outside : tmp[(size_t)clampi(yy, H) * W + x];
+        acc += ty[j + r] * v;
+    }
     store_px<T>(dst, (size_t)y * dp + (size_t)x * T::size, acc);
 }
 
@@ -64,8 +78,9 @@ template <class T>
 hipError_t launch_plain_T(const SepArgs& a) {
     float* tmp = static_cast<float*>(a.ws);
     dim3 grid((a.W + 15) / 16, (a.H + 15) / 16);
-    hipLaunchKernelGGL(sep_row_plain<T>, grid, dim3(256), 0, a.st, a.src, a.sp, tmp, a.W, a.H, a.tx, a.r);
-    hipLaunchKernelGGL(sep_col_plain<T>, grid, dim3(256), 0, a.st, tmp, a.dst, a.dp, a.W, a.H, a.ty, a.r);
+    hipLaunchKernelGGL(sep_row_plain<T>, grid, dim3(256), 0, a.st, a.src, a.sp, tmp, a.W, a.H, a.tx, a.r, a.bd);
+    hipLaunchKernelGGL(sep_col_plain<T>, grid, dim3(256), 0, a.st, tmp, a.dst, a.dp, a.W, a.H, a.tx, a.ty, a.r,
+                       a.bd);
     return hipGetLastError();
 }
 
@@ -88,14 +103,15 @@ namespace {
 template <class T, int R, int TH, int CX>
 __global__ __launch_bounds__(256) void sep_fused(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
                                                  size_t dp, int W, int H, const float* __restrict__ tx,
-                                                 const float* __restrict__ ty, int tiles_x, int vec_ok, int vec_out) {
+                                                 const float* __restrict__ ty, int tiles_x, int vec_ok, int vec_out,
+                                                 Border bd) {
     using G = SepTile<R, TH, CX>;
     __shared__ __attribute__((aligned(16))) float lds[G::LDS_FLOATS];
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
     const int x0 = (int)(t % (unsigned)tiles_x) * G::TW;
     const int y0 = (int)(t / (unsigned)tiles_x) * TH;
     const bool vec = vec_ok && x0 - G::RA >= 0 && x0 + G::TW + G::RA <= W;
-    sep_tile_body<T, R, TH, CX>(src, sp, dst, dp, W, H, tx, ty, x0, y0, vec, vec_out, lds);
+    sep_tile_body<T, R, TH, CX>(src, sp, dst, dp, W, H, tx, ty, x0, y0, vec, vec_out, lds, bd);
 }
 
 template <class T, int R, int TH, int CX>
@@ -107,7 +123,7 @@ hipError_t launch_fused_TR(const SepArgs& a) {
     const int vec_ok = ((uintptr_t)a.src % vec_align == 0) && (a.sp % vec_align == 0);
     const int vec_out = ((uintptr_t)a.dst % vec_align == 0) && (a.dp % vec_align == 0);
     hipLaunchKernelGGL((sep_fused<T, R, TH, CX>), dim3(tiles_x * tiles_y), dim3(256), 0, a.st, a.src, a.sp,
-                       a.dst, a.dp, a.W, a.H, a.tx, a.ty, tiles_x, vec_ok, vec_out);
+                       a.dst, a.dp, a.W, a.H, a.tx, a.ty, tiles_x, vec_ok, vec_out, a.bd);
     return hipGetLastError();
 }
 
@@ -144,7 +160,7 @@ template <class T, int R, int TH, int CX>
 __global__ __launch_bounds__(256) void sep_pers(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
                                                 size_t dp, int W, int H, const float* __restrict__ tx,
                                                 const float* __restrict__ ty, int tiles_x, int tiles_y, int vec_ok,
-                                                int vec_out) {
+                                                int vec_out, Border bd) {
     using G = SepTile<R, TH, CX>;
     constexpr int TW = G::TW, RA = G::RA, LW = G::LW, NR = G::NR;
     __shared__ __attribute__((aligned(16))) float lds[G::LDS_FLOATS];
@@ -156,7 +172,7 @@ __global__ __launch_bounds__(256) void sep_pers(const void* __restrict__ src, si
     if (t < 0) return;
     int x0, y0;
     tile_origin(t, tiles_x, TW, TH, x0, y0);
-    st.load(src, sp, W, H, x0 - RA, y0 - R, vec_ok);
+    st.load(src, sp, W, H, x0 - RA, y0 - R, vec_ok, bd);
     st.store(in_s);
     __syncthreads();
     // Pipeline per tile: issue the next tile's loads, run the row pass, then (after the
@@ -167,7 +183,7 @@ __global__ __launch_bounds__(256) void sep_pers(const void* __restrict__ src, si
         if (tn >= 0) {
             int nx0, ny0;
             tile_origin(tn, tiles_x, TW, TH, nx0, ny0);
-            st.load(src, sp, W, H, nx0 - RA, ny0 - R, vec_ok);
+            st.load(src, sp, W, H, nx0 - RA, ny0 - R, vec_ok, bd);
         }
         sep_row_pass<R, TH, CX>(in_s, t_s, tx);
         __syncthreads();
@@ -189,7 +205,8 @@ hipError_t launch_pers_TR(const SepArgs& a) {
     const int vec_out = ((uintptr_t)a.dst % al == 0) && (a.dp % al == 0);
     const void* k = reinterpret_cast<const void*>(&sep_pers<T, R, TH, CX>);
     hipLaunchKernelGGL((sep_pers<T, R, TH, CX>), dim3(persistent_grid(k, 256, tiles_x * tiles_y)), dim3(256), 0,
-                       a.st, a.src, a.sp, a.dst, a.dp, a.W, a.H, a.tx, a.ty, tiles_x, tiles_y, vec_ok, vec_out);
+                       a.st, a.src, a.sp, a.dst, a.dp, a.W, a.H, a.tx, a.ty, tiles_x, tiles_y, vec_ok, vec_out,
+                       a.bd);
     return hipGetLastError();
 }
 
@@ -221,11 +238,12 @@ hipError_t launch_pers(const SepArgs& a) {
 template <class T, int R, int TH>
 __global__ __launch_bounds__(64) void sep_strip(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
                                                 size_t dp, int W, int H, const float* __restrict__ tx,
-                                                const float* __restrict__ ty, int nstrips, int vec_in, int vec_out) {
+                                                const float* __restrict__ ty, int nstrips, int vec_in, int vec_out,
+                                                Border bd) {
     const int strip = (int)(blockIdx.x % (unsigned)nstrips);
     const int y0 = (int)(blockIdx.x / (unsigned)nstrips) * TH;
     sep_strip_body<T, R, TH>(src, sp, dst, dp, W, H, tx, ty, strip * StripGeom<R>::SW, y0, vec_in != 0,
-                             vec_out != 0);
+                             vec_out != 0, bd);
 }
 
 template <class T, int R, int TH>
@@ -236,7 +254,7 @@ hipError_t launch_strip_TR(const SepArgs& a) {
     const int vec_in = ((uintptr_t)a.src % al == 0) && (a.sp % al == 0);
     const int vec_out = ((uintptr_t)a.dst % al == 0) && (a.dp % al == 0);
     hipLaunchKernelGGL((sep_strip<T, R, TH>), dim3((unsigned)(nstrips * rows)), dim3(64), 0, a.st, a.src, a.sp, a.dst,
-                       a.dp, a.W, a.H, a.tx, a.ty, nstrips, vec_in, vec_out);
+                       a.dp, a.W, a.H, a.tx, a.ty, nstrips, vec_in, vec_out, a.bd);
     return hipGetLastError();
 }
 

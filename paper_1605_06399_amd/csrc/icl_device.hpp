@@ -19,6 +19,13 @@ __device__ __forceinline__ void static_for(F&& f) {
     static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
+// What a read outside the image returns: the closest pixel inside (clamp, the default) or
+// a constant value (Section 5, Fig. 3).
+struct Border {
+    int constant = 0;   // 0: clamp, 1: constant
+    float value = 0.f;
+};
+
 // Neighbour-lane moves within a wave as DPP wave shifts (a VALU operand modifier, no LDS
 // round trip): lane i receives v of lane i-1 (from_left) or of lane i+1 (from_right); the
 // end lane with no such neighbour receives 0.

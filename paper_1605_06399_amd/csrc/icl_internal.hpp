@@ -2,6 +2,8 @@
 // shared by the entry points, the kernels' launchers and the tuner.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include "icl_device.hpp"
 #include <stddef.h>
 #include <stdint.h>
 
@@ -9,7 +11,7 @@
 
 namespace icl {
 
-inline int elem_size(icl_dtype d) { return d == ICL_F32 ? 4 : 2; }
+inline int elem_size(icl_dtype d) { return d == ICL_F32 ? 4 : (d == ICL_U8 ? 1 : 2); }
 
 struct SepArgs {
     const void* src; size_t sp; void* dst; size_t dp;
@@ -17,12 +19,22 @@ struct SepArgs {
     const float* tx; const float* ty; int r;
     void* ws; size_t wsb;
     hipStream_t st;
+    Border bd{};
 };
 
 struct Conv2dArgs {
     const void* src; size_t sp; void* dst; size_t dp;
     int W, H; icl_dtype dt;
     const float* taps; int r;
+    hipStream_t st;
+    Border bd{};
+};
+
+struct U8Args {
+    const uint8_t* src; size_t sp; uint8_t* dst; size_t dp;
+    int W, H;
+    const int16_t* taps; int r; int shift;
+    int cmode; int cval;   // constant boundary flag and its value (0..255)
     hipStream_t st;
 };
 
@@ -67,6 +79,7 @@ template <class A> struct Variant {
 // Variant tables (index 0 = plain one-pixel-per-thread kernel).
 const Variant<SepArgs>* sep_variants(int* count);
 const Variant<Conv2dArgs>* conv2d_variants(int* count);
+const Variant<U8Args>* conv2d_u8_variants(int* count);
 const Variant<HarrisArgs>* harris_variants(int* count);
 const Variant<NmsArgs>* nms_variants(int* count);
 const Variant<BankArgs>* bank_fwd_variants(int* count);
@@ -77,6 +90,7 @@ const Variant<BankSseArgs>* bank_fwd_sse_variants(int* count);
 // Default choice when neither a forced variant nor a tune-cache entry applies.
 int sep_default(const SepArgs&);
 int conv2d_default(const Conv2dArgs&);
+int conv2d_u8_default(const U8Args&);
 int harris_default(const HarrisArgs&);
 int nms_default(const NmsArgs&);
 int bank_fwd_default(const BankArgs&);

@@ -4,8 +4,9 @@
 // Lane l holds the four columns xs - RA + 4l .. xs - RA + 4l + 3 of every input row it
 // walks (RA = r rounded up to whole lanes of four columns).  The HL = RA/4 lanes at each
 // end of the wave only supply the horizontal halo; the others own SW = 4 (64 - 2 HL)
-// output columns.  Columns outside the image are loaded clamped, which is exactly the
-// row pass's clamp, so the first and last strip of an image need no special path.
+// output columns.  Columns outside the image are loaded clamped (or as the constant of a
+// constant boundary), which is exactly the row pass's boundary, so the first and last
+// strip of an image need no special path.
 //
 // Per input row (image row clamp(y0 - r + kk)):
 //   * its four columns arrive from a ring of prefetched rows (Q rows ahead);
@@ -76,7 +77,7 @@ template <class T, int R, int TH>
 __device__ __forceinline__ void sep_strip_body(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
                                                size_t dp, int W, int H, const float* __restrict__ tx,
                                                const float* __restrict__ ty, int xs, int y0, bool vec_in,
-                                               bool vec_out) {
+                                               bool vec_out, Border bd = {}) {
     using G = StripGeom<R>;
     constexpr int D = G::D, U = G::U, Q = G::Q, HL = G::HL;
     constexpr int K = TH + 2 * R;   // input rows walked
@@ -84,11 +85,18 @@ __device__ __forceinline__ void sep_strip_body(const void* __restrict__ src, siz
     const int c = xs - G::RA + 4 * lane;
     const bool inside = vec_in && c >= 0 && c + 4 <= W;
     const int c0 = clampi(c, W), c1 = clampi(c + 1, W), c2 = clampi(c + 2, W), c3 = clampi(c + 3, W);
+    // a column outside the image reads the constant (constant boundary) or its clamped pixel
+    const bool o0 = bd.constant && (c < 0 || c >= W), o1 = bd.constant && (c + 1 < 0 || c + 1 >= W);
+    const bool o2 = bd.constant && (c + 2 < 0 || c + 2 >= W), o3 = bd.constant && (c + 3 < 0 || c + 3 >= W);
     auto load_row = [&](int kk) -> v4f {
-        const size_t row = (size_t)clampi(y0 - R + kk, H) * sp;
+        const int yy = y0 - R + kk;
+        if (bd.constant && (yy < 0 || yy >= H)) return mk4(bd.value, bd.value, bd.value, bd.value);
+        const size_t row = (size_t)clampi(yy, H) * sp;
         if (inside) return load4<T>(src, row + (size_t)c * T::size);
-        return mk4(load_px<T>(src, row + (size_t)c0 * T::size), load_px<T>(src, row + (size_t)c1 * T::size),
-                   load_px<T>(src, row + (size_t)c2 * T::size), load_px<T>(src, row + (size_t)c3 * T::size));
+        return mk4(o0 ? bd.value : load_px<T>(src, row + (size_t)c0 * T::size),
+                   o1 ? bd.value : load_px<T>(src, row + (size_t)c1 * T::size),
+                   o2 ? bd.value : load_px<T>(src, row + (size_t)c2 * T::size),
+                   o3 ? bd.value : load_px<T>(src, row + (size_t)c3 * T::size));
     };
     const bool writer = lane >= HL && lane < 64 - HL && c < W;
     const bool wvec = vec_out && c + 4 <= W;

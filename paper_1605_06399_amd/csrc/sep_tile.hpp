@@ -93,25 +93,29 @@ template <class T, int R, int TH, int CX>
 __device__ __forceinline__ void sep_tile_body(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
                                               size_t dp, int W, int H, const float* __restrict__ tx,
                                               const float* __restrict__ ty, int x0, int y0, bool vec, bool vec_out,
-                                              float* __restrict__ lds) {
+                                              float* __restrict__ lds, Border bd = {}) {
     using G = SepTile<R, TH, CX>;
     constexpr int RA = G::RA, LW = G::LW, NR = G::NR;
     float* in_s = lds;             // [NR][LW]
     float* t_s = lds + NR * LW;    // [NR][TW]
     const int tid = threadIdx.x;
-    if (vec) {
+    if (vec) {   // the tile's columns are inside the image: only rows can be outside
         constexpr int C4 = LW / 4;
         for (int idx = tid; idx < NR * C4; idx += 256) {
             const int rr = idx / C4, c4 = idx - rr * C4;
-            const int y = clampi(y0 - R + rr, H);
-            lds4(&in_s[rr * LW + 4 * c4], load4<T>(src, (size_t)y * sp + (size_t)(x0 - RA + 4 * c4) * T::size));
+            const int yy = y0 - R + rr;
+            const v4f v = (bd.constant && (yy < 0 || yy >= H))
+                              ? mk4(bd.value, bd.value, bd.value, bd.value)
+                              : load4<T>(src, (size_t)clampi(yy, H) * sp + (size_t)(x0 - RA + 4 * c4) * T::size);
+            lds4(&in_s[rr * LW + 4 * c4], v);
         }
     } else {
         for (int idx = tid; idx < NR * LW; idx += 256) {
             const int rr = idx / LW, c = idx - rr * LW;
-            const int y = clampi(y0 - R + rr, H);
-            const int x = clampi(x0 - RA + c, W);
-            in_s[rr * LW + c] = load_px<T>(src, (size_t)y * sp + (size_t)x * T::size);
+            const int yy = y0 - R + rr, xx = x0 - RA + c;
+            in_s[rr * LW + c] = (bd.constant && (yy < 0 || yy >= H || xx < 0 || xx >= W))
+                                    ? bd.value
+                                    : load_px<T>(src, (size_t)clampi(yy, H) * sp + (size_t)clampi(xx, W) * T::size);
         }
     }
     __syncthreads();

@@ -4,8 +4,8 @@
 // top-left element is image pixel (gx0, gy0).  Stage<> loads it from global
 // memory into registers (float4 per slot, 256 lanes), so the loads of the NEXT
 // tile can be in flight while the current one is computed from LDS, and then
-// writes the registers to LDS.  Reads outside the image follow the clamped
-// boundary (or read zero with ZERO_PAD).
+// writes the registers to LDS.  Reads outside the image follow the boundary: clamp or a
+// constant (Border), or zero with ZERO_PAD.
 #pragma once
 #include "icl_device.hpp"
 
@@ -21,10 +21,14 @@ struct Stage {
     // rows (4-pixel aligned base and pitch, x a multiple of 4) a chunk is either fully
     // inside the row (one vector load), fully outside (zeros, or the clamped edge pixel
     // broadcast), or straddles the right edge (per element; only when W % 4 != 0).
-    __device__ __forceinline__ static v4f chunk(const void* __restrict__ src, size_t row, int W, int x, bool aligned) {
+    // bd: the boundary of the convolution kernels (clamp or a constant); ZERO_PAD, the
+    // adjoint's zero extension, takes precedence.
+    __device__ __forceinline__ static v4f chunk(const void* __restrict__ src, size_t row, int W, int x, bool aligned,
+                                                Border bd = {}) {
         if (aligned && x >= 0 && x + 4 <= W) return load4<T>(src, row + (size_t)x * T::size);
         if (aligned && (x + 4 <= 0 || x >= W)) {
             if (ZERO_PAD) return mk4(0.f, 0.f, 0.f, 0.f);
+            if (bd.constant) return mk4(bd.value, bd.value, bd.value, bd.value);
             const float e = load_px<T>(src, row + (size_t)clampi(x, W) * T::size);
             return mk4(e, e, e, e);
         }
@@ -32,7 +36,10 @@ struct Stage {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int xx = x + q;
-            e[q] = (ZERO_PAD && (xx < 0 || xx >= W)) ? 0.f : load_px<T>(src, row + (size_t)clampi(xx, W) * T::size);
+            const bool out = xx < 0 || xx >= W;
+            e[q] = (ZERO_PAD && out) ? 0.f
+                   : (bd.constant && out) ? bd.value
+                                          : load_px<T>(src, row + (size_t)clampi(xx, W) * T::size);
         }
         return mk4(e[0], e[1], e[2], e[3]);
     }
@@ -40,7 +47,7 @@ struct Stage {
     // Load the tile with top-left pixel (gx0, gy0); gx0 must be a multiple of 4 when
     // `aligned` (rows 4-pixel aligned in memory).
     __device__ __forceinline__ void load(const void* __restrict__ src, size_t sp, int W, int H, int gx0, int gy0,
-                                         bool aligned) {
+                                         bool aligned, Border bd = {}) {
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             const int idx = (int)threadIdx.x + 256 * k;
@@ -51,7 +58,11 @@ struct Stage {
                 v[k] = mk4(0.f, 0.f, 0.f, 0.f);
                 continue;
             }
-            v[k] = chunk(src, (size_t)clampi(yy, H) * sp, W, gx0 + 4 * c4, aligned);
+            if (bd.constant && (yy < 0 || yy >= H)) {
+                v[k] = mk4(bd.value, bd.value, bd.value, bd.value);
+                continue;
+            }
+            v[k] = chunk(src, (size_t)clampi(yy, H) * sp, W, gx0 + 4 * c4, aligned, bd);
         }
     }
 

@@ -43,8 +43,17 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(nbytes, 4) // 4 + 1, dtype=torch.float32, device=device)
 
 
+_BORDERS = {"clamp": B.ICL_BORDER_CLAMP, "constant": B.ICL_BORDER_CONSTANT}
+
+
+def _border(border: str) -> int:
+    if border not in _BORDERS:
+        raise ValueError(f"border must be one of {sorted(_BORDERS)}")
+    return _BORDERS[border]
+
+
 def conv_sep(x: torch.Tensor, taps_x: torch.Tensor, taps_y: torch.Tensor, out: torch.Tensor | None = None,
-             workspace: torch.Tensor | None = None) -> torch.Tensor:
+             workspace: torch.Tensor | None = None, border: str = "clamp", constant: float = 0.0) -> torch.Tensor:
     r = (taps_x.numel() - 1) // 2
     if out is None:
         out = torch.empty_like(x, memory_format=torch.contiguous_format)
@@ -55,20 +64,49 @@ def conv_sep(x: torch.Tensor, taps_x: torch.Tensor, taps_y: torch.Tensor, out: t
         _, nb = B.icl_workspace_size(B.ICL_OP_CONV_SEP, W, H, dtype=dt)
         workspace = _workspace(nb, x.device)
     ws, wsb = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None else (0, 0)
-    B.check(B.icl_conv_sep(sp, spitch, dp, dpitch, W, H, dt, _taps(taps_x, 2 * r + 1, "taps_x"),
-                           _taps(taps_y, 2 * r + 1, "taps_y"), r, ws, wsb, _stream()), "icl_conv_sep")
+    tx, ty = _taps(taps_x, 2 * r + 1, "taps_x"), _taps(taps_y, 2 * r + 1, "taps_y")
+    if border == "clamp":
+        B.check(B.icl_conv_sep(sp, spitch, dp, dpitch, W, H, dt, tx, ty, r, ws, wsb, _stream()), "icl_conv_sep")
+    else:
+        B.check(B.icl_conv_sep_border(sp, spitch, dp, dpitch, W, H, dt, tx, ty, r, _border(border), float(constant),
+                                      ws, wsb, _stream()), "icl_conv_sep_border")
     return out
 
 
-def conv2d(x: torch.Tensor, taps: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+def conv2d(x: torch.Tensor, taps: torch.Tensor, out: torch.Tensor | None = None, border: str = "clamp",
+           constant: float = 0.0) -> torch.Tensor:
     n = taps.shape[-1]
     r = (n - 1) // 2
     if out is None:
         out = torch.empty_like(x, memory_format=torch.contiguous_format)
     sp, spitch, W, H = _image(x, "x")
     dp, dpitch, _, _ = _image(out, "out")
-    B.check(B.icl_conv2d(sp, spitch, dp, dpitch, W, H, _DT[x.dtype], _taps(taps, n * n, "taps"), r, _stream()),
-            "icl_conv2d")
+    tp = _taps(taps, n * n, "taps")
+    if border == "clamp":
+        B.check(B.icl_conv2d(sp, spitch, dp, dpitch, W, H, _DT[x.dtype], tp, r, _stream()), "icl_conv2d")
+    else:
+        B.check(B.icl_conv2d_border(sp, spitch, dp, dpitch, W, H, _DT[x.dtype], tp, r, _border(border),
+                                    float(constant), _stream()), "icl_conv2d_border")
+    return out
+
+
+def conv2d_u8(x: torch.Tensor, taps: torch.Tensor, shift: int, out: torch.Tensor | None = None,
+              border: str = "clamp", constant: int = 0) -> torch.Tensor:
+    """unsigned char image, int16 taps [(2r+1), (2r+1)]: exact integer sum, rounded shift, saturated."""
+    if x.dtype != torch.uint8:
+        raise ValueError("x must be a uint8 image")
+    n = taps.shape[-1]
+    r = (n - 1) // 2
+    if not taps.is_cuda or taps.dtype != torch.int16 or not taps.is_contiguous() or taps.numel() != n * n:
+        raise ValueError(f"taps must be a contiguous int16 GPU tensor with {n * n} values")
+    if out is None:
+        out = torch.empty_like(x, memory_format=torch.contiguous_format)
+    if out.dtype != torch.uint8:
+        raise ValueError("out must be a uint8 image")
+    sp, spitch, W, H = _image(x, "x")
+    dp, dpitch, _, _ = _image(out, "out")
+    B.check(B.icl_conv2d_u8(sp, spitch, dp, dpitch, W, H, taps.data_ptr(), r, int(shift), _border(border),
+                            int(constant), _stream()), "icl_conv2d_u8")
     return out
 
 

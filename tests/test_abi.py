@@ -83,6 +83,10 @@ def test_workspace_sizes(L):
     assert B.icl_workspace_size(B.ICL_OP_CONV_SEP, -1, 7)[0] == B.ICL_ERR_INVALID_VALUE
     assert B.icl_workspace_size(B.ICL_OP_CONV_SEP, 1, 7, dtype=7)[0] == B.ICL_ERR_DTYPE
     assert B.icl_workspace_size(42, 1, 7)[0] == B.ICL_ERR_INVALID_VALUE
+    st, nb = B.icl_workspace_size(B.ICL_OP_CONV2D_U8, 10, 10, dtype=B.ICL_U8)
+    assert st == B.ICL_OK and nb == 0
+    assert B.icl_workspace_size(B.ICL_OP_CONV2D_U8, 10, 10, dtype=B.ICL_F32)[0] == B.ICL_ERR_DTYPE
+    assert B.icl_workspace_size(B.ICL_OP_CONV_SEP, 10, 10, dtype=B.ICL_U8)[0] == B.ICL_ERR_DTYPE
 
 
 # Fake "device" addresses: never dereferenced, because validation fails (or the
@@ -126,6 +130,37 @@ def test_conv2d_harris_nms_validation(no_gpu):
     assert B.icl_nms(SRC, 256, DST, 63, 64, 8, 1, 1e-3) == B.ICL_ERR_PITCH
     assert B.icl_nms(SRC, 256, SRC + 64, 64, 64, 8, 1, 1e-3) == B.ICL_ERR_ALIAS
     assert B.icl_nms(SRC, 256, DST, 64, -1, 8, 1, 1e-3) == B.ICL_ERR_INVALID_VALUE
+
+
+def test_border_and_u8_validation(no_gpu):
+    C, K = B.ICL_BORDER_CLAMP, B.ICL_BORDER_CONSTANT
+    sb = B.icl_conv_sep_border
+    assert sb(SRC, 256, DST, 256, 64, 8, B.ICL_F32, TAPS, TAPS, 2, 2, 0.0) == B.ICL_ERR_INVALID_VALUE
+    assert sb(SRC, 256, DST, 256, 64, 8, B.ICL_F32, TAPS, TAPS, 2, -1, 0.0) == B.ICL_ERR_INVALID_VALUE
+    assert sb(SRC, 256, DST, 256, 64, 8, B.ICL_U8, TAPS, TAPS, 2, K, 0.0) == B.ICL_ERR_DTYPE
+    assert sb(SRC, 256, DST, 256, 64, 8, B.ICL_F32, TAPS, TAPS, 17, K, 0.0) == B.ICL_ERR_RADIUS
+    assert sb(SRC, 256, SRC + 4, 256, 64, 8, B.ICL_F32, TAPS, TAPS, 2, K, 0.5) == B.ICL_ERR_ALIAS
+    assert sb(SRC, 256, DST, 256, 0, 8, B.ICL_F32, TAPS, TAPS, 2, K, 0.5) == B.ICL_OK
+    c2 = B.icl_conv2d_border
+    assert c2(SRC, 256, DST, 256, 64, 8, B.ICL_F32, TAPS, 2, 5, 0.0) == B.ICL_ERR_INVALID_VALUE
+    assert c2(SRC, 256, DST, 256, 64, 8, B.ICL_U8, TAPS, 2, C, 0.0) == B.ICL_ERR_DTYPE
+    assert c2(SRC, 256, DST, 256, 64, 8, B.ICL_F32, 0, 2, K, 1.0) == B.ICL_ERR_INVALID_VALUE
+    assert c2(SRC, 255, DST, 256, 64, 8, B.ICL_F32, TAPS, 2, K, 1.0) == B.ICL_ERR_PITCH
+    assert c2(SRC, 256, DST, 256, 64, 0, B.ICL_F32, TAPS, 2, K, 1.0) == B.ICL_OK
+    u8 = B.icl_conv2d_u8
+    assert u8(SRC, 64, DST, 64, 64, 8, TAPS, 8, 12) == B.ICL_ERR_RADIUS
+    assert u8(SRC, 64, DST, 64, 64, 8, TAPS, -1, 12) == B.ICL_ERR_RADIUS
+    assert u8(SRC, 64, DST, 64, 64, 8, TAPS, 2, 17) == B.ICL_ERR_INVALID_VALUE
+    assert u8(SRC, 64, DST, 64, 64, 8, TAPS, 2, -1) == B.ICL_ERR_INVALID_VALUE
+    assert u8(SRC, 64, DST, 64, 64, 8, TAPS, 2, 12, 3, 0) == B.ICL_ERR_INVALID_VALUE
+    assert u8(SRC, 64, DST, 64, 64, 8, TAPS, 2, 12, K, 256) == B.ICL_ERR_INVALID_VALUE
+    assert u8(SRC, 64, DST, 64, 64, 8, TAPS, 2, 12, K, -1) == B.ICL_ERR_INVALID_VALUE
+    assert u8(SRC, 63, DST, 64, 64, 8, TAPS, 2, 12) == B.ICL_ERR_PITCH
+    assert u8(0, 64, DST, 64, 64, 8, TAPS, 2, 12) == B.ICL_ERR_INVALID_VALUE
+    assert u8(SRC, 64, DST, 64, 64, 8, 0, 2, 12) == B.ICL_ERR_INVALID_VALUE
+    assert u8(SRC, 64, SRC + 7 * 64, 64, 64, 8, TAPS, 2, 12) == B.ICL_ERR_ALIAS
+    assert u8(SRC, 64, DST, 64, -1, 8, TAPS, 2, 12) == B.ICL_ERR_INVALID_VALUE
+    assert u8(SRC, 64, DST, 64, 0, 8, TAPS, 2, 12) == B.ICL_OK
 
 
 def test_bank_and_loss_validation(no_gpu):
@@ -186,6 +221,10 @@ def test_no_device_or_launch_path(L):
     assert B.icl_init() == B.ICL_ERR_NO_DEVICE
     assert sep() == B.ICL_ERR_NO_DEVICE
     assert sep(dst=SRC + 8 * 256) == B.ICL_ERR_NO_DEVICE         # adjacent rows are no alias
+    assert B.icl_conv2d_u8(SRC, 64, SRC + 8 * 64, 64, 64, 8, TAPS, 2, 12, B.ICL_BORDER_CONSTANT,
+                           255) == B.ICL_ERR_NO_DEVICE
+    assert B.icl_conv_sep_border(SRC, 256, DST, 256, 64, 8, B.ICL_F32, TAPS, TAPS, 2, B.ICL_BORDER_CONSTANT,
+                                 0.5) == B.ICL_ERR_NO_DEVICE
     _, wsb = B.icl_workspace_size(B.ICL_OP_BANK_FWD_SSE, 8, 8, 2, 4, 4)
     # loss scalar right after the target, y absent: valid, so it reaches the device check
     assert B.icl_bank_fwd_sse(SRC, TAPS, 0x50000000, 0, 0x60000000, 0x50000000 + 2048, 2, 4, 8, 8, 4,

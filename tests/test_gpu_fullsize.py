@@ -216,3 +216,54 @@ def test_filter_bank_full_size():
         np.copyto(gy64, synth.uniform_large(synth.seed(5, 6), N * F * H * W, -1.0, 1.0).reshape(N, F, H, W))
         err = np.max(np.abs(gw[lo:hi] - ref) / scale)
         assert err <= 1e-5, f"filter {f}: normwise {err:.3e}"
+
+
+@pytest.mark.parametrize("c", [0.0, 0.5])
+def test_paper_separable_constant_4096(sweep, c):
+    """The paper's separable workload: 4096^2 float, 5x5, constant boundary (plus c != 0)."""
+    xd, x64 = sweep
+    H, W = x64.shape
+    h, v = synth.sweep_taps_sep(2)
+    th, tv = torch.from_numpy(h).cuda(), torch.from_numpy(v).cuda()
+    xs, ys = sample_points(H, W, 3000, 110)
+    ref = oracle.conv_sep_pts(x64, h, v, xs, ys, border="constant", constant=c)
+    scale = oracle.conv_sep_pts(np.abs(x64), np.abs(h), np.abs(v), xs, ys, border="constant", constant=abs(c))
+    _, nb = B.icl_workspace_size(B.ICL_OP_CONV_SEP, W, H)
+    ws = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
+    out = torch.empty_like(xd)
+    for variant in range(B.icl_variant_count(B.ICL_OP_CONV_SEP)):
+        B.check(B.icl_force_variant(B.ICL_OP_CONV_SEP, variant))
+        try:
+            out.fill_(float("nan"))
+            T.conv_sep(xd, th, tv, out=out, workspace=ws, border="constant", constant=c)
+            err = normwise(gather(out, xs, ys), ref, scale)
+            assert err <= 1e-5, f"variant {variant} c={c}: {err:.3e}"
+            assert not torch.isnan(out).any()
+        finally:
+            B.icl_force_variant(B.ICL_OP_CONV_SEP, -1)
+
+
+def test_paper_u8_8192():
+    """The paper's non-separable workload: 8192^2 unsigned char, 5x5, clamped.  Every variant
+    returns the same bytes over the whole image, and they match the oracle at sampled pixels."""
+    X = synth.paper_u8_image()
+    H, W = X.shape
+    taps = synth.u8_taps(6, 2, synth.U8_SHIFT)
+    xd = torch.from_numpy(X).cuda()
+    td = torch.from_numpy(taps).cuda()
+    xs, ys = sample_points(H, W, 4000, 111)
+    ref = oracle.conv2d_u8_pts(X, taps, synth.U8_SHIFT, xs, ys)
+    first = None
+    for variant in range(B.icl_variant_count(B.ICL_OP_CONV2D_U8)):
+        B.check(B.icl_force_variant(B.ICL_OP_CONV2D_U8, variant))
+        try:
+            out = torch.full_like(xd, 0xA5)
+            T.conv2d_u8(xd, td, synth.U8_SHIFT, out=out)
+            got = out[torch.from_numpy(ys).cuda(), torch.from_numpy(xs).cuda()].cpu().numpy()
+            assert np.array_equal(got, ref), f"variant {variant}: {int(np.sum(got != ref))} sampled bytes differ"
+            if first is None:
+                first = out
+            else:
+                assert torch.equal(out, first), f"variant {variant} differs from variant 0"
+        finally:
+            B.icl_force_variant(B.ICL_OP_CONV2D_U8, -1)
