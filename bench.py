@@ -11,7 +11,9 @@ Alongside: the plain (one pixel per thread) step, per-call Gpixel/s and % of
 the binding roof (HBM 8 TB/s at 8 B/px, or the FP32 FMA rate), the roofline of
 the dominant kernel, the FP64 CPU oracle on a bounded sample of the same
 workload, and (unless --no-extras) the corner pipeline, the uneven half-float
-batch and the filter-bank forward+backward step.
+batch, the filter-bank forward+backward step and the paper's own two convolution
+settings (separable 4096^2 float with the constant boundary; 2-D 8192^2 unsigned
+char, clamped).
 """
 from __future__ import annotations
 
@@ -30,7 +32,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP32_FMA_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, packed FP32 disabled
 FP32_PACKED_PEAK_TFLOPS = 157.3
-EXTRAS = ("corner", "batch", "bank")
+EXTRAS = ("corner", "batch", "bank", "paper")
+INT_DOT2_PEAK_TMACS = 78.6     # v_dot2_i32_i16: 2 int16 MACs per lane per issue, 256 CU x 64 lanes x 2.4 GHz
 METRIC = "Gpixel/s & % HBM peak, autotuned vs plain kernel; fwd+bwd Gpixel/s"
 
 
@@ -43,7 +46,7 @@ def parse():
     p.add_argument("--no-extras", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--only", default="", help="comma list of sweep call labels (sep1 ... 2d7) and extra "
-                   "workloads (corner, batch, bank) to run; a profiling aid")
+                   "workloads (corner, batch, bank, paper) to run; a profiling aid")
     p.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter_collection.csv files of a --calib-copy "
                         "run into profiles/traffic.json and exit")
@@ -331,6 +334,81 @@ def run_extras(torch, B, T, synth, steps, which=EXTRAS):
         res.update(extra_batch(torch, B, T, synth, steps))
     if "bank" in which:
         res.update(extra_bank(torch, B, T, synth, steps))
+    if "paper" in which:
+        res.update(extra_paper(torch, B, T, synth, steps))
+    return res
+
+
+def extra_paper(torch, B, T, synth, steps):
+    """The paper's two convolution benchmarks at their own settings: the separable 5x5 filter on
+    a 4096^2 float image with the constant boundary (c = 0), and the full 5x5 filter on an
+    8192^2 unsigned char image, clamped (int16 taps, exact integer sum, shift 12)."""
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream().cuda_stream
+    res = {}
+    NSET = 4
+    # separable, constant boundary
+    img = synth.sweep_image()
+    H, W = img.shape
+    xs = [torch.from_numpy(img).to(dev) for _ in range(NSET)]
+    ys = [torch.empty_like(xs[0]) for _ in range(NSET)]
+    h, v = synth.sweep_taps_sep(2)
+    th, tv = torch.from_numpy(h).to(dev), torch.from_numpy(v).to(dev)
+    ws = torch.empty(B.icl_workspace_size(B.ICL_OP_CONV_SEP, W, H)[1] // 4 + 1, dtype=torch.float32, device=dev)
+    B.check(B.icl_tune(B.ICL_OP_CONV_SEP, B.ICL_F32, 2, W, H, st))
+
+    def sep(s):
+        T.conv_sep(xs[s % NSET], th, tv, out=ys[s % NSET], workspace=ws, border="constant", constant=0.0)
+
+    dt = _time(torch, sep, 4 * steps)
+    per_variant = {}
+    for vi in range(B.icl_variant_count(B.ICL_OP_CONV_SEP)):
+        B.check(B.icl_force_variant(B.ICL_OP_CONV_SEP, vi))
+        try:
+            per_variant[B.icl_variant_name(B.ICL_OP_CONV_SEP, vi)] = round(_time(torch, sep, 2 * steps) * 1e6, 1)
+        finally:
+            B.icl_force_variant(B.ICL_OP_CONV_SEP, -1)
+    gpx = H * W / dt / 1e9
+    res["paper_sep5_constant_4096_f32"] = {
+        "us": round(dt * 1e6, 2), "gpx_s": round(gpx, 1), "bytes_per_px": 8,
+        "hbm_frac": round(gpx * 8 / HBM_PEAK_GBS, 3),
+        "variant": B.icl_variant_name(B.ICL_OP_CONV_SEP, B.icl_selected_variant(B.ICL_OP_CONV_SEP, B.ICL_F32, 2, W,
+                                                                                 H)[1]),
+        "variants_us": per_variant}
+    del xs, ys, ws
+    torch.cuda.empty_cache()
+    # unsigned char, clamped
+    X = synth.paper_u8_image()
+    H, W = X.shape
+    xs = [torch.from_numpy(X).to(dev) for _ in range(NSET)]
+    ys = [torch.empty_like(xs[0]) for _ in range(NSET)]
+    td = torch.from_numpy(synth.u8_taps(6, 2, synth.U8_SHIFT)).to(dev)
+    B.check(B.icl_tune(B.ICL_OP_CONV2D_U8, B.ICL_U8, 2, W, H, st))
+
+    def u8(s):
+        T.conv2d_u8(xs[s % NSET], td, synth.U8_SHIFT, out=ys[s % NSET])
+
+    dt = _time(torch, u8, 4 * steps)
+    per_variant = {}
+    for vi in range(B.icl_variant_count(B.ICL_OP_CONV2D_U8)):
+        B.check(B.icl_force_variant(B.ICL_OP_CONV2D_U8, vi))
+        try:
+            per_variant[B.icl_variant_name(B.ICL_OP_CONV2D_U8, vi)] = round(
+                _time(torch, u8, steps if vi == 0 else 2 * steps) * 1e6, 1)
+        finally:
+            B.icl_force_variant(B.ICL_OP_CONV2D_U8, -1)
+    gpx = H * W / dt / 1e9
+    macs = 25 * H * W
+    res["paper_conv2d5_u8_8192"] = {
+        "us": round(dt * 1e6, 2), "gpx_s": round(gpx, 1), "bytes_per_px": 2,
+        "hbm_frac": round(gpx * 2 / HBM_PEAK_GBS, 3),
+        "int_tmac_s": round(macs / dt / 1e12, 2), "int_dot2_peak_tmac_s": INT_DOT2_PEAK_TMACS,
+        "int_frac": round(macs / dt / 1e12 / INT_DOT2_PEAK_TMACS, 3),
+        "variant": B.icl_variant_name(B.ICL_OP_CONV2D_U8, B.icl_selected_variant(B.ICL_OP_CONV2D_U8, B.ICL_U8, 2, W,
+                                                                                   H)[1]),
+        "variants_us": per_variant}
+    del xs, ys
+    torch.cuda.empty_cache()
     return res
 
 

@@ -284,7 +284,8 @@ icl_status icl_bank_fwd_sse(const float* x, const float* w, const float* t, floa
  * The tuner plays the role of the paper's auto-tuner (Section 4 and the
  * discussion of tuning cost): it runs every precompiled candidate variant of an
  * operation on synthetic data of the given shape, rejects candidates whose
- * output differs from the plain variant's, times the rest with HIP events on
+ * output differs from the plain variant's (byte for byte for ICL_OP_CONV2D_U8,
+ * whose dtype is ICL_U8), times the rest with HIP events on
  * rotating buffers, and records the fastest in a per-device cache keyed by
  * (device, op, dtype, radius, size class).  Candidates are compiled ahead of
  * time, so a search costs only run time.

@@ -29,6 +29,17 @@ typedef short short2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ int requant(int s, int shift, int bias) { return min(max((s + bias) >> shift, 0), 255); }
 
+// Output byte of a sum that already holds the rounding bias.  The empty asm hides the
+// clamp's range from the compiler, so the four bytes are packed with full 32-bit
+// shifts and ors: otherwise gfx950 code generation may fuse shift, saturation and
+// packing into v_ashr_pk_u8_i32, which writes only the low half of its destination
+// while the or that follows assumes the upper half is zero.
+__device__ __forceinline__ uint32_t out_byte(int s, int shift) {
+    int q = min(max(s >> shift, 0), 255);
+    asm volatile("" : "+v"(q));
+    return (uint32_t)q;
+}
+
 // ------------------------------------------------------------------ plain
 __global__ __launch_bounds__(256) void u8_plain(const uint8_t* __restrict__ src, size_t sp, uint8_t* __restrict__ dst,
                                                 size_t dp, int W, int H, const int16_t* __restrict__ taps, int r,
@@ -60,15 +71,19 @@ hipError_t launch_plain(const U8Args& a) {
 bool supports_plain(const U8Args& a) { return a.r >= 0 && a.r <= ICL_MAX_U8_RADIUS; }
 
 // ------------------------------------------------------------------ register-streaming strips
-template <int R> struct U8Strip {
-    static constexpr int RA = (R + 3) & ~3;              // halo columns per side (whole words)
-    static constexpr int HL = RA / 4;                     // halo lanes per side
-    static constexpr int SW = 4 * (64 - 2 * HL);          // output columns per strip
-    static constexpr int D = 2 * R + 1;                   // pending output rows
-    static constexpr int U = D * ((8 + D - 1) / D);       // unroll: ring slots known at compile time
-    static constexpr int Q = 8;                           // input rows in flight ahead
-    static constexpr int NW = 1 + 2 * HL;                 // words of a row a lane sees
-    static_assert(Q <= U, "prefetch distance must fit the ring");
+// A lane holds PX consecutive pixels (PX / 4 words) of every input row its wave walks.  For
+// r >= 1 the first and last lane of the wave only supply the horizontal halo (r <= 4
+// columns: one word of each neighbour lane), so a strip has PX * 62 output columns; for
+// r = 0 every lane writes.
+template <int R, int PX> struct U8Strip {
+    static_assert(R >= 0 && R <= 4, "strip kernels cover radii 0..4");
+    static constexpr int HL = R > 0 ? 1 : 0;               // halo lanes per side
+    static constexpr int NWL = PX / 4;                     // words a lane loads per row
+    static constexpr int SW = PX * (64 - 2 * HL);          // output columns per strip
+    static constexpr int OFF = HL ? 4 : 0;                 // window column of the lane's first pixel
+    static constexpr int NW = NWL + 2 * HL;                // words of a row a lane sees
+    static constexpr int D = 2 * R + 1;                    // tap rows
+    static constexpr int Q = 8;                            // input rows in flight ahead
 };
 
 __device__ __forceinline__ uint32_t word_from_left(uint32_t v) {
@@ -78,171 +93,189 @@ __device__ __forceinline__ uint32_t word_from_right(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
 }
 
-template <int R, int TH, bool DOT>
-__global__ __launch_bounds__(64) void u8_strip(const uint8_t* __restrict__ src, size_t sp, uint8_t* __restrict__ dst,
-                                               size_t dp, int W, int H, const int16_t* __restrict__ taps, int shift,
-                                               int nstrips, int vec_in, int vec_out, int cmode, int cval) {
-    using G = U8Strip<R>;
-    constexpr int RA = G::RA, HL = G::HL, D = G::D, U = G::U, Q = G::Q, NW = G::NW;
-    constexpr int K = TH + 2 * R;   // input rows walked
-    const int strip = (int)(blockIdx.x % (unsigned)nstrips);
-    const int y0 = (int)(blockIdx.x / (unsigned)nstrips) * TH;
+template <int PX> struct RowWords { uint32_t w[PX / 4]; };
+
+// One strip of TH output rows, all K = TH + 2r input rows unrolled so that every ring slot,
+// accumulator row and output condition is known at compile time.
+//   EDGE = false: every word of every lane lies inside the image, and source and destination
+//                 rows are PX-byte aligned (the interior strips): one vector load and one
+//                 vector store per lane and row.
+//   EDGE = true : any strip; each byte is read through the boundary condition and
+//                 written only if it lies inside the image.
+// Per input row: the neighbour lanes' boundary words arrive by DPP lane shifts, the
+// pixels are widened to 16-bit pairs (v_perm), and each output pixel takes, per tap row,
+// r + 1 packed dot products against tap pairs (taps[j][t], taps[j][t+1]) aligned to its
+// column parity.  The sums start from the rounding bias, so the output is
+// med3(acc >> shift, 0, 255).
+template <int R, int TH, int PX, bool EDGE>
+__device__ __forceinline__ void u8_strip_body(const uint8_t* __restrict__ src, size_t sp, uint8_t* __restrict__ dst,
+                                              size_t dp, int W, int H, const int* __restrict__ tw, int shift,
+                                              int bias, int c, int y0, int cmode, int cval) {
+    using G = U8Strip<R, PX>;
+    constexpr int HL = G::HL, NWL = G::NWL, NW = G::NW, OFF = G::OFF, D = G::D;
+    constexpr int K = TH + 2 * R;
+    constexpr int Q = K < G::Q ? K : G::Q;
     const int lane = threadIdx.x & 63;
-    const int c = strip * G::SW - RA + 4 * lane;   // first column of this lane's word
-    const bool inside = vec_in && c >= 0 && c + 4 <= W;
     const uint32_t cword = (uint32_t)cval * 0x01010101u;
 
-    auto load_row = [&](int kk) -> uint32_t {
+    auto load_row = [&](int kk) -> RowWords<PX> {
+        RowWords<PX> v;
         const int yy = y0 - R + kk;
-        if (cmode && (yy < 0 || yy >= H)) return cword;
-        const size_t row = (size_t)clampi(yy, H) * sp;
-        if (inside) return *reinterpret_cast<const uint32_t*>(src + row + c);
-        uint32_t v = 0;
+        if (cmode && (yy < 0 || yy >= H)) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int xx = c + q;
-            const uint32_t b = (cmode && (xx < 0 || xx >= W)) ? (uint32_t)cval : (uint32_t)src[row + clampi(xx, W)];
-            v |= b << (8 * q);
+            for (int q = 0; q < NWL; ++q) v.w[q] = cword;
+            return v;
+        }
+        const uint8_t* row = src + (size_t)clampi(yy, H) * sp;
+        if constexpr (!EDGE) {
+            if constexpr (PX == 8) {
+                const uint2 t = *reinterpret_cast<const uint2*>(row + c);
+                v.w[0] = t.x;
+                v.w[1] = t.y;
+            } else {
+                v.w[0] = *reinterpret_cast<const uint32_t*>(row + c);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NWL; ++q) {
+                uint32_t word = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int xx = c + 4 * q + b;
+                    const uint32_t px =
+                        (cmode && (xx < 0 || xx >= W)) ? (uint32_t)cval : (uint32_t)row[clampi(xx, W)];
+                    word |= px << (8 * b);
+                }
+                v.w[q] = word;
+            }
         }
         return v;
     };
 
-    // taps: plain values (multiply-add) or packed pairs (dot2): pair t0 + 1 of row j holds
-    // (taps[j][t0], taps[j][t0 + 1]) with zero outside 0..2r, t0 = -1 .. 2r
-    constexpr int NT = DOT ? D * (D + 1) : D * D;
-    int tw[NT];
-    {
-        const int n = D;
+    const bool writer = lane >= HL && lane < 64 - HL && (!EDGE || c < W);
+    RowWords<PX> ring[Q];
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            if constexpr (DOT) {
+    for (int i = 0; i < Q; ++i) ring[i] = load_row(i);
+    int acc[D][PX];
+
+    static_for<K>([&](auto kk_c) {
+        constexpr int kk = decltype(kk_c)::value;
+        uint32_t wd[NW];
 #pragma unroll
-                for (int t = -1; t < D; ++t) {
-                    const int lo = (t >= 0) ? (int)taps[j * n + t] : 0;
-                    const int hi = (t + 1 < D) ? (int)taps[j * n + t + 1] : 0;
-                    tw[j * (D + 1) + t + 1] = (lo & 0xffff) | (hi << 16);
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < D; ++i) tw[j * D + i] = (int)taps[j * n + i];
-            }
+        for (int q = 0; q < NWL; ++q) wd[HL + q] = ring[kk % Q].w[q];
+        if constexpr (kk + Q < K) ring[kk % Q] = load_row(kk + Q);   // slot consumed: refill
+        if constexpr (HL == 1) {
+            wd[0] = word_from_left(wd[NWL]);          // left lane's last word
+            wd[NWL + 1] = word_from_right(wd[1]);     // right lane's first word
         }
-    }
-    const int bias = shift > 0 ? 1 << (shift - 1) : 0;
-    const bool writer = lane >= HL && lane < 64 - HL && c < W;
-    const bool wvec = vec_out && c + 4 <= W;
-
-    uint32_t ring[U];
+        // pixel pairs: pair k holds window columns (2k, 2k + 1) as 16-bit lanes
+        constexpr int NP = 2 * NW;
+        int pr[NP];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) ring[i] = i < K ? load_row(i) : 0u;
-    int acc[D][4];
+        for (int k = 0; k < NP; ++k)
+            pr[k] = (int)__builtin_amdgcn_perm(0u, wd[k / 2], (k & 1) ? 0x0c030c02u : 0x0c010c00u);
+        static_for<D>([&](auto j_c) {
+            constexpr int j = decltype(j_c)::value;
+            constexpr int m = kk - j;   // output row this input row feeds through tap row j
+            if constexpr (m >= 0 && m < TH) {
+                int* a = acc[m % D];
 #pragma unroll
-    for (int i = 0; i < D; ++i)
+                for (int p = 0; p < PX; ++p) {
+                    if constexpr (j == 0) a[p] = bias;   // first contribution to output row m
 #pragma unroll
-        for (int p = 0; p < 4; ++p) acc[i][p] = 0;
-
-    for (int kb = 0; kb < K; kb += U) {
-        static_for<U>([&](auto u_c) {
-            constexpr int u = decltype(u_c)::value;
-            const int kk = kb + u;
-            if (kk >= K) return;
-            // the words this lane sees: w[HL] is its own, w[HL - 1] the left neighbour's, ...
-            uint32_t wd[NW];
-            wd[HL] = ring[u];
-            if constexpr (HL >= 1) {
-                wd[HL - 1] = word_from_left(wd[HL]);
-                wd[HL + 1] = word_from_right(wd[HL]);
-            }
-            if constexpr (HL >= 2) {
-                wd[HL - 2] = word_from_left(wd[HL - 1]);
-                wd[HL + 2] = word_from_right(wd[HL + 1]);
-            }
-            if (kk + Q < K) ring[(u + Q) % U] = load_row(kk + Q);   // that slot's row is consumed
-            if constexpr (DOT) {
-                // pixel pairs: pair k holds columns (c - RA + 2k, c - RA + 2k + 1) as 16-bit lanes
-                constexpr int NP = 2 * NW;
-                int pr[NP];
-#pragma unroll
-                for (int k = 0; k < NP; ++k)
-                    pr[k] = (int)__builtin_amdgcn_perm(0u, wd[k / 2], (k & 1) ? 0x0c030c02u : 0x0c010c00u);
-#pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    const int m = kk - j;
-                    if (m < 0 || m >= TH) continue;
-                    int* a = acc[((u - j) % D + D) % D];
-#pragma unroll
-                    for (int p = 0; p < 4; ++p) {
-#pragma unroll
-                        for (int k = 0; k < NP; ++k) {
-                            const int t0 = 2 * k - (RA + p - R);   // tap index of the pair's first column
-                            if (t0 < -1 || t0 > 2 * R) continue;
-                            a[p] = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, pr[k]),
-                                                          __builtin_bit_cast(short2_t, tw[j * (D + 1) + t0 + 1]),
-                                                          a[p], false);
-                        }
+                    for (int k = 0; k < NP; ++k) {
+                        const int t0 = 2 * k - (OFF + p - R);   // tap index of the pair's first column
+                        if (t0 < -1 || t0 > 2 * R) continue;
+                        a[p] = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, pr[k]),
+                                                      __builtin_bit_cast(short2_t, tw[j * (D + 1) + t0 + 1]), a[p],
+                                                      false);
                     }
                 }
-            } else {
-                int e[4 * NW];
-#pragma unroll
-                for (int k = 0; k < 4 * NW; ++k) e[k] = (int)((wd[k / 4] >> (8 * (k & 3))) & 0xffu);
-#pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    const int m = kk - j;
-                    if (m < 0 || m >= TH) continue;
-                    int* a = acc[((u - j) % D + D) % D];
-#pragma unroll
-                    for (int p = 0; p < 4; ++p)
-#pragma unroll
-                        for (int i = 0; i < D; ++i) a[p] = __mul24(tw[j * D + i], e[RA - R + p + i]) + a[p];
-                }
-            }
-            if (kk >= 2 * R) {
-                constexpr int slot = ((u - 2 * R) % D + D) % D;
-                const int y = y0 + kk - 2 * R;
-                if (writer && y < H) {
-                    uint32_t q[4];
-#pragma unroll
-                    for (int p = 0; p < 4; ++p) q[p] = (uint32_t)requant(acc[slot][p], shift, bias);
-                    uint8_t* o = dst + (size_t)y * dp + c;
-                    if (wvec) {
-                        *reinterpret_cast<uint32_t*>(o) = q[0] | (q[1] << 8) | (q[2] << 16) | (q[3] << 24);
-                    } else {
-#pragma unroll
-                        for (int p = 0; p < 4; ++p)
-                            if (c + p < W) o[p] = (uint8_t)q[p];
-                    }
-                }
-#pragma unroll
-                for (int p = 0; p < 4; ++p) acc[slot][p] = 0;
             }
         });
-    }
+        if constexpr (kk >= 2 * R) {
+            constexpr int m = kk - 2 * R;   // output row complete
+            const int y = y0 + m;
+            if (writer && y < H) {
+                uint32_t o4[NWL];
+#pragma unroll
+                for (int q = 0; q < NWL; ++q) {
+                    uint32_t b[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) b[t] = out_byte(acc[m % D][4 * q + t], shift);
+                    o4[q] = b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
+                }
+                uint8_t* o = dst + (size_t)y * dp + c;
+                if constexpr (!EDGE) {
+                    if constexpr (PX == 8)
+                        *reinterpret_cast<uint2*>(o) = make_uint2(o4[0], o4[1]);
+                    else
+                        *reinterpret_cast<uint32_t*>(o) = o4[0];
+                } else {
+#pragma unroll
+                    for (int p = 0; p < PX; ++p)
+                        if (c + p < W) o[p] = (uint8_t)(o4[p / 4] >> (8 * (p & 3)));
+                }
+            }
+        }
+    });
 }
 
-template <int R, int TH, bool DOT>
+template <int R, int TH, int PX>
+__global__ __launch_bounds__(64) void u8_strip(const uint8_t* __restrict__ src, size_t sp, uint8_t* __restrict__ dst,
+                                               size_t dp, int W, int H, const int16_t* __restrict__ taps, int shift,
+                                               int nstrips, int vec, int cmode, int cval) {
+    using G = U8Strip<R, PX>;
+    constexpr int D = G::D;
+    const int strip = (int)(blockIdx.x % (unsigned)nstrips);
+    const int y0 = (int)(blockIdx.x / (unsigned)nstrips) * TH;
+    const int lane = threadIdx.x & 63;
+    const int x0 = strip * G::SW - G::HL * PX;   // first column of lane 0
+    const int c = x0 + PX * lane;
+
+    // tap pairs: entry t0 + 1 of row j holds (taps[j][t0], taps[j][t0 + 1]), zero outside
+    // 0..2r, for t0 = -1 .. 2r
+    int tw[D * (D + 1)];
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+        for (int t = -1; t < D; ++t) {
+            const int lo = (t >= 0) ? (int)taps[j * D + t] : 0;
+            const int hi = (t + 1 < D) ? (int)taps[j * D + t + 1] : 0;
+            tw[j * (D + 1) + t + 1] = (lo & 0xffff) | (hi << 16);
+        }
+    const int bias = shift > 0 ? 1 << (shift - 1) : 0;
+    const bool interior = vec && x0 >= 0 && x0 + 64 * PX <= W;
+    if (interior)
+        u8_strip_body<R, TH, PX, false>(src, sp, dst, dp, W, H, tw, shift, bias, c, y0, cmode, cval);
+    else
+        u8_strip_body<R, TH, PX, true>(src, sp, dst, dp, W, H, tw, shift, bias, c, y0, cmode, cval);
+}
+
+template <int R, int TH, int PX>
 hipError_t launch_strip_R(const U8Args& a) {
-    using G = U8Strip<R>;
+    using G = U8Strip<R, PX>;
     const int nstrips = (a.W + G::SW - 1) / G::SW;
     const long long blocks = (long long)nstrips * ((a.H + TH - 1) / TH);
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    const int vec_in = ((uintptr_t)a.src % 4 == 0) && (a.sp % 4 == 0);
-    const int vec_out = ((uintptr_t)a.dst % 4 == 0) && (a.dp % 4 == 0);
-    hipLaunchKernelGGL((u8_strip<R, TH, DOT>), dim3((unsigned)blocks), dim3(64), 0, a.st, a.src, a.sp, a.dst, a.dp,
-                       a.W, a.H, a.taps, a.shift, nstrips, vec_in, vec_out, a.cmode, a.cval);
+    // interior strips use PX-byte vector loads and stores: both images' rows must be aligned
+    const int vec = ((uintptr_t)a.src % PX == 0) && (a.sp % PX == 0) && ((uintptr_t)a.dst % PX == 0) &&
+                    (a.dp % PX == 0);
+    hipLaunchKernelGGL((u8_strip<R, TH, PX>), dim3((unsigned)blocks), dim3(64), 0, a.st, a.src, a.sp, a.dst, a.dp,
+                       a.W, a.H, a.taps, a.shift, nstrips, vec, a.cmode, a.cval);
     return hipGetLastError();
 }
 
 constexpr int U8_STRIP_MAX_R = 4;
 
-template <int TH, bool DOT>
+template <int TH, int PX>
 hipError_t launch_strip(const U8Args& a) {
     switch (a.r) {
-        case 0: return launch_strip_R<0, TH, DOT>(a);
-        case 1: return launch_strip_R<1, TH, DOT>(a);
-        case 2: return launch_strip_R<2, TH, DOT>(a);
-        case 3: return launch_strip_R<3, TH, DOT>(a);
-        case 4: return launch_strip_R<4, TH, DOT>(a);
+        case 0: return launch_strip_R<0, TH, PX>(a);
+        case 1: return launch_strip_R<1, TH, PX>(a);
+        case 2: return launch_strip_R<2, TH, PX>(a);
+        case 3: return launch_strip_R<3, TH, PX>(a);
+        case 4: return launch_strip_R<4, TH, PX>(a);
         default: return hipErrorInvalidValue;
     }
 }
@@ -251,9 +284,11 @@ bool supports_strip(const U8Args& a) { return a.r >= 0 && a.r <= U8_STRIP_MAX_R;
 
 const Variant<U8Args> kConv2dU8[] = {
     {"plain", supports_plain, launch_plain},
-    {"strip_mad_t64", supports_strip, launch_strip<64, false>},
-    {"strip_dot_t64", supports_strip, launch_strip<64, true>},
-    {"strip_dot_t32", supports_strip, launch_strip<32, true>},
+    {"strip_p4_t16", supports_strip, launch_strip<16, 4>},
+    {"strip_p4_t32", supports_strip, launch_strip<32, 4>},
+    {"strip_p8_t16", supports_strip, launch_strip<16, 8>},
+    {"strip_p8_t32", supports_strip, launch_strip<32, 8>},
+    {"strip_p4_t24", supports_strip, launch_strip<24, 4>},
 };
 
 }  // namespace
@@ -263,6 +298,6 @@ const Variant<U8Args>* conv2d_u8_variants(int* count) {
     return kConv2dU8;
 }
 
-int conv2d_u8_default(const U8Args& a) { return supports_strip(a) ? 2 : 0; }
+int conv2d_u8_default(const U8Args& a) { return supports_strip(a) ? 1 : 0; }
 
 }  // namespace icl

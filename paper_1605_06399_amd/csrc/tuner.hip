@@ -137,6 +137,16 @@ __global__ void compare_u8_k(const uint8_t* a, const uint8_t* b, size_t pitch, i
     if (a[(size_t)y * pitch + x] != b[(size_t)y * pitch + x]) atomicAdd(&out[0], 1u);
 }
 
+__global__ void fill_u8_k(uint8_t* p, size_t pitch, int W, int H, unsigned long long seed) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (size_t)W * H) return;
+    const int y = (int)(i / W), x = (int)(i % W);
+    unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    p[(size_t)y * pitch + x] = (uint8_t)((z ^ (z >> 31)) >> 56);
+}
+
 __global__ void zero2_k(unsigned* p) {
     if (threadIdx.x < 2) p[threadIdx.x] = 0u;
 }
@@ -352,6 +362,44 @@ icl_status tune_harris(int rg, int W, int H, hipStream_t st) {
     return search(ICL_OP_HARRIS, tab, count, ICL_F32, rg, W, H, sets, make, agree, st);
 }
 
+icl_status tune_conv_u8(int r, int W, int H, hipStream_t st) {
+    const size_t pitch = ((size_t)W + 255) & ~(size_t)255;
+    const int sets = rotation_sets(2 * pitch * H);
+    Buffers b;
+    std::vector<void*> src(sets), dst(sets);
+    for (int s = 0; s < sets; ++s) {
+        src[s] = b.alloc(pitch * H);
+        dst[s] = b.alloc(pitch * H);
+        if (!src[s] || !dst[s]) return ICL_ERR_HIP;
+        hipLaunchKernelGGL(fill_u8_k, dim3(blocks_for((size_t)W * H)), dim3(256), 0, st,
+                           static_cast<uint8_t*>(src[s]), pitch, W, H, 0x77ull + s);
+        if (hipGetLastError() != hipSuccess) return ICL_ERR_HIP;
+    }
+    void* ref = b.alloc(pitch * H);
+    const int n = 2 * r + 1;
+    std::vector<int16_t> taps(n * n);
+    for (int k = 0; k < n * n; ++k) taps[k] = (int16_t)(160 + 97 * ((k * 7) % 5) - 40 * (k % 3));
+    int16_t* d_taps = static_cast<int16_t*>(b.alloc(taps.size() * sizeof(int16_t)));
+    unsigned* d_stat = static_cast<unsigned*>(b.alloc(16));
+    if (!ref || !d_taps || !d_stat) return ICL_ERR_HIP;
+    if (hipMemcpyAsync(d_taps, taps.data(), taps.size() * sizeof(int16_t), hipMemcpyHostToDevice, st) != hipSuccess)
+        return ICL_ERR_HIP;
+    int count;
+    const Variant<U8Args>* tab = conv2d_u8_variants(&count);
+    const int shift = 12;
+    auto make = [&](int s, int) {
+        return U8Args{static_cast<const uint8_t*>(src[s]), pitch, static_cast<uint8_t*>(dst[s]), pitch, W, H, d_taps,
+                      r, shift, 0, 0, st};
+    };
+    U8Args p0 = make(0, 0);
+    p0.dst = static_cast<uint8_t*>(ref);
+    if (tab[0].launch(p0) != hipSuccess) return ICL_ERR_HIP;
+    auto agree = [&]() {   // integer results: every variant must return the same bytes
+        return masks_agree(static_cast<uint8_t*>(dst[0]), static_cast<uint8_t*>(ref), pitch, W, H, d_stat, st);
+    };
+    return search(ICL_OP_CONV2D_U8, tab, count, ICL_U8, r, W, H, sets, make, agree, st);
+}
+
 icl_status tune_nms(int r, int W, int H, hipStream_t st) {
     const size_t pitch = ((size_t)W * 4 + 255) & ~(size_t)255;
     const size_t mpitch = ((size_t)W + 255) & ~(size_t)255;
@@ -439,7 +487,8 @@ extern "C" {
 
 icl_status icl_tune(icl_op op, icl_dtype dtype, int radius, int width, int height, void* stream) {
     if (width < 1 || height < 1) return ICL_ERR_INVALID_VALUE;
-    if (dtype != ICL_F32 && dtype != ICL_F16 && dtype != ICL_BF16) return ICL_ERR_DTYPE;
+    if (op == ICL_OP_CONV2D_U8 ? dtype != ICL_U8 : (dtype != ICL_F32 && dtype != ICL_F16 && dtype != ICL_BF16))
+        return ICL_ERR_DTYPE;
     icl_status s = device_ready();
     if (s != ICL_OK) return s;
     hipStream_t st = (hipStream_t)stream;
@@ -455,6 +504,10 @@ icl_status icl_tune(icl_op op, icl_dtype dtype, int radius, int width, int heigh
             if (radius < 0 || radius > ICL_MAX_WINDOW_RADIUS) return ICL_ERR_RADIUS;
             if (dtype != ICL_F32) return ICL_ERR_DTYPE;
             s = tune_harris(radius, width, height, st);
+            break;
+        case ICL_OP_CONV2D_U8:
+            if (radius < 0 || radius > ICL_MAX_U8_RADIUS) return ICL_ERR_RADIUS;
+            s = tune_conv_u8(radius, width, height, st);
             break;
         case ICL_OP_NMS:
             if (radius < 1 || radius > ICL_MAX_NMS_RADIUS) return ICL_ERR_RADIUS;

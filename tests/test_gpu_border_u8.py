@@ -175,7 +175,10 @@ def test_clamp_border_through_border_entry_points_is_the_plain_call():
 
 # ----------------------------------------------------------------------------- unsigned char
 
-U8_SHAPES = [(389, 517), (1, 1), (1, 3), (2, 70), (70, 1), (3, 5), (64, 64), (33, 250), (17, 497)]
+# widths that are multiples of 4 (aligned rows) and at least two strips wide exercise the
+# interior strips' word loads and stores; the others the byte-wise edge path
+U8_SHAPES = [(389, 517), (1, 1), (1, 3), (2, 70), (70, 1), (3, 5), (64, 64), (33, 250), (17, 497),
+             (37, 1024), (21, 2000), (19, 1536)]
 U8_BORDERS = [("clamp", 0), ("constant", 0), ("constant", 200)]
 
 
@@ -284,3 +287,18 @@ def test_conv2d_u8_delta_reproduces_input():
                 assert torch.equal(out, xd), f"v{variant} shift{shift}"
             finally:
                 B.icl_force_variant(B.ICL_OP_CONV2D_U8, -1)
+
+
+def test_tuner_u8_selects_a_variant_and_stays_exact():
+    H, W, r = 300, 700, 2
+    try:
+        B.check(B.icl_tune(B.ICL_OP_CONV2D_U8, B.ICL_U8, r, W, H), "tune u8")
+        st, idx = B.icl_selected_variant(B.ICL_OP_CONV2D_U8, B.ICL_U8, r, W, H)
+        assert st == B.ICL_OK and idx >= 1
+        assert B.icl_tune(B.ICL_OP_CONV2D_U8, B.ICL_F32, r, W, H) == B.ICL_ERR_DTYPE
+        X = synth.u8_image(74, H, W)
+        taps = synth.u8_taps(74, r, synth.U8_SHIFT)
+        out = T.conv2d_u8(u8_dev(X), i16_dev(taps).view(5, 5), synth.U8_SHIFT)
+        assert np.array_equal(out.cpu().numpy(), oracle.conv2d_u8(X, taps, synth.U8_SHIFT))
+    finally:
+        B.icl_tune_clear()
