@@ -85,7 +85,8 @@ typedef enum icl_op {
     ICL_OP_SSE_LOSS = 8,
     ICL_OP_BANK_FWD_SSE = 9,
     ICL_OP_CONV2D_U8 = 10,
-    ICL_OP_COUNT = 11
+    ICL_OP_CORNERS = 11,
+    ICL_OP_COUNT = 12
 } icl_op;
 
 #define ICL_MAX_RADIUS 16          /* largest stencil radius accepted by the convolution calls */
@@ -108,7 +109,9 @@ const char* icl_version(void);
  * ICL_OP_CONV_SEP this is the float32 row-pass intermediate of the two-pass
  * variants; for ICL_OP_HARRIS the two float32 gradient images of the split
  * (Sobel kernel + Harris kernel) variant; for ICL_OP_BANK_BWD_FILTER,
- * ICL_OP_SSE_LOSS and ICL_OP_BANK_FWD_SSE the per-block partial sums.  Callers that always pass this
+ * ICL_OP_SSE_LOSS and ICL_OP_BANK_FWD_SSE the per-block partial sums; for ICL_OP_CORNERS the
+ * two-kernel variant's float32 response image and, for window radii above 3, the gradient
+ * images (`radius` is the window radius).  Callers that always pass this
  * much workspace may use every variant.  `n` and `f` are the batch and filter
  * counts of the filter-bank ops (ignored otherwise). */
 icl_status icl_workspace_size(icl_op op, int width, int height, int n, int f, int radius,
@@ -205,6 +208,30 @@ icl_status icl_harris(const float* src, size_t src_pitch, float* resp, size_t re
  *   radius in [1, ICL_MAX_NMS_RADIUS]. */
 icl_status icl_nms(const float* resp, size_t resp_pitch, uint8_t* mask, size_t mask_pitch,
                    int width, int height, int radius, float threshold, void* stream);
+
+/* ------------------------------------------------------------------ corner detection, fused
+ * Paper: Section 6, Harris corner detection (a Sobel kernel and a Harris kernel, Tables 4
+ * and 5); the discussion names fusing such stages as what the language could not express.
+ * This call is icl_harris followed by icl_nms in one pass: the response R (exactly the
+ * float32 expression of icl_harris) stays in registers, and
+ *   mask(x,y) = 1 iff R(x,y) > threshold and R(x,y) >= R at every pixel of the
+ *               (2 nms_radius + 1)^2 window (reads of R clamped), else 0.
+ * HBM traffic 5 B/px (image in, mask out) instead of 13 B/px for the two calls.
+ *   src          : device float32 image; window_taps, window_radius, k as in icl_harris
+ *   mask         : device uint8 image (any pitch)
+ *   nms_radius   : 1 .. ICL_MAX_NMS_RADIUS (the single-pass variants cover radius 1 and
+ *                  window radius <= 3; other radii run the two kernels)
+ *   resp         : optional device float32 image (NULL: the response is not written);
+ *                  with it the response is also written, in one pass
+ *   workspace    : icl_workspace_size(ICL_OP_CORNERS, ..., radius = window_radius) bytes,
+ *                  needed only when the two-kernel variant runs (NMS radius > 1 or window
+ *                  radius > 3): room for the response when resp is NULL, plus the gradient
+ *                  images for window radii above 3 (else ICL_ERR_WORKSPACE).
+ * No output may overlap the image or each other (ICL_ERR_ALIAS). */
+icl_status icl_corners(const float* src, size_t src_pitch, uint8_t* mask, size_t mask_pitch,
+                       int width, int height, const float* window_taps, int window_radius, float k,
+                       int nms_radius, float threshold, float* resp, size_t resp_pitch,
+                       void* workspace, size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------ batched separable convolution
  * Many images of uneven size, each with its own radius and taps, in ONE

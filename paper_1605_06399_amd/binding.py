@@ -37,7 +37,7 @@ ICL_BORDER_CLAMP, ICL_BORDER_CONSTANT = 0, 1
 # icl_op
 (ICL_OP_CONV_SEP, ICL_OP_CONV2D, ICL_OP_HARRIS, ICL_OP_NMS, ICL_OP_CONV_SEP_BATCHED, ICL_OP_BANK_FWD,
  ICL_OP_BANK_BWD_INPUT, ICL_OP_BANK_BWD_FILTER, ICL_OP_SSE_LOSS, ICL_OP_BANK_FWD_SSE, ICL_OP_CONV2D_U8,
- ICL_OP_COUNT) = range(12)
+ ICL_OP_CORNERS, ICL_OP_COUNT) = range(13)
 
 ICL_MAX_RADIUS = 16
 ICL_MAX_WINDOW_RADIUS = 7
@@ -77,6 +77,7 @@ _SIGS = {
     "icl_conv2d_u8": ([_vp, _sz, _vp, _sz, _i, _i, _vp, _i, _i, _i, _i, _vp], _i),
     "icl_harris": ([_vp, _sz, _vp, _sz, _i, _i, _vp, _i, _f, _vp, _sz, _vp], _i),
     "icl_nms": ([_vp, _sz, _vp, _sz, _i, _i, _i, _f, _vp], _i),
+    "icl_corners": ([_vp, _sz, _vp, _sz, _i, _i, _vp, _i, _f, _i, _f, _vp, _sz, _vp, _sz, _vp], _i),
     "icl_batch_plan_create": ([ctypes.POINTER(icl_image_desc), _i, _i, ctypes.POINTER(_vp)], _i),
     "icl_conv_sep_batched": ([_vp, _vp], _i),
     "icl_batch_plan_info": ([_vp, ctypes.POINTER(_ll), ctypes.POINTER(_ll)], _i),
@@ -188,6 +189,13 @@ def icl_harris(src, src_pitch, resp, resp_pitch, width, height, window_taps, win
 
 def icl_nms(resp, resp_pitch, mask, mask_pitch, width, height, radius, threshold, stream=0) -> int:
     return lib().icl_nms(resp, resp_pitch, mask, mask_pitch, width, height, radius, threshold, stream or None)
+
+
+def icl_corners(src, src_pitch, mask, mask_pitch, width, height, window_taps, window_radius, k, nms_radius,
+                threshold, resp=0, resp_pitch=0, workspace=0, workspace_bytes=0, stream=0) -> int:
+    return lib().icl_corners(src, src_pitch, mask, mask_pitch, width, height, window_taps, window_radius, k,
+                             nms_radius, threshold, resp or None, resp_pitch, workspace or None, workspace_bytes,
+                             stream or None)
 
 
 def icl_batch_plan_create(descs, dtype):

@@ -27,7 +27,7 @@ static std::mutex g_init_mu;
 
 static const char* kOpNames[ICL_OP_COUNT] = {"conv_sep", "conv2d", "harris", "nms", "conv_sep_batched",
                                              "bank_fwd", "bank_bwd_input", "bank_bwd_filter", "sse_loss",
-                                             "bank_fwd_sse", "conv2d_u8"};
+                                             "bank_fwd_sse", "conv2d_u8", "corners"};
 
 // ICL_FORCE_VARIANT="conv_sep=1,conv2d=3": the analogue of the paper's directives
 // that force optimisations on or off.
@@ -203,6 +203,10 @@ icl_status icl_workspace_size(icl_op op, int width, int height, int n, int f, in
             break;
         case ICL_OP_SSE_LOSS: *bytes = sse_workspace((long long)width * height); break;
         case ICL_OP_BANK_FWD_SSE: *bytes = bank_fwd_sse_workspace(); break;
+        case ICL_OP_CORNERS:
+            if (radius < 0 || radius > ICL_MAX_WINDOW_RADIUS) return ICL_ERR_RADIUS;
+            *bytes = corners_workspace(width, height, radius);
+            break;
         case ICL_OP_CONV2D: case ICL_OP_NMS: case ICL_OP_CONV_SEP_BATCHED: case ICL_OP_BANK_FWD:
         case ICL_OP_BANK_BWD_INPUT: case ICL_OP_CONV2D_U8: break;
         default: return ICL_ERR_INVALID_VALUE;
@@ -346,6 +350,43 @@ icl_status icl_nms(const float* resp, size_t resp_pitch, uint8_t* mask, size_t m
 }
 
 // ------------------------------------------------------------------ filter bank
+icl_status icl_corners(const float* src, size_t src_pitch, uint8_t* mask, size_t mask_pitch, int width, int height,
+                       const float* window_taps, int window_radius, float k, int nms_radius, float threshold,
+                       float* resp, size_t resp_pitch, void* workspace, size_t workspace_bytes, void* stream) {
+    if (width < 0 || height < 0) return ICL_ERR_INVALID_VALUE;
+    if (window_radius < 0 || window_radius > ICL_MAX_WINDOW_RADIUS) return ICL_ERR_RADIUS;
+    if (nms_radius < 1 || nms_radius > ICL_MAX_NMS_RADIUS) return ICL_ERR_RADIUS;
+    if (width == 0 || height == 0) return ICL_OK;
+    icl_status s;
+    if ((s = check_image(src, src_pitch, width, 4)) != ICL_OK) return s;
+    if ((s = check_image(mask, mask_pitch, width, 1)) != ICL_OK) return s;
+    if (resp && (s = check_image(resp, resp_pitch, width, 4)) != ICL_OK) return s;
+    if (!window_taps) return ICL_ERR_INVALID_VALUE;
+    if (overlaps(src, src_pitch, 4, mask, mask_pitch, 1, width, height)) return ICL_ERR_ALIAS;
+    if (resp && (overlaps(src, src_pitch, 4, resp, resp_pitch, 4, width, height) ||
+                 overlaps(mask, mask_pitch, 1, resp, resp_pitch, 4, width, height)))
+        return ICL_ERR_ALIAS;
+    if (workspace && workspace_bytes) {
+        const size_t sb = (size_t)(height - 1) * src_pitch + (size_t)width * 4;
+        const size_t mb = (size_t)(height - 1) * mask_pitch + (size_t)width;
+        const size_t rb = (size_t)(height - 1) * resp_pitch + (size_t)width * 4;
+        if (range_overlaps(workspace, workspace_bytes, src, sb) || range_overlaps(workspace, workspace_bytes, mask, mb) ||
+            (resp && range_overlaps(workspace, workspace_bytes, resp, rb)))
+            return ICL_ERR_ALIAS;
+    }
+    if ((s = device_ready()) != ICL_OK) return s;
+    CornersArgs a{src, src_pitch, mask, mask_pitch, width, height, window_taps, window_radius, k, nms_radius,
+                  threshold, resp, resp ? resp_pitch : 0, workspace, workspace_bytes, (hipStream_t)stream};
+    int count;
+    const Variant<CornersArgs>* tab = corners_variants(&count);
+    const int deflt = corners_default(a);
+    const int v = select_variant(ICL_OP_CORNERS, ICL_F32, window_radius, width, height, deflt);
+    // the two-kernel variant needs somewhere to put the response
+    const bool forced_two = variant_forced(ICL_OP_CORNERS) && v == 0;
+    if ((forced_two || !tab[deflt].supports(a)) && !tab[0].supports(a)) return ICL_ERR_WORKSPACE;
+    return dispatch(ICL_OP_CORNERS, tab, count, a, v, deflt);
+}
+
 static icl_status check_bank(int n, int f, int h, int wd, int radius) {
     if (n < 0 || f < 1 || h < 0 || wd < 0) return ICL_ERR_INVALID_VALUE;
     if (f > 64) return ICL_ERR_UNSUPPORTED;
@@ -472,6 +513,7 @@ int icl_variant_count(icl_op op) {
         case ICL_OP_CONV_SEP: sep_variants(&c); break;
         case ICL_OP_CONV2D: conv2d_variants(&c); break;
         case ICL_OP_CONV2D_U8: conv2d_u8_variants(&c); break;
+        case ICL_OP_CORNERS: corners_variants(&c); break;
         case ICL_OP_HARRIS: harris_variants(&c); break;
         case ICL_OP_NMS: nms_variants(&c); break;
         case ICL_OP_BANK_FWD: bank_fwd_variants(&c); break;
@@ -492,6 +534,7 @@ const char* icl_variant_name(icl_op op, int index) {
         case ICL_OP_CONV_SEP: return sep_variants(&c)[index].name;
         case ICL_OP_CONV2D: return conv2d_variants(&c)[index].name;
         case ICL_OP_CONV2D_U8: return conv2d_u8_variants(&c)[index].name;
+        case ICL_OP_CORNERS: return corners_variants(&c)[index].name;
         case ICL_OP_HARRIS: return harris_variants(&c)[index].name;
         case ICL_OP_NMS: return nms_variants(&c)[index].name;
         case ICL_OP_BANK_FWD: return bank_fwd_variants(&c)[index].name;
@@ -549,6 +592,13 @@ icl_status icl_selected_variant(icl_op op, icl_dtype dtype, int radius, int widt
             U8Args a{};
             a.r = radius;
             deflt = conv2d_u8_default(a);
+            break;
+        }
+        case ICL_OP_CORNERS: {
+            CornersArgs a{};
+            a.rg = radius;
+            a.nr = 1;
+            deflt = corners_default(a);
             break;
         }
         default: break;

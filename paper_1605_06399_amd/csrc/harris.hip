@@ -22,16 +22,12 @@
 //                   row, neighbour columns by DPP lane shifts, rings of prefetched image
 //                   rows and of pending output rows); the 4-column left band and the
 //                   right remainder run through the tile kernel.  16-byte aligned rows.
+#include "harris_strip.hpp"
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
 
 namespace icl {
 namespace {
-
-__device__ __forceinline__ float harris_response(float sxx, float syy, float sxy, float k) {
-    const float tr = sxx + syy;
-    return sxx * syy - sxy * sxy - k * tr * tr;
-}
 
 // ------------------------------------------------------------------ plain split
 __global__ __launch_bounds__(256) void sobel_plain(const float* __restrict__ src, size_t sp, float* __restrict__ ix,
@@ -234,42 +230,6 @@ hipError_t launch_fused_R(const HarrisArgs& a) {
 // rows; the oldest completes and is written each step.  No LDS tile, no barrier.
 constexpr int HS_COLS = 248;   // output columns per strip (62 lanes x 4)
 constexpr int HS_XL = 4;       // left border band (the strips start here), done by the tile kernel
-
-template <int RG>
-__device__ __forceinline__ v4f hwin(v4f p, const float (&gw)[2 * RG + 1]) {
-    float e[4 + 2 * RG];
-#pragma unroll
-    for (int i = 0; i < RG; ++i) e[i] = lane_from_left(p[4 - RG + i]);
-    e[RG] = p.x; e[RG + 1] = p.y; e[RG + 2] = p.z; e[RG + 3] = p.w;
-#pragma unroll
-    for (int i = 0; i < RG; ++i) e[RG + 4 + i] = lane_from_right(p[i]);
-    float o[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        float acc = 0.f;
-#pragma unroll
-        for (int t = 0; t <= 2 * RG; ++t) acc = fmaf(gw[t], e[q + t], acc);
-        o[q] = acc;
-    }
-    return mk4(o[0], o[1], o[2], o[3]);
-}
-
-// Products of one window row: Sobel from image rows ra (above), rb, rc (below), neighbour
-// columns by DPP lane shifts, then the horizontal window of each product.
-template <int RG>
-__device__ __forceinline__ void window_row(const v4f ra, const v4f rb, const v4f rc, const float (&gw)[2 * RG + 1],
-                                           v4f& qa, v4f& qb, v4f& qc) {
-    const v4f vs = ra + 2.f * rb + rc;   // vertical smoothing (for Ix)
-    const v4f vd = rc - ra;              // vertical difference (for Iy)
-    const float vsl = lane_from_left(vs.w), vsr = lane_from_right(vs.x);
-    const float vdl = lane_from_left(vd.w), vdr = lane_from_right(vd.x);
-    const v4f ix = mk4(vs.y - vsl, vs.z - vs.x, vs.w - vs.y, vsr - vs.z);
-    const v4f iy = mk4(vdl + 2.f * vd.x + vd.y, vd.x + 2.f * vd.y + vd.z, vd.y + 2.f * vd.z + vd.w,
-                       vd.z + 2.f * vd.w + vdr);
-    qa = hwin<RG>(ix * ix, gw);
-    qb = hwin<RG>(iy * iy, gw);
-    qc = hwin<RG>(ix * iy, gw);
-}
 
 // One wave per work-group (the register allocation of a 64-lane launch bound keeps the
 // working set at four waves per SIMD without spills).

@@ -52,6 +52,16 @@ struct NmsArgs {
     hipStream_t st;
 };
 
+struct CornersArgs {
+    const float* src; size_t sp; uint8_t* M; size_t mp;
+    int W, H;
+    const float* g; int rg; float k;   // Harris window taps, radius, k
+    int nr; float tau;                 // NMS radius and threshold
+    float* resp; size_t rp;            // optional response output (null: not written)
+    void* ws; size_t wsb;
+    hipStream_t st;
+};
+
 struct BankArgs {
     const float* a;   // x (fwd, bwd_filter) or gy (bwd_input)
     const float* b;   // w (fwd, bwd_input) or x (bwd_filter: a = gy, b = x)
@@ -82,6 +92,7 @@ const Variant<Conv2dArgs>* conv2d_variants(int* count);
 const Variant<U8Args>* conv2d_u8_variants(int* count);
 const Variant<HarrisArgs>* harris_variants(int* count);
 const Variant<NmsArgs>* nms_variants(int* count);
+const Variant<CornersArgs>* corners_variants(int* count);
 const Variant<BankArgs>* bank_fwd_variants(int* count);
 const Variant<BankArgs>* bank_bwd_input_variants(int* count);
 const Variant<BankArgs>* bank_bwd_filter_variants(int* count);
@@ -93,6 +104,7 @@ int conv2d_default(const Conv2dArgs&);
 int conv2d_u8_default(const U8Args&);
 int harris_default(const HarrisArgs&);
 int nms_default(const NmsArgs&);
+int corners_default(const CornersArgs&);
 int bank_fwd_default(const BankArgs&);
 int bank_bwd_input_default(const BankArgs&);
 int bank_bwd_filter_default(const BankArgs&);
@@ -101,6 +113,7 @@ int batched_default();
 
 size_t sep_workspace(int W, int H);
 size_t harris_workspace(int W, int H);
+size_t corners_workspace(int W, int H, int rg);
 size_t bank_bwd_filter_workspace(int n, int f, int h, int w, int r);
 size_t sse_workspace(long long count);
 size_t bank_fwd_sse_workspace();

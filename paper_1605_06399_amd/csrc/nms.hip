@@ -18,6 +18,7 @@
 //   stream_t{TH}: one wave per 248-column strip and TH rows (r = 1): every response row
 //                loaded once, the 3 x 3 neighbourhood from registers and DPP lane shifts;
 //                the border bands run through row4.  16-byte aligned response rows.
+#include "harris_strip.hpp"
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
 
@@ -118,25 +119,6 @@ bool supports_row4(const NmsArgs& a) { return a.r == 1; }
 // 4 columns and the right remainder (under 252 columns) run through the row kernel.
 constexpr int NS_COLS = 248;
 constexpr int NS_XL = 4;
-
-__device__ __forceinline__ uint32_t nms_bits(v4f a, v4f b, v4f c, float tau) {
-    const float al = lane_from_left(a.w), ar = lane_from_right(a.x);
-    const float bl = lane_from_left(b.w), br = lane_from_right(b.x);
-    const float cl = lane_from_left(c.w), cr = lane_from_right(c.x);
-    const float ea[6] = {al, a.x, a.y, a.z, a.w, ar};
-    const float eb[6] = {bl, b.x, b.y, b.z, b.w, br};
-    const float ec[6] = {cl, c.x, c.y, c.z, c.w, cr};
-    uint32_t bits = 0;
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const float v = eb[p + 1];
-        // bitwise & (no short circuit): nine compares, no branches
-        const bool keep = (v > tau) & (v >= ea[p]) & (v >= ea[p + 1]) & (v >= ea[p + 2]) & (v >= eb[p]) &
-                          (v >= eb[p + 2]) & (v >= ec[p]) & (v >= ec[p + 1]) & (v >= ec[p + 2]);
-        bits |= (keep ? 1u : 0u) << (8 * p);
-    }
-    return bits;
-}
 
 // Four independent strip waves per work-group (wave w of group b is strip wave 4b + w).
 template <int TH>

@@ -400,6 +400,46 @@ icl_status tune_conv_u8(int r, int W, int H, hipStream_t st) {
     return search(ICL_OP_CONV2D_U8, tab, count, ICL_U8, r, W, H, sets, make, agree, st);
 }
 
+// Fused corners: the single-pass variants share their arithmetic, so each must return the
+// default single-pass variant's mask byte for byte (the two-kernel variant is not a candidate).
+icl_status tune_corners(int rg, int W, int H, hipStream_t st) {
+    const size_t pitch = ((size_t)W * 4 + 255) & ~(size_t)255;
+    const size_t mpitch = ((size_t)W + 255) & ~(size_t)255;
+    const int sets = rotation_sets(pitch * H + mpitch * H);
+    Buffers b;
+    std::vector<void*> src(sets), dst(sets);
+    for (int s = 0; s < sets; ++s) {
+        src[s] = b.alloc(pitch * H);
+        dst[s] = b.alloc(mpitch * H);
+        if (!src[s] || !dst[s]) return ICL_ERR_HIP;
+        if (fill(ICL_F32, src[s], pitch, W, H, 0x55ull + s, st) != hipSuccess) return ICL_ERR_HIP;
+    }
+    void* ref = b.alloc(mpitch * H);
+    const int n = 2 * rg + 1;
+    std::vector<float> g(n);
+    double sum = 0;
+    for (int i = 0; i < n; ++i) sum += (g[i] = 1.0f + (float)(rg - std::abs(i - rg)));
+    for (auto& t : g) t = (float)(t / sum);
+    float* d_g = static_cast<float*>(b.alloc(n * sizeof(float)));
+    unsigned* d_stat = static_cast<unsigned*>(b.alloc(16));
+    if (!ref || !d_g || !d_stat) return ICL_ERR_HIP;
+    if (hipMemcpyAsync(d_g, g.data(), n * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess) return ICL_ERR_HIP;
+    int count;
+    const Variant<CornersArgs>* tab = corners_variants(&count);
+    auto make = [&](int s, int) {
+        return CornersArgs{static_cast<const float*>(src[s]), pitch, static_cast<uint8_t*>(dst[s]), mpitch, W, H,
+                           d_g, rg, 0.04f, 1, 1e-6f, nullptr, 0, nullptr, 0, st};
+    };
+    CornersArgs p0 = make(0, 0);
+    p0.M = static_cast<uint8_t*>(ref);
+    const int deflt = corners_default(p0);
+    if (deflt == 0 || !tab[deflt].supports(p0) || tab[deflt].launch(p0) != hipSuccess) return ICL_ERR_UNSUPPORTED;
+    auto agree = [&]() {
+        return masks_agree(static_cast<uint8_t*>(dst[0]), static_cast<uint8_t*>(ref), mpitch, W, H, d_stat, st);
+    };
+    return search(ICL_OP_CORNERS, tab, count, ICL_F32, rg, W, H, sets, make, agree, st);
+}
+
 icl_status tune_nms(int r, int W, int H, hipStream_t st) {
     const size_t pitch = ((size_t)W * 4 + 255) & ~(size_t)255;
     const size_t mpitch = ((size_t)W + 255) & ~(size_t)255;
@@ -504,6 +544,12 @@ icl_status icl_tune(icl_op op, icl_dtype dtype, int radius, int width, int heigh
             if (radius < 0 || radius > ICL_MAX_WINDOW_RADIUS) return ICL_ERR_RADIUS;
             if (dtype != ICL_F32) return ICL_ERR_DTYPE;
             s = tune_harris(radius, width, height, st);
+            break;
+        case ICL_OP_CORNERS:
+            if (radius < 0 || radius > ICL_MAX_WINDOW_RADIUS) return ICL_ERR_RADIUS;
+            if (dtype != ICL_F32) return ICL_ERR_DTYPE;
+            if (radius > 3) return ICL_OK;   // only the two-kernel variant: nothing to choose
+            s = tune_corners(radius, width, height, st);
             break;
         case ICL_OP_CONV2D_U8:
             if (radius < 0 || radius > ICL_MAX_U8_RADIUS) return ICL_ERR_RADIUS;

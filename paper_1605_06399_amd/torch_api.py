@@ -139,6 +139,29 @@ def nms(resp: torch.Tensor, threshold: float, radius: int = 1, out: torch.Tensor
     return out
 
 
+def corners(x: torch.Tensor, window_taps: torch.Tensor, k: float = 0.04, threshold: float = 1e-3,
+            nms_radius: int = 1, out: torch.Tensor | None = None, resp: torch.Tensor | None = None,
+            workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Harris response and non-maximum suppression in one call: the uint8 corner mask.  Pass a
+    float32 `resp` image to also receive the response."""
+    if x.dtype != torch.float32:
+        raise ValueError("x must be float32")
+    r = (window_taps.numel() - 1) // 2
+    if out is None:
+        out = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+    sp, spitch, W, H = _image(x, "x")
+    mp, mpitch, _, _ = _image(out, "out")
+    rp, rpitch = (0, 0)
+    if resp is not None:
+        if resp.dtype != torch.float32:
+            raise ValueError("resp must be float32")
+        rp, rpitch, _, _ = _image(resp, "resp")
+    ws, wsb = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None else (0, 0)
+    B.check(B.icl_corners(sp, spitch, mp, mpitch, W, H, _taps(window_taps, 2 * r + 1, "window_taps"), r, float(k),
+                          int(nms_radius), float(threshold), rp, rpitch, ws, wsb, _stream()), "icl_corners")
+    return out
+
+
 def tune(op: int, dtype: torch.dtype, radius: int, width: int, height: int) -> None:
     B.check(B.icl_tune(op, _DT[dtype], radius, width, height, _stream()), "icl_tune")
 

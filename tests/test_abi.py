@@ -163,6 +163,24 @@ def test_border_and_u8_validation(no_gpu):
     assert u8(SRC, 64, DST, 64, 0, 8, TAPS, 2, 12) == B.ICL_OK
 
 
+def test_corners_validation(no_gpu):
+    c = B.icl_corners
+    MASK, RESP = 0x50000000, 0x60000000
+    assert c(SRC, 256, MASK, 64, 64, 8, TAPS, 8, 0.04, 1, 1e-3) == B.ICL_ERR_RADIUS
+    assert c(SRC, 256, MASK, 64, 64, 8, TAPS, 2, 0.04, 0, 1e-3) == B.ICL_ERR_RADIUS
+    assert c(SRC, 256, MASK, 64, 64, 8, TAPS, 2, 0.04, 8, 1e-3) == B.ICL_ERR_RADIUS
+    assert c(SRC, 255, MASK, 64, 64, 8, TAPS, 2, 0.04, 1, 1e-3) == B.ICL_ERR_PITCH
+    assert c(SRC, 256, MASK, 63, 64, 8, TAPS, 2, 0.04, 1, 1e-3) == B.ICL_ERR_PITCH
+    assert c(SRC, 256, MASK, 64, 64, 8, TAPS, 2, 0.04, 1, 1e-3, RESP, 100) == B.ICL_ERR_PITCH
+    assert c(SRC, 256, MASK, 64, 64, 8, 0, 2, 0.04, 1, 1e-3) == B.ICL_ERR_INVALID_VALUE
+    assert c(SRC, 256, SRC + 100, 64, 64, 8, TAPS, 2, 0.04, 1, 1e-3) == B.ICL_ERR_ALIAS
+    assert c(SRC, 256, MASK, 64, 64, 8, TAPS, 2, 0.04, 1, 1e-3, SRC + 256, 256) == B.ICL_ERR_ALIAS
+    assert c(SRC, 256, MASK, 64, 64, 8, TAPS, 2, 0.04, 1, 1e-3, MASK + 8, 256) == B.ICL_ERR_ALIAS
+    assert c(SRC, 256, MASK, 64, 64, 8, TAPS, 2, 0.04, 1, 1e-3, 0, 0, MASK + 4, 64) == B.ICL_ERR_ALIAS
+    assert c(SRC, 256, MASK, 64, -1, 8, TAPS, 2, 0.04, 1, 1e-3) == B.ICL_ERR_INVALID_VALUE
+    assert c(SRC, 256, MASK, 64, 0, 8, TAPS, 2, 0.04, 1, 1e-3) == B.ICL_OK
+
+
 def test_bank_and_loss_validation(no_gpu):
     assert B.icl_bank_fwd(SRC, TAPS, DST, 2, 16, 8, 8, 5) == B.ICL_ERR_RADIUS
     assert B.icl_bank_fwd(SRC, TAPS, DST, 2, 0, 8, 8, 4) == B.ICL_ERR_INVALID_VALUE
