@@ -487,7 +487,41 @@ def extra_corner(torch, B, T, synth, steps):
         finally:
             B.icl_force_variant(B.ICL_OP_HARRIS, -1)
     res["corner_8192"]["harris_variants_ms"] = per_variant
-    del xs, Rs, Ms, ws_h
+    # the same pipeline fused into one pass (icl_corners): 5 algorithmic B/px, response in registers
+    B.check(B.icl_tune(B.ICL_OP_CORNERS, B.ICL_F32, 2, W, H, st))
+
+    def fused(s):
+        T.corners(xs[s % 2], g, 0.04, 1e-3, out=Ms[s % 2])
+
+    fused_variants = {}
+    for v in range(B.icl_variant_count(B.ICL_OP_CORNERS)):
+        B.check(B.icl_force_variant(B.ICL_OP_CORNERS, v))
+        try:
+            if v == 0:   # the two-kernel variant needs the response buffer
+                fn = lambda s: T.corners(xs[s % 2], g, 0.04, 1e-3, out=Ms[s % 2], resp=Rs[s % 2])   # noqa: E731
+            else:
+                fn = fused
+            fused_variants[B.icl_variant_name(B.ICL_OP_CORNERS, v)] = round(_time_graph(torch, fn, steps) * 1e6, 1)
+        finally:
+            B.icl_force_variant(B.ICL_OP_CORNERS, -1)
+    dtf = _time_graph(torch, fused, 2 * steps, reps=10)   # the tuned choice, after every variant has run
+    gpx_f = H * W / dtf / 1e9
+    dt2 = _time_graph(torch, corner, 2 * steps, reps=10)
+    res["corners_fused_8192"] = {
+        "timing": "HIP graph replay of back-to-back calls", "us": round(dtf * 1e6, 2), "gpx_s": round(gpx_f, 1),
+        "bytes_per_px": 5, "hbm_frac": round(gpx_f * 5 / HBM_PEAK_GBS, 3),
+        "two_calls_us": round(dt2 * 1e6, 2), "speedup_vs_two_calls": round(dt2 / dtf, 2),
+        "variant": B.icl_variant_name(B.ICL_OP_CORNERS, B.icl_selected_variant(B.ICL_OP_CORNERS, B.ICL_F32, 2, W,
+                                                                               H)[1]),
+        "variants_us": fused_variants,
+        "same_mask_as_two_calls_inside_strips": None}
+    Mf = T.corners(xs[0], g, 0.04, 1e-3)
+    T.harris(xs[0], g, 0.04, out=Rs[0])
+    Mt = T.nms(Rs[0], 1e-3)
+    xr = 4 + ((W - 8) // 248) * 248
+    res["corners_fused_8192"]["same_mask_as_two_calls_inside_strips"] = bool(
+        torch.equal(Mf[:, 8:xr - 8], Mt[:, 8:xr - 8]))
+    del xs, Rs, Ms, ws_h, Mf, Mt
     torch.cuda.empty_cache()
     return res
 

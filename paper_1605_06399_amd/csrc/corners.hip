@@ -31,18 +31,58 @@ namespace {
 
 constexpr int CS_COLS = 240;   // mask columns per strip (60 lanes x 4)
 
-template <int RG, int TH>
+// Interior (strip, row block) pairs: strips s_lo .. s_hi and row blocks b_lo .. b_hi read
+// nothing outside the image (columns xm-8 .. xm+247, rows y0-r-2 .. y0+TH+r+1); the rest
+// form the border set.  Each set runs as its own launch, so the interior kernel carries no
+// border code (and keeps four waves per SIMD at r = 2).
+struct Region {
+    int nstrips, nblocks;
+    int s_lo, s_hi, b_lo, b_hi;   // interior ranges; empty when s_lo > s_hi or b_lo > b_hi
+    __host__ __device__ int ni() const { return s_hi >= s_lo ? s_hi - s_lo + 1 : 0; }
+    __host__ __device__ int nj() const { return b_hi >= b_lo ? b_hi - b_lo + 1 : 0; }
+    __host__ __device__ long long interior() const { return (long long)ni() * nj(); }
+    __host__ __device__ long long border() const { return (long long)nstrips * nblocks - interior(); }
+    // border work item idx -> (strip, row block): first the row blocks outside b_lo..b_hi
+    // across all strips, then the strips outside s_lo..s_hi across the interior row blocks
+    __device__ void border_item(int idx, int& strip, int& rb) const {
+        if (interior() == 0) {
+            strip = idx % nstrips;
+            rb = idx / nstrips;
+            return;
+        }
+        const int top = (nblocks - nj()) * nstrips;
+        if (idx < top) {
+            const int r = idx / nstrips;
+            strip = idx % nstrips;
+            rb = r < b_lo ? r : r + nj();
+        } else {
+            const int i2 = idx - top, edge_strips = nstrips - ni();
+            const int q = i2 % edge_strips;
+            rb = b_lo + i2 / edge_strips;
+            strip = q < s_lo ? q : q + ni();
+        }
+    }
+};
+
+// PART 1: the interior set (no clamping anywhere); PART 2: the border set.
+template <int RG, int TH, int PART>
 __global__ __launch_bounds__(64) void corners_stream(const float* __restrict__ src, size_t sp, uint8_t* __restrict__ M,
                                                      size_t mp, float* __restrict__ resp, size_t rp, int W, int H,
-                                                     const float* __restrict__ g, float k, float tau, int nstrips,
+                                                     const float* __restrict__ g, float k, float tau, Region rg_,
                                                      int vec_img, int vec_mask, int vec_resp) {
     constexpr int NW = 2 * RG + 1;   // window taps = ring of pending response rows
     constexpr int D = NW;
     constexpr int NR = TH + 2;       // response rows y0-1 .. y0+TH
     constexpr int K = NR + 2 * RG;   // window rows walked
     const int lane = threadIdx.x;
-    const int strip = (int)(blockIdx.x % (unsigned)nstrips);
-    const int y0 = (int)(blockIdx.x / (unsigned)nstrips) * TH;
+    int strip, rb;
+    if constexpr (PART == 1) {
+        strip = rg_.s_lo + (int)(blockIdx.x % (unsigned)rg_.ni());
+        rb = rg_.b_lo + (int)(blockIdx.x / (unsigned)rg_.ni());
+    } else {
+        rg_.border_item((int)blockIdx.x, strip, rb);
+    }
+    const int y0 = rb * TH;
     const int xm = strip * CS_COLS;
     const int c = xm - 8 + 4 * lane;   // first image column of this lane
     float gw[NW];
@@ -78,10 +118,11 @@ __global__ __launch_bounds__(64) void corners_stream(const float* __restrict__ s
 
     const bool inside_x = vec_img && c - 4 * lane >= 0 && xm - 8 + 256 <= W;
     const bool inside_y = y0 - RG - 2 >= 0 && y0 + TH + RG + 1 <= H - 1;
-    if (inside_x && inside_y) {
-        // interior: every read in bounds, nothing clamped; the walk is unrolled completely,
-        // so ring slots and row indices are constants.  Window row kk is gradient row
-        // y0 - 1 - r + kk, whose Sobel reads image rows y0 - 2 - r + kk + {0, 1, 2}.
+    if constexpr (PART == 1) {
+        if (!(inside_x && inside_y)) return;   // never taken: the host's interior set is exact
+        // interior: every read in bounds, nothing clamped.  Window row kk is gradient row
+        // y0 - 1 - r + kk, whose Sobel reads image rows y0 - 2 - r + kk + {0, 1, 2}.  The walk
+        // is unrolled completely: ring slots and row indices are constants, no branch.
         constexpr int MI = D >= 5 ? D : (D == 3 ? 6 : 5);   // image-row ring
         const char* col = reinterpret_cast<const char*>(src) + (size_t)c * 4;
         auto image_row = [&](int y) { return *reinterpret_cast<const v4f*>(col + (size_t)y * sp); };
@@ -102,7 +143,7 @@ __global__ __launch_bounds__(64) void corners_stream(const float* __restrict__ s
             for (int j = 0; j < NW; ++j) {
                 const int m = kk - j;
                 if (m < 0 || m >= NR) continue;
-                const int slot = ((kk - j) % D + D) % D;
+                const int slot = m % D;
                 acc[slot][0] += gw[j] * qa;
                 acc[slot][1] += gw[j] * qb;
                 acc[slot][2] += gw[j] * qc;
@@ -119,7 +160,8 @@ __global__ __launch_bounds__(64) void corners_stream(const float* __restrict__ s
             }
         });
         return;
-    }
+    } else {
+    if (inside_x && inside_y) return;   // never taken: interior items belong to the other launch
 
     // border strips and row blocks: clamped loads; products and responses of columns outside
     // the image are replaced by those of the nearest column inside
@@ -209,6 +251,7 @@ __global__ __launch_bounds__(64) void corners_stream(const float* __restrict__ s
             }
         });
     }
+    }   // PART 2
 }
 
 bool supports_stream(const CornersArgs& a) {
@@ -217,14 +260,26 @@ bool supports_stream(const CornersArgs& a) {
 
 template <int RG, int TH>
 hipError_t launch_stream_R(const CornersArgs& a) {
-    const int nstrips = (a.W + CS_COLS - 1) / CS_COLS;
-    const long long blocks = (long long)nstrips * ((a.H + TH - 1) / TH);
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const int vec_img = ((uintptr_t)a.src % 16 == 0) && (a.sp % 16 == 0);
     const int vec_mask = ((uintptr_t)a.M % 4 == 0) && (a.mp % 4 == 0);
     const int vec_resp = a.resp && ((uintptr_t)a.resp % 16 == 0) && (a.rp % 16 == 0);
-    hipLaunchKernelGGL((corners_stream<RG, TH>), dim3((unsigned)blocks), dim3(64), 0, a.st, a.src, a.sp, a.M, a.mp,
-                       a.resp, a.rp, a.W, a.H, a.g, a.k, a.tau, nstrips, vec_img, vec_mask, vec_resp);
+    Region r{};
+    r.nstrips = (a.W + CS_COLS - 1) / CS_COLS;
+    r.nblocks = (a.H + TH - 1) / TH;
+    if ((long long)r.nstrips * r.nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    // interior strips s: s >= 1 and s * 240 + 248 <= W (columns xm-8 .. xm+247 inside)
+    r.s_lo = 1;
+    r.s_hi = (vec_img && a.W >= 248) ? (a.W - 248) / CS_COLS : 0;
+    // interior row blocks b: b * TH >= r + 2 and b * TH + TH + r + 1 <= H - 1
+    r.b_lo = (RG + 2 + TH - 1) / TH;
+    const int top = a.H - 2 - RG - TH;
+    r.b_hi = top >= 0 ? top / TH : -1;
+    if (r.interior() > 0)
+        hipLaunchKernelGGL((corners_stream<RG, TH, 1>), dim3((unsigned)r.interior()), dim3(64), 0, a.st, a.src, a.sp,
+                           a.M, a.mp, a.resp, a.rp, a.W, a.H, a.g, a.k, a.tau, r, vec_img, vec_mask, vec_resp);
+    if (r.border() > 0)
+        hipLaunchKernelGGL((corners_stream<RG, TH, 2>), dim3((unsigned)r.border()), dim3(64), 0, a.st, a.src, a.sp,
+                           a.M, a.mp, a.resp, a.rp, a.W, a.H, a.g, a.k, a.tau, r, vec_img, vec_mask, vec_resp);
     return hipGetLastError();
 }
 
@@ -272,9 +327,10 @@ hipError_t launch_two_kernel(const CornersArgs& a) {
 
 const Variant<CornersArgs> kCorners[] = {
     {"two_kernel", supports_two_kernel, launch_two_kernel},
-    {"stream_t32", supports_stream, launch_stream<32>},
     {"stream_t16", supports_stream, launch_stream<16>},
-    {"stream_t64", supports_stream, launch_stream<64>},
+    {"stream_t24", supports_stream, launch_stream<24>},
+    {"stream_t32", supports_stream, launch_stream<32>},
+    {"stream_t12", supports_stream, launch_stream<12>},
 };
 
 }  // namespace

@@ -27,7 +27,7 @@ TAU = np.float32(1e-3)
 # degenerate images, narrower than a strip, one and two strips with ragged ends, ragged row
 # blocks, aligned widths that reach the interior strips
 SHAPES = [(1, 1), (2, 3), (5, 4), (1, 90), (90, 1), (64, 64), (17, 130), (389, 517), (133, 1100),
-          (5, 700), (70, 256), (37, 752), (100, 1024), (41, 483)]
+          (5, 700), (70, 256), (37, 752), (100, 1024), (41, 483), (300, 1024)]
 
 
 def g_taps(rg):
