@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP32_FMA_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, packed FP32 disabled
 FP32_PACKED_PEAK_TFLOPS = 157.3
-EXTRAS = ("corner", "batch", "bank", "paper")
+EXTRAS = ("corner", "batch", "bank", "paper", "tuner")
 INT_DOT2_PEAK_TMACS = 78.6     # v_dot2_i32_i16: 2 int16 MACs per lane per issue, 256 CU x 64 lanes x 2.4 GHz
 METRIC = "Gpixel/s & % HBM peak, autotuned vs plain kernel; fwd+bwd Gpixel/s"
 
@@ -46,7 +46,7 @@ def parse():
     p.add_argument("--no-extras", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--only", default="", help="comma list of sweep call labels (sep1 ... 2d7) and extra "
-                   "workloads (corner, batch, bank, paper) to run; a profiling aid")
+                   "workloads (corner, batch, bank, paper, tuner) to run; a profiling aid")
     p.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter_collection.csv files of a --calib-copy "
                         "run into profiles/traffic.json and exit")
@@ -361,6 +361,52 @@ def run_extras(torch, B, T, synth, steps, which=EXTRAS):
         res.update(extra_bank(torch, B, T, synth, steps))
     if "paper" in which:
         res.update(extra_paper(torch, B, T, synth, steps))
+    if "tuner" in which:
+        res.update(extra_tuner(torch, B, T, synth, steps))
+    return res
+
+
+def extra_tuner(torch, B, T, synth, steps):
+    """Exhaustive search against the paper's model-guided search (4 sampled candidates, neural
+    time model, 2 best-predicted confirmed) on the sweep's largest calls: candidates timed,
+    search seconds, and the chosen variant's time measured afterwards."""
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream().cuda_stream
+    img = synth.sweep_image()
+    H, W = img.shape
+    xs = [torch.from_numpy(img).to(dev) for _ in range(4)]
+    ys = [torch.empty_like(xs[0]) for _ in range(4)]
+    ws = torch.empty(B.icl_workspace_size(B.ICL_OP_CONV_SEP, W, H)[1] // 4 + 1, dtype=torch.float32, device=dev)
+    res = {}
+    for kind, r in (("sep", 7), ("2d", 5), ("2d", 7)):
+        op = B.ICL_OP_CONV_SEP if kind == "sep" else B.ICL_OP_CONV2D
+        if kind == "sep":
+            h, v = (torch.from_numpy(t).to(dev) for t in synth.sweep_taps_sep(r))
+            fn = lambda s: T.conv_sep(xs[s % 4], h, v, out=ys[s % 4], workspace=ws)   # noqa: E731
+        else:
+            w = torch.from_numpy(synth.sweep_taps_2d(r)).to(dev)
+            fn = lambda s: T.conv2d(xs[s % 4], w, out=ys[s % 4])   # noqa: E731
+        row = {"candidates": B.icl_variant_count(op) - 1}
+        for mode in ("exhaustive", "model"):
+            B.icl_tune_clear()
+            t0 = time.perf_counter()
+            if mode == "exhaustive":
+                B.check(B.icl_tune(op, B.ICL_F32, r, W, H, st))
+                timed = row["candidates"]
+            else:
+                stat, timed = B.icl_tune_model(op, B.ICL_F32, r, W, H, 4, 2, 2024, st)
+                B.check(stat)
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t0
+            vi = B.icl_selected_variant(op, B.ICL_F32, r, W, H)[1]
+            us = _time_graph(torch, fn, 2 * steps) * 1e6
+            row[mode] = {"variant": B.icl_variant_name(op, vi), "timed": timed, "search_s": round(secs, 3),
+                         "us": round(us, 2)}
+        row["model_vs_exhaustive_time"] = round(row["model"]["us"] / row["exhaustive"]["us"], 3)
+        res[f"tuner_{kind}{r}_4096"] = row
+    B.icl_tune_clear()
+    del xs, ys, ws
+    torch.cuda.empty_cache()
     return res
 
 

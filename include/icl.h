@@ -319,6 +319,25 @@ icl_status icl_bank_fwd_sse(const float* x, const float* w, const float* t, floa
  * icl_tune allocates, synchronises and must not be called during stream capture. */
 icl_status icl_tune(icl_op op, icl_dtype dtype, int radius, int width, int height, void* stream);
 /* Persist / reload the cache (JSON).  path NULL = $ICL_TUNE_CACHE or ~/.cache/icl/tune.json. */
+/* The paper's model-guided search (Section 4) over the same candidates: time `samples`
+ * randomly chosen candidates (seeded), fit a small neural-network model of log execution
+ * time over the candidates' parameters (icl_perf_model_fit_predict), predict the rest, time
+ * the `top_k` best-predicted, and cache the fastest measured.  With fewer than
+ * samples + top_k + 1 candidates every candidate is timed.  `timed` (host, may be NULL)
+ * receives the number of candidates timed.  samples >= 2, top_k >= 1, else
+ * ICL_ERR_INVALID_VALUE; otherwise as icl_tune. */
+icl_status icl_tune_model(icl_op op, icl_dtype dtype, int radius, int width, int height, int samples, int top_k,
+                          unsigned long long seed, int* timed, void* stream);
+
+/* The tuner's time model, exposed for inspection and testing (host memory, no device use):
+ * fit a network with one hidden layer of `hidden` tanh units (inputs and target
+ * standardised; full-batch Adam, `iters` steps, weights from a SplitMix64 stream of `seed`,
+ * so the fit is deterministic) to the n rows of X [n][d] and targets y [n], then write its
+ * predictions for the nq rows of Xq [nq][d] to yq.  ICL_ERR_INVALID_VALUE for null pointers,
+ * n < 2, d < 1, hidden outside 1..256 or iters outside 1..10^6. */
+icl_status icl_perf_model_fit_predict(const double* X, const double* y, int n, int d, const double* Xq, int nq,
+                                      double* yq, int hidden, int iters, unsigned long long seed);
+
 icl_status icl_tune_save(const char* path);
 icl_status icl_tune_load(const char* path);
 void icl_tune_clear(void);

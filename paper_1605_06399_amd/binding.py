@@ -91,6 +91,8 @@ _SIGS = {
     "icl_sse_loss": ([_vp, _vp, _vp, _ll, _vp, _vp, _sz, _vp], _i),
     "icl_bank_fwd_sse": ([_vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _sz, _vp], _i),
     "icl_tune": ([_i, _i, _i, _i, _i, _vp], _i),
+    "icl_tune_model": ([_i, _i, _i, _i, _i, _i, _i, ctypes.c_ulonglong, ctypes.POINTER(_i), _vp], _i),
+    "icl_perf_model_fit_predict": ([_vp, _vp, _i, _i, _vp, _i, _vp, _i, _i, ctypes.c_ulonglong], _i),
     "icl_tune_save": ([ctypes.c_char_p], _i),
     "icl_tune_load": ([ctypes.c_char_p], _i),
     "icl_tune_clear": ([], None),
@@ -258,6 +260,28 @@ def icl_bank_fwd_sse(x, w, t, y, gy, loss, n, f, h, wd, radius, workspace=0, wor
 
 def icl_tune(op, dtype, radius, width, height, stream=0) -> int:
     return lib().icl_tune(op, dtype, radius, width, height, stream or None)
+
+
+def icl_tune_model(op, dtype, radius, width, height, samples, top_k, seed=0, stream=0):
+    """(status, number of candidates timed)."""
+    timed = _i(0)
+    st = lib().icl_tune_model(op, dtype, radius, width, height, samples, top_k, seed, ctypes.byref(timed),
+                              stream or None)
+    return st, timed.value
+
+
+def icl_perf_model_fit_predict(X, y, Xq, hidden=8, iters=2000, seed=0):
+    """(status, predictions) for float64 numpy arrays X [n, d], y [n], Xq [nq, d]."""
+    import numpy as np
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    Xq = np.ascontiguousarray(Xq, dtype=np.float64)
+    n, d = X.shape if X.ndim == 2 else (0, 0)
+    yq = np.zeros(Xq.shape[0] if Xq.ndim == 2 else 0, dtype=np.float64)
+    st = lib().icl_perf_model_fit_predict(X.ctypes.data if X.size else None, y.ctypes.data if y.size else None, n,
+                                          d, Xq.ctypes.data if Xq.size else None, yq.size,
+                                          yq.ctypes.data if yq.size else None, hidden, iters, seed)
+    return st, yq
 
 
 def icl_tune_save(path=None) -> int:

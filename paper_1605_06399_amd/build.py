@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libicl.so")
 
 SOURCES = ["api.hip", "conv_sep.hip", "conv2d.hip", "conv2d_u8.hip", "harris.hip", "nms.hip", "corners.hip", "batched.hip", "bank.hip",
-           "tuner.hip"]
+           "tuner.hip", "perf_model.hip"]
 
 ARCH = os.environ.get("ICL_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

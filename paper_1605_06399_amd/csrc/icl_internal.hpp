@@ -7,6 +7,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
 #include "../../include/icl.h"
 
 namespace icl {
@@ -85,6 +88,18 @@ template <class A> struct Variant {
     bool (*supports)(const A&);        // can this variant run these arguments?
     hipError_t (*launch)(const A&);
 };
+
+// Small neural-network time model of the model-guided tuner (host code).
+struct PerfModel {
+    int d = 0, h = 0;
+    std::vector<double> mu, sd, p;
+    double ymu = 0.0, ysd = 1.0;
+    bool fit(const std::vector<std::vector<double>>& X, const std::vector<double>& y, int hidden, int iters,
+             uint64_t seed);
+    double predict(const std::vector<double>& x) const;
+};
+// Feature vectors of variants from their names (family one-hot, log2 of numeric parameters).
+void variant_features(const std::vector<std::string>& names, std::vector<std::vector<double>>& F);
 
 // Variant tables (index 0 = plain one-pixel-per-thread kernel).
 const Variant<SepArgs>* sep_variants(int* count);

@@ -245,6 +245,17 @@ struct Buffers {
     }
 };
 
+// How a search explores the candidates: every one (exhaustive), or the paper's model-guided
+// search (Section 4): time `samples` random candidates, fit the time model, time the `top_k`
+// best-predicted of the rest, keep the fastest measured.
+struct SearchPlan {
+    bool model = false;
+    int samples = 0, top_k = 0;
+    unsigned long long seed = 0;
+    int timed = 0;   // out: candidates timed
+};
+thread_local SearchPlan g_plan;
+
 // Generic search over an op's variant table.  make(set) builds the argument bundle
 // for buffer set `set`; agree(a) checks a candidate's output (set 0) against the
 // plain output.
@@ -253,22 +264,67 @@ icl_status search(icl_op op, const Variant<A>* tab, int count, icl_dtype dt, int
                   Make&& make, Agree&& agree, hipStream_t st) {
     double best = 1e300;
     int best_i = -1;
-    for (int i = 1; i < count; ++i) {
+    std::vector<double> measured(count, -1.0);   // us, -1 = not timed, -2 = rejected
+    auto try_one = [&](int i) {
         const A a0 = make(0, i);
-        if (!tab[i].supports(a0)) continue;
-        if (tab[i].launch(a0) != hipSuccess) continue;
+        measured[i] = -2.0;
+        if (tab[i].launch(a0) != hipSuccess) return;
         if (!agree()) {
             if (log_on()) std::fprintf(stderr, "icl tune: %s/%s rejected (output differs from plain)\n", op_name(op),
                                        tab[i].name);
-            continue;
+            return;
         }
         bool ok = true;
         const double us = time_launches([&](int s) { return tab[i].launch(make(s, i)); }, sets, 3, 5, 8, st, &ok);
-        if (!ok) continue;
+        ++g_plan.timed;
+        if (!ok) return;
+        measured[i] = us;
         if (log_on()) std::fprintf(stderr, "icl tune: %s/%s %.2f us\n", op_name(op), tab[i].name, us);
         if (us < best) {
             best = us;
             best_i = i;
+        }
+    };
+    std::vector<int> cand;
+    for (int i = 1; i < count; ++i)
+        if (tab[i].supports(make(0, i))) cand.push_back(i);
+    g_plan.timed = 0;
+    const int ns = std::max(2, g_plan.samples);
+    if (!g_plan.model || (int)cand.size() <= ns + std::max(1, g_plan.top_k)) {
+        for (int i : cand) try_one(i);   // exhaustive (also when the model would time everything anyway)
+    } else {
+        // random sample (Fisher-Yates on a SplitMix64 stream)
+        uint64_t s = g_plan.seed;
+        std::vector<int> order = cand;
+        for (int i = (int)order.size() - 1; i > 0; --i) {
+            uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z ^= z >> 31;
+            std::swap(order[i], order[(int)(z % (uint64_t)(i + 1))]);
+        }
+        for (int k = 0; k < ns; ++k) try_one(order[k]);
+        std::vector<std::string> names;
+        for (int i = 0; i < count; ++i) names.push_back(tab[i].name);
+        std::vector<std::vector<double>> F;
+        variant_features(names, F);
+        std::vector<std::vector<double>> X;
+        std::vector<double> y;
+        for (int i : cand)
+            if (measured[i] > 0) {
+                X.push_back(F[i]);
+                y.push_back(std::log(measured[i]));
+            }
+        PerfModel m;
+        std::vector<std::pair<double, int>> pred;
+        if ((int)X.size() >= 2 && m.fit(X, y, 8, 2000, g_plan.seed ^ 0x5bd1e995ull)) {
+            for (int i : cand)
+                if (measured[i] == -1.0) pred.push_back({m.predict(F[i]), i});
+            std::sort(pred.begin(), pred.end());
+            for (int k = 0; k < (int)pred.size() && k < g_plan.top_k; ++k) try_one(pred[k].second);
+        } else {
+            for (int i : cand)
+                if (measured[i] == -1.0) try_one(i);
         }
     }
     if (best_i < 0) return ICL_ERR_UNSUPPORTED;
@@ -524,6 +580,16 @@ int tune_cache_get(icl_op op, icl_dtype dt, int r, int W, int H) {
 using namespace icl;
 
 extern "C" {
+
+icl_status icl_tune_model(icl_op op, icl_dtype dtype, int radius, int width, int height, int samples, int top_k,
+                          unsigned long long seed, int* timed, void* stream) {
+    if (samples < 2 || top_k < 1) return ICL_ERR_INVALID_VALUE;
+    g_plan = SearchPlan{true, samples, top_k, seed, 0};
+    const icl_status s = icl_tune(op, dtype, radius, width, height, stream);
+    g_plan.model = false;
+    if (timed) *timed = g_plan.timed;
+    return s;
+}
 
 icl_status icl_tune(icl_op op, icl_dtype dtype, int radius, int width, int height, void* stream) {
     if (width < 1 || height < 1) return ICL_ERR_INVALID_VALUE;

@@ -250,6 +250,37 @@ def test_no_device_or_launch_path(L):
     assert B.icl_tune(B.ICL_OP_CONV_SEP, B.ICL_F32, 2, 64, 64) == B.ICL_ERR_NO_DEVICE
 
 
+def test_perf_model_learns_a_smooth_function(L):
+    """The tuner's time model is host code: it must fit a smooth function of a few features
+    well enough to rank unseen points, deterministically."""
+    import numpy as np
+    rng = np.random.default_rng(7)
+    f = lambda X: 1.5 * X[:, 0] - 2.0 * X[:, 1] + 0.5 * X[:, 0] * X[:, 2] + 3.0   # noqa: E731
+    X = rng.uniform(-1, 1, (48, 3))
+    Xq = rng.uniform(-1, 1, (24, 3))
+    st, yq = B.icl_perf_model_fit_predict(X, f(X), Xq, hidden=8, iters=3000, seed=11)
+    assert st == B.ICL_OK
+    resid = yq - f(Xq)
+    r2 = 1.0 - np.sum(resid ** 2) / np.sum((f(Xq) - f(Xq).mean()) ** 2)
+    assert r2 > 0.95, r2
+    # ranking: the predicted best of the held-out points is among the true best three
+    assert np.argmin(yq) in np.argsort(f(Xq))[:3]
+    st2, yq2 = B.icl_perf_model_fit_predict(X, f(X), Xq, hidden=8, iters=3000, seed=11)
+    assert st2 == B.ICL_OK and np.array_equal(yq, yq2)
+    # a constant target is predicted exactly; invalid arguments are refused
+    st, yc = B.icl_perf_model_fit_predict(X, np.full(48, 2.5), Xq, seed=1)
+    assert st == B.ICL_OK and np.allclose(yc, 2.5, atol=1e-9)
+    assert B.icl_perf_model_fit_predict(X[:1], f(X[:1]), Xq)[0] == B.ICL_ERR_INVALID_VALUE
+    assert B.icl_perf_model_fit_predict(X, f(X), Xq, hidden=0)[0] == B.ICL_ERR_INVALID_VALUE
+    assert B.icl_perf_model_fit_predict(X, f(X), Xq, iters=0)[0] == B.ICL_ERR_INVALID_VALUE
+
+
+def test_tune_model_validation(no_gpu):
+    assert B.icl_tune_model(B.ICL_OP_CONV_SEP, B.ICL_F32, 2, 64, 64, 1, 2)[0] == B.ICL_ERR_INVALID_VALUE
+    assert B.icl_tune_model(B.ICL_OP_CONV_SEP, B.ICL_F32, 2, 64, 64, 4, 0)[0] == B.ICL_ERR_INVALID_VALUE
+    assert B.icl_tune_model(B.ICL_OP_CONV_SEP, B.ICL_F32, 2, 64, 64, 4, 2)[0] == B.ICL_ERR_NO_DEVICE
+
+
 def test_tune_cache_file_roundtrip_and_corruption(L, tmp_path):
     p = tmp_path / "cache.json"
     assert B.icl_tune_save(str(p)) == B.ICL_OK
