@@ -30,6 +30,10 @@
  *                       to a correlation of the constant-padded image computed
  *                       by numpy slicing; hand-worked 3x3 box sums; a constant
  *                       image equal to the constant gives c * sum(w).
+ *   conv3d_sep        : correlation of the padded volume by numpy slicing with
+ *                       the outer-product taps (clamp and constant); a single
+ *                       slice with taps_z = delta equals the 2-D separable
+ *                       oracle; constant volumes; shifted deltas.
  *   conv2d_u8         : exact integer sums against numpy int64 slicing of the
  *                       padded image; delta taps reproduce the input; rounding
  *                       ties and saturation worked by hand; agreement with the
@@ -159,6 +163,45 @@ EXPORT void orc_conv_sep_pts(const double* X, long W, long H, const double* h, c
         }
         out[p] = acc;
     }
+}
+
+/* ---------------------------------------------------------------- 3-D separable correlation
+ * The Image type also has 3-D indexing (Section 5).  A volume is stored slice after slice,
+ * each slice row-major (x fastest).  The separable 3-D filter is the 3-D correlation with
+ * taps hz (x) hy (x) hx on the volume extended by the boundary condition (per-axis clamp,
+ * or the constant c outside):
+ *   Y(x,y,z) = sum_{k,j,i} hz[k+r] hy[j+r] hx[i+r] X(x+i, y+j, z+k)
+ * written out directly (no passes); the product of the three taps is formed first. */
+static inline double at3(const double* X, long W, long H, long D, long x, long y, long z, int border, double c) {
+    if (border == ORC_CONSTANT && (x < 0 || x >= W || y < 0 || y >= H || z < 0 || z >= D)) return c;
+    return X[(clampi(z, D) * H + clampi(y, H)) * W + clampi(x, W)];
+}
+
+static double conv3d_sep_px(const double* X, long W, long H, long D, const double* hx, const double* hy,
+                            const double* hz, int r, int border, double c, long x, long y, long z) {
+    double acc = 0.0;
+    for (int k = -r; k <= r; ++k)
+        for (int j = -r; j <= r; ++j)
+            for (int i = -r; i <= r; ++i)
+                acc += (hz[k + r] * hy[j + r] * hx[i + r]) * at3(X, W, H, D, x + i, y + j, z + k, border, c);
+    return acc;
+}
+
+EXPORT void orc_conv3d_sep(const double* X, long W, long H, long D, const double* hx, const double* hy,
+                           const double* hz, int r, int border, double c, double* Y, int nthreads) {
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (long z = 0; z < D; ++z)
+        for (long y = 0; y < H; ++y)
+            for (long x = 0; x < W; ++x)
+                Y[(z * H + y) * W + x] = conv3d_sep_px(X, W, H, D, hx, hy, hz, r, border, c, x, y, z);
+}
+
+EXPORT void orc_conv3d_sep_pts(const double* X, long W, long H, long D, const double* hx, const double* hy,
+                               const double* hz, int r, int border, double c, const long* xs, const long* ys,
+                               const long* zs, long npts, double* out, int nthreads) {
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (long p = 0; p < npts; ++p)
+        out[p] = conv3d_sep_px(X, W, H, D, hx, hy, hz, r, border, c, xs[p], ys[p], zs[p]);
 }
 
 /* ---------------------------------------------------------------- 8-bit 2-D correlation

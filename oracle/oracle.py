@@ -54,6 +54,9 @@ def lib():
         L.orc_conv_sep.argtypes = [_D, c_long, c_long, _D, _D, c_int, c_int, c_double, _D, _D, c_int]
         L.orc_conv_sep_pts.argtypes = [_D, c_long, c_long, _D, _D, c_int, c_int, c_double, _L, _L, c_long, _D,
                                        c_int]
+        L.orc_conv3d_sep.argtypes = [_D, c_long, c_long, c_long, _D, _D, _D, c_int, c_int, c_double, _D, c_int]
+        L.orc_conv3d_sep_pts.argtypes = [_D, c_long, c_long, c_long, _D, _D, _D, c_int, c_int, c_double, _L, _L, _L,
+                                         c_long, _D, c_int]
         L.orc_conv2d_u8.argtypes = [_U8, c_long, c_long, _I16, c_int, c_int, c_int, c_int, _U8, c_int]
         L.orc_conv2d_u8_pts.argtypes = [_U8, c_long, c_long, _I16, c_int, c_int, c_int, c_int, _L, _L, c_long,
                                         _U8, c_int]
@@ -172,6 +175,37 @@ def conv_sep_pts(X, h, v, xs, ys, nthreads=None, border="clamp", constant=0.0):
     lib().orc_conv_sep_pts(_p(X), W, H, _p(h), _p(v), r, BORDERS[border], float(constant), _p(xs, _L),
                            _p(ys, _L), xs.size, _p(out), _threads(nthreads))
     return out
+
+
+def conv3d_sep(X, hx, hy, hz, nthreads=None, border="clamp", constant=0.0):
+    """X [D, H, W] (slice, row, column): separable 3-D correlation through the boundary."""
+    X = _f64(X)
+    hx, hy, hz = _f64(hx), _f64(hy), _f64(hz)
+    D, H, W = X.shape
+    r = (hx.size - 1) // 2
+    assert hx.size == hy.size == hz.size == 2 * r + 1
+    Y = np.empty_like(X)
+    lib().orc_conv3d_sep(_p(X), W, H, D, _p(hx), _p(hy), _p(hz), r, BORDERS[border], float(constant), _p(Y),
+                         _threads(nthreads))
+    return Y
+
+
+def conv3d_sep_pts(X, hx, hy, hz, xs, ys, zs, nthreads=None, border="clamp", constant=0.0):
+    X = _f64(X)
+    hx, hy, hz = _f64(hx), _f64(hy), _f64(hz)
+    D, H, W = X.shape
+    r = (hx.size - 1) // 2
+    xs, ys = _pts(xs, ys)
+    zs = np.ascontiguousarray(zs, dtype=np.int64)
+    out = np.empty(xs.shape, dtype=np.float64)
+    lib().orc_conv3d_sep_pts(_p(X), W, H, D, _p(hx), _p(hy), _p(hz), r, BORDERS[border], float(constant),
+                             _p(xs, _L), _p(ys, _L), _p(zs, _L), xs.size, _p(out), _threads(nthreads))
+    return out
+
+
+def normwise_scale_sep3d(X, hx, hy, hz, nthreads=None, border="clamp", constant=0.0):
+    return conv3d_sep(np.abs(_f64(X)), np.abs(_f64(hx)), np.abs(_f64(hy)), np.abs(_f64(hz)), nthreads,
+                      border=border, constant=abs(constant))
 
 
 def _u8_args(X, w, shift, constant):

@@ -325,6 +325,73 @@ def test_constant_border_points_match_full(orc):
                        rtol=0, atol=1e-13)
 
 
+# ----------------------------------------------------------------------------- 3-D separable
+
+def padded_correlation3(X, hx, hy, hz, mode, c=0.0):
+    """3-D correlation of the padded volume by whole-array slicing with the outer-product taps."""
+    D, H, W = X.shape
+    r = (hx.size - 1) // 2
+    if mode == "constant":
+        Xp = np.pad(np.asarray(X, dtype=np.float64), r, mode="constant", constant_values=c)
+    else:
+        Xp = np.pad(np.asarray(X, dtype=np.float64), r, mode="edge")
+    Y = np.zeros((D, H, W))
+    for k in range(2 * r + 1):
+        for j in range(2 * r + 1):
+            for i in range(2 * r + 1):
+                Y += float(hz[k]) * float(hy[j]) * float(hx[i]) * Xp[k:k + D, j:j + H, i:i + W]
+    return Y
+
+
+@pytest.mark.parametrize("r,D,H,W,mode,c", [(1, 5, 7, 9, "clamp", 0.0), (2, 4, 6, 5, "constant", 0.75),
+                                            (2, 1, 3, 8, "clamp", 0.0), (3, 3, 2, 4, "constant", -1.25)])
+def test_conv3d_matches_padded_slicing(orc, r, D, H, W, mode, c):
+    n = 2 * r + 1
+    X = synth.uniform01(synth.seed(60 + r, 0), D * H * W).reshape(D, H, W).astype(np.float64)
+    hx, hy, hz = (synth.normal(synth.seed(60 + r, q), n).astype(np.float64) for q in (1, 2, 3))
+    ref = padded_correlation3(X, hx, hy, hz, mode, c)
+    assert np.allclose(orc.conv3d_sep(X, hx, hy, hz, border=mode, constant=c), ref, rtol=0, atol=1e-12)
+
+
+def test_conv3d_single_slice_is_the_2d_filter(orc):
+    """One slice with z taps (0, 1, 0): the clamped slices above and below are the slice
+    itself, so the result is the 2-D separable filter of that slice, exactly."""
+    X = synth.image_uniform(63, 11, 13).astype(np.float64)
+    h = np.array([0.25, 0.5, 0.25])
+    v = np.array([-1.0, 0.0, 2.0])
+    z = np.array([0.0, 1.0, 0.0])
+    Y3 = orc.conv3d_sep(X[None], h, v, z)[0]
+    assert np.array_equal(Y3, orc.conv_sep(X, h, v))
+
+
+def test_conv3d_delta_constant_and_shift(orc):
+    D, H, W = 4, 5, 6
+    X = synth.uniform01(synth.seed(64, 0), D * H * W).reshape(D, H, W).astype(np.float64)
+    d = np.array([0.0, 1.0, 0.0])
+    assert np.array_equal(orc.conv3d_sep(X, d, d, d), X)
+    b = np.array([1, 4, 6, 4, 1], dtype=np.float64) / 16.0
+    C = np.full((D, H, W), 0.375)
+    assert np.array_equal(orc.conv3d_sep(C, b, b, b), C)
+    assert np.array_equal(orc.conv3d_sep(C, b, b, b, border="constant", constant=0.375), C)
+    # a tap at z offset +1 only: slices shift by one, clamped at the end / constant outside
+    s = np.array([0.0, 0.0, 1.0])
+    Ys = orc.conv3d_sep(X, d, d, s)
+    assert np.array_equal(Ys[:-1], X[1:]) and np.array_equal(Ys[-1], X[-1])
+    Yc = orc.conv3d_sep(X, d, d, s, border="constant", constant=9.0)
+    assert np.array_equal(Yc[:-1], X[1:]) and np.all(Yc[-1] == 9.0)
+
+
+def test_conv3d_points_match_full(orc):
+    D, H, W, r = 5, 9, 8, 2
+    X = synth.uniform01(synth.seed(65, 0), D * H * W).reshape(D, H, W).astype(np.float64)
+    hx, hy, hz = (synth.normal(synth.seed(65, q), 5).astype(np.float64) for q in (1, 2, 3))
+    zs, ys, xs = (a.ravel() for a in np.meshgrid(np.arange(D), np.arange(H), np.arange(W), indexing="ij"))
+    for mode in ("clamp", "constant"):
+        full = orc.conv3d_sep(X, hx, hy, hz, border=mode, constant=0.5).ravel()
+        pts = orc.conv3d_sep_pts(X, hx, hy, hz, xs, ys, zs, border=mode, constant=0.5)
+        assert np.allclose(pts, full, rtol=0, atol=1e-13)
+
+
 # ----------------------------------------------------------------------------- unsigned char, integer taps
 
 def u8_reference(X, w, shift, mode, c=0):
