@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP32_FMA_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, packed FP32 disabled
 FP32_PACKED_PEAK_TFLOPS = 157.3
-EXTRAS = ("corner", "batch", "bank", "paper", "tuner")
+EXTRAS = ("corner", "batch", "bank", "paper", "tuner", "volume")
 INT_DOT2_PEAK_TMACS = 78.6     # v_dot2_i32_i16: 2 int16 MACs per lane per issue, 256 CU x 64 lanes x 2.4 GHz
 METRIC = "Gpixel/s & % HBM peak, autotuned vs plain kernel; fwd+bwd Gpixel/s"
 
@@ -46,7 +46,7 @@ def parse():
     p.add_argument("--no-extras", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--only", default="", help="comma list of sweep call labels (sep1 ... 2d7) and extra "
-                   "workloads (corner, batch, bank, paper, tuner) to run; a profiling aid")
+                   "workloads (corner, batch, bank, paper, tuner, volume) to run; a profiling aid")
     p.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter_collection.csv files of a --calib-copy "
                         "run into profiles/traffic.json and exit")
@@ -363,6 +363,46 @@ def run_extras(torch, B, T, synth, steps, which=EXTRAS):
         res.update(extra_paper(torch, B, T, synth, steps))
     if "tuner" in which:
         res.update(extra_tuner(torch, B, T, synth, steps))
+    if "volume" in which:
+        res.update(extra_volume(torch, B, T, synth, steps))
+    return res
+
+
+def extra_volume(torch, B, T, synth, steps):
+    """Separable 3-D correlation of a 256^3 float32 volume (the Image type's 3-D indexing):
+    radii 1..3, every variant, 8 algorithmic B/voxel."""
+    dev = torch.device("cuda:0")
+    side = 256
+    vol = synth.volume_uniform(7, side, side, side)
+    xs = [torch.from_numpy(vol).to(dev) for _ in range(2)]
+    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    _, nb = B.icl_workspace_size(B.ICL_OP_CONV3D_SEP, side, side, n=side)
+    ws = torch.empty(nb // 4 + 1, dtype=torch.float32, device=dev)
+    res = {}
+    for r in (1, 2, 3):
+        tx, ty, tz = (torch.from_numpy(synth.gaussian_taps(r, max(1.0, r / 2.0))).to(dev) for _ in range(3))
+
+        def call(s):
+            T.conv3d_sep(xs[s % 2], tx, ty, tz, out=ys[s % 2], workspace=ws)
+
+        per_variant = {}
+        for v in range(B.icl_variant_count(B.ICL_OP_CONV3D_SEP)):
+            B.check(B.icl_force_variant(B.ICL_OP_CONV3D_SEP, v))
+            try:
+                per_variant[B.icl_variant_name(B.ICL_OP_CONV3D_SEP, v)] = round(
+                    _time_graph(torch, call, steps) * 1e6, 1)
+            finally:
+                B.icl_force_variant(B.ICL_OP_CONV3D_SEP, -1)
+        dt = _time_graph(torch, call, 2 * steps)
+        gvx = side ** 3 / dt / 1e9
+        res[f"volume_sep3d_r{r}_256_f32"] = {
+            "us": round(dt * 1e6, 2), "gvoxel_s": round(gvx, 1), "bytes_per_voxel": 8,
+            "hbm_frac": round(gvx * 8 / HBM_PEAK_GBS, 3),
+            "variant": B.icl_variant_name(B.ICL_OP_CONV3D_SEP, B.icl_selected_variant(
+                B.ICL_OP_CONV3D_SEP, B.ICL_F32, r, side, side)[1]),
+            "variants_us": per_variant}
+    del xs, ys, ws
+    torch.cuda.empty_cache()
     return res
 
 

@@ -86,7 +86,8 @@ typedef enum icl_op {
     ICL_OP_BANK_FWD_SSE = 9,
     ICL_OP_CONV2D_U8 = 10,
     ICL_OP_CORNERS = 11,
-    ICL_OP_COUNT = 12
+    ICL_OP_CONV3D_SEP = 12,
+    ICL_OP_COUNT = 13
 } icl_op;
 
 #define ICL_MAX_RADIUS 16          /* largest stencil radius accepted by the convolution calls */
@@ -94,6 +95,7 @@ typedef enum icl_op {
 #define ICL_MAX_NMS_RADIUS 7
 #define ICL_MAX_U8_RADIUS 7        /* largest radius of icl_conv2d_u8 (keeps its int32 sum exact) */
 #define ICL_MAX_U8_SHIFT 16
+#define ICL_MAX_RADIUS_3D 7        /* largest radius of icl_conv3d_sep */
 
 /* ------------------------------------------------------------------ library */
 
@@ -111,9 +113,10 @@ const char* icl_version(void);
  * (Sobel kernel + Harris kernel) variant; for ICL_OP_BANK_BWD_FILTER,
  * ICL_OP_SSE_LOSS and ICL_OP_BANK_FWD_SSE the per-block partial sums; for ICL_OP_CORNERS the
  * two-kernel variant's float32 response image and, for window radii above 3, the gradient
- * images (`radius` is the window radius).  Callers that always pass this
+ * images (`radius` is the window radius); for ICL_OP_CONV3D_SEP the two float32 intermediate
+ * volumes of the three-pass variant (`n` is the depth).  Callers that always pass this
  * much workspace may use every variant.  `n` and `f` are the batch and filter
- * counts of the filter-bank ops (ignored otherwise). */
+ * counts of the filter-bank ops, `n` the depth for ICL_OP_CONV3D_SEP (ignored otherwise). */
 icl_status icl_workspace_size(icl_op op, int width, int height, int n, int f, int radius,
                               icl_dtype dtype, size_t* bytes /* host */);
 
@@ -163,6 +166,29 @@ icl_status icl_conv2d_border(const void* src, size_t src_pitch, void* dst, size_
                              int width, int height, icl_dtype dtype,
                              const float* taps, int radius, icl_border border, float constant,
                              void* stream);
+
+/* ------------------------------------------------------------------ 3-D separable correlation
+ * Paper: Section 5, the Image type's 3-D indexing; the separable passes of the Section 6
+ * benchmark with a third (z) pass.  A volume is `depth` slices of `height` rows:
+ * voxel (x, y, z) lives at base + z * slice_pitch + y * row_pitch + x * elem_size.
+ *   T1(x,y,z) = sum_i taps_x[i+r] V(x+i, y, z)
+ *   T2(x,y,z) = sum_j taps_y[j+r] T1(x, y+j, z)
+ *   dst(x,y,z) = sum_k taps_z[k+r] T2(x, y, z+k)
+ * i.e. the 3-D correlation with taps taps_z (x) taps_y (x) taps_x of the volume extended by
+ * the boundary condition (clamp per axis, or `constant` for every voxel outside; with the
+ * constant the intermediates outside are the passes of the constant, as for icl_conv_sep_border).
+ * Intermediates are float32.
+ *   row_pitch  >= width * elem, slice_pitch >= (height-1) * row_pitch + width * elem, both
+ *              multiples of elem (ICL_ERR_PITCH)
+ *   radius     : 0 .. ICL_MAX_RADIUS_3D (the single-pass variants cover 0..3)
+ *   workspace  : icl_workspace_size(ICL_OP_CONV3D_SEP, width, height, depth) bytes for the
+ *                three-pass variant, or NULL (then radii above 3 are ICL_ERR_WORKSPACE). */
+icl_status icl_conv3d_sep(const void* src, size_t src_row_pitch, size_t src_slice_pitch,
+                          void* dst, size_t dst_row_pitch, size_t dst_slice_pitch,
+                          int width, int height, int depth, icl_dtype dtype,
+                          const float* taps_x, const float* taps_y, const float* taps_z, int radius,
+                          icl_border border, float constant,
+                          void* workspace, size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------ 8-bit 2-D correlation
  * Paper: Section 6, non-separable convolution benchmark, run on unsigned char

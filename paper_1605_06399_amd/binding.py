@@ -37,13 +37,14 @@ ICL_BORDER_CLAMP, ICL_BORDER_CONSTANT = 0, 1
 # icl_op
 (ICL_OP_CONV_SEP, ICL_OP_CONV2D, ICL_OP_HARRIS, ICL_OP_NMS, ICL_OP_CONV_SEP_BATCHED, ICL_OP_BANK_FWD,
  ICL_OP_BANK_BWD_INPUT, ICL_OP_BANK_BWD_FILTER, ICL_OP_SSE_LOSS, ICL_OP_BANK_FWD_SSE, ICL_OP_CONV2D_U8,
- ICL_OP_CORNERS, ICL_OP_COUNT) = range(13)
+ ICL_OP_CORNERS, ICL_OP_CONV3D_SEP, ICL_OP_COUNT) = range(14)
 
 ICL_MAX_RADIUS = 16
 ICL_MAX_WINDOW_RADIUS = 7
 ICL_MAX_NMS_RADIUS = 7
 ICL_MAX_U8_RADIUS = 7
 ICL_MAX_U8_SHIFT = 16
+ICL_MAX_RADIUS_3D = 7
 
 _vp = ctypes.c_void_p
 _sz = ctypes.c_size_t
@@ -75,6 +76,7 @@ _SIGS = {
     "icl_conv2d": ([_vp, _sz, _vp, _sz, _i, _i, _i, _vp, _i, _vp], _i),
     "icl_conv2d_border": ([_vp, _sz, _vp, _sz, _i, _i, _i, _vp, _i, _i, _f, _vp], _i),
     "icl_conv2d_u8": ([_vp, _sz, _vp, _sz, _i, _i, _vp, _i, _i, _i, _i, _vp], _i),
+    "icl_conv3d_sep": ([_vp, _sz, _sz, _vp, _sz, _sz, _i, _i, _i, _i, _vp, _vp, _vp, _i, _i, _f, _vp, _sz, _vp], _i),
     "icl_harris": ([_vp, _sz, _vp, _sz, _i, _i, _vp, _i, _f, _vp, _sz, _vp], _i),
     "icl_nms": ([_vp, _sz, _vp, _sz, _i, _i, _i, _f, _vp], _i),
     "icl_corners": ([_vp, _sz, _vp, _sz, _i, _i, _vp, _i, _f, _i, _f, _vp, _sz, _vp, _sz, _vp], _i),
@@ -175,6 +177,14 @@ def icl_conv2d_border(src, src_pitch, dst, dst_pitch, width, height, dtype, taps
                       stream=0) -> int:
     return lib().icl_conv2d_border(src, src_pitch, dst, dst_pitch, width, height, dtype, taps, radius, border,
                                    constant, stream or None)
+
+
+def icl_conv3d_sep(src, src_row_pitch, src_slice_pitch, dst, dst_row_pitch, dst_slice_pitch, width, height, depth,
+                   dtype, taps_x, taps_y, taps_z, radius, border=ICL_BORDER_CLAMP, constant=0.0, workspace=0,
+                   workspace_bytes=0, stream=0) -> int:
+    return lib().icl_conv3d_sep(src, src_row_pitch, src_slice_pitch, dst, dst_row_pitch, dst_slice_pitch, width,
+                                height, depth, dtype, taps_x, taps_y, taps_z, radius, border, constant,
+                                workspace or None, workspace_bytes, stream or None)
 
 
 def icl_conv2d_u8(src, src_pitch, dst, dst_pitch, width, height, taps, radius, shift, border=ICL_BORDER_CLAMP,

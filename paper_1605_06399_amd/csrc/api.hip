@@ -27,7 +27,7 @@ static std::mutex g_init_mu;
 
 static const char* kOpNames[ICL_OP_COUNT] = {"conv_sep", "conv2d", "harris", "nms", "conv_sep_batched",
                                              "bank_fwd", "bank_bwd_input", "bank_bwd_filter", "sse_loss",
-                                             "bank_fwd_sse", "conv2d_u8", "corners"};
+                                             "bank_fwd_sse", "conv2d_u8", "corners", "conv3d_sep"};
 
 // ICL_FORCE_VARIANT="conv_sep=1,conv2d=3": the analogue of the paper's directives
 // that force optimisations on or off.
@@ -207,6 +207,7 @@ icl_status icl_workspace_size(icl_op op, int width, int height, int n, int f, in
             if (radius < 0 || radius > ICL_MAX_WINDOW_RADIUS) return ICL_ERR_RADIUS;
             *bytes = corners_workspace(width, height, radius);
             break;
+        case ICL_OP_CONV3D_SEP: *bytes = sep3d_workspace(width, height, n); break;
         case ICL_OP_CONV2D: case ICL_OP_NMS: case ICL_OP_CONV_SEP_BATCHED: case ICL_OP_BANK_FWD:
         case ICL_OP_BANK_BWD_INPUT: case ICL_OP_CONV2D_U8: break;
         default: return ICL_ERR_INVALID_VALUE;
@@ -282,6 +283,43 @@ icl_status icl_conv2d_border(const void* src, size_t src_pitch, void* dst, size_
     const int deflt = conv2d_default(a);
     return dispatch(ICL_OP_CONV2D, tab, count, a, select_variant(ICL_OP_CONV2D, dtype, radius, width, height, deflt),
                     deflt);
+}
+
+icl_status icl_conv3d_sep(const void* src, size_t src_row_pitch, size_t src_slice_pitch, void* dst,
+                          size_t dst_row_pitch, size_t dst_slice_pitch, int width, int height, int depth,
+                          icl_dtype dtype, const float* taps_x, const float* taps_y, const float* taps_z, int radius,
+                          icl_border border, float constant, void* workspace, size_t workspace_bytes, void* stream) {
+    if (width < 0 || height < 0 || depth < 0) return ICL_ERR_INVALID_VALUE;
+    if (!dtype_ok(dtype)) return ICL_ERR_DTYPE;
+    if (radius < 0 || radius > ICL_MAX_RADIUS_3D) return ICL_ERR_RADIUS;
+    if (border != ICL_BORDER_CLAMP && border != ICL_BORDER_CONSTANT) return ICL_ERR_INVALID_VALUE;
+    if (width == 0 || height == 0 || depth == 0) return ICL_OK;
+    const int es = elem_size(dtype);
+    icl_status s;
+    if ((s = check_image(src, src_row_pitch, width, es)) != ICL_OK) return s;
+    if ((s = check_image(dst, dst_row_pitch, width, es)) != ICL_OK) return s;
+    const size_t sslice = (size_t)(height - 1) * src_row_pitch + (size_t)width * es;
+    const size_t dslice = (size_t)(height - 1) * dst_row_pitch + (size_t)width * es;
+    if (src_slice_pitch < sslice || src_slice_pitch % es || dst_slice_pitch < dslice || dst_slice_pitch % es)
+        return ICL_ERR_PITCH;
+    if (!taps_x || !taps_y || !taps_z) return ICL_ERR_INVALID_VALUE;
+    const size_t sbytes = (size_t)(depth - 1) * src_slice_pitch + sslice;
+    const size_t dbytes = (size_t)(depth - 1) * dst_slice_pitch + dslice;
+    if (range_overlaps(src, sbytes, dst, dbytes)) return ICL_ERR_ALIAS;
+    if (workspace && workspace_bytes &&
+        (range_overlaps(workspace, workspace_bytes, src, sbytes) || range_overlaps(workspace, workspace_bytes, dst, dbytes)))
+        return ICL_ERR_ALIAS;
+    if ((s = device_ready()) != ICL_OK) return s;
+    Sep3Args a{src, src_row_pitch, src_slice_pitch, dst, dst_row_pitch, dst_slice_pitch, width, height, depth,
+               dtype, taps_x, taps_y, taps_z, radius, workspace, workspace_bytes, (hipStream_t)stream,
+               border_of(border, constant)};
+    int count;
+    const Variant<Sep3Args>* tab = sep3d_variants(&count);
+    const int deflt = sep3d_default(a);
+    const int v = select_variant(ICL_OP_CONV3D_SEP, dtype, radius, width, height, deflt);
+    const bool forced_plain = variant_forced(ICL_OP_CONV3D_SEP) && v == 0;
+    if ((forced_plain || !tab[deflt].supports(a)) && !tab[0].supports(a)) return ICL_ERR_WORKSPACE;
+    return dispatch(ICL_OP_CONV3D_SEP, tab, count, a, v, deflt);
 }
 
 icl_status icl_conv2d_u8(const uint8_t* src, size_t src_pitch, uint8_t* dst, size_t dst_pitch, int width,
@@ -514,6 +552,7 @@ int icl_variant_count(icl_op op) {
         case ICL_OP_CONV2D: conv2d_variants(&c); break;
         case ICL_OP_CONV2D_U8: conv2d_u8_variants(&c); break;
         case ICL_OP_CORNERS: corners_variants(&c); break;
+        case ICL_OP_CONV3D_SEP: sep3d_variants(&c); break;
         case ICL_OP_HARRIS: harris_variants(&c); break;
         case ICL_OP_NMS: nms_variants(&c); break;
         case ICL_OP_BANK_FWD: bank_fwd_variants(&c); break;
@@ -535,6 +574,7 @@ const char* icl_variant_name(icl_op op, int index) {
         case ICL_OP_CONV2D: return conv2d_variants(&c)[index].name;
         case ICL_OP_CONV2D_U8: return conv2d_u8_variants(&c)[index].name;
         case ICL_OP_CORNERS: return corners_variants(&c)[index].name;
+        case ICL_OP_CONV3D_SEP: return sep3d_variants(&c)[index].name;
         case ICL_OP_HARRIS: return harris_variants(&c)[index].name;
         case ICL_OP_NMS: return nms_variants(&c)[index].name;
         case ICL_OP_BANK_FWD: return bank_fwd_variants(&c)[index].name;
@@ -592,6 +632,12 @@ icl_status icl_selected_variant(icl_op op, icl_dtype dtype, int radius, int widt
             U8Args a{};
             a.r = radius;
             deflt = conv2d_u8_default(a);
+            break;
+        }
+        case ICL_OP_CONV3D_SEP: {
+            Sep3Args a{};
+            a.r = radius;
+            deflt = sep3d_default(a);
             break;
         }
         case ICL_OP_CORNERS: {

@@ -41,6 +41,16 @@ struct U8Args {
     hipStream_t st;
 };
 
+struct Sep3Args {
+    const void* src; size_t srp, ssp;   // row and slice pitches (bytes)
+    void* dst; size_t drp, dsp;
+    int W, H, D; icl_dtype dt;
+    const float *tx, *ty, *tz; int r;
+    void* ws; size_t wsb;
+    hipStream_t st;
+    Border bd{};
+};
+
 struct HarrisArgs {
     const float* src; size_t sp; float* resp; size_t rp;
     int W, H;
@@ -108,6 +118,7 @@ const Variant<U8Args>* conv2d_u8_variants(int* count);
 const Variant<HarrisArgs>* harris_variants(int* count);
 const Variant<NmsArgs>* nms_variants(int* count);
 const Variant<CornersArgs>* corners_variants(int* count);
+const Variant<Sep3Args>* sep3d_variants(int* count);
 const Variant<BankArgs>* bank_fwd_variants(int* count);
 const Variant<BankArgs>* bank_bwd_input_variants(int* count);
 const Variant<BankArgs>* bank_bwd_filter_variants(int* count);
@@ -120,6 +131,7 @@ int conv2d_u8_default(const U8Args&);
 int harris_default(const HarrisArgs&);
 int nms_default(const NmsArgs&);
 int corners_default(const CornersArgs&);
+int sep3d_default(const Sep3Args&);
 int bank_fwd_default(const BankArgs&);
 int bank_bwd_input_default(const BankArgs&);
 int bank_bwd_filter_default(const BankArgs&);
@@ -129,6 +141,7 @@ int batched_default();
 size_t sep_workspace(int W, int H);
 size_t harris_workspace(int W, int H);
 size_t corners_workspace(int W, int H, int rg);
+size_t sep3d_workspace(int W, int H, int D);
 size_t bank_bwd_filter_workspace(int n, int f, int h, int w, int r);
 size_t sse_workspace(long long count);
 size_t bank_fwd_sse_workspace();

@@ -66,6 +66,12 @@ struct Stage {
         }
     }
 
+    // Every element the constant c (a whole staged region outside the image).
+    __device__ __forceinline__ void fill(float c) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = mk4(c, c, c, c);
+    }
+
     __device__ __forceinline__ void store(float* __restrict__ s) const {
 #pragma unroll
         for (int k = 0; k < N; ++k) {

@@ -104,6 +104,11 @@ def integer_image(config: int, height: int, width: int, hi: int = 255) -> np.nda
     return randint(seed(config, PIXELS), height * width, 0, hi).reshape(height, width).astype(np.float32)
 
 
+def volume_uniform(config: int, depth: int, height: int, width: int) -> np.ndarray:
+    """D x H x W float32 volume, voxels U[0,1), slices of row-major rows."""
+    return uniform01(seed(config, PIXELS), depth * height * width).reshape(depth, height, width)
+
+
 def u8_image(config: int, height: int, width: int) -> np.ndarray:
     """unsigned char image, bytes uniform on 0..255."""
     return randint(seed(config, PIXELS), height * width, 0, 255).reshape(height, width).astype(np.uint8)

@@ -90,6 +90,44 @@ def conv2d(x: torch.Tensor, taps: torch.Tensor, out: torch.Tensor | None = None,
     return out
 
 
+def _volume(t: torch.Tensor, name: str):
+    """(pointer, row pitch, slice pitch, W, H, D) of a 3-D [D, H, W] view with contiguous rows."""
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dim() != 3:
+        raise ValueError(f"{name} must be 3-D (D, H, W)")
+    es = t.element_size()
+    D, H, W = t.shape
+    if t.numel() == 0:
+        return 0, W * es, H * W * es, W, H, D
+    if t.stride(2) != 1 and W > 1:
+        raise ValueError(f"{name} rows must be contiguous (stride(2) == 1)")
+    rp = t.stride(1) * es if H > 1 else W * es
+    sp = t.stride(0) * es if D > 1 else (H - 1) * rp + W * es
+    return t.data_ptr(), rp, sp, W, H, D
+
+
+def conv3d_sep(x: torch.Tensor, taps_x: torch.Tensor, taps_y: torch.Tensor, taps_z: torch.Tensor,
+               out: torch.Tensor | None = None, workspace: torch.Tensor | None = None, border: str = "clamp",
+               constant: float = 0.0) -> torch.Tensor:
+    """Separable 3-D correlation of a [D, H, W] volume."""
+    r = (taps_x.numel() - 1) // 2
+    if out is None:
+        out = torch.empty_like(x, memory_format=torch.contiguous_format)
+    sp, srp, ssp, W, H, D = _volume(x, "x")
+    dp, drp, dsp, _, _, _ = _volume(out, "out")
+    dt = _DT[x.dtype]
+    if workspace is None and r > 3:
+        _, nb = B.icl_workspace_size(B.ICL_OP_CONV3D_SEP, W, H, n=D, dtype=dt)
+        workspace = _workspace(nb, x.device)
+    ws, wsb = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None else (0, 0)
+    n = 2 * r + 1
+    B.check(B.icl_conv3d_sep(sp, srp, ssp, dp, drp, dsp, W, H, D, dt, _taps(taps_x, n, "taps_x"),
+                             _taps(taps_y, n, "taps_y"), _taps(taps_z, n, "taps_z"), r, _border(border),
+                             float(constant), ws, wsb, _stream()), "icl_conv3d_sep")
+    return out
+
+
 def conv2d_u8(x: torch.Tensor, taps: torch.Tensor, shift: int, out: torch.Tensor | None = None,
               border: str = "clamp", constant: int = 0) -> torch.Tensor:
     """unsigned char image, int16 taps [(2r+1), (2r+1)]: exact integer sum, rounded shift, saturated."""

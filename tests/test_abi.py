@@ -181,6 +181,27 @@ def test_corners_validation(no_gpu):
     assert c(SRC, 256, MASK, 64, 0, 8, TAPS, 2, 0.04, 1, 1e-3) == B.ICL_OK
 
 
+def test_conv3d_validation(no_gpu):
+    def c3(**kw):
+        a = dict(src=SRC, srp=256, ssp=256 * 8, dst=DST, drp=256, dsp=256 * 8, w=64, h=8, d=4, dt=B.ICL_F32,
+                 tx=TAPS, ty=TAPS, tz=TAPS, r=2, border=B.ICL_BORDER_CLAMP, c=0.0, ws=0, wsb=0)
+        a.update(kw)
+        return B.icl_conv3d_sep(*a.values())
+    assert c3(d=-1) == B.ICL_ERR_INVALID_VALUE
+    assert c3(r=8) == B.ICL_ERR_RADIUS
+    assert c3(dt=B.ICL_U8) == B.ICL_ERR_DTYPE
+    assert c3(border=4) == B.ICL_ERR_INVALID_VALUE
+    assert c3(srp=255) == B.ICL_ERR_PITCH
+    assert c3(ssp=256 * 7) == B.ICL_ERR_PITCH
+    assert c3(dsp=256 * 8 + 2) == B.ICL_ERR_PITCH
+    assert c3(tz=0) == B.ICL_ERR_INVALID_VALUE
+    assert c3(dst=SRC + 256 * 8 * 3) == B.ICL_ERR_ALIAS
+    assert c3(ws=DST + 64, wsb=1024) == B.ICL_ERR_ALIAS
+    assert c3(d=0) == B.ICL_OK
+    st, nb = B.icl_workspace_size(B.ICL_OP_CONV3D_SEP, 10, 20, n=30)
+    assert st == B.ICL_OK and nb == 2 * 10 * 20 * 30 * 4
+
+
 def test_bank_and_loss_validation(no_gpu):
     assert B.icl_bank_fwd(SRC, TAPS, DST, 2, 16, 8, 8, 5) == B.ICL_ERR_RADIUS
     assert B.icl_bank_fwd(SRC, TAPS, DST, 2, 0, 8, 8, 4) == B.ICL_ERR_INVALID_VALUE
