@@ -749,6 +749,115 @@ __global__ __launch_bounds__(256) void bank_bwd_w4_k(const float* __restrict__ g
         }
 }
 
+// ------------------------------------------------------------------ filter gradient on the matrix cores
+// gw[f][k] = sum_p gy[f][p] x[p + off(k)] is a matrix product: filters as rows, taps as
+// columns, pixels as the reduction.  v_mfma_f32_16x16x4f32 takes four pixels per step:
+//   A[f][q] = gy[f][p_q]           lane f + 16q
+//   B[q][j] = x[p_q + off(16t + j)] lane j + 16q      (tap column block t of ceil(NK/16))
+//   D[f][j] += sum_q A[f][q] B[q][j] lane j + 16(f/4), register f % 4
+// Each work-group stages a 64-column x 64-row x tile (with halo, clamped) in LDS; its four
+// waves take 16 rows each, every row as 16 four-pixel steps, the 16 x 4 gy values of a row
+// loaded ahead in registers.  The four waves' sums are added in a fixed order and written as
+// one partial per (filter, tap, tile), so the result is deterministic.  Up to 16 filters.
+constexpr int GWM_T = 64;
+
+template <int R, int TY>
+__global__ __launch_bounds__(256) void bank_bwd_wm_k(const float* __restrict__ gy, const float* __restrict__ x,
+                                                     float* __restrict__ part, int F, int H, int W, int tiles_x,
+                                                     int tiles_img, int ntiles) {
+    constexpr int N = 2 * R + 1, NK = N * N, NT = (NK + 15) / 16;
+    constexpr int RA = (R + 3) & ~3, LW = GWM_T + 2 * RA, NR = GWM_T + 2 * R;
+    __shared__ __attribute__((aligned(16))) float s[NR * LW];
+    __shared__ float red[4][16][NT * 16];
+    const unsigned id = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = (int)id;
+    const int n = tile / tiles_img, ti = tile - n * tiles_img;
+    int x0, y0;
+    tile_origin(ti, tiles_x, GWM_T, GWM_T * TY, x0, y0);
+    const size_t hw = (size_t)H * W;
+    const float* xp = x + (size_t)n * hw;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int fl = lane & 15, q = lane >> 4;   // A row (filter) / B column (tap in block); pixel of the step
+    const bool frow = fl < F;
+    const float* g = gy + ((size_t)n * F + (frow ? fl : 0)) * hw;
+    int off[NT];   // LDS offset of this lane's tap (clamped into range for the padding columns)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int k = min(16 * t + fl, NK - 1);
+        off[t] = (k / N) * LW + (k % N) + RA - R;
+    }
+    v4f acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = mk4(0.f, 0.f, 0.f, 0.f);
+    // a row's 16 x 4 gy values; pixels outside the image (and filters past F) contribute 0.
+    // The load itself always reads a valid (clamped) address, so no lane branches around it.
+    auto gy_row = [&](int yy, float (&ga)[16]) {
+        const float* grow = g + (size_t)min(yy, H - 1) * W;
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            const int xx = x0 + 4 * st + q;
+            const float v = grow[min(xx, W - 1)];
+            ga[st] = (frow && xx < W && yy < H) ? v : 0.f;
+        }
+    };
+    for (int sub = 0; sub < TY; ++sub) {
+        const int ys = y0 + sub * GWM_T;
+        if (ys >= H) break;   // uniform over the work-group
+        if (sub) __syncthreads();
+        for (int idx = threadIdx.x; idx < NR * LW; idx += 256) {
+            const int rr = idx / LW, c = idx - rr * LW;
+            s[idx] = xp[(size_t)clampi(ys - R + rr, H) * W + clampi(x0 - RA + c, W)];
+        }
+        __syncthreads();
+        float ga[16], gb[16];
+        gy_row(ys + wave * 16, ga);
+#pragma unroll 1
+        for (int row = 0; row < 16; row += 2) {
+            const int py = wave * 16 + row;
+            gy_row(ys + py + 1, gb);   // the next row's gy in flight during this row's products
+#pragma unroll
+            for (int st = 0; st < 16; ++st) {
+                const int base = py * LW + 4 * st + q;
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[st], s[base + off[t]], acc[t], 0, 0, 0);
+            }
+            if (row + 2 < 16) gy_row(ys + py + 2, ga);
+#pragma unroll
+            for (int st = 0; st < 16; ++st) {
+                const int base = (py + 1) * LW + 4 * st + q;
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gb[st], s[base + off[t]], acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // lane holds D[4 (lane / 16) + i][16 t + lane % 16] in acc[t][i]
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[wave][4 * q + i][16 * t + fl] = acc[t][i];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 16 * NK; e += 256) {
+        const int f = e / NK, k = e - f * NK;
+        if (f >= F) continue;
+        const float v = ((red[0][f][k] + red[1][f][k]) + red[2][f][k]) + red[3][f][k];
+        part[((size_t)f * NK + k) * ntiles + tile] = v;
+    }
+}
+
+template <int R, int TY>
+hipError_t bwd_wm_RT(const BankArgs& a) {
+    const int tx = (a.w + GWM_T - 1) / GWM_T, ty = (a.h + GWM_T * TY - 1) / (GWM_T * TY);
+    const int ntiles = a.n * tx * ty;
+    float* part = static_cast<float*>(a.ws);
+    hipLaunchKernelGGL((bank_bwd_wm_k<R, TY>), dim3((unsigned)ntiles), dim3(256), 0, a.st, a.a, a.b, part, a.f, a.h,
+                       a.w, tx, tx * ty, ntiles);
+    const int nk = (2 * R + 1) * (2 * R + 1);
+    hipLaunchKernelGGL(bank_bwd_w2_k, dim3((unsigned)(a.f * nk)), dim3(256), 0, a.st, part, a.out, ntiles);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ launchers
 int bank_vec(const float* a, const float* b, int W) {
     return ((uintptr_t)a % 16 == 0) && ((uintptr_t)b % 16 == 0) && (W % 4 == 0);
@@ -849,7 +958,14 @@ hipError_t bwd_w4_R(const BankArgs& a) { return bwd_w4_RT<R, 1>(a); }
 template <int R>
 hipError_t bwd_w4x4_R(const BankArgs& a) { return bwd_w4_RT<R, 4>(a); }
 
+template <int R>
+hipError_t bwd_wm_R(const BankArgs& a) { return bwd_wm_RT<R, 1>(a); }
+template <int R>
+hipError_t bwd_wm4_R(const BankArgs& a) { return bwd_wm_RT<R, 4>(a); }
+
 hipError_t launch_bwd_w4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_w4_R) }
+hipError_t launch_bwd_wm(const BankArgs& a) { ICL_BANK_SWITCH(bwd_wm_R) }
+hipError_t launch_bwd_wm4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_wm4_R) }
 hipError_t launch_bwd_w4x4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_w4x4_R) }
 
 
@@ -858,6 +974,7 @@ bool supports_pers(const BankArgs& a) { return supports_bank(a) && a.f <= PERS_F
 bool supports_bwd_w(const BankArgs& a) {
     return supports_bank(a) && a.ws != nullptr && a.wsb >= bank_bwd_filter_workspace(a.n, a.f, a.h, a.w, a.r);
 }
+bool supports_bwd_wm(const BankArgs& a) { return supports_bwd_w(a) && a.f <= 16; }
 
 const Variant<BankArgs> kFwd[] = {{"plain", supports_bank, launch_fwd_plain},
                                    {"tile64_p4x4", supports_bank, launch_fwd},
@@ -867,7 +984,9 @@ const Variant<BankArgs> kBwdIn[] = {{"plain", supports_bank, launch_bwd_in_plain
                                     {"pers_p4x4_fold", supports_pers, launch_bwd_in_pers}};
 const Variant<BankArgs> kBwdW[] = {{"wave_t32x64", supports_bwd_w, launch_bwd_w},
                                    {"block4_t64", supports_bwd_w, launch_bwd_w4},
-                                   {"block4_t64x256", supports_bwd_w, launch_bwd_w4x4}};
+                                   {"block4_t64x256", supports_bwd_w, launch_bwd_w4x4},
+                                   {"mfma_t64", supports_bwd_wm, launch_bwd_wm},
+                                   {"mfma_t64x256", supports_bwd_wm, launch_bwd_wm4}};
 
 // ------------------------------------------------------------------ sum of squares loss
 constexpr int SSE_BLOCKS = 2048;
@@ -1069,7 +1188,7 @@ const Variant<BankArgs>* bank_bwd_filter_variants(int* count) {
 
 int bank_fwd_default(const BankArgs& a) { return supports_pers(a) ? 2 : 1; }
 int bank_bwd_input_default(const BankArgs& a) { return supports_pers(a) ? 2 : 1; }
-int bank_bwd_filter_default(const BankArgs&) { return 2; }   // block4_t64x256
+int bank_bwd_filter_default(const BankArgs& a) { return a.f <= 16 ? 3 : 2; }   // mfma_t64, else block4_t64x256
 const Variant<BankSseArgs>* bank_fwd_sse_variants(int* count) {
     *count = (int)(sizeof(kFwdSse) / sizeof(kFwdSse[0]));
     return kFwdSse;
