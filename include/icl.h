@@ -322,8 +322,9 @@ icl_status icl_sse_loss(const float* y, const float* t, float* gy, long long cou
  *   when gy != NULL, the forward output y written when y != NULL.
  * The training step of a learnable filter bank needs gy and L but not y, so with
  * y == NULL the 4-byte-per-element write of y and its re-read by the loss drop out.
- * y and gy are bit-identical to icl_bank_fwd followed by icl_sse_loss (every forward
- * variant sums the taps in the same order).  L is accumulated in float64 per
+ * y and gy are bit-identical to icl_bank_fwd followed by icl_sse_loss when both run
+ * variants of one family: the FMA variants all sum the taps in one order, the matrix-core
+ * (MFMA) variants in another (their results differ in rounding only).  L is accumulated in float64 per
  * work-group and summed in a fixed order, so it is reproducible run to run.
  *   workspace : icl_workspace_size(ICL_OP_BANK_FWD_SSE) bytes of device scratch
  *               (ICL_ERR_WORKSPACE if NULL or smaller).

@@ -141,15 +141,25 @@ def test_bank_forward_fused_with_loss(shape):
 
 @pytest.mark.parametrize("shape", [(2, 5, 70, 133, 4), (1, 16, 64, 64, 2), (1, 3, 33, 70, 3), (2, 2, 5, 3, 1)])
 def test_fused_outputs_equal_forward_then_loss(shape):
-    """Every forward variant sums the taps in the same order, so the fused y and gy are the
-    same bits as icl_bank_fwd followed by icl_sse_loss."""
+    """A fused variant sums the taps in the same order as the forward variant of its family
+    (the FMA variants all alike, the matrix-core variant its own way), so its y and gy are
+    the same bits as that forward followed by icl_sse_loss."""
     N, F, H, W, r = shape
     x, w, t = inputs(N, F, H, W, r, cfg=77)
     xt, wt, tt = cu(x), cu(w), cu(t)
-    y_ref = T.bank_fwd(xt, wt)
-    _, gy_ref = T.sse_loss(y_ref, tt)
+    fwd_names = B.variant_names(B.ICL_OP_BANK_FWD)
+    refs = {}
+    for fam in ("pers_p4x4", "mfma_t64"):
+        B.check(B.icl_force_variant(B.ICL_OP_BANK_FWD, fwd_names.index(fam)))
+        try:
+            y_ref = T.bank_fwd(xt, wt)
+        finally:
+            B.icl_force_variant(B.ICL_OP_BANK_FWD, -1)
+        refs[fam] = (y_ref, T.sse_loss(y_ref, tt)[1])
+    sse_names = B.variant_names(B.ICL_OP_BANK_FWD_SSE)
     for v in each_variant(B.ICL_OP_BANK_FWD_SSE):
         _, gy, y = T.bank_fwd_sse(xt, wt, tt, want_y=True)
+        y_ref, gy_ref = refs["mfma_t64" if sse_names[v].startswith("mfma") else "pers_p4x4"]
         assert torch.equal(y, y_ref), f"variant {v}: y"
         assert torch.equal(gy, gy_ref), f"variant {v}: gy"
 
