@@ -1029,6 +1029,20 @@ __global__ __launch_bounds__(256) void bank_fwd_mfma_k(const float* __restrict__
 #pragma unroll 1
         for (int row = 0; row < 16; ++row) {
             const int py = wave * 16 + row;
+            const int yg = y0 + py;
+            // the lane's 4 x 4 targets, loaded before the products so that their latency hides
+            // under the matrix work (a valid clamped address, zero weight outside the image)
+            float tv[4][4];
+            if constexpr (SSE) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int f = min(4 * kq + i, F - 1);
+                        const int xg = min(x0 + 16 * c + j, W - 1);
+                        tv[c][i] = tg[((size_t)n * F + f) * hw + (size_t)min(yg, H - 1) * W + xg];
+                    }
+            }
             v4f acc[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[c] = mk4(0.f, 0.f, 0.f, 0.f);
@@ -1038,7 +1052,6 @@ __global__ __launch_bounds__(256) void bank_fwd_mfma_k(const float* __restrict__
                 for (int c = 0; c < 4; ++c)
                     acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st], s[py * LW + 16 * c + j + off[st]], acc[c],
                                                                   0, 0, 0);
-            const int yg = y0 + py;
             if (yg >= H) continue;
             float ssum = 0.f;
 #pragma unroll
@@ -1051,7 +1064,7 @@ __global__ __launch_bounds__(256) void bank_fwd_mfma_k(const float* __restrict__
                     if (f >= F) continue;
                     const size_t q = ((size_t)n * F + f) * hw + (size_t)yg * W + xg;
                     if constexpr (SSE) {
-                        const float d = acc[c][i] - tg[q];
+                        const float d = acc[c][i] - tv[c][i];
                         ssum = fmaf(d, d, ssum);
                         if (gy) gy[q] = 2.f * d;
                         if (y) y[q] = acc[c][i];
@@ -1314,8 +1327,6 @@ const Variant<BankSseArgs>* bank_fwd_sse_variants(int* count) {
     *count = (int)(sizeof(kFwdSse) / sizeof(kFwdSse[0]));
     return kFwdSse;
 }
-// the fused loss keeps the FMA forward: its float4 target and gradient blocks beat the matrix
-// core variant's per-filter epilogue (2.0 ms against 1.37 ms at 32 x 16 x 1024^2, r = 4)
-int bank_fwd_sse_default(const BankSseArgs& a) { return supports_sse_pers(a) ? 1 : 0; }
+int bank_fwd_sse_default(const BankSseArgs& a) { return supports_sse_mfma(a) ? 3 : supports_sse_pers(a) ? 1 : 0; }
 
 }  // namespace icl
