@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libicl.so")
 
-SOURCES = ["api.hip", "conv_sep.hip", "conv2d.hip", "conv2d_u8.hip", "conv3d.hip", "harris.hip", "nms.hip", "corners.hip", "batched.hip", "bank.hip",
+SOURCES = ["api.hip", "conv_sep.hip", "conv2d.hip", "conv2d_mfma.hip", "conv2d_u8.hip", "conv3d.hip", "harris.hip", "nms.hip", "corners.hip", "batched.hip", "bank.hip",
            "tuner.hip", "perf_model.hip"]
 
 ARCH = os.environ.get("ICL_OFFLOAD_ARCH", "gfx950")

@@ -341,6 +341,7 @@ const Variant<Conv2dArgs> kConv2d[] = {
     {"pers_p8x2", supports_lds, launch_pers<8, 2>},
     {"pers_p4x2", supports_lds, launch_pers<4, 2>},
     {"pers_p8x4", supports_lds, launch_pers<8, 4>},
+    {"mfma_f16x3", supports_conv2d_mfma, launch_conv2d_mfma},
 };
 
 }  // namespace

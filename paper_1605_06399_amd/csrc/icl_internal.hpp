@@ -127,6 +127,8 @@ const Variant<BankSseArgs>* bank_fwd_sse_variants(int* count);
 // Default choice when neither a forced variant nor a tune-cache entry applies.
 int sep_default(const SepArgs&);
 int conv2d_default(const Conv2dArgs&);
+bool supports_conv2d_mfma(const Conv2dArgs&);       // the matrix-core variant (conv2d_mfma.hip)
+hipError_t launch_conv2d_mfma(const Conv2dArgs&);
 int conv2d_u8_default(const U8Args&);
 int harris_default(const HarrisArgs&);
 int nms_default(const NmsArgs&);

@@ -219,3 +219,51 @@ def test_tuner_selects_a_valid_variant(tmp_path):
     st, idx = B.icl_selected_variant(B.ICL_OP_CONV2D, B.ICL_F32, 3, W, H)
     assert idx >= 1
     B.icl_tune_clear()
+
+
+def _mfma_index():
+    names = B.variant_names(B.ICL_OP_CONV2D)
+    return names.index("mfma_f16x3") if "mfma_f16x3" in names else None
+
+
+@pytest.mark.parametrize("r", [3, 7])
+@pytest.mark.parametrize("img_exp,tap_exp", [(60, 0), (-60, 0), (0, 40), (-100, -20), (90, 20)])
+def test_mfma_variant_power_of_two_scaling(force, r, img_exp, tap_exp):
+    """The matrix-core variant scales each tile and the taps by powers of two: inputs far from
+    float16's range give the same normwise error as unit-range ones."""
+    idx = _mfma_index()
+    if idx is None:
+        pytest.skip("no matrix-core variant")
+    force(B.ICL_OP_CONV2D, idx)
+    H, W = 150, 210
+    img = np.ldexp(synth.image_uniform(49, H, W).astype(np.float64) - 0.5, img_exp).astype(np.float32)
+    w = np.ldexp(taps_2d(r).astype(np.float64), tap_exp).astype(np.float32)
+    xd, x64 = storage(img, "f32")
+    out = T.conv2d(xd, dev_taps(w).view(w.shape))
+    torch.cuda.synchronize()
+    w64 = w.astype(np.float64)
+    assert_close(out, oracle.conv2d(x64, w64), oracle.normwise_scale_conv2d(x64, w64), "f32", f"mfma 2^{img_exp} 2^{tap_exp}")
+
+
+@pytest.mark.parametrize("r", [2, 7])
+def test_mfma_variant_wide_range_bound(force, r):
+    """Dark regions 2^-30 below a bright one in the same tile: every output is within the
+    variant's stated operand bound 2^-20 S + 2^-37 (2r+1)^2 M max|w| (plus the float32
+    accumulation allowance 1e-5 S of every variant)."""
+    idx = _mfma_index()
+    if idx is None:
+        pytest.skip("no matrix-core variant")
+    force(B.ICL_OP_CONV2D, idx)
+    H, W = 130, 200
+    img = synth.image_uniform(50, H, W).astype(np.float64)
+    img[:, W // 2:] *= 2.0 ** -30
+    img = img.astype(np.float32)
+    w = taps_2d(r)
+    xd, x64 = storage(img, "f32")
+    out = to_host(T.conv2d(xd, dev_taps(w).view(w.shape)))
+    w64 = w.astype(np.float64)
+    ref = oracle.conv2d(x64, w64)
+    S = oracle.normwise_scale_conv2d(x64, w64)
+    M = float(np.abs(x64).max())
+    bound = 1e-5 * S + 2.0 ** -20 * S + 2.0 ** -37 * (2 * r + 1) ** 2 * M * float(np.abs(w64).max())
+    assert np.all(np.abs(out - ref) <= bound)
