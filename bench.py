@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP32_FMA_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, packed FP32 disabled
 FP32_PACKED_PEAK_TFLOPS = 157.3
+FP16_MFMA_PEAK_TFLOPS = 2500.0  # dense FP16 matrix cores, published
 EXTRAS = ("corner", "batch", "bank", "paper", "tuner", "volume")
 INT_DOT2_PEAK_TMACS = 78.6     # v_dot2_i32_i16: 2 int16 MACs per lane per issue, 256 CU x 64 lanes x 2.4 GHz
 METRIC = "Gpixel/s & % HBM peak, autotuned vs plain kernel; fwd+bwd Gpixel/s"
@@ -67,7 +68,7 @@ def roof_gpx(kind, r, bytes_px=8.0):
 
 
 # kernel source files per call kind: traffic figures are valid only for the source they were taken on
-KERNEL_SOURCES = {"2d": ["conv2d.hip", "tile_stage.hpp", "corr_tile.hpp", "icl_device.hpp"],
+KERNEL_SOURCES = {"2d": ["conv2d.hip", "conv2d_mfma.hip", "tile_stage.hpp", "corr_tile.hpp", "icl_device.hpp"],
                   "sep": ["conv_sep.hip", "sep_tile.hpp", "sep_strip.hpp", "tile_stage.hpp", "icl_device.hpp"]}
 
 
@@ -98,6 +99,7 @@ def kernel_variant(name):
     import re
     pats = [("2d", r"conv2d_pers<icl::F32, (\d+), (\d+), (\d+)>", "pers_p{1}x{2}"),
             ("2d", r"conv2d_lds<icl::F32, (\d+), (\d+), (\d+), (\d+)>", "lds_p{1}x{2}_o{3}"),
+            ("2d", r"conv2d_mfma_k<icl::F32, (\d+)>", "mfma_f16x3"),
             ("sep", r"sep_pers<icl::F32, (\d+), (\d+), (\d+)>", "pers_t{1}_c{2}"),
             ("sep", r"sep_fused<icl::F32, (\d+), (\d+), (\d+)>", "fused_t{1}_c{2}"),
             ("sep", r"sep_strip<icl::F32, (\d+), (\d+)>", "strip_t{1}")]
@@ -251,6 +253,8 @@ def main():
         us, usp = per_tuned[(kind, r)], per_plain[(kind, r)]
         gpx = px / (us * 1e-6) / 1e9
         roof, bound = roof_gpx(kind, r)
+        if chosen[f"{kind}{r}"].startswith("mfma"):
+            roof, bound = FP16_MFMA_PEAK_TFLOPS * 1e3 / flops_per_px(kind, r), "mfma"
         per_op.append({"call": f"{kind}{r}", "variant": chosen[f"{kind}{r}"], "us": round(us, 2),
                        "gpx_s": round(gpx, 1), "hbm_frac": round(gpx * 8 / HBM_PEAK_GBS, 3),
                        "binding_roof": bound, "roof_frac": round(gpx / roof, 3),
@@ -259,7 +263,17 @@ def main():
     kind, r = dom
     us = per_tuned[dom]
     _, bound = roof_gpx(kind, r)
-    if bound == "alu":
+    if chosen[f"{kind}{r}"].startswith("mfma"):
+        # the matrix-core variant: FP16 MFMAs (hi/lo split) against the dense FP16 matrix peak;
+        # executed = 3 products x 2 flop x 32 band columns x (2r+1) tap rows per pixel
+        achieved = flops_per_px(kind, r) * px / (us * 1e-6) / 1e12
+        executed = 3 * 2 * 32 * (2 * r + 1) * px
+        roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP16_MFMA_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP16_MFMA_PEAK_TFLOPS, 4),
+                    "executed_flops_per_launch": executed,
+                    "executed_frac": round(executed / (us * 1e-6) / 1e12 / FP16_MFMA_PEAK_TFLOPS, 3),
+                    "hbm_frac": round(8.0 * px / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 3)}
+    elif bound == "alu":
         achieved = flops_per_px(kind, r) * px / (us * 1e-6) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_FMA_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / FP32_FMA_PEAK_TFLOPS, 3)}
