@@ -65,8 +65,10 @@ __device__ __forceinline__ float block_max(float v, float* red) {
 // ldexpf, so an exponent beyond the float range (subnormal m) is still applied exactly.
 __device__ __forceinline__ int pow2_exp(float m) { return m > 0.f ? 13 - ilogbf(m) : 0; }
 
+// Up to r = 5 the LDS tile leaves room for three work-groups per CU, so the register budget is
+// set for three waves per SIMD; wider windows keep two.
 template <class T, int R>
-__global__ __launch_bounds__(256) void conv2d_mfma_k(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
+__global__ __launch_bounds__(256, (R <= 5 ? 3 : 2)) void conv2d_mfma_k(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
                                                      size_t dp, int W, int H, const float* __restrict__ taps,
                                                      int tiles_x, int tiles_y, int vec_in, Border bd) {
     using G = MTile<R>;
