@@ -48,6 +48,19 @@ struct Stage {
     // `aligned` (rows 4-pixel aligned in memory).
     __device__ __forceinline__ void load(const void* __restrict__ src, size_t sp, int W, int H, int gx0, int gy0,
                                          bool aligned, Border bd = {}) {
+        // A tile that lies inside the image (the work-group's usual case) takes straight vector
+        // loads: no branch between them, so they are all in flight together.  The general path
+        // below branches per chunk, and the compiler then waits on each chunk's loads.
+        if (aligned && gx0 >= 0 && gx0 + LW <= W && gy0 >= 0 && gy0 + NR <= H) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const int idx = (int)threadIdx.x + 256 * k;
+                if (N * 256 != NR * C4 && idx >= NR * C4) break;
+                const int rr = idx / C4, c4 = idx - rr * C4;
+                v[k] = load4<T>(src, (size_t)(gy0 + rr) * sp + (size_t)(gx0 + 4 * c4) * T::size);
+            }
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             const int idx = (int)threadIdx.x + 256 * k;
