@@ -54,14 +54,25 @@ __device__ __forceinline__ void stage_plane(const float* __restrict__ plane, int
     constexpr int LW = G::LW, NR = G::NR, RA = G::RA;
     const int tid = threadIdx.x;
     if (vec && x0 - RA >= 0 && x0 + BT + RA <= W) {
-        constexpr int C4 = LW / 4;
-        for (int idx = tid; idx < NR * C4; idx += 256) {
+        // all loads first (from the clamped row), then the zero rows and the LDS writes: a
+        // load-then-write loop would wait on each load in turn
+        constexpr int C4 = LW / 4, NCH = NR * C4, PER = (NCH + 255) / 256;
+        v4f v[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = tid + 256 * i;
+            if (NCH % 256 != 0 && idx >= NCH) break;
+            const int rr = idx / C4, c4 = idx - rr * C4;
+            v[i] = *reinterpret_cast<const v4f*>(plane + (size_t)clampi(y0 - R + rr, H) * W + (x0 - RA + 4 * c4));
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = tid + 256 * i;
+            if (NCH % 256 != 0 && idx >= NCH) break;
             const int rr = idx / C4, c4 = idx - rr * C4;
             const int yy = y0 - R + rr;
-            v4f v;
-            if (ZERO_PAD && (yy < 0 || yy >= H)) v = mk4(0.f, 0.f, 0.f, 0.f);
-            else v = *reinterpret_cast<const v4f*>(plane + (size_t)clampi(yy, H) * W + (x0 - RA + 4 * c4));
-            lds4(&s[rr * LW + 4 * c4], v);
+            if (ZERO_PAD && (yy < 0 || yy >= H)) v[i] = mk4(0.f, 0.f, 0.f, 0.f);
+            lds4(&s[rr * LW + 4 * c4], v[i]);
         }
     } else {
         for (int idx = tid; idx < NR * LW; idx += 256) {

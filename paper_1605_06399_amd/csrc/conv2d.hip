@@ -90,14 +90,25 @@ __global__ __launch_bounds__(256) void conv2d_lds(const void* __restrict__ src, 
     const int y0 = (int)(t / (unsigned)tiles_x) * TH;
 
     if (vec_ok && x0 - RA >= 0 && x0 + TW + RA <= W) {
-        constexpr int C4 = LW / 4;
-        for (int idx = tid; idx < NR * C4; idx += 256) {
+        // all loads first (rows clamped), then the constant rows and the LDS writes: a
+        // load-then-write loop would wait on each load in turn
+        constexpr int C4 = LW / 4, NCH = NR * C4, PER = (NCH + 255) / 256;
+        v4f v[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = tid + 256 * i;
+            if (NCH % 256 != 0 && idx >= NCH) break;
+            const int rr = idx / C4, c4 = idx - rr * C4;
+            v[i] = load4<T>(src, (size_t)clampi(y0 - R + rr, H) * sp + (size_t)(x0 - RA + 4 * c4) * T::size);
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = tid + 256 * i;
+            if (NCH % 256 != 0 && idx >= NCH) break;
             const int rr = idx / C4, c4 = idx - rr * C4;
             const int yy = y0 - R + rr;
-            const v4f v = (bd.constant && (yy < 0 || yy >= H))
-                              ? mk4(bd.value, bd.value, bd.value, bd.value)
-                              : load4<T>(src, (size_t)clampi(yy, H) * sp + (size_t)(x0 - RA + 4 * c4) * T::size);
-            lds4(&in_s[rr * LW + 4 * c4], v);
+            if (bd.constant && (yy < 0 || yy >= H)) v[i] = mk4(bd.value, bd.value, bd.value, bd.value);
+            lds4(&in_s[rr * LW + 4 * c4], v[i]);
         }
     } else {
         for (int idx = tid; idx < NR * LW; idx += 256) {
