@@ -45,6 +45,40 @@ template <int R> struct BankTile {
     static constexpr int WIN = BPX + 2 * RA;
 };
 
+// Stage NR rows x LW columns of a dense W-wide plane, top-left pixel (xs, ys), clamped, into
+// s[NR * LW].  A tile inside the image in x with 16-byte aligned rows issues all its float4
+// loads before the LDS writes (a load-then-write loop would wait on each load in turn); edge
+// tiles go element by element.
+template <int NR, int LW>
+__device__ __forceinline__ void stage_clamped(const float* __restrict__ xp, int W, int H, int xs, int ys,
+                                              float* __restrict__ s) {
+    const int tid = threadIdx.x;
+    if ((W & 3) == 0 && ((uintptr_t)xp & 15) == 0 && (xs & 3) == 0 && xs >= 0 && xs + LW <= W) {
+        static_assert(LW % 4 == 0, "vector staging needs whole float4 rows");
+        constexpr int C4 = LW / 4, NCH = NR * C4, PER = (NCH + 255) / 256;
+        v4f v[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = tid + 256 * i;
+            if (NCH % 256 != 0 && idx >= NCH) break;
+            const int rr = idx / C4, c4 = idx - rr * C4;
+            v[i] = *reinterpret_cast<const v4f*>(xp + (size_t)clampi(ys + rr, H) * W + xs + 4 * c4);
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = tid + 256 * i;
+            if (NCH % 256 != 0 && idx >= NCH) break;
+            const int rr = idx / C4, c4 = idx - rr * C4;
+            lds4(&s[rr * LW + 4 * c4], v[i]);
+        }
+        return;
+    }
+    for (int idx = tid; idx < NR * LW; idx += 256) {   // edge tiles
+        const int rr = idx / LW, c = idx - rr * LW;
+        s[idx] = xp[(size_t)clampi(ys + rr, H) * W + clampi(xs + c, W)];
+    }
+}
+
 // Stage rows y0-R .. y0+BT+R-1 and columns x0-RA .. x0+BT+RA-1 of a dense W-wide
 // plane into LDS.  ZERO_PAD: outside pixels read as 0; otherwise clamped.
 template <int R, bool ZERO_PAD>
@@ -54,25 +88,14 @@ __device__ __forceinline__ void stage_plane(const float* __restrict__ plane, int
     constexpr int LW = G::LW, NR = G::NR, RA = G::RA;
     const int tid = threadIdx.x;
     if (vec && x0 - RA >= 0 && x0 + BT + RA <= W) {
-        // all loads first (from the clamped row), then the zero rows and the LDS writes: a
-        // load-then-write loop would wait on each load in turn
-        constexpr int C4 = LW / 4, NCH = NR * C4, PER = (NCH + 255) / 256;
-        v4f v[PER];
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int idx = tid + 256 * i;
-            if (NCH % 256 != 0 && idx >= NCH) break;
-            const int rr = idx / C4, c4 = idx - rr * C4;
-            v[i] = *reinterpret_cast<const v4f*>(plane + (size_t)clampi(y0 - R + rr, H) * W + (x0 - RA + 4 * c4));
-        }
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int idx = tid + 256 * i;
-            if (NCH % 256 != 0 && idx >= NCH) break;
+        constexpr int C4 = LW / 4;
+        for (int idx = tid; idx < NR * C4; idx += 256) {
             const int rr = idx / C4, c4 = idx - rr * C4;
             const int yy = y0 - R + rr;
-            if (ZERO_PAD && (yy < 0 || yy >= H)) v[i] = mk4(0.f, 0.f, 0.f, 0.f);
-            lds4(&s[rr * LW + 4 * c4], v[i]);
+            v4f v;
+            if (ZERO_PAD && (yy < 0 || yy >= H)) v = mk4(0.f, 0.f, 0.f, 0.f);
+            else v = *reinterpret_cast<const v4f*>(plane + (size_t)clampi(yy, H) * W + (x0 - RA + 4 * c4));
+            lds4(&s[rr * LW + 4 * c4], v);
         }
     } else {
         for (int idx = tid; idx < NR * LW; idx += 256) {
@@ -721,9 +744,13 @@ __global__ __launch_bounds__(256) void bank_bwd_w4_k(const float* __restrict__ g
         const int ys = y0 + sub * GW4_T;
         if (ys >= H) break;   // uniform over the work-group
         if (sub) __syncthreads();   // the previous sub-tile is consumed
-        for (int idx = threadIdx.x; idx < NR * LW; idx += 256) {
-            const int rr = idx / LW, c = idx - rr * LW;
-            s[idx] = xp[(size_t)clampi(ys - R + rr, H) * W + clampi(x0 - RA + c, W)];
+        if constexpr (TY == 1) {
+            stage_clamped<NR, LW>(xp, W, H, x0 - RA, ys - R, s);
+        } else {   // accumulators live across the sub-tiles leave no registers for a batch of loads
+            for (int idx = threadIdx.x; idx < NR * LW; idx += 256) {
+                const int rr = idx / LW, c = idx - rr * LW;
+                s[idx] = xp[(size_t)clampi(ys - R + rr, H) * W + clampi(x0 - RA + c, W)];
+            }
         }
         __syncthreads();
         if (!live) continue;
@@ -815,9 +842,13 @@ __global__ __launch_bounds__(256) void bank_bwd_wm_k(const float* __restrict__ g
         const int ys = y0 + sub * GWM_T;
         if (ys >= H) break;   // uniform over the work-group
         if (sub) __syncthreads();
-        for (int idx = threadIdx.x; idx < NR * LW; idx += 256) {
-            const int rr = idx / LW, c = idx - rr * LW;
-            s[idx] = xp[(size_t)clampi(ys - R + rr, H) * W + clampi(x0 - RA + c, W)];
+        if constexpr (TY == 1) {
+            stage_clamped<NR, LW>(xp, W, H, x0 - RA, ys - R, s);
+        } else {   // accumulators live across the sub-tiles leave no registers for a batch of loads
+            for (int idx = threadIdx.x; idx < NR * LW; idx += 256) {
+                const int rr = idx / LW, c = idx - rr * LW;
+                s[idx] = xp[(size_t)clampi(ys - R + rr, H) * W + clampi(x0 - RA + c, W)];
+            }
         }
         __syncthreads();
         float ga[16], gb[16];
