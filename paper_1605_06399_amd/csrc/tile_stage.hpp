@@ -7,6 +7,8 @@
 // writes the registers to LDS.  Reads outside the image follow the boundary: clamp or a
 // constant (Border), or zero with ZERO_PAD.
 #pragma once
+#include <type_traits>
+
 #include "icl_device.hpp"
 
 namespace icl {
@@ -147,7 +149,9 @@ namespace icl {
 template <class T, int NRMAX>
 struct RStage {
     static constexpr int K = (NRMAX + 7) / 8;
+    static constexpr bool BF = std::is_same<T, BF16>::value;
     v4f v[K];
+    bool raw = false;   // bfloat16 fast path: v[k].x, .y hold the four packed values, unpacked at store
 
     // vec: rows 4-pixel aligned in memory (gx0 a multiple of 4)
     __device__ __forceinline__ void load(const void* __restrict__ src, size_t sp, int W, int H, int gx0, int gy0,
@@ -155,6 +159,26 @@ struct RStage {
         const int c4 = threadIdx.x & 31, ry = threadIdx.x >> 5;
         if (c4 >= C4) return;
         const int x = gx0 + 4 * c4;
+        raw = false;
+        // inside the image: straight vector loads, all in flight together (bfloat16 stays
+        // packed until the LDS store, which keeps the registers of the walk in check)
+        if (vec && gx0 >= 0 && gx0 + 4 * C4 <= W && gy0 >= 0 && gy0 + NR <= H) {
+            raw = BF;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int rr = ry + 8 * k;
+                if (rr >= NR) break;
+                const size_t off = (size_t)(gy0 + rr) * sp + (size_t)x * T::size;
+                if constexpr (BF) {
+                    const v2u u = *reinterpret_cast<const v2u*>(static_cast<const char*>(src) + off);
+                    v[k].x = __uint_as_float(u.x);
+                    v[k].y = __uint_as_float(u.y);
+                } else {
+                    v[k] = load4<T>(src, off);
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int rr = ry + 8 * k;
@@ -170,7 +194,13 @@ struct RStage {
         for (int k = 0; k < K; ++k) {
             const int rr = ry + 8 * k;
             if (rr >= NR) break;
-            lds4(&s[rr * 4 * C4 + 4 * c4], v[k]);
+            v4f e = v[k];
+            if (BF && raw) {
+                const unsigned a = __float_as_uint(v[k].x), b = __float_as_uint(v[k].y);
+                e = mk4(__uint_as_float(a << 16), __uint_as_float(a & 0xffff0000u), __uint_as_float(b << 16),
+                        __uint_as_float(b & 0xffff0000u));
+            }
+            lds4(&s[rr * 4 * C4 + 4 * c4], e);
         }
     }
 };
