@@ -132,10 +132,9 @@ def write_traffic(fetch_csv, write_csv, side=4096):
                      "dispatch, mean over dispatches), each scaled by the factor that maps the same counter on a "
                      "1 GiB device-to-device copy to 1 GiB; source_hash covers the kernel's source files and "
                      "bench.py reports traffic only while it matches.",
-           "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_fetch -o fetch -- "
-                        "python3 bench.py --only 2d7,sep7 --steps 3 --warmup 1 --no-extras --no-cpu --calib-copy",
-                        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_write -o write -- "
-                        "python3 bench.py --only 2d7,sep7 --steps 3 --warmup 1 --no-extras --no-cpu --calib-copy"],
+           "commands": [f"rocprofv3 --pmc {ctr} --output-format csv -d {os.path.dirname(csv_path)} -o {tag} -- "
+                        "python3 bench.py --only 2d7,sep7 --steps 3 --warmup 1 --no-extras --no-cpu --calib-copy"
+                        for ctr, csv_path, tag in (("FETCH_SIZE", fetch_csv, "fetch"), ("WRITE_SIZE", write_csv, "write"))],
            "calibration": {"fetch_factor": round(fcal, 4), "write_factor": round(wcal, 4),
                            "copy_fetch_kib": [round(v, 1) for v in cf], "copy_write_kib": [round(v, 1) for v in cw]}}
     for k in fe:
@@ -160,8 +159,8 @@ def main():
         write_traffic(*a.write_traffic, side=a.side)
         return
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU design is "
-              "described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); sharding over several GPUs "
+              "is a design, not part of this library.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1605_06399_amd import binding as B, synth

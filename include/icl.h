@@ -59,7 +59,7 @@ typedef enum icl_status {
     ICL_ERR_WORKSPACE = 6,     /* workspace missing or smaller than icl_workspace_size() */
     ICL_ERR_NO_DEVICE = 7,     /* no HIP device visible */
     ICL_ERR_HIP = 8,           /* a HIP runtime call failed (see icl_last_hip_error) */
-    ICL_ERR_UNSUPPORTED = 9,   /* valid request this build does not implement */
+    ICL_ERR_UNSUPPORTED = 9,   /* valid request the library does not implement */
     ICL_ERR_TUNE_CACHE = 10    /* tune cache unreadable or written for another device */
 } icl_status;
 
@@ -302,7 +302,7 @@ void icl_graph_destroy(void* exec);
  *   forward      y[n,f,p]  = sum_k w[f,k] x[n, clamp(p+k)]
  *   input grad   gx[n,q]   = sum over (f, p, k) with clamp(p+k) = q of w[f,k] gy[n,f,p]
  *   filter grad  gw[f,k]   = sum_{n,p} gy[n,f,p] x[n, clamp(p+k)]   (fixed-order reduction)
- * radius in [1, 4] and f in [1, 64] for this build. */
+ * radius in [1, 4] and f in [1, 64]. */
 icl_status icl_bank_fwd(const float* x, const float* w, float* y, int n, int f, int h, int wd,
                         int radius, void* stream);
 icl_status icl_bank_bwd_input(const float* gy, const float* w, float* gx, int n, int f, int h, int wd,
