@@ -119,21 +119,43 @@ __global__ __launch_bounds__(256) void harris_fused(const float* __restrict__ sr
     const int y0 = (int)(t / (unsigned)tiles_x) * TH;
 
     // 1. stage image rows y0-HX .. y0+TH+HX-1, columns x0-HXA .. x0+TW+HXA-1 (clamped)
+    // every load is issued before the LDS writes (a load-then-write loop would wait on each)
     if (vec_ok && x0 - HXA >= 0 && x0 + TW + HXA <= W) {
-        constexpr int C4 = IW / 4;
-        for (int idx = tid; idx < IR * C4; idx += 256) {
+        constexpr int C4 = IW / 4, NCH = IR * C4, PER = (NCH + 255) / 256;
+        v4f v[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = tid + 256 * i;
+            if (NCH % 256 != 0 && idx >= NCH) break;
             const int rr = idx / C4, c4 = idx - rr * C4;
             const int y = clampi(y0 - HX + rr, H);
-            lds4(&img[rr * IW + 4 * c4], *reinterpret_cast<const v4f*>(
-                reinterpret_cast<const char*>(src) + (size_t)y * sp + (size_t)(x0 - HXA + 4 * c4) * 4));
+            v[i] = *reinterpret_cast<const v4f*>(reinterpret_cast<const char*>(src) + (size_t)y * sp +
+                                                 (size_t)(x0 - HXA + 4 * c4) * 4);
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = tid + 256 * i;
+            if (NCH % 256 != 0 && idx >= NCH) break;
+            const int rr = idx / C4, c4 = idx - rr * C4;
+            lds4(&img[rr * IW + 4 * c4], v[i]);
         }
     } else {
-        for (int idx = tid; idx < IR * IW; idx += 256) {
+        constexpr int NE = IR * IW, PER = (NE + 255) / 256;
+        float v[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = tid + 256 * i;
+            if (NE % 256 != 0 && idx >= NE) break;
             const int rr = idx / IW, c = idx - rr * IW;
             const int y = clampi(y0 - HX + rr, H);
             const int x = clampi(x0 - HXA + c, W);
-            img[rr * IW + c] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(src) +
-                                                               (size_t)y * sp + (size_t)x * 4);
+            v[i] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(src) + (size_t)y * sp + (size_t)x * 4);
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = tid + 256 * i;
+            if (NE % 256 != 0 && idx >= NE) break;
+            img[idx] = v[i];
         }
     }
     __syncthreads();
