@@ -30,8 +30,9 @@
  *  - Input and output images must not overlap (ICL_ERR_ALIAS): the paper's
  *    language forbids aliasing and local-memory staging needs read-only inputs
  *    (Section 5.2, memory spaces).
- *  - Arithmetic is float32 with float32 accumulation; float16 / bfloat16 storage
- *    is decoded exactly on load and rounded to nearest even on store.
+ *  - Arithmetic is float32 with float32 accumulation (unless the caller opts into
+ *    ICL_MATH_F16_SPLIT, see icl_set_math); float16 / bfloat16 storage is decoded
+ *    exactly on load and rounded to nearest even on store.
  *  - width == 0 or height == 0 is an empty image: the call returns ICL_OK and
  *    touches nothing.  Negative sizes are ICL_ERR_INVALID_VALUE.
  *  - Errors: arguments are checked on the host before anything is launched and
@@ -281,6 +282,15 @@ typedef struct icl_batch_plan icl_batch_plan;   /* opaque */
  * capture-safe).  All images share `dtype`. */
 icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dtype dtype,
                                  icl_batch_plan** plan /* host out */);
+/* The auto-tuner for a plan (the paper's Section 4 search, per device): runs each walk of
+ * the plan (tile shapes and orders, the strip walk) on the plan's own buffers, rejects a
+ * walk whose output differs from the default walk's, times the rest with HIP events and
+ * keeps the fastest for this plan; later icl_conv_sep_batched calls (and graphs created
+ * after it) launch that walk.  It writes the plan's outputs, allocates, synchronises and
+ * must not be called during stream capture.  A forced variant still takes precedence. */
+icl_status icl_batch_plan_tune(icl_batch_plan* plan, void* stream);
+/* Variant (walk) index icl_conv_sep_batched would launch for this plan (host out). */
+icl_status icl_batch_plan_variant(const icl_batch_plan* plan, int* index);
 /* One persistent launch over the plan's tiles.  Allocates nothing: capture-safe. */
 icl_status icl_conv_sep_batched(const icl_batch_plan* plan, void* stream);
 /* Number of tiles and total pixels of a plan (host out pointers, either may be NULL). */
@@ -345,6 +355,25 @@ icl_status icl_bank_fwd_sse(const float* x, const float* w, const float* t, floa
  * time, so a search costs only run time.
  * icl_tune allocates, synchronises and must not be called during stream capture. */
 icl_status icl_tune(icl_op op, icl_dtype dtype, int radius, int width, int height, void* stream);
+
+/* A problem for tuning and selection when more than the image size matters:
+ *   depth : slices of a volume (ICL_OP_CONV3D_SEP)
+ *   n, f  : batch and filter counts of the filter-bank ops (ICL_OP_BANK_*); width and
+ *           height are then the image width and height
+ * Unused fields are 0 or 1.  The cache keys on (op, dtype, radius, floor(log2(width *
+ * height * depth * n)), f, icl_get_math()), so the later calls of the same problem class
+ * pick the tuned variant.  icl_tune(op, ...) is icl_tune_problem with depth = n = f = 1.
+ * ICL_ERR_INVALID_VALUE for a null pointer or sizes below 1; ranges as the operation's. */
+typedef struct icl_problem {
+    icl_op op;
+    icl_dtype dtype;
+    int radius;
+    int width, height;
+    int depth, n, f;
+} icl_problem;
+icl_status icl_tune_problem(const icl_problem* problem, void* stream);
+/* Variant the next call of this problem would launch (host out). */
+icl_status icl_selected_variant_problem(const icl_problem* problem, int* index);
 /* Persist / reload the cache (JSON).  path NULL = $ICL_TUNE_CACHE or ~/.cache/icl/tune.json. */
 /* The paper's model-guided search (Section 4) over the same candidates: time `samples`
  * randomly chosen candidates (seeded), fit a small neural-network model of log execution
@@ -365,9 +394,42 @@ icl_status icl_tune_model(icl_op op, icl_dtype dtype, int radius, int width, int
 icl_status icl_perf_model_fit_predict(const double* X, const double* y, int n, int d, const double* Xq, int nq,
                                       double* yq, int hidden, int iters, unsigned long long seed);
 
+/* Arithmetic of the variants that tuning and default selection may pick.
+ *   ICL_MATH_F32 (the default): only variants with float32 products and float32
+ *     accumulation (vector FMA or the float32 matrix instructions), so every
+ *     result meets the float32 error model of the conventions above.
+ *   ICL_MATH_F16_SPLIT: also the matrix-core 2-D correlation ("mfma_f16x3") that
+ *     splits each float32 operand into float16 hi + lo parts and adds three
+ *     float16 products with float32 accumulation.  Besides float32 rounding its
+ *     result errs by up to 2^-37 (2r+1)^2 M max|w| per pixel, M the largest |src|
+ *     of the 64x64 tile holding the pixel: windows far darker than their tile's
+ *     brightest pixel (about 2^20 below it) keep fewer bits than float32.  A
+ *     caller opts in when its images have no such contrast.
+ * The mode is process-wide.  Tune-cache entries are keyed by it, so a variant tuned
+ * under one mode is never selected under the other; a forced variant
+ * (icl_force_variant) runs whatever the mode.  ICL_ERR_INVALID_VALUE for another
+ * value.  Not thread-safe against calls running concurrently on other threads. */
+typedef enum icl_math { ICL_MATH_F32 = 0, ICL_MATH_F16_SPLIT = 1 } icl_math;
+icl_status icl_set_math(icl_math mode);
+icl_math icl_get_math(void);
+/* Arithmetic a variant computes in (static string, NULL if out of range):
+ *   "fp32_valu"   float32 vector FMA          "fp32_mfma"  float32 matrix instructions
+ *   "fp16x3_mfma" float16 hi/lo split on the matrix cores (see ICL_MATH_F16_SPLIT)
+ *   "int32_valu"  exact integer arithmetic (icl_conv2d_u8) */
+const char* icl_variant_arith(icl_op op, int index);
+
 icl_status icl_tune_save(const char* path);
 icl_status icl_tune_load(const char* path);
 void icl_tune_clear(void);
+
+/* Environment (read once, at the first call that selects a variant):
+ *   ICL_TUNE=off     ignore the tune cache: every call runs the forced or default variant
+ *   ICL_TUNE=cache   (default) use tuned entries when present, the default otherwise
+ *   ICL_TUNE=search  as cache, and on a miss tune that problem first (icl_tune, which
+ *                    allocates and synchronises; skipped while the stream is capturing),
+ *                    then save the cache, so an interrupted series of searches resumes
+ *   ICL_TUNE_CACHE   cache file, loaded at that first call when it exists
+ *   ICL_FORCE_VARIANT=op=index[,op=index...]   as icl_force_variant, e.g. "conv2d=3" */
 
 /* Variant table of an operation (index 0 is always the plain one-pixel-per-thread kernel). */
 int icl_variant_count(icl_op op);

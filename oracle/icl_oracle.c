@@ -362,6 +362,72 @@ EXPORT void orc_harris_scale_pts(const double* X, long W, long H, const double* 
     }
 }
 
+/* Rounding-error bound of a float32 evaluation of the Harris chain (Section 6, Tables 4
+ * and 5), at single pixels.  Not part of the method: the tests use it as the tolerance of
+ * float32 responses and to find the pixels where rounding may decide a corner mask.
+ *
+ * Model: the input X holds float32 values (exact in double); every float32 operation
+ * rounds to nearest with unit roundoff u = 2^-24 (an FMA rounds once); no underflow.
+ * gamma(n) = n u / (1 - n u) bounds the relative error of a path of n roundings (Higham,
+ * "Accuracy and Stability of Numerical Algorithms", Lemma 3.1), and a sum of products
+ * evaluated in any order errs by at most gamma(depth) times the sum of |terms|.  The
+ * bound holds for every evaluation order, so it serves each kernel variant.  Stages:
+ *   Sobel    : 9 terms with exact coefficients (0, +-1, +-2), any order:
+ *              |dIx| <= e_x = gamma(8) * sum |s d| |X|        (likewise Iy)
+ *   products : A = Ix^2, B = Iy^2, C = Ix Iy, one rounding each:
+ *              |dA| <= (2|Ix| + e_x) e_x + u (|Ix| + e_x)^2
+ *              |dC| <= |Ix| e_y + |Iy| e_x + e_x e_y + u (|Ix| + e_x)(|Iy| + e_y)
+ *   window   : S = sum g_j g_i A over (2r+1)^2 clamped positions; a path holds at most
+ *              (2r+1)^2 + 1 roundings (tap product, term product, sum; a separable
+ *              evaluation has 2 (2r+1) <= that), so with m = (2r+1)^2 + 1
+ *              |dS| <= sum |g_j g_i| (|dA| + gamma(m) (|A| + |dA|))
+ *   response : R(S + e) - R(S) expanded exactly,
+ *              |dR| <= |Syy - 2k tr| d_xx + |Sxx - 2k tr| d_yy + 2 |Sxy| d_xy
+ *                      + d_xx d_yy + d_xy^2 + |k| (d_xx + d_yy)^2
+ *              plus its own evaluation (at most 5 roundings on a path, gamma(6) taken)
+ *              on the magnitudes |S| + d:  gamma(6) (|Sxx||Syy| + Sxy^2 + |k| (|Sxx| + |Syy|)^2).
+ * All quantities on the right are exact values computed here in double. */
+static inline double gam(int n) {
+    const double u = 0x1p-24;
+    return n * u / (1.0 - n * u);
+}
+
+EXPORT void orc_harris_f32_bound_pts(const double* X, long W, long H, const double* g, int rg, double k,
+                                     const long* xs, const long* ys, long npts, double* out, int nthreads) {
+    const double u = 0x1p-24;
+    const double gs = gam(8), gw = gam((2 * rg + 1) * (2 * rg + 1) + 1), gr = gam(6);
+    const double ak = fabs(k);
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (long p = 0; p < npts; ++p) {
+        double sxx = 0.0, syy = 0.0, sxy = 0.0, dxx = 0.0, dyy = 0.0, dxy = 0.0;
+        for (int j = -rg; j <= rg; ++j)
+            for (int i = -rg; i <= rg; ++i) {
+                const long gxp = clampi(xs[p] + i, W), gyp = clampi(ys[p] + j, H);
+                double ix, iy, ax, ay;
+                sobel_px(X, W, H, gxp, gyp, &ix, &iy);
+                sobel_abs_px(X, W, H, gxp, gyp, &ax, &ay);
+                const double ex = gs * ax, ey = gs * ay;
+                const double mx = fabs(ix) + ex, my = fabs(iy) + ey;
+                const double ea = (2.0 * fabs(ix) + ex) * ex + u * mx * mx;
+                const double eb = (2.0 * fabs(iy) + ey) * ey + u * my * my;
+                const double ec = fabs(ix) * ey + fabs(iy) * ex + ex * ey + u * mx * my;
+                const double wgt = g[j + rg] * g[i + rg], aw = fabs(wgt);
+                sxx += wgt * ix * ix;
+                syy += wgt * iy * iy;
+                sxy += wgt * ix * iy;
+                dxx += aw * (ea + gw * (ix * ix + ea));
+                dyy += aw * (eb + gw * (iy * iy + eb));
+                dxy += aw * (ec + gw * (fabs(ix * iy) + ec));
+            }
+        const double tr = sxx + syy;
+        const double first = fabs(syy - 2.0 * k * tr) * dxx + fabs(sxx - 2.0 * k * tr) * dyy + 2.0 * fabs(sxy) * dxy;
+        const double second = dxx * dyy + dxy * dxy + ak * (dxx + dyy) * (dxx + dyy);
+        const double mxx = fabs(sxx) + dxx, myy = fabs(syy) + dyy, mxy = fabs(sxy) + dxy;
+        const double rnd = gr * (mxx * myy + mxy * mxy + ak * (mxx + myy) * (mxx + myy));
+        out[p] = first + second + rnd;
+    }
+}
+
 /* Response at single pixels: gradients recomputed at every clamped window position. */
 EXPORT void orc_harris_pts(const double* X, long W, long H, const double* g, int rg, double k,
                            const long* xs, const long* ys, long npts, double* R, double* Sxx,

@@ -64,6 +64,8 @@ def lib():
         L.orc_harris_pts.argtypes = [_D, c_long, c_long, _D, c_int, c_double, _L, _L, c_long,
                                      _D, _D, _D, _D, c_int]
         L.orc_harris_scale_pts.argtypes = [_D, c_long, c_long, _D, c_int, c_double, _L, _L, c_long, _D, c_int]
+        L.orc_harris_f32_bound_pts.argtypes = [_D, c_long, c_long, _D, c_int, c_double, _L, _L, c_long, _D,
+                                               c_int]
         L.orc_nms.argtypes = [_D, c_long, c_long, c_int, c_double, _U8, c_int]
         L.orc_bank_fwd.argtypes = [_D, _D, c_long, c_long, c_long, c_long, c_int, _D, c_int]
         L.orc_sse_loss.argtypes = [_D, _D, c_long, _D]
@@ -283,6 +285,27 @@ def harris_scale(X, g, k, nthreads=None):
     H, W = np.shape(X)
     ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
     return harris_scale_pts(X, g, k, xs.ravel(), ys.ravel(), nthreads).reshape(H, W)
+
+
+def harris_f32_bound_pts(X, g, k, xs, ys, nthreads=None):
+    """Bound on |R_float32 - R| at the given pixels for any float32 evaluation order of the
+    Harris chain (Sobel, products, window, response); see the C source for the derivation."""
+    X = _f64(X)
+    g = _f64(g)
+    H, W = X.shape
+    rg = (g.size - 1) // 2
+    xs, ys = _pts(xs, ys)
+    out = np.empty(xs.shape, dtype=np.float64)
+    lib().orc_harris_f32_bound_pts(_p(X), W, H, _p(g), rg, float(k), _p(xs, _L), _p(ys, _L), xs.size, _p(out),
+                                   _threads(nthreads))
+    return out
+
+
+def harris_f32_bound(X, g, k, nthreads=None):
+    """harris_f32_bound_pts at every pixel, as an H x W array."""
+    H, W = np.shape(X)
+    ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    return harris_f32_bound_pts(X, g, k, xs.ravel(), ys.ravel(), nthreads).reshape(H, W)
 
 
 def nms(R, tau, radius=1, nthreads=None):

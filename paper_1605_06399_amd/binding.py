@@ -58,6 +58,15 @@ class icl_image_desc(ctypes.Structure):
                 ("width", _i), ("height", _i), ("radius", _i), ("taps_x", _vp), ("taps_y", _vp)]
 
 
+# icl_math
+ICL_MATH_F32, ICL_MATH_F16_SPLIT = 0, 1
+
+
+class icl_problem(ctypes.Structure):
+    _fields_ = [("op", _i), ("dtype", _i), ("radius", _i), ("width", _i), ("height", _i), ("depth", _i),
+                ("n", _i), ("f", _i)]
+
+
 class IclError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
@@ -102,6 +111,13 @@ _SIGS = {
     "icl_variant_name": ([_i, _i], ctypes.c_char_p),
     "icl_force_variant": ([_i, _i], _i),
     "icl_selected_variant": ([_i, _i, _i, _i, _i, ctypes.POINTER(_i)], _i),
+    "icl_tune_problem": ([ctypes.POINTER(icl_problem), _vp], _i),
+    "icl_selected_variant_problem": ([ctypes.POINTER(icl_problem), ctypes.POINTER(_i)], _i),
+    "icl_batch_plan_tune": ([_vp, _vp], _i),
+    "icl_batch_plan_variant": ([_vp, ctypes.POINTER(_i)], _i),
+    "icl_set_math": ([_i], _i),
+    "icl_get_math": ([], _i),
+    "icl_variant_arith": ([_i, _i], ctypes.c_char_p),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -327,3 +343,42 @@ def icl_selected_variant(op, dtype, radius, width, height):
 
 def variant_names(op):
     return [icl_variant_name(op, i) for i in range(icl_variant_count(op))]
+
+
+def _problem(op, dtype, radius, width, height, depth=1, n=1, f=1):
+    return icl_problem(op, dtype, radius, width, height, depth, n, f)
+
+
+def icl_tune_problem(op, dtype, radius, width, height, depth=1, n=1, f=1, stream=0) -> int:
+    q = _problem(op, dtype, radius, width, height, depth, n, f)
+    return lib().icl_tune_problem(ctypes.byref(q), stream or None)
+
+
+def icl_selected_variant_problem(op, dtype, radius, width, height, depth=1, n=1, f=1):
+    q = _problem(op, dtype, radius, width, height, depth, n, f)
+    out = _i(-1)
+    st = lib().icl_selected_variant_problem(ctypes.byref(q), ctypes.byref(out))
+    return st, out.value
+
+
+def icl_batch_plan_tune(plan, stream=0) -> int:
+    return lib().icl_batch_plan_tune(plan, stream or None)
+
+
+def icl_batch_plan_variant(plan):
+    out = _i(-1)
+    st = lib().icl_batch_plan_variant(plan, ctypes.byref(out))
+    return st, out.value
+
+
+def icl_set_math(mode) -> int:
+    return lib().icl_set_math(mode)
+
+
+def icl_get_math() -> int:
+    return lib().icl_get_math()
+
+
+def icl_variant_arith(op, index):
+    s = lib().icl_variant_arith(op, index)
+    return s.decode() if s is not None else None

@@ -59,12 +59,67 @@ bool variant_forced(icl_op op) {
     return g_forced[op].load() >= 0;
 }
 
-int select_variant(icl_op op, icl_dtype dt, int r, int W, int H, int fallback) {
+static std::atomic<int> g_math{ICL_MATH_F32};
+int math_mode() { return g_math.load(); }
+
+static const char* arith_of(icl_op op, const char* name) {
+    if (!name) return nullptr;
+    if (op == ICL_OP_CONV2D_U8) return "int32_valu";
+    if (std::strncmp(name, "mfma_f16", 8) == 0) return "fp16x3_mfma";
+    if (std::strstr(name, "mfma")) return "fp32_mfma";
+    return "fp32_valu";
+}
+
+bool variant_allowed(icl_op op, int index) {
+    const char* a = arith_of(op, icl_variant_name(op, index));
+    if (!a) return false;
+    return std::strcmp(a, "fp16x3_mfma") != 0 || g_math.load() == ICL_MATH_F16_SPLIT;
+}
+
+// ICL_TUNE: 0 off (cache ignored), 1 cache (default), 2 search on a miss
+static int g_tune_mode = 1;
+static std::string g_tune_file;
+static std::once_flag g_tune_env_once;
+
+static void parse_tune_env() {
+    if (const char* e = std::getenv("ICL_TUNE")) {
+        const std::string v(e);
+        if (v == "off") g_tune_mode = 0;
+        else if (v == "search") g_tune_mode = 2;
+        else g_tune_mode = 1;
+    }
+    if (const char* f = std::getenv("ICL_TUNE_CACHE")) {
+        g_tune_file = f;
+        if (g_tune_mode > 0) icl_tune_load(f);   // a missing or foreign file leaves the cache empty
+    }
+}
+
+static bool tunable(icl_op op) {
+    switch (op) {
+        case ICL_OP_CONV_SEP: case ICL_OP_CONV2D: case ICL_OP_HARRIS: case ICL_OP_NMS: case ICL_OP_CONV2D_U8:
+        case ICL_OP_CORNERS: case ICL_OP_CONV3D_SEP: case ICL_OP_BANK_FWD: case ICL_OP_BANK_BWD_INPUT:
+        case ICL_OP_BANK_BWD_FILTER: case ICL_OP_BANK_FWD_SSE: return true;
+        default: return false;
+    }
+}
+
+int select_variant(const Problem& p, int fallback, hipStream_t st) {
     ensure_force_env();
-    const int f = g_forced[op].load();
+    std::call_once(g_tune_env_once, parse_tune_env);
+    const int f = g_forced[p.op].load();
     if (f >= 0) return f;
-    const int c = tune_cache_get(op, dt, r, W, H);
-    if (c >= 0) return c;
+    if (g_tune_mode == 0) return fallback;
+    int c = tune_cache_get(p);
+    if (c < 0 && g_tune_mode == 2 && st != nullptr && tunable(p.op)) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        const icl_problem q{p.op, p.dt, p.r, p.W, p.H, p.D, p.N, p.F};
+        if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone &&
+            icl_tune_problem(&q, st) == ICL_OK) {
+            icl_tune_save(g_tune_file.empty() ? nullptr : g_tune_file.c_str());
+            c = tune_cache_get(p);
+        }
+    }
+    if (c >= 0 && variant_allowed(p.op, c)) return c;
     return fallback;
 }
 
@@ -248,7 +303,7 @@ icl_status icl_conv_sep_border(const void* src, size_t src_pitch, void* dst, siz
     int count;
     const Variant<SepArgs>* tab = sep_variants(&count);
     const int deflt = sep_default(a);
-    const int v = select_variant(ICL_OP_CONV_SEP, dtype, radius, width, height, deflt);
+    const int v = select_variant(ICL_OP_CONV_SEP, dtype, radius, width, height, deflt, a.st);
     // the two-pass variants (and every radius above the fused kernels' range) need the intermediate
     const bool forced_two_pass = variant_forced(ICL_OP_CONV_SEP) && v == 0;
     if ((forced_two_pass || !tab[deflt].supports(a)) && !tab[0].supports(a)) return ICL_ERR_WORKSPACE;
@@ -281,7 +336,7 @@ icl_status icl_conv2d_border(const void* src, size_t src_pitch, void* dst, size_
     int count;
     const Variant<Conv2dArgs>* tab = conv2d_variants(&count);
     const int deflt = conv2d_default(a);
-    return dispatch(ICL_OP_CONV2D, tab, count, a, select_variant(ICL_OP_CONV2D, dtype, radius, width, height, deflt),
+    return dispatch(ICL_OP_CONV2D, tab, count, a, select_variant(ICL_OP_CONV2D, dtype, radius, width, height, deflt, a.st),
                     deflt);
 }
 
@@ -316,7 +371,7 @@ icl_status icl_conv3d_sep(const void* src, size_t src_row_pitch, size_t src_slic
     int count;
     const Variant<Sep3Args>* tab = sep3d_variants(&count);
     const int deflt = sep3d_default(a);
-    const int v = select_variant(ICL_OP_CONV3D_SEP, dtype, radius, width, height, deflt);
+    const int v = select_variant(Problem{ICL_OP_CONV3D_SEP, dtype, radius, width, height, depth}, deflt, a.st);
     const bool forced_plain = variant_forced(ICL_OP_CONV3D_SEP) && v == 0;
     if ((forced_plain || !tab[deflt].supports(a)) && !tab[0].supports(a)) return ICL_ERR_WORKSPACE;
     return dispatch(ICL_OP_CONV3D_SEP, tab, count, a, v, deflt);
@@ -344,7 +399,7 @@ icl_status icl_conv2d_u8(const uint8_t* src, size_t src_pitch, uint8_t* dst, siz
     const Variant<U8Args>* tab = conv2d_u8_variants(&count);
     const int deflt = conv2d_u8_default(a);
     return dispatch(ICL_OP_CONV2D_U8, tab, count, a,
-                    select_variant(ICL_OP_CONV2D_U8, ICL_U8, radius, width, height, deflt), deflt);
+                    select_variant(ICL_OP_CONV2D_U8, ICL_U8, radius, width, height, deflt, a.st), deflt);
 }
 
 icl_status icl_harris(const float* src, size_t src_pitch, float* resp, size_t resp_pitch, int width, int height,
@@ -364,7 +419,7 @@ icl_status icl_harris(const float* src, size_t src_pitch, float* resp, size_t re
     int count;
     const Variant<HarrisArgs>* tab = harris_variants(&count);
     const int deflt = harris_default(a);
-    const int v = select_variant(ICL_OP_HARRIS, ICL_F32, window_radius, width, height, deflt);
+    const int v = select_variant(ICL_OP_HARRIS, ICL_F32, window_radius, width, height, deflt, a.st);
     const bool forced_split = variant_forced(ICL_OP_HARRIS) && v == 0;
     if ((forced_split || !tab[deflt].supports(a)) && !tab[0].supports(a)) return ICL_ERR_WORKSPACE;
     return dispatch(ICL_OP_HARRIS, tab, count, a, v, deflt);
@@ -384,7 +439,7 @@ icl_status icl_nms(const float* resp, size_t resp_pitch, uint8_t* mask, size_t m
     int count;
     const Variant<NmsArgs>* tab = nms_variants(&count);
     const int deflt = nms_default(a);
-    return dispatch(ICL_OP_NMS, tab, count, a, select_variant(ICL_OP_NMS, ICL_F32, radius, width, height, deflt), deflt);
+    return dispatch(ICL_OP_NMS, tab, count, a, select_variant(ICL_OP_NMS, ICL_F32, radius, width, height, deflt, a.st), deflt);
 }
 
 // ------------------------------------------------------------------ filter bank
@@ -418,7 +473,7 @@ icl_status icl_corners(const float* src, size_t src_pitch, uint8_t* mask, size_t
     int count;
     const Variant<CornersArgs>* tab = corners_variants(&count);
     const int deflt = corners_default(a);
-    const int v = select_variant(ICL_OP_CORNERS, ICL_F32, window_radius, width, height, deflt);
+    const int v = select_variant(ICL_OP_CORNERS, ICL_F32, window_radius, width, height, deflt, a.st);
     // the two-kernel variant needs somewhere to put the response
     const bool forced_two = variant_forced(ICL_OP_CORNERS) && v == 0;
     if ((forced_two || !tab[deflt].supports(a)) && !tab[0].supports(a)) return ICL_ERR_WORKSPACE;
@@ -447,7 +502,7 @@ icl_status icl_bank_fwd(const float* x, const float* w, float* y, int n, int f, 
     int count;
     const Variant<BankArgs>* tab = bank_fwd_variants(&count);
     const int deflt = bank_fwd_default(a);
-    return dispatch(ICL_OP_BANK_FWD, tab, count, a, select_variant(ICL_OP_BANK_FWD, ICL_F32, radius, wd, h, deflt),
+    return dispatch(ICL_OP_BANK_FWD, tab, count, a, select_variant(Problem{ICL_OP_BANK_FWD, ICL_F32, radius, wd, h, 1, n, f}, deflt, a.st),
                     deflt);
 }
 
@@ -467,7 +522,7 @@ icl_status icl_bank_bwd_input(const float* gy, const float* w, float* gx, int n,
     const Variant<BankArgs>* tab = bank_bwd_input_variants(&count);
     const int deflt = bank_bwd_input_default(a);
     return dispatch(ICL_OP_BANK_BWD_INPUT, tab, count, a,
-                    select_variant(ICL_OP_BANK_BWD_INPUT, ICL_F32, radius, wd, h, deflt), deflt);
+                    select_variant(Problem{ICL_OP_BANK_BWD_INPUT, ICL_F32, radius, wd, h, 1, n, f}, deflt, a.st), deflt);
 }
 
 icl_status icl_bank_bwd_filter(const float* gy, const float* x, float* gw, int n, int f, int h, int wd, int radius,
@@ -495,7 +550,7 @@ icl_status icl_bank_bwd_filter(const float* gy, const float* x, float* gw, int n
     const Variant<BankArgs>* tab = bank_bwd_filter_variants(&count);
     const int deflt = bank_bwd_filter_default(a);
     return dispatch(ICL_OP_BANK_BWD_FILTER, tab, count, a,
-                    select_variant(ICL_OP_BANK_BWD_FILTER, ICL_F32, radius, wd, h, deflt), deflt);
+                    select_variant(Problem{ICL_OP_BANK_BWD_FILTER, ICL_F32, radius, wd, h, 1, n, f}, deflt, a.st), deflt);
 }
 
 icl_status icl_sse_loss(const float* y, const float* t, float* gy, long long count, float* loss, void* workspace,
@@ -541,7 +596,7 @@ icl_status icl_bank_fwd_sse(const float* x, const float* w, const float* t, floa
     const Variant<BankSseArgs>* tab = bank_fwd_sse_variants(&count);
     const int deflt = bank_fwd_sse_default(a);
     return dispatch(ICL_OP_BANK_FWD_SSE, tab, count, a,
-                    select_variant(ICL_OP_BANK_FWD_SSE, ICL_F32, radius, wd, h, deflt), deflt);
+                    select_variant(Problem{ICL_OP_BANK_FWD_SSE, ICL_F32, radius, wd, h, 1, n, f}, deflt, a.st), deflt);
 }
 
 // ------------------------------------------------------------------ variants
@@ -591,6 +646,16 @@ const char* icl_variant_name(icl_op op, int index) {
     }
 }
 
+icl_status icl_set_math(icl_math mode) {
+    if (mode != ICL_MATH_F32 && mode != ICL_MATH_F16_SPLIT) return ICL_ERR_INVALID_VALUE;
+    g_math = (int)mode;
+    return ICL_OK;
+}
+
+icl_math icl_get_math(void) { return (icl_math)g_math.load(); }
+
+const char* icl_variant_arith(icl_op op, int index) { return arith_of(op, icl_variant_name(op, index)); }
+
 icl_status icl_force_variant(icl_op op, int index) {
     if (op < 0 || op >= ICL_OP_COUNT) return ICL_ERR_INVALID_VALUE;
     if (index < -1 || index >= icl_variant_count(op)) return ICL_ERR_INVALID_VALUE;
@@ -600,7 +665,15 @@ icl_status icl_force_variant(icl_op op, int index) {
 }
 
 icl_status icl_selected_variant(icl_op op, icl_dtype dtype, int radius, int width, int height, int* index) {
-    if (!index || op < 0 || op >= ICL_OP_COUNT) return ICL_ERR_INVALID_VALUE;
+    const icl_problem q{op, dtype, radius, width, height, 1, 1, 1};
+    return icl_selected_variant_problem(&q, index);
+}
+
+icl_status icl_selected_variant_problem(const icl_problem* q, int* index) {
+    if (!index || !q || q->op < 0 || q->op >= ICL_OP_COUNT) return ICL_ERR_INVALID_VALUE;
+    const icl_op op = q->op;
+    const icl_dtype dtype = q->dtype;
+    const int radius = q->radius, width = q->width, height = q->height;
     int deflt = 0;
     switch (op) {
         case ICL_OP_CONV_SEP: {
@@ -647,9 +720,22 @@ icl_status icl_selected_variant(icl_op op, icl_dtype dtype, int radius, int widt
             deflt = corners_default(a);
             break;
         }
+        case ICL_OP_BANK_FWD: case ICL_OP_BANK_BWD_INPUT: case ICL_OP_BANK_BWD_FILTER: {
+            BankArgs a{};
+            a.n = q->n; a.f = q->f; a.h = height; a.w = width; a.r = radius;
+            deflt = op == ICL_OP_BANK_FWD ? bank_fwd_default(a)
+                    : op == ICL_OP_BANK_BWD_INPUT ? bank_bwd_input_default(a) : bank_bwd_filter_default(a);
+            break;
+        }
+        case ICL_OP_BANK_FWD_SSE: {
+            BankSseArgs a{};
+            a.n = q->n; a.f = q->f; a.h = height; a.wd = width; a.r = radius;
+            deflt = bank_fwd_sse_default(a);
+            break;
+        }
         default: break;
     }
-    *index = select_variant(op, dtype, radius, width, height, deflt);
+    *index = select_variant(problem_of(*q), deflt);
     return ICL_OK;
 }
 

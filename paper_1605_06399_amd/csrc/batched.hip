@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <new>
 #include <vector>
 
@@ -178,6 +180,8 @@ struct icl_batch_plan {
     int nitems;
     int strip_grid;
     long long pixels;
+    int nimg, rmax;
+    int tuned;   // walk picked by icl_batch_plan_tune, -1 before
 };
 
 namespace {
@@ -217,6 +221,64 @@ const void* strip_kernel_for(icl_dtype dt) {
 }
 
 bool ranges_overlap(uintptr_t a0, uintptr_t a1, uintptr_t b0, uintptr_t b1) { return a0 < b1 && b0 < a1; }
+
+// The plan's problem class for the tune cache: storage type, largest radius, tile count
+// (size class) and image count.
+Problem plan_problem(const icl_batch_plan* p) {
+    return Problem{ICL_OP_CONV_SEP_BATCHED, p->dt, p->rmax, std::max(p->ntiles[0], 1), 64 * 64, 1, 1,
+                   std::max(p->nimg, 1)};
+}
+
+int plan_variant(const icl_batch_plan* p) {
+    if (variant_forced(ICL_OP_CONV_SEP_BATCHED) || p->tuned < 0)
+        return select_variant(plan_problem(p), batched_default());
+    return p->tuned;
+}
+
+// Order-independent digest of every output pixel of a plan (sum over pixels of a SplitMix64
+// mix of image, position and stored bits, modulo 2^64), for the tuner's bit-exact check.
+template <class T>
+__global__ __launch_bounds__(256) void batch_digest_k(const DevImage* __restrict__ imgs,
+                                                      const BatchTile* __restrict__ tiles, int ntiles,
+                                                      unsigned long long* out) {
+    unsigned long long h = 0;
+    for (int t = (int)blockIdx.x; t < ntiles; t += (int)gridDim.x) {
+        const BatchTile bt = tiles[t];
+        const DevImage d = imgs[bt.img];
+        for (int q = (int)threadIdx.x; q < 64 * 64; q += 256) {
+            const int x = bt.x0 + (q & 63), y = bt.y0 + (q >> 6);
+            if (x >= d.W || y >= d.H) continue;
+            const unsigned char* p = static_cast<const unsigned char*>(d.dst) + (size_t)y * d.dp + (size_t)x * T::size;
+            unsigned long long bits = T::size == 4 ? *reinterpret_cast<const unsigned*>(p)
+                                                   : *reinterpret_cast<const unsigned short*>(p);
+            unsigned long long z = bits + ((unsigned long long)bt.img << 40) + ((unsigned long long)y << 20) +
+                                   (unsigned long long)x + 0x9E3779B97F4A7C15ull;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            h += z ^ (z >> 31);
+        }
+    }
+    atomicAdd(out, h);
+}
+
+hipError_t plan_digest(const icl_batch_plan* p, unsigned long long* d_out, unsigned long long* h_out, hipStream_t st) {
+    hipError_t e = hipMemsetAsync(d_out, 0, sizeof(unsigned long long), st);
+    if (e != hipSuccess) return e;
+    const int grid = std::min(std::max(p->ntiles[0], 1), 4096);
+    switch (p->dt) {
+        case ICL_F32: hipLaunchKernelGGL(batch_digest_k<F32>, dim3(grid), dim3(256), 0, st, p->d_imgs, p->d_tiles[0],
+                                         p->ntiles[0], d_out); break;
+        case ICL_F16: hipLaunchKernelGGL(batch_digest_k<F16>, dim3(grid), dim3(256), 0, st, p->d_imgs, p->d_tiles[0],
+                                         p->ntiles[0], d_out); break;
+        default: hipLaunchKernelGGL(batch_digest_k<BF16>, dim3(grid), dim3(256), 0, st, p->d_imgs, p->d_tiles[0],
+                                    p->ntiles[0], d_out); break;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(h_out, d_out, sizeof(unsigned long long), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+
+hipError_t launch_plan(const icl_batch_plan* plan, int v, hipStream_t st);
 
 }  // namespace
 
@@ -303,6 +365,11 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
     p->dt = dtype;
     p->nitems = (int)items.size();
     p->pixels = pixels;
+    p->nimg = count;
+    p->rmax = 0;
+    for (const DevImage& d : imgs)
+        if (d.src) p->rmax = std::max(p->rmax, d.r);
+    p->tuned = -1;
     hipError_t e = hipSuccess;
     if (!imgs.empty()) e = hipMalloc(&p->d_imgs, imgs.size() * sizeof(DevImage));
     for (int w = 0; w < NWALKS; ++w) {
@@ -345,8 +412,84 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
 icl_status icl_conv_sep_batched(const icl_batch_plan* plan, void* stream) {
     if (!plan) return ICL_ERR_INVALID_VALUE;
     if (plan->ntiles[0] == 0) return ICL_OK;
+    const int v = plan_variant(plan);
+    if (v < 0 || v >= icl_variant_count(ICL_OP_CONV_SEP_BATCHED)) return ICL_ERR_UNSUPPORTED;
+    return hip_status(launch_plan(plan, v, (hipStream_t)stream));
+}
+
+icl_status icl_batch_plan_variant(const icl_batch_plan* plan, int* index) {
+    if (!plan || !index) return ICL_ERR_INVALID_VALUE;
+    *index = plan_variant(plan);
+    return ICL_OK;
+}
+
+icl_status icl_batch_plan_tune(icl_batch_plan* plan, void* stream) {
+    if (!plan) return ICL_ERR_INVALID_VALUE;
+    if (plan->ntiles[0] == 0) return ICL_OK;
+    icl_status s = device_ready();
+    if (s != ICL_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    const int v = select_variant(ICL_OP_CONV_SEP_BATCHED, plan->dt, 0, 0, 0, batched_default());
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return ICL_ERR_UNSUPPORTED;
+    unsigned long long* d_h = nullptr;
+    hipError_t e = hipMalloc(&d_h, sizeof(unsigned long long));
+    if (e != hipSuccess) return hip_status(e);
+    const int nv = icl_variant_count(ICL_OP_CONV_SEP_BATCHED);
+    const int ref_v = batched_default();
+    unsigned long long ref = 0;
+    e = launch_plan(plan, ref_v, st);
+    if (e == hipSuccess) e = plan_digest(plan, d_h, &ref, st);
+    hipEvent_t ev[2];
+    hipEventCreate(&ev[0]);
+    hipEventCreate(&ev[1]);
+    double best = 1e300;
+    int best_v = -1;
+    const bool log = std::getenv("ICL_LOG") && std::atoi(std::getenv("ICL_LOG")) >= 1;
+    for (int v = 0; v < nv && e == hipSuccess; ++v) {
+        if (!variant_allowed(ICL_OP_CONV_SEP_BATCHED, v)) continue;
+        unsigned long long h = 0;
+        if ((e = launch_plan(plan, v, st)) != hipSuccess || (e = plan_digest(plan, d_h, &h, st)) != hipSuccess) break;
+        if (h != ref) {   // every walk evaluates the same float32 expression: the outputs must match bit for bit
+            if (log) std::fprintf(stderr, "icl tune: conv_sep_batched/%s rejected (output differs)\n",
+                                  icl_variant_name(ICL_OP_CONV_SEP_BATCHED, v));
+            continue;
+        }
+        constexpr int reps = 5, per = 4;
+        std::vector<double> t;
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = launch_plan(plan, v, st);
+        for (int k = 0; k < reps && e == hipSuccess; ++k) {
+            hipEventRecord(ev[0], st);
+            for (int j = 0; j < per && e == hipSuccess; ++j) e = launch_plan(plan, v, st);
+            hipEventRecord(ev[1], st);
+            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, ev[0], ev[1]);
+            t.push_back(ms * 1000.0 / per);
+        }
+        if (e != hipSuccess) break;
+        std::sort(t.begin(), t.end());
+        const double us = t[t.size() / 2];
+        if (log) std::fprintf(stderr, "icl tune: conv_sep_batched/%s %.2f us\n", icl_variant_name(ICL_OP_CONV_SEP_BATCHED, v), us);
+        if (us < best) {
+            best = us;
+            best_v = v;
+        }
+    }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    hipFree(d_h);
+    if (e != hipSuccess) return hip_status(e);
+    if (best_v < 0) return ICL_ERR_UNSUPPORTED;
+    plan->tuned = best_v;
+    tune_cache_put(plan_problem(plan), best_v, best);
+    return ICL_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+hipError_t launch_plan(const icl_batch_plan* plan, int v, hipStream_t st) {
     if (v == 1) {
         switch (plan->dt) {
             case ICL_F32:
@@ -362,7 +505,7 @@ icl_status icl_conv_sep_batched(const icl_batch_plan* plan, void* stream) {
                                    plan->d_items, plan->nitems);
                 break;
         }
-        return hip_status(hipGetLastError());
+        return hipGetLastError();
     }
     const int w = v == 0 ? 0 : v - 1;   // variants 0, 2, 3 are tile walks 0, 1, 2
     switch (plan->dt) {
@@ -370,8 +513,12 @@ icl_status icl_conv_sep_batched(const icl_batch_plan* plan, void* stream) {
         case ICL_F16: launch_walk<F16>(plan, w, st); break;
         default: launch_walk<BF16>(plan, w, st); break;
     }
-    return hip_status(hipGetLastError());
+    return hipGetLastError();
 }
+
+}  // namespace
+
+extern "C" {
 
 icl_status icl_batch_plan_info(const icl_batch_plan* plan, long long* tiles, long long* pixels) {
     if (!plan) return ICL_ERR_INVALID_VALUE;

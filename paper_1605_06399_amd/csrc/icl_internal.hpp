@@ -151,13 +151,37 @@ size_t bank_fwd_sse_workspace();
 hipError_t sse_launch(const float* y, const float* t, float* gy, long long count, float* loss,
                       void* ws, size_t wsb, hipStream_t st);
 
-// Variant selection shared by the entry points: forced > tune cache > default.
-int select_variant(icl_op op, icl_dtype dt, int r, int W, int H, int fallback);
-bool variant_forced(icl_op op);
+// A problem as the tuner keys it: the operation, storage type, radius and the sizes that
+// change which variant is fastest (depth of a volume, batch and filter counts of the bank).
+struct Problem {
+    icl_op op;
+    icl_dtype dt;
+    int r;
+    int W, H;
+    int D = 1, N = 1, F = 1;
+};
+inline Problem problem_of(const icl_problem& p) {
+    return Problem{p.op, p.dtype, p.radius, p.width, p.height, p.depth > 1 ? p.depth : 1, p.n > 1 ? p.n : 1,
+                   p.f > 1 ? p.f : 1};
+}
 
-// Tuner hooks (tuner.cpp).
-void tune_cache_put(icl_op op, icl_dtype dt, int r, int W, int H, int variant, double us);
-int tune_cache_get(icl_op op, icl_dtype dt, int r, int W, int H);
+// Variant selection shared by the entry points: forced > tune cache > default.  With
+// ICL_TUNE=search and a stream, a cache miss is tuned first (outside stream capture).
+int select_variant(const Problem& p, int fallback, hipStream_t st = nullptr);
+inline int select_variant(icl_op op, icl_dtype dt, int r, int W, int H, int fallback, hipStream_t st = nullptr) {
+    return select_variant(Problem{op, dt, r, W, H}, fallback, st);
+}
+bool variant_forced(icl_op op);
+// Whether the process-wide arithmetic mode (icl_set_math) lets tuning and default
+// selection pick this variant.
+bool variant_allowed(icl_op op, int index);
+int math_mode();
+
+// Tuner hooks (tuner.hip).
+void tune_cache_put(const Problem& p, int variant, double us);
+int tune_cache_get(const Problem& p);
+// Plan-level search of the batched walks (batched.hip); caches the winner for the plan.
+icl_status tune_batch_plan(icl_batch_plan* plan, hipStream_t st);
 
 // Lazily checks that a HIP device is visible (ICL_ERR_NO_DEVICE otherwise).
 icl_status device_ready();

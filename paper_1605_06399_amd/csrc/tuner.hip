@@ -57,14 +57,16 @@ const std::string& device_tag() {
     return g_device_tag;
 }
 
-int size_class(int W, int H) {
-    const double px = std::max(1.0, (double)W * (double)H);
+int size_class(const Problem& p) {
+    const double px = std::max(1.0, (double)p.W * (double)p.H * (double)std::max(p.D, 1) * (double)std::max(p.N, 1));
     return (int)std::floor(std::log2(px));
 }
 
-std::string make_key(icl_op op, icl_dtype dt, int r, int W, int H) {
-    return device_tag() + "|" + op_name(op) + "|" + std::to_string((int)dt) + "|" + std::to_string(r) + "|" +
-           std::to_string(size_class(W, H));
+// device | op | dtype | radius | size class | filters | arithmetic mode
+std::string make_key(const Problem& p) {
+    return device_tag() + "|" + op_name(p.op) + "|" + std::to_string((int)p.dt) + "|" + std::to_string(p.r) + "|" +
+           std::to_string(size_class(p)) + "|f" + std::to_string(std::max(p.F, 1)) + "|m" +
+           std::to_string(math_mode());
 }
 
 int index_of(icl_op op, const std::string& name) {
@@ -97,36 +99,42 @@ __global__ void fill_k(void* dst, size_t pitch, int W, int H, unsigned long long
     store_px<T>(dst, (size_t)y * pitch + (size_t)x * T::size, hash_uniform(i, seed));
 }
 
-// out[0] = max |a - b|, out[1] = max |b| (as float bits; values are non-negative).
-// Each block reduces in LDS first, so only one pair of atomics per block reaches memory.
+// out[0] = max |a - b|, out[1] = max |b|, out[2] = max |a - b| / |b| (as float bits; values
+// are non-negative, so the bit patterns order like the values).  Each block reduces in LDS
+// first, so only one set of atomics per block reaches memory.
 template <class T>
 __global__ __launch_bounds__(256) void compare_k(const void* a, const void* b, size_t pitch, int W, int H,
                                                  unsigned* out) {
-    __shared__ unsigned red[2][256];
+    __shared__ unsigned red[3][256];
     const size_t n = (size_t)W * H;
-    unsigned md = 0, mb = 0;
+    unsigned md = 0, mb = 0, mr = 0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
         const int y = (int)(i / W), x = (int)(i % W);
         const size_t off = (size_t)y * pitch + (size_t)x * T::size;
         const float va = load_px<T>(a, off), vb = load_px<T>(b, off);
         float d = fabsf(va - vb);
         if (!(d == d)) d = 3.0e38f;   // NaN counts as a mismatch
+        float rel = d / fmaxf(fabsf(vb), 1e-30f);
+        if (!(rel <= 3.0e38f)) rel = 3.0e38f;
         md = max(md, __float_as_uint(d));
         mb = max(mb, __float_as_uint(fabsf(vb)));
+        mr = max(mr, __float_as_uint(rel));
     }
     red[0][threadIdx.x] = md;
     red[1][threadIdx.x] = mb;
+    red[2][threadIdx.x] = mr;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
-            red[0][threadIdx.x] = max(red[0][threadIdx.x], red[0][threadIdx.x + s]);
-            red[1][threadIdx.x] = max(red[1][threadIdx.x], red[1][threadIdx.x + s]);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = max(red[q][threadIdx.x], red[q][threadIdx.x + s]);
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         atomicMax(&out[0], red[0][0]);
         atomicMax(&out[1], red[1][0]);
+        atomicMax(&out[2], red[2][0]);
     }
 }
 
@@ -148,7 +156,7 @@ __global__ void fill_u8_k(uint8_t* p, size_t pitch, int W, int H, unsigned long 
 }
 
 __global__ void zero2_k(unsigned* p) {
-    if (threadIdx.x < 2) p[threadIdx.x] = 0u;
+    if (threadIdx.x < 4) p[threadIdx.x] = 0u;
 }
 
 unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
@@ -163,9 +171,20 @@ hipError_t fill(icl_dtype dt, void* p, size_t pitch, int W, int H, unsigned long
     return hipGetLastError();
 }
 
-// true when a matches b to within rel * max|b| (+ a tiny absolute floor)
+// Storage-type tolerance of the candidate check: the float32 normwise contract (1e-5) for
+// float32, one output rounding for the half formats (a binary16 ulp is 2^-10 relative, a
+// bfloat16 ulp 2^-7).
+float storage_tol(icl_dtype dt) { return dt == ICL_F32 ? 1e-5f : (dt == ICL_F16 ? 2e-3f : 1e-2f); }
+
+// How a candidate's output is compared with the reference output.
+enum class Agree {
+    PerPixel,   // |a - b| <= tol |b| at every pixel: the normwise error of a filter with non-negative
+                // taps on non-negative data (the tuner's inputs), where S(p) is the exact output itself
+    Max         // max |a - b| <= tol max |b|: for outputs with cancellation (the Harris response)
+};
+
 bool outputs_agree(icl_dtype dt, const void* a, const void* b, size_t pitch, int W, int H, unsigned* d_stat,
-                   hipStream_t st) {
+                   hipStream_t st, Agree how = Agree::PerPixel, float tol = 0.f) {
     hipLaunchKernelGGL(zero2_k, dim3(1), dim3(64), 0, st, d_stat);
     const unsigned nb = std::min(blocks_for((size_t)W * H), 2048u);
     switch (dt) {
@@ -173,14 +192,16 @@ bool outputs_agree(icl_dtype dt, const void* a, const void* b, size_t pitch, int
         case ICL_F16: hipLaunchKernelGGL(compare_k<F16>, dim3(nb), dim3(256), 0, st, a, b, pitch, W, H, d_stat); break;
         default: hipLaunchKernelGGL(compare_k<BF16>, dim3(nb), dim3(256), 0, st, a, b, pitch, W, H, d_stat); break;
     }
-    unsigned h[2] = {0, 0};
+    unsigned h[3] = {0, 0, 0};
     if (hipMemcpyAsync(h, d_stat, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return false;
     if (hipStreamSynchronize(st) != hipSuccess) return false;
-    float maxd, maxb;
+    float maxd, maxb, maxr;
     std::memcpy(&maxd, &h[0], 4);
     std::memcpy(&maxb, &h[1], 4);
-    const float rel = dt == ICL_F32 ? 1e-4f : 1e-2f;
-    return maxd <= rel * maxb + 1e-6f;
+    std::memcpy(&maxr, &h[2], 4);
+    if (tol <= 0.f) tol = storage_tol(dt);
+    if (how == Agree::PerPixel) return maxr <= tol;
+    return maxd <= tol * maxb;
 }
 
 bool masks_agree(const uint8_t* a, const uint8_t* b, size_t pitch, int W, int H, unsigned* d_stat, hipStream_t st) {
@@ -223,6 +244,7 @@ double time_launches(F&& launch, int sets, int warm, int reps, int per, hipStrea
 
 int rotation_sets(size_t bytes_per_set) {
     const size_t target = (size_t)1 << 30;
+    if (bytes_per_set >= target) return 1;   // one set already exceeds the Infinity Cache fourfold
     size_t k = (target + bytes_per_set - 1) / std::max<size_t>(bytes_per_set, 1);
     return (int)std::min<size_t>(std::max<size_t>(k, 2), 8);
 }
@@ -259,9 +281,10 @@ thread_local SearchPlan g_plan;
 // Generic search over an op's variant table.  make(set) builds the argument bundle
 // for buffer set `set`; agree(a) checks a candidate's output (set 0) against the
 // plain output.
-template <class A, class Make, class Agree>
-icl_status search(icl_op op, const Variant<A>* tab, int count, icl_dtype dt, int r, int W, int H, int sets,
-                  Make&& make, Agree&& agree, hipStream_t st) {
+template <class A, class Make, class AgreeFn>
+icl_status search(const Problem& pb, const Variant<A>* tab, int count, int sets, Make&& make, AgreeFn&& agree,
+                  hipStream_t st) {
+    const icl_op op = pb.op;
     double best = 1e300;
     int best_i = -1;
     std::vector<double> measured(count, -1.0);   // us, -1 = not timed, -2 = rejected
@@ -285,9 +308,10 @@ icl_status search(icl_op op, const Variant<A>* tab, int count, icl_dtype dt, int
             best_i = i;
         }
     };
+    // every variant but the reference (index 0) that runs the problem under the arithmetic mode
     std::vector<int> cand;
     for (int i = 1; i < count; ++i)
-        if (tab[i].supports(make(0, i))) cand.push_back(i);
+        if (variant_allowed(op, i) && tab[i].supports(make(0, i))) cand.push_back(i);
     g_plan.timed = 0;
     const int ns = std::max(2, g_plan.samples);
     if (!g_plan.model || (int)cand.size() <= ns + std::max(1, g_plan.top_k)) {
@@ -328,11 +352,14 @@ icl_status search(icl_op op, const Variant<A>* tab, int count, icl_dtype dt, int
         }
     }
     if (best_i < 0) return ICL_ERR_UNSUPPORTED;
-    tune_cache_put(op, dt, r, W, H, best_i, best);
+    tune_cache_put(pb, best_i, best);
     return ICL_OK;
 }
 
-icl_status tune_conv(icl_op op, icl_dtype dt, int r, int W, int H, hipStream_t st) {
+icl_status tune_conv(const Problem& pb, hipStream_t st) {
+    const icl_op op = pb.op;
+    const icl_dtype dt = pb.dt;
+    const int r = pb.r, W = pb.W, H = pb.H;
     const int es = elem_size(dt);
     const size_t pitch = ((size_t)W * es + 255) & ~(size_t)255;
     const size_t bytes = pitch * H;
@@ -369,7 +396,7 @@ icl_status tune_conv(icl_op op, icl_dtype dt, int r, int W, int H, hipStream_t s
         p0.dst = ref;
         if (!tab[0].supports(p0) || tab[0].launch(p0) != hipSuccess) return ICL_ERR_HIP;
         auto agree = [&]() { return outputs_agree(dt, dst[0], ref, pitch, W, H, d_stat, st); };
-        return search(op, tab, count, dt, r, W, H, sets, make, agree, st);
+        return search(pb, tab, count, sets, make, agree, st);
     } else {
         int count;
         const Variant<Conv2dArgs>* tab = conv2d_variants(&count);
@@ -378,11 +405,12 @@ icl_status tune_conv(icl_op op, icl_dtype dt, int r, int W, int H, hipStream_t s
         p0.dst = ref;
         if (!tab[0].supports(p0) || tab[0].launch(p0) != hipSuccess) return ICL_ERR_HIP;
         auto agree = [&]() { return outputs_agree(dt, dst[0], ref, pitch, W, H, d_stat, st); };
-        return search(op, tab, count, dt, r, W, H, sets, make, agree, st);
+        return search(pb, tab, count, sets, make, agree, st);
     }
 }
 
-icl_status tune_harris(int rg, int W, int H, hipStream_t st) {
+icl_status tune_harris(const Problem& pb, hipStream_t st) {
+    const int rg = pb.r, W = pb.W, H = pb.H;
     const size_t pitch = ((size_t)W * 4 + 255) & ~(size_t)255;
     const size_t bytes = pitch * H;
     const int sets = rotation_sets(2 * bytes);
@@ -414,11 +442,13 @@ icl_status tune_harris(int rg, int W, int H, hipStream_t st) {
     HarrisArgs p0 = make(0, 0);
     p0.resp = static_cast<float*>(ref);
     if (tab[0].launch(p0) != hipSuccess) return ICL_ERR_HIP;
-    auto agree = [&]() { return outputs_agree(ICL_F32, dst[0], ref, pitch, W, H, d_stat, st); };
-    return search(ICL_OP_HARRIS, tab, count, ICL_F32, rg, W, H, sets, make, agree, st);
+    // the response cancels (det - k tr^2), so it is compared against its largest magnitude
+    auto agree = [&]() { return outputs_agree(ICL_F32, dst[0], ref, pitch, W, H, d_stat, st, Agree::Max); };
+    return search(pb, tab, count, sets, make, agree, st);
 }
 
-icl_status tune_conv_u8(int r, int W, int H, hipStream_t st) {
+icl_status tune_conv_u8(const Problem& pb, hipStream_t st) {
+    const int r = pb.r, W = pb.W, H = pb.H;
     const size_t pitch = ((size_t)W + 255) & ~(size_t)255;
     const int sets = rotation_sets(2 * pitch * H);
     Buffers b;
@@ -453,12 +483,13 @@ icl_status tune_conv_u8(int r, int W, int H, hipStream_t st) {
     auto agree = [&]() {   // integer results: every variant must return the same bytes
         return masks_agree(static_cast<uint8_t*>(dst[0]), static_cast<uint8_t*>(ref), pitch, W, H, d_stat, st);
     };
-    return search(ICL_OP_CONV2D_U8, tab, count, ICL_U8, r, W, H, sets, make, agree, st);
+    return search(pb, tab, count, sets, make, agree, st);
 }
 
 // Fused corners: the single-pass variants share their arithmetic, so each must return the
 // default single-pass variant's mask byte for byte (the two-kernel variant is not a candidate).
-icl_status tune_corners(int rg, int W, int H, hipStream_t st) {
+icl_status tune_corners(const Problem& pb, hipStream_t st) {
+    const int rg = pb.r, W = pb.W, H = pb.H;
     const size_t pitch = ((size_t)W * 4 + 255) & ~(size_t)255;
     const size_t mpitch = ((size_t)W + 255) & ~(size_t)255;
     const int sets = rotation_sets(pitch * H + mpitch * H);
@@ -493,10 +524,11 @@ icl_status tune_corners(int rg, int W, int H, hipStream_t st) {
     auto agree = [&]() {
         return masks_agree(static_cast<uint8_t*>(dst[0]), static_cast<uint8_t*>(ref), mpitch, W, H, d_stat, st);
     };
-    return search(ICL_OP_CORNERS, tab, count, ICL_F32, rg, W, H, sets, make, agree, st);
+    return search(pb, tab, count, sets, make, agree, st);
 }
 
-icl_status tune_nms(int r, int W, int H, hipStream_t st) {
+icl_status tune_nms(const Problem& pb, hipStream_t st) {
+    const int r = pb.r, W = pb.W, H = pb.H;
     const size_t pitch = ((size_t)W * 4 + 255) & ~(size_t)255;
     const size_t mpitch = ((size_t)W + 255) & ~(size_t)255;
     const int sets = rotation_sets(pitch * H + mpitch * H);
@@ -523,7 +555,172 @@ icl_status tune_nms(int r, int W, int H, hipStream_t st) {
     auto agree = [&]() {
         return masks_agree(static_cast<uint8_t*>(dst[0]), static_cast<uint8_t*>(ref), mpitch, W, H, d_stat, st);
     };
-    return search(ICL_OP_NMS, tab, count, ICL_F32, r, W, H, sets, make, agree, st);
+    return search(pb, tab, count, sets, make, agree, st);
+}
+
+// Separable 3-D correlation: volumes of W x H x D voxels whose slices follow each other
+// (slice pitch = H row pitches), so the whole volume reads as one W x (H D) image for
+// filling and comparing.
+icl_status tune_sep3d(const Problem& pb, hipStream_t st) {
+    const icl_dtype dt = pb.dt;
+    const int r = pb.r, W = pb.W, H = pb.H, D = pb.D;
+    const int es = elem_size(dt);
+    const size_t pitch = ((size_t)W * es + 255) & ~(size_t)255, spitch = pitch * H, bytes = spitch * D;
+    if ((size_t)H * D > (size_t)INT32_MAX) return ICL_ERR_UNSUPPORTED;
+    const int HD = H * D;
+    const int sets = rotation_sets(2 * bytes);
+    Buffers b;
+    std::vector<void*> src(sets), dst(sets);
+    for (int s = 0; s < sets; ++s) {
+        src[s] = b.alloc(bytes);
+        dst[s] = b.alloc(bytes);
+        if (!src[s] || !dst[s]) return ICL_ERR_HIP;
+        if (fill(dt, src[s], pitch, W, HD, 0x3d3dull + s, st) != hipSuccess) return ICL_ERR_HIP;
+    }
+    void* ref = b.alloc(bytes);
+    const int n = 2 * r + 1;
+    std::vector<float> taps(3 * n);
+    for (int a = 0; a < 3; ++a) {
+        double sum = 0;
+        for (int k = 0; k < n; ++k) sum += (taps[a * n + k] = 1.0f + 0.25f * (float)(((k + a) * 7) % 5));
+        for (int k = 0; k < n; ++k) taps[a * n + k] = (float)(taps[a * n + k] / sum);
+    }
+    float* d_taps = static_cast<float*>(b.alloc(taps.size() * sizeof(float)));
+    unsigned* d_stat = static_cast<unsigned*>(b.alloc(16));
+    const size_t wsb = sep3d_workspace(W, H, D);
+    void* ws = b.alloc(wsb);
+    if (!ref || !d_taps || !d_stat || !ws) return ICL_ERR_HIP;
+    if (hipMemcpyAsync(d_taps, taps.data(), taps.size() * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess)
+        return ICL_ERR_HIP;
+    int count;
+    const Variant<Sep3Args>* tab = sep3d_variants(&count);
+    auto make = [&](int s, int) {
+        return Sep3Args{src[s], pitch, spitch, dst[s], pitch, spitch, W, H, D, dt, d_taps, d_taps + n, d_taps + 2 * n,
+                        r, ws, wsb, st};
+    };
+    Sep3Args p0 = make(0, 0);
+    p0.dst = ref;
+    if (!tab[0].supports(p0) || tab[0].launch(p0) != hipSuccess) return ICL_ERR_HIP;
+    auto agree = [&]() { return outputs_agree(dt, dst[0], ref, pitch, W, HD, d_stat, st); };
+    return search(pb, tab, count, sets, make, agree, st);
+}
+
+// Filter bank (forward, input adjoint, filter adjoint): x [N][H][W], w [F][k][k], y or gy
+// [N][F][H][W], on positive inputs and positive normalised taps so that every output is a
+// sum of non-negative terms and the per-element comparison is the normwise one.
+icl_status tune_bank(const Problem& pb, hipStream_t st) {
+    const icl_op op = pb.op;
+    const int r = pb.r, W = pb.W, H = pb.H, N = pb.N, F = pb.F;
+    const size_t hw = (size_t)H * W, nk = (size_t)(2 * r + 1) * (2 * r + 1);
+    const size_t xb = (size_t)N * hw * 4, yb = (size_t)N * F * hw * 4, wb = (size_t)F * nk * 4;
+    if ((size_t)N * F * H > (size_t)INT32_MAX) return ICL_ERR_UNSUPPORTED;
+    // the operation's input and output
+    const size_t inb = op == ICL_OP_BANK_BWD_INPUT ? yb : xb;
+    const size_t outb = op == ICL_OP_BANK_FWD ? yb : (op == ICL_OP_BANK_BWD_INPUT ? xb : wb);
+    const size_t sideb = op == ICL_OP_BANK_BWD_FILTER ? yb : 0;   // gy beside x for the filter adjoint
+    const int sets = rotation_sets(inb + outb + sideb);
+    Buffers b;
+    std::vector<void*> in(sets), out(sets), side(sets);
+    for (int s = 0; s < sets; ++s) {
+        in[s] = b.alloc(inb);
+        out[s] = b.alloc(outb);
+        side[s] = sideb ? b.alloc(sideb) : nullptr;
+        if (!in[s] || !out[s] || (sideb && !side[s])) return ICL_ERR_HIP;
+        if (fill(ICL_F32, in[s], (size_t)W * 4, W, (int)(inb / 4 / W), 0xb0ull + s, st) != hipSuccess) return ICL_ERR_HIP;
+        if (sideb && fill(ICL_F32, side[s], (size_t)W * 4, W, (int)(sideb / 4 / W), 0xc0ull + s, st) != hipSuccess)
+            return ICL_ERR_HIP;
+    }
+    void* ref = b.alloc(outb);
+    std::vector<float> w(F * nk);
+    for (int f = 0; f < F; ++f) {
+        double sum = 0;
+        for (size_t k = 0; k < nk; ++k) sum += (w[f * nk + k] = 1.0f + 0.25f * (float)((k * 7 + f) % 5));
+        for (size_t k = 0; k < nk; ++k) w[f * nk + k] = (float)(w[f * nk + k] / sum);
+    }
+    float* d_w = static_cast<float*>(b.alloc(wb));
+    unsigned* d_stat = static_cast<unsigned*>(b.alloc(16));
+    const size_t wsb = op == ICL_OP_BANK_BWD_FILTER ? bank_bwd_filter_workspace(N, F, H, W, r) : 0;
+    void* ws = wsb ? b.alloc(wsb) : nullptr;
+    if (!ref || !d_w || !d_stat || (wsb && !ws)) return ICL_ERR_HIP;
+    if (hipMemcpyAsync(d_w, w.data(), wb, hipMemcpyHostToDevice, st) != hipSuccess) return ICL_ERR_HIP;
+    int count;
+    const Variant<BankArgs>* tab = op == ICL_OP_BANK_FWD ? bank_fwd_variants(&count)
+                                   : op == ICL_OP_BANK_BWD_INPUT ? bank_bwd_input_variants(&count)
+                                                                 : bank_bwd_filter_variants(&count);
+    auto make = [&](int s, int) {
+        if (op == ICL_OP_BANK_BWD_FILTER)   // a = gy, b = x
+            return BankArgs{static_cast<const float*>(side[s]), static_cast<const float*>(in[s]),
+                            static_cast<float*>(out[s]), N, F, H, W, r, ws, wsb, st};
+        return BankArgs{static_cast<const float*>(in[s]), d_w, static_cast<float*>(out[s]), N, F, H, W, r, nullptr, 0,
+                        st};
+    };
+    BankArgs p0 = make(0, 0);
+    p0.out = static_cast<float*>(ref);
+    if (!tab[0].supports(p0) || tab[0].launch(p0) != hipSuccess) return ICL_ERR_HIP;
+    // output viewed as an image of W-wide rows (the filter gradient as one row of F k^2 values)
+    const int ow = op == ICL_OP_BANK_BWD_FILTER ? (int)(F * nk) : W;
+    const int oh = (int)(outb / 4 / ow);
+    // the filter gradient reduces N H W terms per tap in blocks: a looser bound than one stencil
+    const float tol = op == ICL_OP_BANK_BWD_FILTER ? 1e-4f : 1e-5f;
+    auto agree = [&]() {
+        return outputs_agree(ICL_F32, out[0], ref, (size_t)ow * 4, ow, oh, d_stat, st, Agree::PerPixel, tol);
+    };
+    return search(pb, tab, count, sets, make, agree, st);
+}
+
+// Filter-bank forward fused with the loss: candidates must reproduce the reference
+// variant's gradient gy = 2 (y - t) (relative to its largest magnitude: gy changes sign)
+// and its loss.
+icl_status tune_bank_sse(const Problem& pb, hipStream_t st) {
+    const int r = pb.r, W = pb.W, H = pb.H, N = pb.N, F = pb.F;
+    const size_t hw = (size_t)H * W, nk = (size_t)(2 * r + 1) * (2 * r + 1);
+    const size_t xb = (size_t)N * hw * 4, yb = (size_t)N * F * hw * 4, wb = (size_t)F * nk * 4;
+    if ((size_t)N * F * H > (size_t)INT32_MAX) return ICL_ERR_UNSUPPORTED;
+    const int sets = rotation_sets(xb + 2 * yb);
+    Buffers b;
+    std::vector<void*> x(sets), t(sets), gy(sets);
+    for (int s = 0; s < sets; ++s) {
+        x[s] = b.alloc(xb);
+        t[s] = b.alloc(yb);
+        gy[s] = b.alloc(yb);
+        if (!x[s] || !t[s] || !gy[s]) return ICL_ERR_HIP;
+        if (fill(ICL_F32, x[s], (size_t)W * 4, W, N * H, 0xd0ull + s, st) != hipSuccess) return ICL_ERR_HIP;
+        if (fill(ICL_F32, t[s], (size_t)W * 4, W, N * F * H, 0xe0ull + s, st) != hipSuccess) return ICL_ERR_HIP;
+    }
+    void* ref = b.alloc(yb);
+    std::vector<float> w(F * nk);
+    for (int f = 0; f < F; ++f) {
+        double sum = 0;
+        for (size_t k = 0; k < nk; ++k) sum += (w[f * nk + k] = 1.0f + 0.25f * (float)((k * 7 + f) % 5));
+        for (size_t k = 0; k < nk; ++k) w[f * nk + k] = (float)(w[f * nk + k] / sum);
+    }
+    float* d_w = static_cast<float*>(b.alloc(wb));
+    unsigned* d_stat = static_cast<unsigned*>(b.alloc(16));
+    float* d_loss = static_cast<float*>(b.alloc(16));
+    const size_t wsb = bank_fwd_sse_workspace();
+    void* ws = b.alloc(wsb);
+    if (!ref || !d_w || !d_stat || !d_loss || !ws) return ICL_ERR_HIP;
+    if (hipMemcpyAsync(d_w, w.data(), wb, hipMemcpyHostToDevice, st) != hipSuccess) return ICL_ERR_HIP;
+    int count;
+    const Variant<BankSseArgs>* tab = bank_fwd_sse_variants(&count);
+    auto make = [&](int s, int) {
+        return BankSseArgs{static_cast<const float*>(x[s]), d_w, static_cast<const float*>(t[s]), nullptr,
+                           static_cast<float*>(gy[s]), d_loss, N, F, H, W, r, ws, wsb, st};
+    };
+    BankSseArgs p0 = make(0, 0);
+    p0.gy = static_cast<float*>(ref);
+    if (!tab[0].supports(p0) || tab[0].launch(p0) != hipSuccess) return ICL_ERR_HIP;
+    float ref_loss = 0.f;
+    if (hipMemcpyAsync(&ref_loss, d_loss, 4, hipMemcpyDeviceToHost, st) != hipSuccess) return ICL_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return ICL_ERR_HIP;
+    auto agree = [&]() {
+        float l = 0.f;
+        if (hipMemcpyAsync(&l, d_loss, 4, hipMemcpyDeviceToHost, st) != hipSuccess) return false;
+        if (hipStreamSynchronize(st) != hipSuccess) return false;
+        if (!(std::fabs(l - ref_loss) <= 1e-5f * std::fabs(ref_loss))) return false;
+        return outputs_agree(ICL_F32, gy[0], ref, (size_t)W * 4, W, N * F * H, d_stat, st, Agree::Max, 1e-5f);
+    };
+    return search(pb, tab, count, sets, make, agree, st);
 }
 
 // ------------------------------------------------------------------ tiny JSON reader for our own cache file
@@ -560,19 +757,24 @@ bool parse_cache(const std::string& text, std::map<std::string, Entry>& out) {
 
 }  // namespace
 
-void tune_cache_put(icl_op op, icl_dtype dt, int r, int W, int H, int variant, double us) {
-    const char* name = icl_variant_name(op, variant);
+void tune_cache_put(const Problem& p, int variant, double us) {
+    const char* name = icl_variant_name(p.op, variant);
     if (!name) return;
+    const std::string key = make_key(p);
     std::lock_guard<std::mutex> lk(g_mu);
-    g_cache[make_key(op, dt, r, W, H)] = Entry{name, us};
+    g_cache[key] = Entry{name, us};
 }
 
-int tune_cache_get(icl_op op, icl_dtype dt, int r, int W, int H) {
+int tune_cache_get(const Problem& p) {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (g_cache.empty()) return -1;
+    }
+    const std::string key = make_key(p);
     std::lock_guard<std::mutex> lk(g_mu);
-    if (g_cache.empty()) return -1;
-    auto it = g_cache.find(make_key(op, dt, r, W, H));
+    auto it = g_cache.find(key);
     if (it == g_cache.end()) return -1;
-    return index_of(op, it->second.variant);
+    return index_of(p.op, it->second.variant);
 }
 
 }  // namespace icl
@@ -592,9 +794,47 @@ icl_status icl_tune_model(icl_op op, icl_dtype dtype, int radius, int width, int
 }
 
 icl_status icl_tune(icl_op op, icl_dtype dtype, int radius, int width, int height, void* stream) {
-    if (width < 1 || height < 1) return ICL_ERR_INVALID_VALUE;
+    const icl_problem q{op, dtype, radius, width, height, 1, 1, 1};
+    return icl_tune_problem(&q, stream);
+}
+
+icl_status icl_tune_problem(const icl_problem* q, void* stream) {
+    if (!q) return ICL_ERR_INVALID_VALUE;
+    const Problem pb = problem_of(*q);
+    const icl_op op = pb.op;
+    const icl_dtype dtype = pb.dt;
+    const int radius = pb.r;
+    if (pb.W < 1 || pb.H < 1 || q->depth < 0 || q->n < 0 || q->f < 0) return ICL_ERR_INVALID_VALUE;
+    if (op == ICL_OP_CONV_SEP_BATCHED) return ICL_ERR_INVALID_VALUE;   // tuned per plan: icl_batch_plan_tune
     if (op == ICL_OP_CONV2D_U8 ? dtype != ICL_U8 : (dtype != ICL_F32 && dtype != ICL_F16 && dtype != ICL_BF16))
         return ICL_ERR_DTYPE;
+    // every argument is checked before the device is touched
+    switch (op) {
+        case ICL_OP_CONV_SEP: case ICL_OP_CONV2D:
+            if (radius < 0 || radius > ICL_MAX_RADIUS) return ICL_ERR_RADIUS;
+            break;
+        case ICL_OP_HARRIS: case ICL_OP_CORNERS:
+            if (radius < 0 || radius > ICL_MAX_WINDOW_RADIUS) return ICL_ERR_RADIUS;
+            if (dtype != ICL_F32) return ICL_ERR_DTYPE;
+            break;
+        case ICL_OP_NMS:
+            if (radius < 1 || radius > ICL_MAX_NMS_RADIUS) return ICL_ERR_RADIUS;
+            if (dtype != ICL_F32) return ICL_ERR_DTYPE;
+            break;
+        case ICL_OP_CONV2D_U8:
+            if (radius < 0 || radius > ICL_MAX_U8_RADIUS) return ICL_ERR_RADIUS;
+            break;
+        case ICL_OP_CONV3D_SEP:
+            if (radius < 0 || radius > ICL_MAX_RADIUS_3D) return ICL_ERR_RADIUS;
+            break;
+        case ICL_OP_BANK_FWD: case ICL_OP_BANK_BWD_INPUT: case ICL_OP_BANK_BWD_FILTER: case ICL_OP_BANK_FWD_SSE:
+            if (dtype != ICL_F32) return ICL_ERR_DTYPE;
+            if (radius < 1 || radius > 4) return ICL_ERR_RADIUS;
+            if (pb.F > 64) return ICL_ERR_UNSUPPORTED;
+            break;
+        case ICL_OP_SSE_LOSS: break;
+        default: return ICL_ERR_INVALID_VALUE;
+    }
     icl_status s = device_ready();
     if (s != ICL_OK) return s;
     hipStream_t st = (hipStream_t)stream;
@@ -603,32 +843,32 @@ icl_status icl_tune(icl_op op, icl_dtype dtype, int radius, int width, int heigh
     switch (op) {
         case ICL_OP_CONV_SEP:
         case ICL_OP_CONV2D:
-            if (radius < 0 || radius > ICL_MAX_RADIUS) return ICL_ERR_RADIUS;
-            s = tune_conv(op, dtype, radius, width, height, st);
+            s = tune_conv(pb, st);
             break;
         case ICL_OP_HARRIS:
-            if (radius < 0 || radius > ICL_MAX_WINDOW_RADIUS) return ICL_ERR_RADIUS;
-            if (dtype != ICL_F32) return ICL_ERR_DTYPE;
-            s = tune_harris(radius, width, height, st);
+            s = tune_harris(pb, st);
             break;
         case ICL_OP_CORNERS:
-            if (radius < 0 || radius > ICL_MAX_WINDOW_RADIUS) return ICL_ERR_RADIUS;
-            if (dtype != ICL_F32) return ICL_ERR_DTYPE;
-            if (radius > 3) return ICL_OK;   // only the two-kernel variant: nothing to choose
-            s = tune_corners(radius, width, height, st);
+            if (radius > 3) return ICL_OK;   // only the two-kernel variant runs such windows: nothing to choose
+            s = tune_corners(pb, st);
             break;
         case ICL_OP_CONV2D_U8:
-            if (radius < 0 || radius > ICL_MAX_U8_RADIUS) return ICL_ERR_RADIUS;
-            s = tune_conv_u8(radius, width, height, st);
+            s = tune_conv_u8(pb, st);
             break;
         case ICL_OP_NMS:
-            if (radius < 1 || radius > ICL_MAX_NMS_RADIUS) return ICL_ERR_RADIUS;
-            if (dtype != ICL_F32) return ICL_ERR_DTYPE;
-            s = tune_nms(radius, width, height, st);
+            s = tune_nms(pb, st);
             break;
-        case ICL_OP_CONV_SEP_BATCHED: case ICL_OP_BANK_FWD: case ICL_OP_BANK_BWD_INPUT: case ICL_OP_BANK_BWD_FILTER:
+        case ICL_OP_CONV3D_SEP:
+            s = tune_sep3d(pb, st);
+            break;
+        case ICL_OP_BANK_FWD: case ICL_OP_BANK_BWD_INPUT: case ICL_OP_BANK_BWD_FILTER:
+            s = tune_bank(pb, st);
+            break;
+        case ICL_OP_BANK_FWD_SSE:
+            s = tune_bank_sse(pb, st);
+            break;
         case ICL_OP_SSE_LOSS:
-            return ICL_OK;   // a single variant: nothing to choose
+            return ICL_OK;   // one variant (the fixed-order two-stage reduction): nothing to choose
         default: return ICL_ERR_INVALID_VALUE;
     }
     hipStreamSynchronize(st);

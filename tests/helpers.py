@@ -7,6 +7,10 @@ Tolerances (stated per result):
   float16 storage : normwise error against the FP64 oracle <= 2e-3 (binary16's
                     half-ulp is 4.9e-4 relative, so the budget covers one output
                     rounding plus float32 accumulation).
+  Harris response : |R_gpu - R| <= D(p), the oracle's bound on the rounding error of any
+                    float32 evaluation order of the chain (Sobel, products, window,
+                    response; oracle.harris_f32_bound).  The same D decides which
+                    corner-mask pixels rounding may flip (nms_ambiguous).
   bfloat16 storage: |y_gpu - y| <= ulp_bf16(y) + 1e-5 * S: at most one bfloat16
                     ulp of output rounding on top of the float32 accumulation
                     budget.  (bfloat16's own half-ulp, up to 2^-8 = 3.9e-3
@@ -103,3 +107,21 @@ def ulp_bf16(y: np.ndarray) -> np.ndarray:
 
 def bf16_violations(got: np.ndarray, ref64: np.ndarray, scale: np.ndarray) -> int:
     return int(np.sum(np.abs(got - ref64) > ulp_bf16(ref64) + 1e-5 * scale))
+
+
+def nms_ambiguous(R: np.ndarray, D: np.ndarray, tau: float, radius: int = 1) -> np.ndarray:
+    """Pixels whose 3x3 (or (2r+1)^2) NMS decision float32 rounding of the response may flip:
+    |R - tau| <= D(p), or |R(p) - R(q)| <= D(p) + D(q) for a clamped neighbour q other than p
+    itself (a neighbour clamped onto p compares R(p) >= R(p), which no rounding changes).
+    Elsewhere the mask of a response within D of R equals the mask of R."""
+    H, W = R.shape
+    amb = np.abs(R - tau) <= D
+    for dy in range(-radius, radius + 1):
+        for dx in range(-radius, radius + 1):
+            if dx == 0 and dy == 0:
+                continue
+            yy = np.clip(np.arange(H)[:, None] + dy, 0, H - 1)
+            xx = np.clip(np.arange(W)[None, :] + dx, 0, W - 1)
+            other = (yy != np.arange(H)[:, None]) | (xx != np.arange(W)[None, :])
+            amb |= other & (np.abs(R - R[yy, xx]) <= D + D[yy, xx])
+    return amb

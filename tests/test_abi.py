@@ -315,3 +315,87 @@ def test_tune_cache_file_roundtrip_and_corruption(L, tmp_path):
     st, idx = B.icl_selected_variant(B.ICL_OP_CONV2D, B.ICL_F32, 3, 1024, 1024)
     assert st == B.ICL_OK and idx == 1      # the default (first LDS variant), not the foreign entry
     B.icl_tune_clear()
+
+
+def test_math_mode_and_variant_arithmetic(L):
+    assert B.icl_get_math() == B.ICL_MATH_F32
+    assert B.icl_set_math(2) == B.ICL_ERR_INVALID_VALUE and B.icl_get_math() == B.ICL_MATH_F32
+    names = B.variant_names(B.ICL_OP_CONV2D)
+    for i, n in enumerate(names):
+        want = "fp16x3_mfma" if n.startswith("mfma_f16") else "fp32_valu"
+        assert B.icl_variant_arith(B.ICL_OP_CONV2D, i) == want, n
+    for op in (B.ICL_OP_BANK_FWD, B.ICL_OP_BANK_BWD_FILTER, B.ICL_OP_BANK_FWD_SSE):
+        for i, n in enumerate(B.variant_names(op)):
+            assert B.icl_variant_arith(op, i) == ("fp32_mfma" if "mfma" in n else "fp32_valu"), n
+    assert all(B.icl_variant_arith(B.ICL_OP_CONV2D_U8, i) == "int32_valu"
+               for i in range(B.icl_variant_count(B.ICL_OP_CONV2D_U8)))
+    assert B.icl_variant_arith(B.ICL_OP_CONV2D, len(names)) is None
+
+
+def _cache_with(tmp_path, key_tail, variant):
+    p = tmp_path / "cache.json"
+    p.write_text('{"version": 1, "entries": [\n  {"key": "unknown|0|%s", "variant": "%s", "us": 1.0}\n]}\n'
+                 % (key_tail, variant))
+    return str(p)
+
+
+def test_split_arithmetic_is_selected_only_after_opting_in(no_gpu, tmp_path):
+    """A tuned entry that names the float16-split variant is never selected in the float32 mode:
+    cache keys carry the arithmetic mode, and a selection re-checks the variant's arithmetic."""
+    idx = B.variant_names(B.ICL_OP_CONV2D).index("mfma_f16x3")
+    side = 4096
+    sc = (side * side).bit_length() - 1
+    try:
+        for mode in (0, 1):   # an entry under each mode's key, both naming the split variant
+            assert B.icl_tune_load(_cache_with(tmp_path, f"conv2d|0|7|{sc}|f1|m{mode}", "mfma_f16x3")) == B.ICL_OK
+        st, got = B.icl_selected_variant(B.ICL_OP_CONV2D, B.ICL_F32, 7, side, side)
+        assert st == B.ICL_OK and got == 1          # float32 mode: the default FMA tile
+        assert B.icl_set_math(B.ICL_MATH_F16_SPLIT) == B.ICL_OK
+        st, got = B.icl_selected_variant(B.ICL_OP_CONV2D, B.ICL_F32, 7, side, side)
+        assert st == B.ICL_OK and got == idx        # opted in: the tuned split variant
+        B.icl_tune_clear()
+        assert B.icl_tune_load(_cache_with(tmp_path, f"conv2d|0|7|{sc}|f1|m0", "lds_p4x8_o0")) == B.ICL_OK
+        st, got = B.icl_selected_variant(B.ICL_OP_CONV2D, B.ICL_F32, 7, side, side)
+        assert got == 1                             # an entry of the other mode does not apply
+    finally:
+        B.icl_set_math(B.ICL_MATH_F32)
+        B.icl_tune_clear()
+
+
+def test_problem_tuning_validation(no_gpu):
+    P = B.icl_tune_problem
+    assert B.lib().icl_tune_problem(None, None) == B.ICL_ERR_INVALID_VALUE
+    assert P(B.ICL_OP_CONV_SEP_BATCHED, B.ICL_F16, 2, 64, 64) == B.ICL_ERR_INVALID_VALUE   # tuned per plan
+    assert P(B.ICL_OP_BANK_FWD, B.ICL_F32, 5, 64, 64, n=2, f=4) == B.ICL_ERR_RADIUS
+    assert P(B.ICL_OP_BANK_FWD, B.ICL_F32, 4, 64, 64, n=2, f=65) == B.ICL_ERR_UNSUPPORTED
+    assert P(B.ICL_OP_BANK_BWD_FILTER, B.ICL_F16, 4, 64, 64, n=2, f=4) == B.ICL_ERR_DTYPE
+    assert P(B.ICL_OP_CONV3D_SEP, B.ICL_F32, 8, 64, 64, depth=8) == B.ICL_ERR_RADIUS
+    assert P(B.ICL_OP_CONV2D, B.ICL_F32, 2, 0, 64) == B.ICL_ERR_INVALID_VALUE
+    assert P(B.ICL_OP_BANK_FWD_SSE, B.ICL_F32, 4, 64, 64, n=2, f=16) == B.ICL_ERR_NO_DEVICE
+    assert P(B.ICL_OP_CONV3D_SEP, B.ICL_F32, 1, 64, 64, depth=64) == B.ICL_ERR_NO_DEVICE
+    # defaults of the problem form: the matrix-core forward and filter adjoint up to 16 filters
+    st, v = B.icl_selected_variant_problem(B.ICL_OP_BANK_FWD, B.ICL_F32, 4, 1024, 1024, n=32, f=16)
+    assert st == B.ICL_OK and B.icl_variant_name(B.ICL_OP_BANK_FWD, v) == "mfma_t64"
+    st, v = B.icl_selected_variant_problem(B.ICL_OP_BANK_BWD_FILTER, B.ICL_F32, 4, 1024, 1024, n=32, f=32)
+    assert st == B.ICL_OK and B.icl_variant_name(B.ICL_OP_BANK_BWD_FILTER, v) == "block4_t64x256"
+    assert B.icl_batch_plan_tune(0) == B.ICL_ERR_INVALID_VALUE
+    assert B.icl_batch_plan_variant(0)[0] == B.ICL_ERR_INVALID_VALUE
+
+
+def test_tune_environment_modes(tmp_path):
+    """ICL_TUNE_CACHE is loaded at the first selection; ICL_TUNE=off ignores it (fresh processes,
+    since the environment is read once)."""
+    import subprocess
+    import sys
+    side = 1024
+    sc = (side * side).bit_length() - 1
+    path = _cache_with(tmp_path, f"conv2d|0|3|{sc}|f1|m0", "pers_p8x2")
+    code = ("import sys; sys.path.insert(0, %r); from paper_1605_06399_amd import binding as B; "
+            "print(B.icl_variant_name(B.ICL_OP_CONV2D, B.icl_selected_variant(B.ICL_OP_CONV2D, B.ICL_F32, 3, %d, %d)[1]))"
+            % (ROOT, side, side))
+    env = dict(os.environ, ICL_TUNE_CACHE=path, HIP_VISIBLE_DEVICES="")
+    for mode, want in (("cache", "pers_p8x2"), ("off", "lds_p4x4_o0")):
+        out = subprocess.run([sys.executable, "-c", code], env=dict(env, ICL_TUNE=mode), capture_output=True,
+                             text=True, timeout=120)
+        assert out.returncode == 0, out.stderr
+        assert out.stdout.strip() == want, (mode, out.stdout, out.stderr)

@@ -245,19 +245,54 @@ def test_mfma_variant_power_of_two_scaling(force, r, img_exp, tap_exp):
     assert_close(out, oracle.conv2d(x64, w64), oracle.normwise_scale_conv2d(x64, w64), "f32", f"mfma 2^{img_exp} 2^{tap_exp}")
 
 
+def _wide_contrast(seed, H, W):
+    """U[0,1) image whose right half is scaled by 2^-30: windows there sit 2^30 below the
+    brightest pixel of tiles that straddle the step."""
+    img = synth.image_uniform(seed, H, W).astype(np.float64)
+    img[:, W // 2:] *= 2.0 ** -30
+    return img.astype(np.float32)
+
+
+@pytest.mark.parametrize("r", [2, 5, 7])
+def test_float32_mode_variants_meet_1e5_at_wide_contrast(force, r):
+    """In the default float32 arithmetic mode the tuner may pick every variant but the float16
+    split one; each of them meets the float32 normwise tolerance 1e-5 on an image spanning 2^30
+    in contrast, and the tuner's choice is one of them."""
+    assert B.icl_get_math() == B.ICL_MATH_F32
+    H, W = 130, 200
+    img = _wide_contrast(50, H, W)
+    w = taps_2d(r)
+    xd, x64 = storage(img, "f32")
+    w64 = w.astype(np.float64)
+    ref, S = oracle.conv2d(x64, w64), oracle.normwise_scale_conv2d(x64, w64)
+    for i in range(B.icl_variant_count(B.ICL_OP_CONV2D)):
+        if B.icl_variant_arith(B.ICL_OP_CONV2D, i) == "fp16x3_mfma":
+            continue
+        force(B.ICL_OP_CONV2D, i)
+        out = T.conv2d(xd, dev_taps(w).view(w.shape))
+        torch.cuda.synchronize()
+        assert_close(out, ref, S, "f32", f"variant {i} r{r} at 2^-30 contrast")
+    B.icl_force_variant(B.ICL_OP_CONV2D, -1)
+    try:
+        B.check(B.icl_tune(B.ICL_OP_CONV2D, B.ICL_F32, r, 1024, 1024), "tune")
+        st, idx = B.icl_selected_variant(B.ICL_OP_CONV2D, B.ICL_F32, r, 1024, 1024)
+        assert st == B.ICL_OK and B.icl_variant_arith(B.ICL_OP_CONV2D, idx) == "fp32_valu"
+    finally:
+        B.icl_tune_clear()
+
+
 @pytest.mark.parametrize("r", [2, 7])
 def test_mfma_variant_wide_range_bound(force, r):
-    """Dark regions 2^-30 below a bright one in the same tile: every output is within the
-    variant's stated operand bound 2^-20 S + 2^-37 (2r+1)^2 M max|w| (plus the float32
-    accumulation allowance 1e-5 S of every variant)."""
+    """The float16-split variant runs only when forced or after opting into ICL_MATH_F16_SPLIT,
+    whose stated accuracy it is tested against here: dark regions 2^-30 below a bright one in
+    the same tile stay within the operand bound 2^-20 S + 2^-37 (2r+1)^2 M max|w| (plus the
+    float32 accumulation allowance 1e-5 S of every variant)."""
     idx = _mfma_index()
     if idx is None:
         pytest.skip("no matrix-core variant")
     force(B.ICL_OP_CONV2D, idx)
     H, W = 130, 200
-    img = synth.image_uniform(50, H, W).astype(np.float64)
-    img[:, W // 2:] *= 2.0 ** -30
-    img = img.astype(np.float32)
+    img = _wide_contrast(50, H, W)
     w = taps_2d(r)
     xd, x64 = storage(img, "f32")
     out = to_host(T.conv2d(xd, dev_taps(w).view(w.shape)))
@@ -267,3 +302,47 @@ def test_mfma_variant_wide_range_bound(force, r):
     M = float(np.abs(x64).max())
     bound = 1e-5 * S + 2.0 ** -20 * S + 2.0 ** -37 * (2 * r + 1) ** 2 * M * float(np.abs(w64).max())
     assert np.all(np.abs(out - ref) <= bound)
+
+
+def test_split_mode_opt_in_tunes_every_candidate():
+    """After opting into ICL_MATH_F16_SPLIT the tuner's candidates include the split variant; the
+    choice is cached under that mode only, and going back to float32 never selects it."""
+    W = H = 1024
+    try:
+        B.check(B.icl_set_math(B.ICL_MATH_F16_SPLIT))
+        B.check(B.icl_tune(B.ICL_OP_CONV2D, B.ICL_F32, 7, W, H), "tune split mode")
+        st, idx_split = B.icl_selected_variant(B.ICL_OP_CONV2D, B.ICL_F32, 7, W, H)
+        assert st == B.ICL_OK and idx_split >= 1
+        B.check(B.icl_set_math(B.ICL_MATH_F32))
+        st, idx = B.icl_selected_variant(B.ICL_OP_CONV2D, B.ICL_F32, 7, W, H)
+        assert B.icl_variant_arith(B.ICL_OP_CONV2D, idx) == "fp32_valu"
+    finally:
+        B.icl_set_math(B.ICL_MATH_F32)
+        B.icl_tune_clear()
+
+
+def test_single_image_512_gaussian_whole_image(force):
+    """The single-image workload: 512^2 float32 U[0,1) (seed config 1), the 5-tap Gaussian sigma = 1
+    in both passes, clamped; the plain two-pass kernel, every fused variant and the tuned choice
+    against the oracle over the whole image."""
+    H = W = 512
+    img = synth.image_uniform(1, H, W)
+    g = synth.gaussian_taps(2, 1.0)
+    xd, x64 = storage(img, "f32")
+    ref, sc = oracle.conv_sep(x64, g, g), oracle.normwise_scale_sep(x64, g, g)
+    _, nb = B.icl_workspace_size(B.ICL_OP_CONV_SEP, W, H)
+    ws = torch.empty(nb // 4 + 1, dtype=torch.float32, device="cuda")
+    tg = dev_taps(g)
+    for i in range(B.icl_variant_count(B.ICL_OP_CONV_SEP)):
+        force(B.ICL_OP_CONV_SEP, i)
+        out = T.conv_sep(xd, tg, tg, workspace=ws)
+        torch.cuda.synchronize()
+        assert_close(out, ref, sc, "f32", f"512^2 gaussian, variant {i}")
+    B.icl_force_variant(B.ICL_OP_CONV_SEP, -1)
+    try:
+        B.check(B.icl_tune(B.ICL_OP_CONV_SEP, B.ICL_F32, 2, W, H), "tune")
+        out = T.conv_sep(xd, tg, tg, workspace=ws)
+        torch.cuda.synchronize()
+        assert_close(out, ref, sc, "f32", "512^2 gaussian, tuned")
+    finally:
+        B.icl_tune_clear()

@@ -3,7 +3,8 @@
 Every variant runs with the response written too, so that two exact checks apply:
   * the mask is the oracle's NMS of the kernel's own response, bit for bit (the NMS
     decision takes float32 values, which double holds exactly);
-  * the response matches the oracle's Harris response within the Harris tolerance.
+  * the response matches the oracle's Harris response within the oracle's bound on the
+    rounding error of a float32 evaluation of the chain.
 The single-pass variants must also agree with each other byte for byte (mask) and bit for
 bit (response), with and without the response output, and on padded or misaligned images.
 """
@@ -44,8 +45,8 @@ def corner_image(seed, H, W):
 
 def check_against_oracle(img64, g, R, M, what):
     Rr = oracle.harris(img64, g, float(K))
-    err = normwise(to_host(R), Rr, oracle.harris_scale(img64, g, float(K)))
-    assert err <= 1e-5, f"{what}: response normwise {err:.3e}"
+    err = normwise(to_host(R), Rr, oracle.harris_f32_bound(img64, g, float(K)))
+    assert err <= 1.0, f"{what}: response error {err:.3f} x the float32 bound"
     own = oracle.nms(to_host(R), float(TAU))
     got = M.cpu().numpy()
     assert np.array_equal(got, own), f"{what}: mask differs from NMS of its own response at {np.argwhere(got != own)[:5]}"

@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 from conftest import gpu_available
-from helpers import empty_padded, normwise, padded_view, storage, to_host
+from helpers import empty_padded, nms_ambiguous, normwise, padded_view, storage, to_host
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
@@ -71,8 +71,8 @@ def test_harris_variants(variant, rg):
             R = T.harris(xd, dev(g), float(K), workspace=harris_ws(H, W))
             torch.cuda.synchronize()
             Rr = oracle.harris(x64, g, float(K))
-            err = normwise(to_host(R), Rr, oracle.harris_scale(x64, g, float(K)))
-            assert err <= 1e-5, f"harris v{variant} rg{rg} {H}x{W}: normwise {err:.3e}"
+            err = normwise(to_host(R), Rr, oracle.harris_f32_bound(x64, g, float(K)))
+            assert err <= 1.0, f"harris v{variant} rg{rg} {H}x{W}: error {err:.3f} x the float32 bound"
     finally:
         B.icl_force_variant(B.ICL_OP_HARRIS, -1)
 
@@ -85,7 +85,7 @@ def test_harris_large_window_uses_split_path():
     R = T.harris(xd, dev(g), float(K))
     torch.cuda.synchronize()
     Rr = oracle.harris(x64, g, float(K))
-    assert normwise(to_host(R), Rr, oracle.harris_scale(x64, g, float(K))) <= 1e-5
+    assert normwise(to_host(R), Rr, oracle.harris_f32_bound(x64, g, float(K))) <= 1.0
 
 
 @pytest.mark.parametrize("variant", range(N_HARRIS))
@@ -128,14 +128,14 @@ def test_harris_strip_variants_refuse_unaligned_rows():
             B.icl_force_variant(B.ICL_OP_HARRIS, -1)
     R = T.harris(xv, dev(g), float(K))
     torch.cuda.synchronize()
-    assert normwise(to_host(R), ref, oracle.harris_scale(x64, g, float(K))) <= 1e-5
+    assert normwise(to_host(R), ref, oracle.harris_f32_bound(x64, g, float(K))) <= 1.0
     # an odd width in rows padded to a 16-byte pitch: the strips take it
     H, W = 45, 517
     img = synth.image_with_rectangles(54, H, W, count=5)
     xd, x64 = storage(img, "f32")
     xv = padded_view(xd, 3, 0)
     out = empty_padded(H, W, torch.float32, 7, 0)
-    ref, sc = oracle.harris(x64, g, float(K)), oracle.harris_scale(x64, g, float(K))
+    ref, sc = oracle.harris(x64, g, float(K)), oracle.harris_f32_bound(x64, g, float(K))
     for v in range(B.icl_variant_count(B.ICL_OP_HARRIS)):
         if not B.icl_variant_name(B.ICL_OP_HARRIS, v).startswith("stream"):
             continue
@@ -143,7 +143,7 @@ def test_harris_strip_variants_refuse_unaligned_rows():
         try:
             R = T.harris(xv, dev(g), float(K), out=out)
             torch.cuda.synchronize()
-            assert normwise(to_host(R), ref, sc) <= 1e-5, f"variant {v} padded pitch"
+            assert normwise(to_host(R), ref, sc) <= 1.0, f"variant {v} padded pitch"
         finally:
             B.icl_force_variant(B.ICL_OP_HARRIS, -1)
 
@@ -212,9 +212,9 @@ def test_nms_bit_exact(variant, radius):
 
 
 def test_harris_nms_pipeline_masks_agree_away_from_ties():
-    """Corner masks from GPU responses vs oracle responses.  Where float rounding decides the mask
-    (R within its error bound of tau or of a neighbour) both answers are correct; everywhere else the
-    masks must be identical."""
+    """Corner masks from GPU responses vs oracle responses.  Where float rounding may decide the
+    mask (R within its float32 error bound of tau or of a neighbour) both answers are correct;
+    everywhere else the masks must be identical.  The bound leaves under 1% of pixels open."""
     H, W = 600, 500
     img = synth.image_with_rectangles(3, H, W, count=12)
     g = synth.gaussian_taps(2, 1.0)
@@ -223,17 +223,13 @@ def test_harris_nms_pipeline_masks_agree_away_from_ties():
     M = T.nms(R, float(TAU))
     torch.cuda.synchronize()
     Rr = oracle.harris(x64, g, float(K))
+    D = oracle.harris_f32_bound(x64, g, float(K))
+    assert normwise(to_host(R), Rr, D) <= 1.0
     ref = oracle.nms(Rr, float(TAU))
-    delta = 1e-5 * oracle.harris_scale(x64, g, float(K))
-    amb = np.abs(Rr - float(TAU)) <= delta
-    for dy in (-1, 0, 1):
-        for dx in (-1, 0, 1):
-            if dx == 0 and dy == 0:
-                continue
-            yy = np.clip(np.arange(H)[:, None] + dy, 0, H - 1)
-            xx = np.clip(np.arange(W)[None, :] + dx, 0, W - 1)
-            amb |= np.abs(Rr - Rr[yy, xx]) <= delta + delta[yy, xx]
+    amb = nms_ambiguous(Rr, D, float(TAU))
     got = M.cpu().numpy()
     assert ref.sum() > 20
     assert np.array_equal(got[~amb], ref[~amb]), f"{np.sum(got[~amb] != ref[~amb])} unambiguous mismatches"
-    print(f"pipeline: {ref.sum()} corners, {amb.sum()} ambiguous pixels")
+    frac = float(amb.mean())
+    print(f"pipeline: {ref.sum()} corners, {amb.sum()} ambiguous pixels ({100 * frac:.2f}%)")
+    assert frac <= 0.01, f"{100 * frac:.2f}% of pixels ambiguous"

@@ -551,6 +551,72 @@ def test_harris_scale_bounds_and_homogeneity(orc):
     assert np.allclose(orc.harris_scale(3.0 * X, G5, K), 81.0 * S, rtol=1e-12)
 
 
+def _bound_cases():
+    H, W = 96, 113
+    u = synth.image_uniform(24, H, W)
+    wide = np.where(np.arange(W)[None, :] < W // 2, np.float32(2.0 ** 20), np.float32(2.0 ** -20))
+    return [("rectangles", synth.image_with_rectangles(25, H, W, count=4)),
+            ("uniform", u),
+            ("near_flat", (np.float32(0.5) + u * np.float32(2.0 ** -18)).astype(np.float32)),
+            ("wide_range", (u * wide).astype(np.float32))]
+
+
+@pytest.mark.parametrize("rg", [0, 1, 2, 3])
+def test_harris_f32_bound_covers_float32_evaluations(orc, rg):
+    """The float32 rounding bound holds for honest float32 evaluations of the chain in 18
+    summation orders, for window radius 0..3, on rectangles, noise, a nearly flat image and an
+    image spanning 2^40 in contrast; and it is not loose by orders of magnitude (the worst
+    evaluation reaches at least 1% of it)."""
+    from f32_chain import ORDERS, harris32
+    g = synth.gaussian_taps(rg, max(rg, 1) / 2.0 if rg != 2 else 1.0)
+    k = float(np.float32(K))
+    for name, img in _bound_cases():
+        X = img.astype(np.float64)
+        R = orc.harris(X, g, k)
+        D = orc.harris_f32_bound(X, g, k)
+        assert np.all(D > 0), name
+        worst = 0.0
+        for so, wo, ro in ORDERS:
+            d = np.abs(harris32(img, g, k, so, wo, ro).astype(np.float64) - R)
+            worst = max(worst, float(np.max(d / D)))
+        assert worst <= 1.0, f"{name} rg{rg}: float32 evaluation at {worst:.3f} x the bound"
+        assert worst >= 0.01, f"{name} rg{rg}: the bound is {1 / max(worst, 1e-300):.0f} x the worst error"
+
+
+def test_harris_f32_bound_detects_lower_precision(orc):
+    """A chain whose window taps lose precision (rounded to bfloat16, 8 significant bits) or whose
+    Sobel sums run in float16 leaves the bound: it separates float32 arithmetic from less."""
+    from f32_chain import harris32
+    import torch
+    img = synth.image_with_rectangles(26, 80, 90, count=3)
+    X = img.astype(np.float64)
+    k = float(np.float32(K))
+    D = orc.harris_f32_bound(X, G5, k)
+    R = orc.harris(X, G5, k)
+    g_bf16 = torch.from_numpy(G5.astype(np.float32)).to(torch.bfloat16).float().numpy()
+    R1 = orc.harris(X, g_bf16.astype(np.float64), k)
+    assert np.mean(np.abs(R1 - R) > D) > 0.5
+    img16 = img.astype(np.float16).astype(np.float32)
+    R2 = harris32(img16, G5, k).astype(np.float64)
+    assert np.mean(np.abs(R2 - R) > D) > 0.5
+
+
+def test_harris_f32_bound_scaling_and_corner_workload(orc):
+    """The bound is homogeneous of degree 4 (exact under a power-of-two scaling of the image), and
+    on the corner workload (noise plus bright rectangles) it is far below the absolute-value
+    scale: at most 1e-2 of it everywhere, and under 1% of the pixels' NMS decisions overlap."""
+    from helpers import nms_ambiguous
+    k, tau = float(np.float32(K)), float(np.float32(1e-3))
+    img = synth.image_with_rectangles(3, 384, 416, count=12)
+    X = img.astype(np.float64)
+    D = orc.harris_f32_bound(X, G5, k)
+    assert np.array_equal(orc.harris_f32_bound(4.0 * X, G5, k), 256.0 * D)
+    S = orc.harris_scale(X, G5, k)
+    assert np.max(D / S) <= 1e-2
+    R = orc.harris(X, G5, k)
+    assert np.mean(nms_ambiguous(R, D, tau)) <= 0.01
+
+
 def test_harris_transpose(orc):
     X = synth.image_uniform(22, 17, 23).astype(np.float64)
     assert np.allclose(orc.harris(X.T.copy(), G5, K), orc.harris(X, G5, K).T, rtol=1e-12, atol=1e-12)
