@@ -207,10 +207,12 @@ def main():
         B.check(B.icl_tune(op, B.ICL_F32, r, side, side, stream.cuda_stream), "icl_tune")
     torch.cuda.synchronize()
     t_tune = time.perf_counter() - t_tune
-    chosen = {}
+    chosen, arith = {}, {}
     for kind, r in calls:
         op = B.ICL_OP_CONV_SEP if kind == "sep" else B.ICL_OP_CONV2D
-        chosen[f"{kind}{r}"] = B.icl_variant_name(op, B.icl_selected_variant(op, B.ICL_F32, r, side, side)[1])
+        vi = B.icl_selected_variant(op, B.ICL_F32, r, side, side)[1]
+        chosen[f"{kind}{r}"] = B.icl_variant_name(op, vi)
+        arith[f"{kind}{r}"] = B.icl_variant_arith(op, vi)
 
     def run(steps, warmup, label):
         """Time `steps` steps.  The calls of the steps run grouped by call (all launches of one
@@ -247,22 +249,25 @@ def main():
     B.icl_force_variant(B.ICL_OP_CONV2D, -1)
 
     px = side * side
+    ceiling = copy_ceiling(torch, dev)
+    copy_gbs = ceiling["64MiB"]["GB_s"]     # a copy of the same bytes as one call (64 MiB in, 64 MiB out)
     per_op = []
     for kind, r in calls:
         us, usp = per_tuned[(kind, r)], per_plain[(kind, r)]
         gpx = px / (us * 1e-6) / 1e9
         roof, bound = roof_gpx(kind, r)
-        if chosen[f"{kind}{r}"].startswith("mfma"):
+        if arith[f"{kind}{r}"] == "fp16x3_mfma":
             roof, bound = FP16_MFMA_PEAK_TFLOPS * 1e3 / flops_per_px(kind, r), "mfma"
-        per_op.append({"call": f"{kind}{r}", "variant": chosen[f"{kind}{r}"], "us": round(us, 2),
-                       "gpx_s": round(gpx, 1), "hbm_frac": round(gpx * 8 / HBM_PEAK_GBS, 3),
+        per_op.append({"call": f"{kind}{r}", "variant": chosen[f"{kind}{r}"], "arith": arith[f"{kind}{r}"],
+                       "us": round(us, 2), "gpx_s": round(gpx, 1), "hbm_frac": round(gpx * 8 / HBM_PEAK_GBS, 3),
+                       "copy_frac": round(gpx * 8 / copy_gbs, 3),
                        "binding_roof": bound, "roof_frac": round(gpx / roof, 3),
                        "plain_us": round(usp, 2), "speedup_vs_plain": round(usp / us, 2)})
     dom = max(calls, key=lambda c: per_tuned[c])
     kind, r = dom
     us = per_tuned[dom]
     _, bound = roof_gpx(kind, r)
-    if chosen[f"{kind}{r}"].startswith("mfma"):
+    if arith[f"{kind}{r}"] == "fp16x3_mfma":
         # the matrix-core variant: FP16 MFMAs (hi/lo split) against the dense FP16 matrix peak;
         # executed = 3 products x 2 flop x 32 band columns x (2r+1) tap rows per pixel
         achieved = flops_per_px(kind, r) * px / (us * 1e-6) / 1e12
@@ -300,6 +305,10 @@ def main():
         "plain": {"value": round(plain_value, 2), "ms_per_step": round(dt_plain * 1e3, 4),
                   "tuned_speedup": round(dt_plain / dt_tuned, 2)},
         "hbm_frac_step": round(value * 8 / HBM_PEAK_GBS, 3),
+        "copy_frac_step": round(value * 8 / copy_gbs, 3),
+        "math_mode": "fp32" if B.icl_get_math() == B.ICL_MATH_F32 else "fp16_split",
+        "arith_per_call": sorted(set(arith.values())),
+        "copy_ceiling": ceiling,
         "tune_seconds": round(t_tune, 2),
         "per_call": per_op,
         "roofline": roofline,
@@ -325,6 +334,33 @@ def main():
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(synth, radii, side)
     print(json.dumps(out), flush=True)
+
+
+def copy_ceiling(torch, dev, reps=10):
+    """Achievable copy bandwidth: device-to-device copies (the runtime's copy kernel) of 64 MiB,
+    256 MiB and 2 GiB, rotating over enough source/destination pairs that the 256 MB Infinity Cache
+    cannot hold them (1 GiB or more in flight), events around `reps` copies each.  GB/s counts the
+    bytes read plus the bytes written."""
+    out = {}
+    for label, nbytes, pairs in (("64MiB", 64 << 20, 8), ("256MiB", 256 << 20, 4), ("2GiB", 2 << 30, 1)):
+        n = nbytes // 4
+        srcs = [torch.ones(n, dtype=torch.float32, device=dev) for _ in range(pairs)]
+        dsts = [torch.empty_like(srcs[0]) for _ in range(pairs)]
+        for k in range(2 * pairs):
+            dsts[k % pairs].copy_(srcs[k % pairs])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(reps):
+            dsts[k % pairs].copy_(srcs[k % pairs])
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        out[label] = {"us": round(us, 2), "GB_s": round(2 * nbytes / (us * 1e-6) / 1e9, 1),
+                      "frac_of_peak": round(2 * nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 3)}
+        del srcs, dsts
+        torch.cuda.empty_cache()
+    return out
 
 
 def _time(torch, fn, steps, warmup=2):
@@ -398,6 +434,8 @@ def extra_volume(torch, B, T, synth, steps):
         def call(s):
             T.conv3d_sep(xs[s % 2], tx, ty, tz, out=ys[s % 2], workspace=ws)
 
+        B.check(B.icl_tune_problem(B.ICL_OP_CONV3D_SEP, B.ICL_F32, r, side, side, depth=side,
+                                   stream=torch.cuda.current_stream().cuda_stream), "tune volume")
         per_variant = {}
         for v in range(B.icl_variant_count(B.ICL_OP_CONV3D_SEP)):
             B.check(B.icl_force_variant(B.ICL_OP_CONV3D_SEP, v))
@@ -411,8 +449,8 @@ def extra_volume(torch, B, T, synth, steps):
         res[f"volume_sep3d_r{r}_256_f32"] = {
             "us": round(dt * 1e6, 2), "gvoxel_s": round(gvx, 1), "bytes_per_voxel": 8,
             "hbm_frac": round(gvx * 8 / HBM_PEAK_GBS, 3),
-            "variant": B.icl_variant_name(B.ICL_OP_CONV3D_SEP, B.icl_selected_variant(
-                B.ICL_OP_CONV3D_SEP, B.ICL_F32, r, side, side)[1]),
+            "variant": B.icl_variant_name(B.ICL_OP_CONV3D_SEP, B.icl_selected_variant_problem(
+                B.ICL_OP_CONV3D_SEP, B.ICL_F32, r, side, side, depth=side)[1]),
             "variants_us": per_variant}
     del xs, ys, ws
     torch.cuda.empty_cache()
@@ -653,14 +691,17 @@ def extra_batch(torch, B, T, synth, steps):
                     _time(torch, lambda s: plan.launch(), steps) * 1e3, 3)
             finally:
                 B.icl_force_variant(B.ICL_OP_CONV_SEP_BATCHED, -1)
-        plan.graph()   # the default variant, captured once and replayed
+        t0 = time.perf_counter()
+        plan.tune()    # per-device choice of the walk for this plan
+        tune_s = time.perf_counter() - t0
+        plan.graph()   # the tuned walk, captured once and replayed
         dt = _time(torch, lambda s: plan.replay(), steps)
         gpx = plan.pixels / dt / 1e9
         res[f"batch256_{name}"] = {"ms": round(dt * 1e3, 3), "gpx_s": round(gpx, 1), "pixels": plan.pixels,
                                    "tiles": plan.tiles, "bytes_per_px": 4,
                                    "hbm_frac": round(gpx * 4 / HBM_PEAK_GBS, 3),
-                                   "variant": B.icl_variant_name(B.ICL_OP_CONV_SEP_BATCHED, B.icl_selected_variant(
-                                       B.ICL_OP_CONV_SEP_BATCHED, B.ICL_F16, 0, 0, 0)[1]),
+                                   "variant": B.icl_variant_name(B.ICL_OP_CONV_SEP_BATCHED, plan.variant()),
+                                   "tune_seconds": round(tune_s, 2),
                                    "variants_ms": per_variant}
         plan.close()
         del ims, outs
@@ -687,6 +728,16 @@ def extra_bank(torch, B, T, synth, steps):
     wsl = torch.empty(nb // 4 + 1, dtype=torch.float32, device=dev)
     _, nb = B.icl_workspace_size(B.ICL_OP_BANK_FWD_SSE, Wb, Hb, N, F, r)
     wsf = torch.empty(nb // 4 + 1, dtype=torch.float32, device=dev)
+    # per-device tuning of every kernel of the step (outside the timed region)
+    st = torch.cuda.current_stream().cuda_stream
+    ops = {"fwd_loss": B.ICL_OP_BANK_FWD_SSE, "bwd_input": B.ICL_OP_BANK_BWD_INPUT,
+           "bwd_filter": B.ICL_OP_BANK_BWD_FILTER, "fwd": B.ICL_OP_BANK_FWD}
+    t0 = time.perf_counter()
+    for op in ops.values():
+        B.check(B.icl_tune_problem(op, B.ICL_F32, r, Wb, Hb, n=N, f=F, stream=st), "tune bank")
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    sel = {k: B.icl_selected_variant_problem(op, B.ICL_F32, r, Wb, Hb, n=N, f=F)[1] for k, op in ops.items()}
 
     def fused(s, ev=None):
         if ev: ev[0].record()
@@ -737,42 +788,79 @@ def extra_bank(torch, B, T, synth, steps):
         finally:
             B.icl_force_variant(B.ICL_OP_BANK_BWD_FILTER, -1)
         per_variant_w[B.icl_variant_name(B.ICL_OP_BANK_BWD_FILTER, v)] = round(fv * 1e3, 3)
-    flops = 3 * 2 * 81 * N * F * Hb * Wb
+    # each phase against the peak of the unit its kernel runs on: float32 matrix instructions
+    # (157.3 TFLOP/s) or float32 vector FMA (78.6, packed FMA disabled)
+    flops_phase = 2 * 81 * N * F * Hb * Wb
+    phases_out, roof_time = {}, 0.0
+    for k in ("fwd_loss", "bwd_input", "bwd_filter"):
+        ar = B.icl_variant_arith(ops[k], sel[k])
+        peak = FP32_PACKED_PEAK_TFLOPS if ar == "fp32_mfma" else FP32_FMA_PEAK_TFLOPS
+        tf = flops_phase / (ph[k] * 1e-3) / 1e12
+        roof_time += flops_phase / (peak * 1e12)
+        phases_out[k] = {"ms": ph[k], "variant": B.icl_variant_name(ops[k], sel[k]), "arith": ar,
+                         "tflops": round(tf, 2), "peak_tflops": peak, "frac": round(tf / peak, 3)}
+    flops = 3 * flops_phase
     res["filter_bank_fwd_bwd"] = {"ms": round(dt * 1e3, 3), "gpx_s": round(N * Hb * Wb / dt / 1e9, 2),
                                   "output_gpx_s": round(N * F * Hb * Wb / dt / 1e9, 1),
                                   "tflops": round(flops / dt / 1e12, 2),
-                                  "alu_frac": round(flops / dt / 1e12 / FP32_FMA_PEAK_TFLOPS, 3),
-                                  "phase_ms": ph,
+                                  "roof_frac": round(roof_time / dt, 3),
+                                  "roof_note": "time the three phases would take at the peak of the unit each "
+                                               "kernel uses, over the measured step",
+                                  "phases": phases_out, "tune_seconds": round(tune_s, 2),
                                   "fwd_loss_variants_ms": per_variant,
                                   "bwd_filter_variants_ms": per_variant_w,
                                   "unfused": {"ms": round(dt_u * 1e3, 3), "phase_ms": ph_u}}
     return res
 
 
+def cpu_cores():
+    """(threads to use, nproc, why): every core this process may run on.  A GPU job's share of the
+    host is fixed by OMP_NUM_THREADS where the launcher sets it (the CPU share of one GPU)."""
+    nproc = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = nproc
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        return min(int(omp), avail), nproc, f"OMP_NUM_THREADS={omp} (this job's CPU share), {avail} cores in affinity"
+    return avail, nproc, f"{avail} cores in affinity"
+
+
 def cpu_baseline(synth, radii, side, min_seconds=10.0):
     """The FP64 oracle, as it stands, on the same step: all ten calls over the full image, rows
-    split over the host threads, repeated until at least `min_seconds` (and 3 steps) have run."""
+    split over every host thread this job may use, repeated until at least `min_seconds` (and 3
+    steps) have run; then a single-thread run (median of 3) on a 256-row strip of every call."""
     from oracle import oracle
     rows = int(os.environ.get("ICL_CPU_SAMPLE_ROWS", str(side)))
-    threads = min(os.cpu_count() or 1, 16)
+    threads, nproc, why = cpu_cores()
     img = synth.sweep_image(side)[:rows].astype(np.float64)
     taps = [(synth.sweep_taps_sep(r), synth.sweep_taps_2d(r)) for r in radii]
-    times = []
-    while len(times) < 3 or sum(times) < min_seconds:
+
+    def step(im, nt):
         t0 = time.perf_counter()
         for (h, v), w in taps:
-            oracle.conv_sep(img, h, v, nthreads=threads)
-            oracle.conv2d(img, w, nthreads=threads)
-        times.append(time.perf_counter() - t0)
+            oracle.conv_sep(im, h, v, nthreads=nt)
+            oracle.conv2d(im, w, nthreads=nt)
+        return time.perf_counter() - t0
+
+    times = []
+    while len(times) < 3 or sum(times) < min_seconds:
+        times.append(step(img, threads))
         if len(times) % 5 == 1:
             print(f"[bench] cpu oracle step {len(times)}: {times[-1]:.2f} s", file=sys.stderr, flush=True)
     total = sum(times)
     px = rows * side * len(radii) * 2
+    strip = min(256, rows)
+    t1 = sorted(step(img[:strip], 1) for _ in range(3))[1]
+    print(f"[bench] cpu oracle single thread, {strip}-row strip: {t1:.2f} s", file=sys.stderr, flush=True)
     what = "the full step" if rows == side else f"rows 0..{rows - 1} of every call (a {rows}x{side} strip)"
     return {"value": round(len(times) * px / total / 1e9, 5), "unit": "Gpixel/s", "cores": threads,
-            "kind": "oracle",
+            "nproc": nproc, "cores_note": why, "kind": "oracle",
             "sample": f"{what}: {2 * len(radii)} calls on the {side}x{side} sweep image, {len(times)} steps "
-                      f"in {total:.1f} s ({sorted(times)[len(times) // 2]:.2f} s median per step)"}
+                      f"in {total:.1f} s ({sorted(times)[len(times) // 2]:.2f} s median per step)",
+            "single_thread": {"value": round(strip * side * len(radii) * 2 / t1 / 1e9, 6), "unit": "Gpixel/s",
+                              "sample": f"rows 0..{strip - 1} of every call, median of 3 runs ({t1:.2f} s)"}}
 
 
 if __name__ == "__main__":

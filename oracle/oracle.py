@@ -17,7 +17,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "icl_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_DEFAULT = os.path.join(_HERE, "liboracle.so")
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+# ICL_ORACLE_SANITIZED=1 loads the AddressSanitizer + UndefinedBehaviorSanitizer build (the
+# process must preload the sanitizer runtime: LD_PRELOAD=$(gcc -print-file-name=libasan.so))
+_LIB = _LIB_SAN if os.environ.get("ICL_ORACLE_SANITIZED") == "1" else _LIB_DEFAULT
 
 _lib = None
 
@@ -31,15 +35,20 @@ _I16 = ctypes.POINTER(ctypes.c_int16)
 BORDERS = {"clamp": 0, "constant": 1}
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no fast-math, OpenMP for row splitting)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP for row splitting); with `sanitize`,
+    a separate library built with AddressSanitizer and UndefinedBehaviorSanitizer (every UB report
+    fatal) for checking the oracle's own memory accesses and arithmetic on the CPU."""
+    out = _LIB_SAN if sanitize else _LIB_DEFAULT
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"] \
+            if sanitize else []
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-                               "-fno-fast-math", "-ffp-contract=off", "-Wall", "-Wextra",
+                               "-fno-fast-math", "-ffp-contract=off", "-Wall", "-Wextra", *san,
                                "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
 
 
 def lib():

@@ -238,6 +238,16 @@ class BatchPlan:
     def launch(self) -> None:
         B.check(B.icl_conv_sep_batched(self.handle, _stream()), "icl_conv_sep_batched")
 
+    def tune(self) -> None:
+        """Per-device choice of the walk for this plan (writes the outputs; a graph made before
+        keeps the walk it captured, so tune first)."""
+        B.check(B.icl_batch_plan_tune(self.handle, _stream()), "icl_batch_plan_tune")
+
+    def variant(self) -> int:
+        st, v = B.icl_batch_plan_variant(self.handle)
+        B.check(st, "icl_batch_plan_variant")
+        return v
+
     def graph(self):
         """hipGraphExec holding the single persistent launch (created once)."""
         if self._graph is None:

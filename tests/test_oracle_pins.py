@@ -754,3 +754,25 @@ def test_sse_loss_and_gradient(orc):
     L, gy = orc.sse_loss(y, t)
     assert L == 0.25 + 0.0 + 4.0
     assert np.array_equal(gy, np.array([1.0, 0.0, -4.0]))
+
+
+def test_oracle_pins_under_address_and_ub_sanitizers(tmp_path):
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer (reports fatal) passes a
+    cross-section of its pins: every entry point of the C library runs at least once, on tiny and
+    ragged images, so an out-of-bounds index or undefined arithmetic in it would abort the run."""
+    import subprocess
+    import sys
+    from oracle import oracle as O
+    O.build(force=True, sanitize=True)
+    asan = subprocess.run(["gcc", "-print-file-name=libasan.so"], capture_output=True, text=True).stdout.strip()
+    ubsan = subprocess.run(["gcc", "-print-file-name=libubsan.so"], capture_output=True, text=True).stdout.strip()
+    env = dict(os.environ, ICL_ORACLE_SANITIZED="1", LD_PRELOAD=f"{asan}:{ubsan}",
+               ASAN_OPTIONS="detect_leaks=0", OMP_NUM_THREADS="2")
+    here = os.path.dirname(os.path.abspath(__file__))
+    sel = "tiny or brute or golden or hand or conv3d or u8 or adjoint or f32_bound or closest or codec or constant"
+    out = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "-k", sel,
+                          "-m", "not gpu", os.path.join(here, "test_oracle_pins.py"),
+                          "--deselect", "tests/test_oracle_pins.py::test_oracle_pins_under_address_and_ub_sanitizers"],
+                         env=env, capture_output=True, text=True, timeout=600, cwd=os.path.dirname(here))
+    assert out.returncode == 0, out.stdout[-3000:] + out.stderr[-3000:]
+    assert " passed" in out.stdout
