@@ -315,10 +315,14 @@ void icl_graph_destroy(void* exec);
  * radius in [1, 4] and f in [1, 64]. */
 icl_status icl_bank_fwd(const float* x, const float* w, float* y, int n, int f, int h, int wd,
                         int radius, void* stream);
+/* The adjoints take an optional `scale` (device float32 scalar, NULL = 1) multiplying their
+ * output: the chain-rule factor of an upstream gradient dJ/dL on a scalar loss L, so that
+ * gx = scale * dL/dx and gw = scale * dL/dw come out of the kernels with no extra pass. */
 icl_status icl_bank_bwd_input(const float* gy, const float* w, float* gx, int n, int f, int h, int wd,
-                              int radius, void* stream);
+                              int radius, const float* scale, void* stream);
 icl_status icl_bank_bwd_filter(const float* gy, const float* x, float* gw, int n, int f, int h, int wd,
-                               int radius, void* workspace, size_t workspace_bytes, void* stream);
+                               int radius, const float* scale, void* workspace, size_t workspace_bytes,
+                               void* stream);
 
 /* Sum-of-squares loss L = sum (y - t)^2 over `count` elements and its gradient
  * gy = 2 (y - t) (gy may be NULL).  `loss` is a device float32 written with L;

@@ -97,8 +97,8 @@ _SIGS = {
     "icl_graph_launch": ([_vp, _vp], _i),
     "icl_graph_destroy": ([_vp], None),
     "icl_bank_fwd": ([_vp, _vp, _vp, _i, _i, _i, _i, _i, _vp], _i),
-    "icl_bank_bwd_input": ([_vp, _vp, _vp, _i, _i, _i, _i, _i, _vp], _i),
-    "icl_bank_bwd_filter": ([_vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _sz, _vp], _i),
+    "icl_bank_bwd_input": ([_vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _vp], _i),
+    "icl_bank_bwd_filter": ([_vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _vp, _sz, _vp], _i),
     "icl_sse_loss": ([_vp, _vp, _vp, _ll, _vp, _vp, _sz, _vp], _i),
     "icl_bank_fwd_sse": ([_vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _sz, _vp], _i),
     "icl_tune": ([_i, _i, _i, _i, _i, _vp], _i),
@@ -266,13 +266,13 @@ def icl_bank_fwd(x, w, y, n, f, h, wd, radius, stream=0) -> int:
     return lib().icl_bank_fwd(x, w, y, n, f, h, wd, radius, stream or None)
 
 
-def icl_bank_bwd_input(gy, w, gx, n, f, h, wd, radius, stream=0) -> int:
-    return lib().icl_bank_bwd_input(gy, w, gx, n, f, h, wd, radius, stream or None)
+def icl_bank_bwd_input(gy, w, gx, n, f, h, wd, radius, stream=0, scale=0) -> int:
+    return lib().icl_bank_bwd_input(gy, w, gx, n, f, h, wd, radius, scale or None, stream or None)
 
 
-def icl_bank_bwd_filter(gy, x, gw, n, f, h, wd, radius, workspace=0, workspace_bytes=0, stream=0) -> int:
-    return lib().icl_bank_bwd_filter(gy, x, gw, n, f, h, wd, radius, workspace or None, workspace_bytes,
-                                     stream or None)
+def icl_bank_bwd_filter(gy, x, gw, n, f, h, wd, radius, workspace=0, workspace_bytes=0, stream=0, scale=0) -> int:
+    return lib().icl_bank_bwd_filter(gy, x, gw, n, f, h, wd, radius, scale or None, workspace or None,
+                                     workspace_bytes, stream or None)
 
 
 def icl_sse_loss(y, t, gy, count, loss, workspace=0, workspace_bytes=0, stream=0) -> int:

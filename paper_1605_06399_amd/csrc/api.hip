@@ -507,7 +507,7 @@ icl_status icl_bank_fwd(const float* x, const float* w, float* y, int n, int f, 
 }
 
 icl_status icl_bank_bwd_input(const float* gy, const float* w, float* gx, int n, int f, int h, int wd, int radius,
-                              void* stream) {
+                              const float* scale, void* stream) {
     icl_status s;
     if ((s = check_bank(n, f, h, wd, radius)) != ICL_OK) return s;
     if (n == 0 || h == 0 || wd == 0) return ICL_OK;
@@ -516,8 +516,9 @@ icl_status icl_bank_bwd_input(const float* gy, const float* w, float* gx, int n,
     if (range_overlaps(gy, (size_t)n * f * hw * 4, gx, (size_t)n * hw * 4) ||
         range_overlaps(w, (size_t)f * (2 * radius + 1) * (2 * radius + 1) * 4, gx, (size_t)n * hw * 4))
         return ICL_ERR_ALIAS;
+    if (scale && range_overlaps(scale, 4, gx, (size_t)n * hw * 4)) return ICL_ERR_ALIAS;
     if ((s = device_ready()) != ICL_OK) return s;
-    BankArgs a{gy, w, gx, n, f, h, wd, radius, nullptr, 0, (hipStream_t)stream};
+    BankArgs a{gy, w, gx, n, f, h, wd, radius, nullptr, 0, (hipStream_t)stream, scale};
     int count;
     const Variant<BankArgs>* tab = bank_bwd_input_variants(&count);
     const int deflt = bank_bwd_input_default(a);
@@ -526,7 +527,7 @@ icl_status icl_bank_bwd_input(const float* gy, const float* w, float* gx, int n,
 }
 
 icl_status icl_bank_bwd_filter(const float* gy, const float* x, float* gw, int n, int f, int h, int wd, int radius,
-                               void* workspace, size_t workspace_bytes, void* stream) {
+                               const float* scale, void* workspace, size_t workspace_bytes, void* stream) {
     icl_status s;
     if ((s = check_bank(n, f, h, wd, radius)) != ICL_OK) return s;
     if (!gw) return ICL_ERR_INVALID_VALUE;
@@ -544,8 +545,10 @@ icl_status icl_bank_bwd_filter(const float* gy, const float* x, float* gw, int n
         range_overlaps(workspace, need, gy, (size_t)n * f * hw * 4) ||
         range_overlaps(workspace, need, x, (size_t)n * hw * 4) || range_overlaps(workspace, need, gw, (size_t)f * nk * 4))
         return ICL_ERR_ALIAS;
+    if (scale && (range_overlaps(scale, 4, gw, (size_t)f * nk * 4) || range_overlaps(scale, 4, workspace, need)))
+        return ICL_ERR_ALIAS;
     if ((s = device_ready()) != ICL_OK) return s;
-    BankArgs a{gy, x, gw, n, f, h, wd, radius, workspace, workspace_bytes, (hipStream_t)stream};
+    BankArgs a{gy, x, gw, n, f, h, wd, radius, workspace, workspace_bytes, (hipStream_t)stream, scale};
     int count;
     const Variant<BankArgs>* tab = bank_bwd_filter_variants(&count);
     const int deflt = bank_bwd_filter_default(a);
@@ -566,8 +569,14 @@ icl_status icl_sse_loss(const float* y, const float* t, float* gy, long long cou
     return hip_status(sse_launch(y, t, gy, count, loss, workspace, workspace_bytes, (hipStream_t)stream));
 }
 
-icl_status icl_bank_fwd_sse(const float* x, const float* w, const float* t, float* y, float* gy, float* loss, int n,
-                            int f, int h, int wd, int radius, void* workspace, size_t workspace_bytes, void* stream) {
+}  // extern "C"
+
+namespace icl {
+
+// The fused forward + loss entry point.
+icl_status bank_fwd_sse_entry(const float* x, const float* w, const float* t, float* y, float* gy, float* loss, int n,
+                              int f, int h, int wd, int radius, void* workspace, size_t workspace_bytes,
+                              void* stream) {
     icl_status s;
     if ((s = check_bank(n, f, h, wd, radius)) != ICL_OK) return s;
     if (!loss) return ICL_ERR_INVALID_VALUE;
@@ -595,8 +604,17 @@ icl_status icl_bank_fwd_sse(const float* x, const float* w, const float* t, floa
     int count;
     const Variant<BankSseArgs>* tab = bank_fwd_sse_variants(&count);
     const int deflt = bank_fwd_sse_default(a);
-    return dispatch(ICL_OP_BANK_FWD_SSE, tab, count, a,
-                    select_variant(Problem{ICL_OP_BANK_FWD_SSE, ICL_F32, radius, wd, h, 1, n, f}, deflt, a.st), deflt);
+    const int v = select_variant(Problem{ICL_OP_BANK_FWD_SSE, ICL_F32, radius, wd, h, 1, n, f}, deflt, a.st);
+    return dispatch(ICL_OP_BANK_FWD_SSE, tab, count, a, v, deflt);
+}
+
+}  // namespace icl
+
+extern "C" {
+
+icl_status icl_bank_fwd_sse(const float* x, const float* w, const float* t, float* y, float* gy, float* loss, int n,
+                            int f, int h, int wd, int radius, void* workspace, size_t workspace_bytes, void* stream) {
+    return bank_fwd_sse_entry(x, w, t, y, gy, loss, n, f, h, wd, radius, workspace, workspace_bytes, stream);
 }
 
 // ------------------------------------------------------------------ variants

@@ -180,10 +180,21 @@ __global__ __launch_bounds__(256) void bank_fwd_k(const float* __restrict__ x, c
     }
 }
 
+// The adjoints' output factor: *scale when given (an upstream gradient on the loss), else 1.
+// Multiplying by 1.0f is exact, so without a factor the outputs are unchanged bit for bit.
+__device__ __forceinline__ float out_scale(const float* __restrict__ scale) { return scale ? *scale : 1.f; }
+
+__device__ __forceinline__ void scale_acc(float (&acc)[BPY][BPX], float sc) {
+#pragma unroll
+    for (int py = 0; py < BPY; ++py)
+#pragma unroll
+        for (int px = 0; px < BPX; ++px) acc[py][px] *= sc;
+}
+
 template <int R>
 __global__ __launch_bounds__(256) void bank_bwd_in_k(const float* __restrict__ gy, const float* __restrict__ w,
                                                      float* __restrict__ gx, int F, int H, int W, int tiles_x,
-                                                     int tiles_img, int vec) {
+                                                     int tiles_img, int vec, const float* __restrict__ scale) {
     using G = BankTile<R>;
     __shared__ __attribute__((aligned(16))) float s[G::NR * G::LW];
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
@@ -199,6 +210,7 @@ __global__ __launch_bounds__(256) void bank_bwd_in_k(const float* __restrict__ g
         __syncthreads();
         corr_block<R, true>(s, w + (size_t)f * NK, acc);
     }
+    scale_acc(acc, out_scale(scale));
     store_block(gx + (size_t)n * hw, W, H, x0, y0, vec, acc);
 }
 
@@ -233,7 +245,8 @@ EdgeSegments edge_segments(int W, int H) {
 template <int R>
 __global__ __launch_bounds__(256) void bank_bwd_edge_k(const float* __restrict__ gy, const float* __restrict__ w,
                                                        float* __restrict__ gx, int F, int H, int W, int top,
-                                                       int bottom, int left, int per_img) {
+                                                       int bottom, int left, int per_img,
+                                                       const float* __restrict__ scale) {
     constexpr int N = 2 * R + 1, L = EDGE_SEG + 2 * R;
     __shared__ float wl[64 * N * N];
     __shared__ float strip[L * (R + 1)];
@@ -366,7 +379,7 @@ __global__ __launch_bounds__(256) void bank_bwd_edge_k(const float* __restrict__
             }
         }
     }
-    if (active) gx[(size_t)n * hw + (size_t)qy * W + qx] = acc;
+    if (active) gx[(size_t)n * hw + (size_t)qy * W + qx] = acc * out_scale(scale);
 }
 
 template <int R>
@@ -374,7 +387,7 @@ hipError_t launch_edge(const BankArgs& a) {
     const EdgeSegments e = edge_segments(a.w, a.h);
     const int per = e.per_image();
     hipLaunchKernelGGL(bank_bwd_edge_k<R>, dim3((unsigned)(a.n * per)), dim3(256), 0, a.st, a.a, a.b, a.out, a.f,
-                       a.h, a.w, e.top, e.bottom, e.left, per);
+                       a.h, a.w, e.top, e.bottom, e.left, per, a.scale);
     return hipGetLastError();
 }
 
@@ -451,7 +464,7 @@ __global__ __launch_bounds__(64) void bank_bwd_w1_k(const float* __restrict__ gy
 
 // gw[f,k] = sum over tiles of part[f][k][tile], fixed-order tree per (f, k)
 __global__ __launch_bounds__(256) void bank_bwd_w2_k(const float* __restrict__ part, float* __restrict__ gw,
-                                                     int ntiles) {
+                                                     int ntiles, const float* __restrict__ scale) {
     __shared__ float red[256];
     const float* p = part + (size_t)blockIdx.x * ntiles;
     float v = 0.f;
@@ -462,7 +475,7 @@ __global__ __launch_bounds__(256) void bank_bwd_w2_k(const float* __restrict__ p
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) gw[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) gw[blockIdx.x] = red[0] * out_scale(scale);
 }
 
 // ------------------------------------------------------------------ plain baselines
@@ -488,7 +501,8 @@ __global__ __launch_bounds__(256) void bank_fwd_plain_k(const float* __restrict_
 // Input gradient straight from the adjoint's definition: gx[q] = sum over padded u with
 // clamp(u) = q of z[u], z[u] = sum_f sum_k w[f,k] gy0[f, u-k].
 __global__ __launch_bounds__(256) void bank_bwd_in_plain_k(const float* __restrict__ gy, const float* __restrict__ w,
-                                                           float* __restrict__ gx, int N, int F, int H, int W, int r) {
+                                                           float* __restrict__ gx, int N, int F, int H, int W, int r,
+                                                           const float* __restrict__ scale) {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long hw = (long long)H * W;
     if (i >= (long long)N * hw) return;
@@ -513,7 +527,7 @@ __global__ __launch_bounds__(256) void bank_bwd_in_plain_k(const float* __restri
                     }
                 }
             }
-    gx[i] = acc;
+    gx[i] = acc * out_scale(scale);
 }
 
 // ------------------------------------------------------------------ persistent, prefetching, taps in LDS
@@ -671,7 +685,8 @@ __global__ __launch_bounds__(256) void bank_fwd_sse_tpre_k(const float* __restri
 template <int R>
 __global__ __launch_bounds__(256) void bank_bwd_in_pers_k(const float* __restrict__ gy, const float* __restrict__ w,
                                                           float* __restrict__ gx, int F, int H, int W, int tiles_x,
-                                                          int tiles_img, int ntiles, int vec) {
+                                                          int tiles_img, int ntiles, int vec,
+                                                          const float* __restrict__ scale) {
     using G = BankTile<R>;
     constexpr int LW = G::LW, NR = G::NR, RA = G::RA, N = 2 * R + 1, NP = (N + 3) & ~3;
     __shared__ __attribute__((aligned(16))) float s[NR * LW];
@@ -704,6 +719,7 @@ __global__ __launch_bounds__(256) void bank_bwd_in_pers_k(const float* __restric
             corr_rows<R, BPX, BPY, LW, true>(&s[(ty * BPY) * LW + tx * BPX], &wl[f * N * NP], acc);
             __syncthreads();
         }
+        scale_acc(acc, out_scale(scale));
         store_block(gx + (size_t)n * hw, W, H, x0, y0, vec, acc);
     }
 }
@@ -896,7 +912,7 @@ hipError_t bwd_wm_RT(const BankArgs& a) {
     hipLaunchKernelGGL((bank_bwd_wm_k<R, TY>), dim3((unsigned)ntiles), dim3(256), 0, a.st, a.a, a.b, part, a.f, a.h,
                        a.w, tx, tx * ty, ntiles);
     const int nk = (2 * R + 1) * (2 * R + 1);
-    hipLaunchKernelGGL(bank_bwd_w2_k, dim3((unsigned)(a.f * nk)), dim3(256), 0, a.st, part, a.out, ntiles);
+    hipLaunchKernelGGL(bank_bwd_w2_k, dim3((unsigned)(a.f * nk)), dim3(256), 0, a.st, part, a.out, ntiles, a.scale);
     return hipGetLastError();
 }
 
@@ -917,7 +933,7 @@ template <int R>
 hipError_t bwd_in_R(const BankArgs& a) {
     const int tx = (a.w + BT - 1) / BT, ty = (a.h + BT - 1) / BT;
     hipLaunchKernelGGL(bank_bwd_in_k<R>, dim3((unsigned)(a.n * tx * ty)), dim3(256), 0, a.st, a.a, a.b, a.out, a.f,
-                       a.h, a.w, tx, tx * ty, bank_vec(a.a, a.out, a.w));
+                       a.h, a.w, tx, tx * ty, bank_vec(a.a, a.out, a.w), a.scale);
     return launch_edge<R>(a);
 }
 
@@ -929,7 +945,7 @@ hipError_t bwd_w_R(const BankArgs& a) {
     hipLaunchKernelGGL(bank_bwd_w1_k<R>, dim3((unsigned)(ntiles * a.f)), dim3(64), 0, a.st, a.a, a.b, part, a.f, a.h,
                        a.w, tx, tx * ty, ntiles);
     const int nk = (2 * R + 1) * (2 * R + 1);
-    hipLaunchKernelGGL(bank_bwd_w2_k, dim3((unsigned)(a.f * nk)), dim3(256), 0, a.st, part, a.out, ntiles);
+    hipLaunchKernelGGL(bank_bwd_w2_k, dim3((unsigned)(a.f * nk)), dim3(256), 0, a.st, part, a.out, ntiles, a.scale);
     return hipGetLastError();
 }
 
@@ -943,7 +959,7 @@ hipError_t launch_fwd_plain(const BankArgs& a) {
 hipError_t launch_bwd_in_plain(const BankArgs& a) {
     const long long tot = (long long)a.n * a.h * a.w;
     hipLaunchKernelGGL(bank_bwd_in_plain_k, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, a.st, a.a, a.b, a.out,
-                       a.n, a.f, a.h, a.w, a.r);
+                       a.n, a.f, a.h, a.w, a.r, a.scale);
     return hipGetLastError();
 }
 
@@ -964,7 +980,7 @@ hipError_t bwd_in_pers_R(const BankArgs& a) {
     const int ntiles = a.n * tx * ty;
     const void* k = reinterpret_cast<const void*>(&bank_bwd_in_pers_k<R>);
     hipLaunchKernelGGL(bank_bwd_in_pers_k<R>, dim3(persistent_grid(k, 256, ntiles)), dim3(256), 0, a.st, a.a, a.b,
-                       a.out, a.f, a.h, a.w, tx, tx * ty, ntiles, bank_vec(a.a, a.out, a.w));
+                       a.out, a.f, a.h, a.w, tx, tx * ty, ntiles, bank_vec(a.a, a.out, a.w), a.scale);
     return launch_edge<R>(a);
 }
 
@@ -977,7 +993,7 @@ hipError_t bwd_w4_RT(const BankArgs& a) {
     hipLaunchKernelGGL((bank_bwd_w4_k<R, TY, CH>), dim3((unsigned)(ntiles * fgroups)), dim3(256), 0, a.st, a.a, a.b,
                        part, a.f, a.h, a.w, tx, tx * ty, ntiles, fgroups);
     const int nk = (2 * R + 1) * (2 * R + 1);
-    hipLaunchKernelGGL(bank_bwd_w2_k, dim3((unsigned)(a.f * nk)), dim3(256), 0, a.st, part, a.out, ntiles);
+    hipLaunchKernelGGL(bank_bwd_w2_k, dim3((unsigned)(a.f * nk)), dim3(256), 0, a.st, part, a.out, ntiles, a.scale);
     return hipGetLastError();
 }
 

@@ -82,6 +82,7 @@ struct BankArgs {
     int n, f, h, w, r;
     void* ws; size_t wsb;
     hipStream_t st;
+    const float* scale = nullptr;   // adjoints: device factor on the output (null = 1)
 };
 
 struct BankSseArgs {
@@ -150,6 +151,7 @@ size_t bank_fwd_sse_workspace();
 
 hipError_t sse_launch(const float* y, const float* t, float* gy, long long count, float* loss,
                       void* ws, size_t wsb, hipStream_t st);
+
 
 // A problem as the tuner keys it: the operation, storage type, radius and the sizes that
 // change which variant is fastest (depth of a volume, batch and filter counts of the bank).

@@ -292,18 +292,28 @@ def bank_fwd(x: torch.Tensor, w: torch.Tensor, out: torch.Tensor | None = None) 
     return out
 
 
-def bank_bwd_input(gy: torch.Tensor, w: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+def _scale(scale: torch.Tensor | None) -> int:
+    """Device address of a float32 scalar output factor (0: none)."""
+    if scale is None:
+        return 0
+    if scale.numel() != 1 or scale.dtype != torch.float32 or not scale.is_cuda:
+        raise ValueError("scale must be a one-element float32 GPU tensor")
+    return scale.data_ptr()
+
+
+def bank_bwd_input(gy: torch.Tensor, w: torch.Tensor, out: torch.Tensor | None = None,
+                   scale: torch.Tensor | None = None) -> torch.Tensor:
     N, F, H, W = gy.shape
     r = (w.shape[-1] - 1) // 2
     if out is None:
         out = torch.empty((N, 1, H, W), dtype=torch.float32, device=gy.device)
-    B.check(B.icl_bank_bwd_input(_dense(gy, "gy"), _dense(w, "w"), _dense(out, "gx"), N, F, H, W, r, _stream()),
-            "icl_bank_bwd_input")
+    B.check(B.icl_bank_bwd_input(_dense(gy, "gy"), _dense(w, "w"), _dense(out, "gx"), N, F, H, W, r, _stream(),
+                                 scale=_scale(scale)), "icl_bank_bwd_input")
     return out
 
 
 def bank_bwd_filter(gy: torch.Tensor, x: torch.Tensor, radius: int, out: torch.Tensor | None = None,
-                    workspace: torch.Tensor | None = None) -> torch.Tensor:
+                    workspace: torch.Tensor | None = None, scale: torch.Tensor | None = None) -> torch.Tensor:
     N, F, H, W = gy.shape
     k = 2 * radius + 1
     if out is None:
@@ -312,7 +322,8 @@ def bank_bwd_filter(gy: torch.Tensor, x: torch.Tensor, radius: int, out: torch.T
         _, nb = B.icl_workspace_size(B.ICL_OP_BANK_BWD_FILTER, W, H, N, F, radius)
         workspace = _workspace(nb, gy.device)
     B.check(B.icl_bank_bwd_filter(_dense(gy, "gy"), _dense(x, "x"), _dense(out, "gw"), N, F, H, W, radius,
-                                  workspace.data_ptr(), workspace.numel() * 4, _stream()), "icl_bank_bwd_filter")
+                                  workspace.data_ptr(), workspace.numel() * 4, _stream(), scale=_scale(scale)),
+            "icl_bank_bwd_filter")
     return out
 
 
@@ -390,13 +401,11 @@ class FilterBankLossFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gL):
         x, w, gy = ctx.saved_tensors
-        gx = bank_bwd_input(gy, w.contiguous()).view_as(x) if ctx.needs_input_grad[0] else None
-        gw = bank_bwd_filter(gy, x.contiguous(), (w.shape[-1] - 1) // 2) if ctx.needs_input_grad[1] else None
-        # chain rule for an upstream factor on L (1 for loss.backward()); the adjoints are linear in gy
-        if gx is not None:
-            gx.mul_(gL)
-        if gw is not None:
-            gw.mul_(gL)
+        # chain rule for the upstream factor on L (1 for loss.backward()): the adjoint kernels take
+        # it as their output factor (read on the device, so no host synchronisation)
+        sc = gL.detach().to(device=gy.device, dtype=torch.float32).reshape(1).contiguous()
+        gx = bank_bwd_input(gy, w.contiguous(), scale=sc).view_as(x) if ctx.needs_input_grad[0] else None
+        gw = bank_bwd_filter(gy, x.contiguous(), (w.shape[-1] - 1) // 2, scale=sc) if ctx.needs_input_grad[1] else None
         return gx, gw, None
 
 

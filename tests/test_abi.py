@@ -399,3 +399,12 @@ def test_tune_environment_modes(tmp_path):
                              text=True, timeout=120)
         assert out.returncode == 0, out.stderr
         assert out.stdout.strip() == want, (mode, out.stdout, out.stderr)
+
+
+def test_adjoint_scale_validation(no_gpu):
+    # a factor that overlaps the output is an alias; a separate one reaches the device check
+    assert B.icl_bank_bwd_input(SRC, TAPS, DST, 2, 4, 8, 8, 4, scale=DST + 8) == B.ICL_ERR_ALIAS
+    assert B.icl_bank_bwd_input(SRC, TAPS, DST, 2, 4, 8, 8, 4, scale=WS) == B.ICL_ERR_NO_DEVICE
+    _, nb = B.icl_workspace_size(B.ICL_OP_BANK_BWD_FILTER, 8, 8, 2, 4, 4)
+    assert B.icl_bank_bwd_filter(SRC, DST, 0x70000000, 2, 4, 8, 8, 4, WS, nb, scale=0x70000000 + 4) == B.ICL_ERR_ALIAS
+    assert B.icl_bank_bwd_filter(SRC, DST, 0x70000000, 2, 4, 8, 8, 4, WS, nb, scale=WS + 4) == B.ICL_ERR_ALIAS

@@ -196,11 +196,40 @@ def test_loss_function_backward_matches_oracle_chain():
     sw = oracle.bank_bwd_filter(np.abs(gyr), np.abs(x), r) + 2 * oracle.bank_bwd_filter(ys, np.abs(x), r)
     assert rel_normwise(host(xt.grad), gxr, sx) <= 1e-5
     assert rel_normwise(host(wt.grad), gwr, sw) <= 1e-5
-    # an upstream factor scales both gradients
+    # an upstream factor scales both gradients inside the adjoint kernels: each output is the
+    # float32 product of the unscaled sum and the factor, rounded once (bit for bit on the host)
+    gx1 = xt.grad.detach().clone()
+    gw1 = wt.grad.detach().clone()
     xt.grad = None
     wt.grad = None
     (3.0 * T.filter_bank_loss(xt, wt, cu(t))).backward()
     assert rel_normwise(host(xt.grad), 3 * gxr, 3 * sx) <= 1e-5
+    three = np.float32(3.0)
+    assert np.array_equal(xt.grad.cpu().numpy(), gx1.cpu().numpy() * three)
+    assert np.array_equal(wt.grad.cpu().numpy(), gw1.cpu().numpy() * three)
+
+
+@pytest.mark.parametrize("shape", SHAPES[:6])
+def test_adjoint_output_factor_every_variant(shape):
+    """The `scale` argument of both adjoints multiplies each output once: with a factor of one the
+    result equals the call without it bit for bit, and with -0.75 it equals the float32 product of
+    that result and the factor, for every variant."""
+    N, F, H, W, r = shape
+    x, w, _ = inputs(N, F, H, W, r, cfg=81)
+    gy = synth.uniform01(synth.seed(81, 6), N * F * H * W).reshape(N, F, H, W) * 2 - 1
+    gyt, wt, xt = cu(gy), cu(w), cu(x)
+    one = torch.ones(1, dtype=torch.float32, device="cuda")
+    fac = torch.full((1,), -0.75, dtype=torch.float32, device="cuda")
+    for _ in each_variant(B.ICL_OP_BANK_BWD_INPUT):
+        g0 = T.bank_bwd_input(gyt, wt)
+        assert torch.equal(T.bank_bwd_input(gyt, wt, scale=one), g0)
+        g1 = T.bank_bwd_input(gyt, wt, scale=fac)
+        assert np.array_equal(g1.cpu().numpy(), g0.cpu().numpy() * np.float32(-0.75))
+    for _ in each_variant(B.ICL_OP_BANK_BWD_FILTER):
+        w0 = T.bank_bwd_filter(gyt, xt, r)
+        assert torch.equal(T.bank_bwd_filter(gyt, xt, r, scale=one), w0)
+        w1 = T.bank_bwd_filter(gyt, xt, r, scale=fac)
+        assert np.array_equal(w1.cpu().numpy(), w0.cpu().numpy() * np.float32(-0.75))
 
 
 def test_autograd_function_matches_oracle_chain():
