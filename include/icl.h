@@ -348,6 +348,22 @@ icl_status icl_bank_fwd_sse(const float* x, const float* w, const float* t, floa
                             int n, int f, int h, int wd, int radius, void* workspace, size_t workspace_bytes,
                             void* stream);
 
+/* icl_bank_fwd_sse without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It calls no hipMalloc, hipFree or allocating routine, and never starts a
+ * tuner search (a tune-cache miss takes the default variant).  The loss partials live in
+ * a fixed device array of FWD_SSE_PARTS (2048) float64 values = 16 KiB, one copy per
+ * device, looked up on the first call on that device (or by icl_init) and held until the
+ * process ends.  The partial count is capped at that size for every problem, so no
+ * problem size is rejected for lack of scratch.  Every call on one device shares that
+ * device's array: calls that overlap in time on one device (concurrent streams, threads)
+ * race on it and must be serialised by the caller.  Each call writes every partial it
+ * reads, so nothing needs clearing between calls.
+ * Arguments, outputs, limits and errors as icl_bank_fwd_sse; y, gy and L are bit-identical
+ * to icl_bank_fwd_sse's when both run the same variant. */
+icl_status icl_bank_fwd_sse_noalloc(const float* x, const float* w, const float* t, float* y, float* gy,
+                                    float* loss, int n, int f, int h, int wd, int radius, void* stream);
+
 /* ------------------------------------------------------------------ auto-tuning and variants
  * The tuner plays the role of the paper's auto-tuner (Section 4 and the
  * discussion of tuning cost): it runs every precompiled candidate variant of an

@@ -101,6 +101,7 @@ _SIGS = {
     "icl_bank_bwd_filter": ([_vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _vp, _sz, _vp], _i),
     "icl_sse_loss": ([_vp, _vp, _vp, _ll, _vp, _vp, _sz, _vp], _i),
     "icl_bank_fwd_sse": ([_vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, _sz, _vp], _i),
+    "icl_bank_fwd_sse_noalloc": ([_vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp], _i),
     "icl_tune": ([_i, _i, _i, _i, _i, _vp], _i),
     "icl_tune_model": ([_i, _i, _i, _i, _i, _i, _i, ctypes.c_ulonglong, ctypes.POINTER(_i), _vp], _i),
     "icl_perf_model_fit_predict": ([_vp, _vp, _i, _i, _vp, _i, _vp, _i, _i, ctypes.c_ulonglong], _i),
@@ -282,6 +283,10 @@ def icl_sse_loss(y, t, gy, count, loss, workspace=0, workspace_bytes=0, stream=0
 def icl_bank_fwd_sse(x, w, t, y, gy, loss, n, f, h, wd, radius, workspace=0, workspace_bytes=0, stream=0) -> int:
     return lib().icl_bank_fwd_sse(x, w, t, y or None, gy or None, loss, n, f, h, wd, radius, workspace or None,
                                   workspace_bytes, stream or None)
+
+
+def icl_bank_fwd_sse_noalloc(x, w, t, y, gy, loss, n, f, h, wd, radius, stream=0) -> int:
+    return lib().icl_bank_fwd_sse_noalloc(x, w, t, y or None, gy or None, loss, n, f, h, wd, radius, stream or None)
 
 
 def icl_tune(op, dtype, radius, width, height, stream=0) -> int:

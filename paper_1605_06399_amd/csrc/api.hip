@@ -18,6 +18,7 @@ using namespace icl;
 namespace icl {
 
 static thread_local int g_last_hip_error = 0;
+static void* scratch_on_current_device();
 void set_hip_error(hipError_t e) { g_last_hip_error = (int)e; }
 
 static std::atomic<int> g_forced[ICL_OP_COUNT] = {};
@@ -220,7 +221,11 @@ icl_status dispatch(icl_op op, const Variant<A>* tab, int count, const A& a, int
 
 extern "C" {
 
-icl_status icl_init(void) { return device_ready(); }
+icl_status icl_init(void) {
+    const icl_status s = device_ready();
+    if (s != ICL_OK) return s;
+    return scratch_on_current_device() ? ICL_OK : ICL_ERR_HIP;
+}
 
 const char* icl_version(void) { return "icl 0.1 (gfx950)"; }
 
@@ -574,9 +579,11 @@ icl_status icl_sse_loss(const float* y, const float* t, float* gy, long long cou
 namespace icl {
 
 // The fused forward + loss entry point.
+// may_tune: whether a tune-cache miss may start a search (ICL_TUNE=search); a search
+// allocates, so the allocation-free entry point passes false.
 icl_status bank_fwd_sse_entry(const float* x, const float* w, const float* t, float* y, float* gy, float* loss, int n,
                               int f, int h, int wd, int radius, void* workspace, size_t workspace_bytes,
-                              void* stream) {
+                              void* stream, bool may_tune) {
     icl_status s;
     if ((s = check_bank(n, f, h, wd, radius)) != ICL_OK) return s;
     if (!loss) return ICL_ERR_INVALID_VALUE;
@@ -604,8 +611,45 @@ icl_status bank_fwd_sse_entry(const float* x, const float* w, const float* t, fl
     int count;
     const Variant<BankSseArgs>* tab = bank_fwd_sse_variants(&count);
     const int deflt = bank_fwd_sse_default(a);
-    const int v = select_variant(Problem{ICL_OP_BANK_FWD_SSE, ICL_F32, radius, wd, h, 1, n, f}, deflt, a.st);
+    const int v = select_variant(Problem{ICL_OP_BANK_FWD_SSE, ICL_F32, radius, wd, h, 1, n, f}, deflt,
+                                 may_tune ? a.st : nullptr);
     return dispatch(ICL_OP_BANK_FWD_SSE, tab, count, a, v, deflt);
+}
+
+// ------------------------------------------------------------------ fixed device scratch
+// The loss partials of icl_bank_fwd_sse_noalloc live in this array, one copy per device,
+// held until the process ends.  Host code never passes the array's name to a kernel (on
+// the host it is a stand-in, not a device address): it looks up each device's address
+// once, with that device current, and passes that.
+constexpr size_t kScratchBytes = FWD_SSE_PARTS * sizeof(double);
+static __device__ __align__(256) double scratch[FWD_SSE_PARTS];
+static_assert(sizeof(scratch) == kScratchBytes, "scratch holds the fused loss partials");
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (null and the HIP error recorded when
+// the lookup fails).
+static void* scratch_on_current_device() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_hip_error(e);
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            set_hip_error(e);
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
 }
 
 }  // namespace icl
@@ -614,7 +658,17 @@ extern "C" {
 
 icl_status icl_bank_fwd_sse(const float* x, const float* w, const float* t, float* y, float* gy, float* loss, int n,
                             int f, int h, int wd, int radius, void* workspace, size_t workspace_bytes, void* stream) {
-    return bank_fwd_sse_entry(x, w, t, y, gy, loss, n, f, h, wd, radius, workspace, workspace_bytes, stream);
+    return bank_fwd_sse_entry(x, w, t, y, gy, loss, n, f, h, wd, radius, workspace, workspace_bytes, stream, true);
+}
+
+icl_status icl_bank_fwd_sse_noalloc(const float* x, const float* w, const float* t, float* y, float* gy, float* loss,
+                                    int n, int f, int h, int wd, int radius, void* stream) {
+    icl_status s = device_ready();
+    if (s != ICL_OK) return s;
+    if (bank_fwd_sse_workspace() > kScratchBytes) return ICL_ERR_WORKSPACE;
+    void* ws = scratch_on_current_device();
+    if (!ws) return ICL_ERR_HIP;
+    return bank_fwd_sse_entry(x, w, t, y, gy, loss, n, f, h, wd, radius, ws, kScratchBytes, stream, false);
 }
 
 // ------------------------------------------------------------------ variants

@@ -1209,7 +1209,6 @@ __global__ __launch_bounds__(256) void sse_k2(const float* __restrict__ part, in
 }
 
 // ------------------------------------------------------------------ forward fused with the loss
-constexpr int FWD_SSE_PARTS = 2048;   // most work-groups of a fused launch = double partials in the workspace
 
 // Plain fused forward: grid-stride over the outputs, each from its clamped taps directly
 // (the same tap order as every FMA forward variant), double partial per work-group.

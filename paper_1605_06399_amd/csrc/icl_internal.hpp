@@ -148,6 +148,9 @@ size_t sep3d_workspace(int W, int H, int D);
 size_t bank_bwd_filter_workspace(int n, int f, int h, int w, int r);
 size_t sse_workspace(long long count);
 size_t bank_fwd_sse_workspace();
+// Most work-groups of a fused forward + loss launch: one float64 loss partial each in the
+// workspace, so the workspace is the same for every problem size.
+constexpr int FWD_SSE_PARTS = 2048;
 
 hipError_t sse_launch(const float* y, const float* t, float* gy, long long count, float* loss,
                       void* ws, size_t wsb, hipStream_t st);
