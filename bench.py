@@ -189,7 +189,12 @@ def main():
     if not calls:
         # profiling aid: the extra workloads alone, no sweep line
         del src, dst, ws
-        print(json.dumps({"extras": run_extras(torch, B, T, synth, max(3, a.steps // 2), extras)}), flush=True)
+        torch.cuda.empty_cache()
+        out = {}
+        if a.calib_copy:
+            out["calib_copy_bytes_each_way"] = calib_copies(torch, dev)
+        out["extras"] = run_extras(torch, B, T, synth, max(3, a.steps // 2), extras)
+        print(json.dumps(out), flush=True)
         return
     stream = torch.cuda.current_stream()
 
@@ -316,14 +321,7 @@ def main():
     del src, dst, ws
     torch.cuda.empty_cache()
     if a.calib_copy:
-        n = (1 << 30) // 4
-        c_src = torch.ones(n, dtype=torch.float32, device=dev)
-        c_dst = torch.empty_like(c_src)
-        for _ in range(3):
-            c_dst.copy_(c_src)
-        torch.cuda.synchronize()
-        out["calib_copy_bytes_each_way"] = 1 << 30
-        del c_src, c_dst
+        out["calib_copy_bytes_each_way"] = calib_copies(torch, dev)
 
     if not a.no_extras:
         try:
@@ -334,6 +332,19 @@ def main():
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(synth, radii, side)
     print(json.dumps(out), flush=True)
+
+
+def calib_copies(torch, dev):
+    """Three 1 GiB device-to-device copies: a known byte count that scales the traffic counters."""
+    n = (1 << 30) // 4
+    c_src = torch.ones(n, dtype=torch.float32, device=dev)
+    c_dst = torch.empty_like(c_src)
+    for _ in range(3):
+        c_dst.copy_(c_src)
+    torch.cuda.synchronize()
+    del c_src, c_dst
+    torch.cuda.empty_cache()
+    return 1 << 30
 
 
 def copy_ceiling(torch, dev, reps=10):
