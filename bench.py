@@ -51,6 +51,9 @@ def parse():
     p.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter_collection.csv files of a --calib-copy "
                         "run into profiles/traffic.json and exit")
+    p.add_argument("--write-workload-traffic", metavar="DIR",
+                   help="turn the per-workload FETCH_SIZE / WRITE_SIZE runs under DIR into profiles/traffic.json "
+                        "entries and profiles/hbm_traffic_workloads.md, and exit")
     p.add_argument("--calib-copy", action="store_true",
                    help="also run three 1 GiB device-to-device copies (a known byte count for counter calibration)")
     return p.parse_args()
@@ -153,10 +156,111 @@ def write_traffic(fetch_csv, write_csv, side=4096):
     print(f"wrote {path}")
 
 
+# Kernels of the extra workloads whose HBM traffic is summarised: (workload, symbol pattern, label,
+# source files, algorithmic bytes per launch).  The symbols are those of the workloads' main launches
+# (the border-band launches of corners and NMS are listed by the summary as they are).
+_B_PX = 273398743          # pixels of the 256-image uneven batch (seeded recipe)
+_BANK = (32, 16, 1024 * 1024)
+WORKLOAD_KERNELS = [
+    ("batch", r"sep_batched_k<icl::(F16|BF16), (\d+)>", "walk_t{1}_{0}", ["batched.hip", "sep_tile.hpp",
+     "tile_stage.hpp", "icl_device.hpp"], 4 * _B_PX),
+    ("batch", r"sep_batched_strip_k<icl::(F16|BF16)>", "strip_{0}", ["batched.hip", "sep_strip.hpp",
+     "icl_device.hpp"], 4 * _B_PX),
+    ("corner", r"harris_(fused|stream)<(\d+), (\d+)>", "harris_{0}_t{2}", ["harris.hip", "harris_strip.hpp",
+     "icl_device.hpp"], 8 * 8192 * 8192),
+    ("corner", r"nms_stream<(\d+)>", "nms_stream_t{0}", ["nms.hip", "harris_strip.hpp", "icl_device.hpp"],
+     5 * 8192 * 8192),
+    ("corner", r"corners_stream<(\d+), (\d+), 1>", "corners_stream_t{1}", ["corners.hip", "harris_strip.hpp",
+     "icl_device.hpp"], 5 * 8192 * 8192),
+    ("bank", r"bank_fwd_(mfma_k<4, true>|pers_k<4, true>|sse_tpre_k<4>)", "fwd_sse:{0}", ["bank.hip"],
+     4 * (_BANK[0] * _BANK[2] + 2 * _BANK[0] * _BANK[1] * _BANK[2])),
+    ("bank", r"bank_bwd_in_(pers_k|k)<4>", "bwd_input:{0}", ["bank.hip"],
+     4 * (_BANK[0] * _BANK[1] * _BANK[2] + _BANK[0] * _BANK[2])),
+    ("bank", r"bank_bwd_(wm_k<4, \d>|w4_k<4, \d, 16>)", "bwd_filter:{0}", ["bank.hip"],
+     4 * (_BANK[0] * _BANK[1] * _BANK[2] + _BANK[0] * _BANK[2])),
+    ("paper", r"sep_(fused|pers)<icl::F32, 2, (\d+), (\d+)>", "sep5_constant:{0}_t{1}_c{2}",
+     KERNEL_SOURCES["sep"], 8 * 4096 * 4096),
+    ("paper", r"u8_strip<2, (\d+), (\d+)>", "u8_5x5:strip_p{1}_t{0}", ["conv2d_u8.hip", "icl_device.hpp"],
+     2 * 8192 * 8192),
+    ("volume", r"sep3_stream<icl::F32, (\d+), (\d+)>", "sep3d_r{0}:stream_z{1}", ["conv3d.hip", "icl_device.hpp"],
+     8 * 256 ** 3),
+]
+
+
+def write_workload_traffic(root):
+    """HBM bytes per dispatch of the extra workloads' kernels from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+    runs of `bench.py --only <workload> --calib-copy` (one directory per workload and counter under root),
+    scaled by the run's 1 GiB calibration copies; merged into profiles/traffic.json and tabulated in
+    profiles/hbm_traffic_workloads.md."""
+    import collections
+    import csv
+    import re
+
+    def load(p):
+        # per kernel, the dispatches of its largest grid (the full-size launches; a kernel that is also
+        # launched on small checks or border bands has other grid sizes)
+        agg = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in csv.DictReader(open(p)):
+            agg[r["Kernel_Name"]][int(r["Grid_Size"])].append(float(r["Counter_Value"]))
+        return {k: g[max(g)] for k, g in agg.items()}
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    out = json.load(open(path)) if os.path.exists(path) else {}
+    rows, cmds = [], []
+    for wl in EXTRAS:
+        fp = os.path.join(root, f"tr_{wl}_FETCH_SIZE", "tr_counter_collection.csv")
+        wp = os.path.join(root, f"tr_{wl}_WRITE_SIZE", "tr_counter_collection.csv")
+        if not (os.path.exists(fp) and os.path.exists(wp)):
+            continue
+        for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+            cmds.append(f"rocprofv3 --pmc {ctr} --output-format csv -d {root}/tr_{wl}_{ctr} -o tr -- "
+                        f"python3 bench.py --only {wl} --steps 4 --warmup 1 --no-cpu --calib-copy")
+        fe, wr = load(fp), load(wp)
+        cf = sorted(v for k, vs in fe.items() if "copyBuffer" in k for v in vs)[-3:]
+        cw = sorted(v for k, vs in wr.items() if "copyBuffer" in k for v in vs)[-3:]
+        fcal, wcal = (1 << 20) / (sum(cf) / 3), (1 << 20) / (sum(cw) / 3)
+        for kname in sorted(fe):
+            for w2, pat, label, srcs, alg in WORKLOAD_KERNELS:
+                m = re.search(pat, kname)
+                if w2 != wl or not m or kname not in wr:
+                    continue
+                f, w = float(np.mean(fe[kname])), float(np.mean(wr[kname]))
+                b = (f * fcal + w * wcal) * 1024
+                key = f"{wl}:{label.format(*m.groups())}"
+                out[key] = {"fetch_kib": round(f, 1), "write_kib": round(w, 1), "dispatches": len(fe[kname]),
+                            "fetch_factor": round(fcal, 4), "write_factor": round(wcal, 4),
+                            "bytes_per_launch": int(b), "algorithmic_bytes": alg, "ratio": round(b / alg, 3),
+                            "source_hash": source_hash(*srcs)}
+                rows.append((key, f, w, len(fe[kname]), int(b), alg, b / alg))
+    out["_workload_commands"] = cmds
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    md = ["# HBM traffic per launch: the extra workloads' kernels", "",
+          "Commands (repository root, one MI355X), one counter per pass; then "
+          f"`python3 bench.py --write-workload-traffic {root}`:", "", "```", *cmds, "```", "",
+          "Each counter is scaled by what it reads on the same run's three 1 GiB device-to-device copies "
+          "(FETCH_SIZE reads half the copied bytes, WRITE_SIZE all of them); the mean is over a kernel's "
+          "dispatches of its largest grid (the full-size launches).  Algorithmic bytes: what the call "
+          "must read and write once (batch 4 B/px over 273,398,743 px; Harris 8 B/px, NMS and fused corners "
+          "5 B/px at 8192^2; filter bank at 32 x 16 x 1024^2: x + t read and gy written for the fused "
+          "forward+loss, gy + x (+ gx) for the adjoints; separable 5x5 8 B/px at 4096^2; unsigned char 5x5 "
+          "2 B/px at 8192^2; separable 3-D 8 B/voxel at 256^3).", "",
+          "| workload:kernel | dispatches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | HBM bytes / launch | algorithmic "
+          "| ratio |", "|---|---|---|---|---|---|---|"]
+    for key, f, w, n, b, alg, ratio in rows:
+        md.append(f"| {key} | {n} | {f:.0f} | {w:.0f} | {b:,} | {alg:,} | {ratio:.3f} |")
+    with open(os.path.join(ROOT, "profiles", "hbm_traffic_workloads.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print(f"wrote {path} and profiles/hbm_traffic_workloads.md ({len(rows)} kernels)")
+
+
 def main():
     a = parse()
     if a.write_traffic:
         write_traffic(*a.write_traffic, side=a.side)
+        return
+    if a.write_workload_traffic:
+        write_workload_traffic(a.write_workload_traffic)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); sharding over several GPUs "
