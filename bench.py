@@ -739,6 +739,21 @@ def extra_corner(torch, B, T, synth, steps):
         finally:
             B.icl_force_variant(B.ICL_OP_HARRIS, -1)
     res["corner_8192"]["harris_variants_ms"] = per_variant
+    T.harris(xs[0], g, 0.04, out=Rs[0])
+    T.harris(xs[1], g, 0.04, out=Rs[1])
+    nms_variants = {}
+    for v in range(B.icl_variant_count(B.ICL_OP_NMS)):
+        B.check(B.icl_force_variant(B.ICL_OP_NMS, v))
+        try:
+            dv = _time_graph(torch, lambda s: T.nms(Rs[s % 2], 1e-3, out=Ms[s % 2]), 2 * steps)
+            nms_variants[B.icl_variant_name(B.ICL_OP_NMS, v)] = round(dv * 1e6, 1)
+        except Exception as e:   # a variant that does not take this input
+            nms_variants[B.icl_variant_name(B.ICL_OP_NMS, v)] = repr(e)[:60]
+        finally:
+            B.icl_force_variant(B.ICL_OP_NMS, -1)
+    res["corner_8192"]["nms_variant"] = B.icl_variant_name(B.ICL_OP_NMS, B.icl_selected_variant(
+        B.ICL_OP_NMS, B.ICL_F32, 1, W, H)[1])
+    res["corner_8192"]["nms_variants_us"] = nms_variants
     # the same pipeline fused into one pass (icl_corners): 5 algorithmic B/px, response in registers
     B.check(B.icl_tune(B.ICL_OP_CORNERS, B.ICL_F32, 2, W, H, st))
 

@@ -38,7 +38,13 @@ struct DevImage {
     unsigned long long sp, dp;
     const float* tx;
     const float* ty;
-    int W, H, r, vec_ok, vec_out, pad;
+    int W, H, r, vec_ok, vec_out;
+    unsigned src_bytes;   // extent of the source rows in bytes (the column walk's buffer size; 0 if >= 2^31)
+};
+
+// A column-walk item: output columns x0 .. x0 + 63 of image img over rows y0 .. y0 + rows - 1.
+struct ColItem {
+    int img, x0, y0, rows;
 };
 
 struct BatchTile {
@@ -145,6 +151,164 @@ __global__ __launch_bounds__(64) void sep_batched_strip_k(const DevImage* __rest
     }
 }
 
+// ------------------------------------------------------------------ column walk
+// A work-group walks one item: a 64-column strip of one image over a segment of rows, in
+// steps of 64 output rows.  A step stages only the 64 input rows it adds, row-passes them
+// into the T rows below the 2r T rows the previous step left (moved to the top), and
+// column-passes 64 + 2r T rows.  So inside a segment every input row is loaded and
+// row-passed once; a walk of separate 64 x 64 tiles loads and row-passes 64 + 2r rows per
+// 64 output rows.  The whole item body is instantiated per radius (one wave-uniform switch
+// per item), with the same row and column passes, in the same tap order, as every other
+// separable kernel.  The source is read through a buffer descriptor with 32-bit offsets.
+constexpr int CSTEP = 64;                     // output rows per step
+constexpr int CLW_MAX = 64 + 16;              // staged row length at RA = 8 (floats)
+constexpr int CT_ROWS = CSTEP + 2 * RMAX;     // T rows
+
+template <class T, int R, int NROWS>
+struct ColStage {
+    static constexpr int RA = (R + 3) & ~3, LW = 64 + 2 * RA, C4 = LW / 4;
+    static constexpr int NCH = NROWS * C4, PER = (NCH + 255) / 256;
+    typename Raw4<T>::type v[PER > 0 ? PER : 1];
+    int gy = 0;
+
+    // Staged rows gy .. gy + NROWS - 1 (clamped into the image), columns x0 - RA .. x0 + 63 + RA.
+    // inside (the columns lie in the image, rows 4-pixel aligned): straight vector loads into
+    // registers, all in flight together, written to LDS by store().  Otherwise nothing is
+    // loaded here: store() reads the chunks through the clamp itself (a strip at an image's
+    // left or right edge, one in about eight), which keeps the rare edge path out of the
+    // register budget of the prefetch.
+    __device__ __forceinline__ void load(const DevImage& d, Rsrc rs, int x0, int row0, bool inside) {
+        gy = row0;
+        if (!inside) return;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int idx = (int)threadIdx.x + 256 * k;
+            if (NCH % 256 != 0 && idx >= NCH) break;
+            const int rr = idx / C4, c4 = idx - rr * C4;
+            const unsigned row = (unsigned)clampi(gy + rr, d.H) * (unsigned)d.sp;
+            v[k] = bload4_raw<T>(rs, row + (unsigned)(x0 - RA + 4 * c4) * T::size);
+        }
+    }
+    __device__ __forceinline__ void store(float* __restrict__ in_s, const DevImage& d, Rsrc rs, int x0,
+                                          bool inside) const {
+        if (inside) {
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int idx = (int)threadIdx.x + 256 * k;
+                if (NCH % 256 != 0 && idx >= NCH) break;
+                const int rr = idx / C4, c4 = idx - rr * C4;
+                lds4(&in_s[rr * LW + 4 * c4], decode4<T>(v[k]));
+            }
+            return;
+        }
+        for (int idx = (int)threadIdx.x; idx < NCH; idx += 256) {
+            const int rr = idx / C4, c4 = idx - rr * C4;
+            const unsigned row = (unsigned)clampi(gy + rr, d.H) * (unsigned)d.sp;
+            const int x = x0 - RA + 4 * c4;
+            typename Raw4<T>::type r;
+            if (d.vec_ok && x >= 0 && x + 4 <= d.W) {
+                r = bload4_raw<T>(rs, row + (unsigned)x * T::size);
+            } else {
+                unsigned e[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) e[q] = bload1_raw<T>(rs, row + (unsigned)clampi(x + q, d.W) * T::size);
+                r = pack4_raw<T>(e[0], e[1], e[2], e[3]);
+            }
+            lds4(&in_s[rr * LW + 4 * c4], decode4<T>(r));
+        }
+    }
+};
+
+// A value every lane loaded from the same address, moved to a scalar register: the item
+// table and the images' descriptors and taps are read with vector loads (the compiler cannot
+// prove that the kernel's stores leave them unchanged), and this keeps them out of the
+// vector register budget.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+template <class P> __device__ __forceinline__ P* uni(P* p) {
+    const unsigned long long a = (unsigned long long)p;
+    const unsigned long long lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)a);
+    const unsigned long long hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
+    return reinterpret_cast<P*>(lo | (hi << 32));
+}
+__device__ __forceinline__ DevImage uni(const DevImage& d) {
+    DevImage u;
+    u.src = uni(d.src); u.dst = uni(d.dst);
+    u.sp = (unsigned long long)uni((int)d.sp) & 0xffffffffull;
+    u.dp = ((unsigned long long)(unsigned)uni((int)(d.dp >> 32)) << 32) | (unsigned)uni((int)d.dp);
+    u.tx = uni(d.tx); u.ty = uni(d.ty);
+    u.W = uni(d.W); u.H = uni(d.H); u.r = uni(d.r); u.vec_ok = uni(d.vec_ok); u.vec_out = uni(d.vec_out);
+    u.src_bytes = (unsigned)uni((int)d.src_bytes);
+    return u;
+}
+
+template <class T, int R>
+__device__ __forceinline__ void col_item(const DevImage& d, const ColItem& it, float* __restrict__ in_s,
+                                         float* __restrict__ t_s) {
+    constexpr int RA = (R + 3) & ~3;
+    const Rsrc rs = make_rsrc(d.src, d.src_bytes);
+    float tx[2 * R + 1], ty[2 * R + 1];
+#pragma unroll
+    for (int i = 0; i <= 2 * R; ++i) {
+        tx[i] = uni(d.tx[i]);
+        ty[i] = uni(d.ty[i]);
+    }
+    const bool inside = d.vec_ok && it.x0 - RA >= 0 && it.x0 + 64 + RA <= d.W;
+    const int nsteps = (it.rows + CSTEP - 1) / CSTEP;
+    // prologue: T rows 0 .. 2r - 1 from input rows y0 - r .. y0 + r - 1
+    ColStage<T, R, CSTEP> st;
+    if constexpr (R > 0) {
+        ColStage<T, R, 2 * R> pro;
+        pro.load(d, rs, it.x0, it.y0 - R, inside);
+        st.load(d, rs, it.x0, it.y0 + R, inside);
+        pro.store(in_s, d, rs, it.x0, inside);
+        __syncthreads();
+        sep_row_pass<R, 0, 1, 1>(in_s, t_s, tx);
+        __syncthreads();
+    } else {
+        st.load(d, rs, it.x0, it.y0 + R, inside);
+    }
+    for (int s = 0; s < nsteps; ++s) {
+        st.store(in_s, d, rs, it.x0, inside);
+        if (R > 0 && s > 0) {   // the previous step's last 2r T rows become the first
+            const int q = (int)threadIdx.x;
+            if (q < 2 * R * 16) lds4(&t_s[4 * q], lds4(&t_s[CSTEP * 64 + 4 * q]));
+        }
+        __syncthreads();
+        if (s + 1 < nsteps) st.load(d, rs, it.x0, it.y0 + CSTEP * (s + 1) + R, inside);
+        sep_row_pass<R, CSTEP - 2 * R, 1, 1>(in_s, t_s + 2 * R * 64, tx);
+        __syncthreads();
+        sep_col_pass<T, R, CSTEP, 1, 6>(t_s, d.dst, d.dp, d.W, d.H, ty, it.x0, it.y0 + CSTEP * s, d.vec_out);
+        __syncthreads();
+    }
+}
+
+// Items are ordered by decreasing radius; end[R] is one past the last item of radius R (the
+// radius-7 items come first).  A work-group takes items b, b + grid, b + 2 grid, ... of that
+// order, and the walk is split into one loop per radius, so each loop's body is compiled for
+// its radius alone (one loop with a switch over the radius would hold the registers of all
+// eight bodies at once).
+struct ColRanges {
+    int end[RMAX + 1];
+};
+
+template <class T>
+__global__ __launch_bounds__(256, 4) void sep_batched_col_k(const DevImage* __restrict__ imgs,
+                                                            const ColItem* __restrict__ items, ColRanges rg) {
+    __shared__ __attribute__((aligned(16))) float in_s[CSTEP * CLW_MAX];
+    __shared__ __attribute__((aligned(16))) float t_s[CT_ROWS * 64];
+    int i = first_tile();
+    static_for<RMAX + 1>([&](auto k) {
+        constexpr int R = RMAX - decltype(k)::value;
+        for (; i < rg.end[R]; i += (int)gridDim.x) {
+            const ColItem li = items[i];
+            const ColItem it{uni(li.img), uni(li.x0), uni(li.y0), uni(li.rows)};
+            const DevImage d = uni(imgs[it.img]);
+            col_item<T, R>(d, it, in_s, t_s);
+        }
+    });
+}
+
 }  // namespace
 
 // the tile walk: on the 256-image workload the strip walk's waves hold too many registers
@@ -169,6 +333,10 @@ using namespace icl;
 // Tile tables of the tile-walk variants: 64-row tiles in image order, 64-row tiles with
 // the largest radius first, 32-row tiles with the largest radius first.
 constexpr int NWALKS = 3;
+// Column walks: segments of 256, 512 and 2048 rows (2048: a whole image of the usual batch).
+constexpr int NCOL = 3;
+constexpr int kColSeg[NCOL] = {256, 512, 2048};
+constexpr int kFirstCol = 4;   // variant index of the first column walk
 
 struct icl_batch_plan {
     icl_dtype dt;
@@ -179,6 +347,11 @@ struct icl_batch_plan {
     StripItem* d_items;
     int nitems;
     int strip_grid;
+    ColItem* d_col[NCOL];
+    int ncol[NCOL];
+    ColRanges col_rg[NCOL];
+    int col_grid[NCOL];
+    bool col_ok;   // every image's source extent fits a 31-bit buffer offset
     long long pixels;
     int nimg, rmax;
     int tuned;   // walk picked by icl_batch_plan_tune, -1 before
@@ -212,6 +385,14 @@ void launch_walk(const icl_batch_plan* p, int w, hipStream_t st) {
                            p->ntiles[w]);
 }
 
+const void* col_kernel_for(icl_dtype dt) {
+    switch (dt) {
+        case ICL_F32: return reinterpret_cast<const void*>(&sep_batched_col_k<F32>);
+        case ICL_F16: return reinterpret_cast<const void*>(&sep_batched_col_k<F16>);
+        default: return reinterpret_cast<const void*>(&sep_batched_col_k<BF16>);
+    }
+}
+
 const void* strip_kernel_for(icl_dtype dt) {
     switch (dt) {
         case ICL_F32: return reinterpret_cast<const void*>(&sep_batched_strip_k<F32>);
@@ -229,10 +410,15 @@ Problem plan_problem(const icl_batch_plan* p) {
                    std::max(p->nimg, 1)};
 }
 
+// the first column walk where it can address every image, else the tile walk
+int plan_default(const icl_batch_plan* p) { return p->col_ok ? kFirstCol : batched_default(); }
+
 int plan_variant(const icl_batch_plan* p) {
-    if (variant_forced(ICL_OP_CONV_SEP_BATCHED) || p->tuned < 0)
-        return select_variant(plan_problem(p), batched_default());
-    return p->tuned;
+    int v = (variant_forced(ICL_OP_CONV_SEP_BATCHED) || p->tuned < 0) ? select_variant(plan_problem(p), plan_default(p))
+                                                                      : p->tuned;
+    // a cached column walk for a plan whose images it cannot address takes the default
+    if (v >= kFirstCol && !p->col_ok && !variant_forced(ICL_OP_CONV_SEP_BATCHED)) v = plan_default(p);
+    return v;
 }
 
 // Order-independent digest of every output pixel of a plan (sum over pixels of a SplitMix64
@@ -315,7 +501,8 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
         di.tx = d.taps_x; di.ty = d.taps_y; di.W = d.width; di.H = d.height; di.r = d.radius;
         di.vec_ok = ((uintptr_t)d.src % al == 0) && (d.src_pitch % al == 0);
         di.vec_out = ((uintptr_t)d.dst % al == 0) && (d.dst_pitch % al == 0);
-        di.pad = 0;
+        const size_t ext = (size_t)(d.height - 1) * d.src_pitch + (size_t)d.width * es;
+        di.src_bytes = ext < ((size_t)1 << 31) ? (unsigned)ext : 0u;
         imgs.push_back(di);
         pixels += (long long)d.width * d.height;
         const int tx = (d.width + 64 * BCX - 1) / (64 * BCX);
@@ -334,6 +521,31 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
     // radius body at a time), then image, row, column
     std::stable_sort(items.begin(), items.end(),
                      [](const StripItem& a, const StripItem& b) { return a.r > b.r; });
+    // column-walk items: images by decreasing radius, then by decreasing work of one item
+    // (segment rows x (2r + 3)), so the longest items start first; inside an image by
+    // segment, then column, so the items running side by side share their halo columns
+    std::vector<ColItem> cols[NCOL];
+    bool col_ok = true;
+    {
+        std::vector<int> order;
+        for (int i = 0; i < (int)imgs.size(); ++i)
+            if (imgs[i].src) order.push_back(i);
+        for (int c = 0; c < NCOL; ++c) {
+            const int seg = kColSeg[c];
+            auto work = [&](int i) { return (long long)std::min(imgs[i].H, seg) * (2 * imgs[i].r + 3); };
+            std::vector<int> o = order;
+            std::stable_sort(o.begin(), o.end(), [&](int a, int b) {
+                return imgs[a].r != imgs[b].r ? imgs[a].r > imgs[b].r : work(a) > work(b);
+            });
+            for (int i : o) {
+                const DevImage& d = imgs[i];
+                for (int y = 0; y < d.H; y += seg)
+                    for (int x = 0; x < d.W; x += 64) cols[c].push_back(ColItem{i, x, y, std::min(seg, d.H - y)});
+            }
+        }
+        for (const DevImage& d : imgs)
+            if (d.src && (d.src_bytes == 0 || d.sp >= ((size_t)1 << 31))) col_ok = false;
+    }
     tiles[1] = tiles[0];
     auto by_radius = [](const BatchTile& a, const BatchTile& b) { return a.r > b.r; };
     std::stable_sort(tiles[1].begin(), tiles[1].end(), by_radius);
@@ -383,6 +595,19 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
         e = hipMemcpy(p->d_imgs, imgs.data(), imgs.size() * sizeof(DevImage), hipMemcpyHostToDevice);
     if (e == hipSuccess && !items.empty())
         e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(StripItem), hipMemcpyHostToDevice);
+    p->col_ok = col_ok;
+    for (int c = 0; c < NCOL; ++c) {
+        p->ncol[c] = (int)cols[c].size();
+        for (int r = 0; r <= RMAX; ++r) {   // items of radius r end after those of radius >= r
+            int n = 0;
+            for (const ColItem& it : cols[c]) n += imgs[it.img].r >= r ? 1 : 0;
+            p->col_rg[c].end[r] = n;
+        }
+        if (e == hipSuccess && !cols[c].empty()) e = hipMalloc(&p->d_col[c], cols[c].size() * sizeof(ColItem));
+        if (e == hipSuccess && !cols[c].empty())
+            e = hipMemcpy(p->d_col[c], cols[c].data(), cols[c].size() * sizeof(ColItem), hipMemcpyHostToDevice);
+    }
+    int per_cu_col = 0;
     int per_cu[NWALKS] = {}, per_cu_strip = 0, dev = 0, cus = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -390,12 +615,15 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[w], kernel_for(dtype, w), 256, 0);
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_strip, strip_kernel_for(dtype), 64, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_col, col_kernel_for(dtype), 256, 0);
     if (e != hipSuccess) {
-        hipFree(p->d_imgs);
-        for (int w = 0; w < NWALKS; ++w) hipFree(p->d_tiles[w]);
-        hipFree(p->d_items);
-        delete p;
+        icl_batch_plan_destroy(p);
         return hip_status(e);
+    }
+    for (int c = 0; c < NCOL; ++c) {
+        const long long resident = (long long)std::max(per_cu_col, 1) * std::max(cus, 1);
+        p->col_grid[c] = (int)std::min<long long>(resident, std::max(p->ncol[c], 1));
+        if (p->col_grid[c] > 8) p->col_grid[c] -= p->col_grid[c] % 8;
     }
     for (int w = 0; w < NWALKS; ++w) {
         const long long resident = (long long)std::max(per_cu[w], 1) * std::max(cus, 1);
@@ -490,6 +718,25 @@ icl_status icl_batch_plan_tune(icl_batch_plan* plan, void* stream) {
 namespace {
 
 hipError_t launch_plan(const icl_batch_plan* plan, int v, hipStream_t st) {
+    if (v >= kFirstCol) {
+        const int c = v - kFirstCol;
+        if (!plan->col_ok) return hipErrorInvalidValue;
+        switch (plan->dt) {
+            case ICL_F32:
+                hipLaunchKernelGGL(sep_batched_col_k<F32>, dim3(plan->col_grid[c]), dim3(256), 0, st, plan->d_imgs,
+                                   plan->d_col[c], plan->col_rg[c]);
+                break;
+            case ICL_F16:
+                hipLaunchKernelGGL(sep_batched_col_k<F16>, dim3(plan->col_grid[c]), dim3(256), 0, st, plan->d_imgs,
+                                   plan->d_col[c], plan->col_rg[c]);
+                break;
+            default:
+                hipLaunchKernelGGL(sep_batched_col_k<BF16>, dim3(plan->col_grid[c]), dim3(256), 0, st, plan->d_imgs,
+                                   plan->d_col[c], plan->col_rg[c]);
+                break;
+        }
+        return hipGetLastError();
+    }
     if (v == 1) {
         switch (plan->dt) {
             case ICL_F32:
@@ -532,6 +779,7 @@ void icl_batch_plan_destroy(icl_batch_plan* plan) {
     hipFree(plan->d_imgs);
     for (int w = 0; w < NWALKS; ++w) hipFree(plan->d_tiles[w]);
     hipFree(plan->d_items);
+    for (int c = 0; c < NCOL; ++c) hipFree(plan->d_col[c]);
     delete plan;
 }
 

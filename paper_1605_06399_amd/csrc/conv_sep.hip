@@ -19,6 +19,9 @@
 //                       work-group, Fig. 4c), keeping stores coalesced.
 //   pers_t{TH}_c{CX}  : the fused tile body in a persistent grid that prefetches the
 //                       next tile into registers while computing the current one.
+//   fused_img_t{TH}_c{CX}: the fused tile staged through one buffer descriptor per row,
+//                       whose hardware range check supplies the constant-0 boundary (the
+//                       stand-in for the paper's image-memory candidate; see below).
 //   strip_t{TH}       : one wave per strip of 256 - 8*ceil(r/4) output columns and TH
 //                       rows, walking down the rows with both passes in registers:
 //                       horizontal neighbours by DPP lane shifts, a ring of 2r+1
@@ -234,6 +237,107 @@ hipError_t launch_pers(const SepArgs& a) {
     }
 }
 
+// ------------------------------------------------------------------ image-memory stand-in
+// The paper's image-memory candidate reads pixels through the texture unit, whose sampler
+// applies the boundary condition (Section 5.2).  gfx950 has no image instructions; the
+// nearest it has is a buffer descriptor, whose hardware range check returns 0 for any read
+// at or past the descriptor's size.  Here each staged row is read through a descriptor of
+// its own, wave-uniform: base at the row, size W pixels for a row inside the image and 0
+// for a row outside.  With the constant boundary at 0 the hardware then supplies both
+// bounds: a column left of the image is a negative (as unsigned, huge) offset and a column
+// at or right of W an offset past the size, so the staging has no boundary arithmetic at
+// all.  With the clamp boundary the offsets are clamped (the row by its base, the column in
+// software, as the sampler's clamp-to-edge mode would); a nonzero constant is applied after
+// the read.  One pixel per lane and load (a dword or short buffer load), each wave a row.
+template <class T> __device__ __forceinline__ float decode1(unsigned bits);
+template <> __device__ __forceinline__ float decode1<F32>(unsigned b) { return __uint_as_float(b); }
+template <> __device__ __forceinline__ float decode1<F16>(unsigned b) {
+    return decode(__builtin_bit_cast(_Float16, (unsigned short)b));
+}
+template <> __device__ __forceinline__ float decode1<BF16>(unsigned b) { return __uint_as_float(b << 16); }
+
+template <class T, int NR, int LW>
+__device__ __forceinline__ void stage_rows_img(const void* __restrict__ src, size_t sp, int W, int H, int gx0, int gy0,
+                                               Border bd, float* __restrict__ in_s) {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = (int)(threadIdx.x & 63);
+    const bool cst = bd.constant != 0, cnz = cst && bd.value != 0.f;
+    for (int rr = wave; rr < NR; rr += 4) {
+        const int y = gy0 + rr;
+        const bool yin = y >= 0 && y < H;
+        const char* base = static_cast<const char*>(src) + (size_t)clampi(y, H) * sp;
+        const Rsrc rs = make_rsrc(base, (cst && !yin) ? 0u : (unsigned)W * T::size);
+#pragma unroll
+        for (int c0 = 0; c0 < LW; c0 += 64) {
+            const int c = c0 + lane;
+            if (LW % 64 != 0 && c >= LW) break;
+            const int x = gx0 + c;
+            const unsigned off = (unsigned)(cst ? x : clampi(x, W)) * (unsigned)T::size;
+            float v = decode1<T>(bload1_raw<T>(rs, off));
+            if (cnz && (!yin || x < 0 || x >= W)) v = bd.value;
+            in_s[rr * LW + c] = v;
+        }
+    }
+}
+
+template <class T, int R, int TH, int CX>
+__global__ __launch_bounds__(256) void sep_fused_img(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
+                                                     size_t dp, int W, int H, const float* __restrict__ tx,
+                                                     const float* __restrict__ ty, int tiles_x, int vec_out, Border bd) {
+    using G = SepTile<R, TH, CX>;
+    __shared__ __attribute__((aligned(16))) float lds[G::LDS_FLOATS];
+    float* in_s = lds;
+    float* t_s = lds + G::NR * G::LW;
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int x0 = (int)(t % (unsigned)tiles_x) * G::TW;
+    const int y0 = (int)(t / (unsigned)tiles_x) * TH;
+    stage_rows_img<T, G::NR, G::LW>(src, sp, W, H, x0 - G::RA, y0 - R, bd, in_s);
+    __syncthreads();
+    sep_row_pass<R, TH, CX>(in_s, t_s, tx);
+    __syncthreads();
+    sep_col_pass<T, R, TH, CX>(t_s, dst, dp, W, H, ty, x0, y0, vec_out != 0);
+}
+
+template <class T, int R, int TH, int CX>
+hipError_t launch_img_TR(const SepArgs& a) {
+    using G = SepTile<R, TH, CX>;
+    const int tiles_x = (a.W + G::TW - 1) / G::TW;
+    const int tiles_y = (a.H + TH - 1) / TH;
+    const size_t al = 4 * (size_t)T::size;
+    const int vec_out = ((uintptr_t)a.dst % al == 0) && (a.dp % al == 0);
+    hipLaunchKernelGGL((sep_fused_img<T, R, TH, CX>), dim3(tiles_x * tiles_y), dim3(256), 0, a.st, a.src, a.sp, a.dst,
+                       a.dp, a.W, a.H, a.tx, a.ty, tiles_x, vec_out, a.bd);
+    return hipGetLastError();
+}
+
+template <class T, int TH, int CX>
+hipError_t launch_img_T(const SepArgs& a) {
+    switch (a.r) {
+        case 0: return launch_img_TR<T, 0, TH, CX>(a);
+        case 1: return launch_img_TR<T, 1, TH, CX>(a);
+        case 2: return launch_img_TR<T, 2, TH, CX>(a);
+        case 3: return launch_img_TR<T, 3, TH, CX>(a);
+        case 4: return launch_img_TR<T, 4, TH, CX>(a);
+        case 5: return launch_img_TR<T, 5, TH, CX>(a);
+        case 6: return launch_img_TR<T, 6, TH, CX>(a);
+        case 7: return launch_img_TR<T, 7, TH, CX>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int TH, int CX>
+hipError_t launch_img(const SepArgs& a) {
+    switch (a.dt) {
+        case ICL_F32: return launch_img_T<F32, TH, CX>(a);
+        case ICL_F16: return launch_img_T<F16, TH, CX>(a);
+        default: return launch_img_T<BF16, TH, CX>(a);
+    }
+}
+
+// the row descriptors address a row with 32-bit offsets: the row must be under 2^31 bytes
+bool supports_img(const SepArgs& a) {
+    return supports_fused(a) && (size_t)a.W * (a.dt == ICL_F32 ? 4 : 2) < ((size_t)1 << 31);
+}
+
 // ------------------------------------------------------------------ register strips
 template <class T, int R, int TH>
 __global__ __launch_bounds__(64) void sep_strip(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
@@ -295,6 +399,8 @@ const Variant<SepArgs> kSep[] = {
     {"strip_t32", supports_fused, launch_strip<32>},
     {"strip_t16", supports_fused, launch_strip<16>},
     {"strip_t64", supports_fused, launch_strip<64>},
+    {"fused_img_t32_c1", supports_img, launch_img<32, 1>},
+    {"fused_img_t16_c2", supports_img, launch_img<16, 2>},
 };
 
 }  // namespace

@@ -36,6 +36,20 @@ __device__ __forceinline__ float lane_from_right(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130 /* wave_shl:1 */, 0xf, 0xf, true));
 }
 
+// The same shifts with the end lane's value supplied: lane 0 (from_left) or lane 63
+// (from_right) receives `edge`.  One DPP move whose old value is `edge` (bound_ctrl off: a
+// lane without a source keeps the old value), with every lane active.  (A select on the lane
+// index around a plain shift is not equivalent: the compiler may turn it into a branch that
+// masks the end lane off, and a DPP read from a masked-off lane yields 0 for its neighbour.)
+__device__ __forceinline__ float lane_from_left_or(float v, float edge) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_from_right_or(float v, float edge) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130 /* wave_shl:1 */, 0xf, 0xf, false));
+}
+
 // Native 4 x float32 vector: loads and stores of it lower to single dwordx4 /
 // ds_read_b128 instructions (HIP's float4 struct is copied member by member).
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -128,6 +142,53 @@ template <> __device__ __forceinline__ void store4<BF16>(void* base, size_t off,
     *reinterpret_cast<v2u*>(static_cast<char*>(base) + off) = u;
 }
 
+// ------------------------------------------------------------------ buffer-descriptor access
+// A raw buffer descriptor (base, size in bytes) lets a lane address the buffer with a 32-bit
+// byte offset (one VALU add instead of 64-bit address arithmetic), and the hardware's range
+// check returns 0 for a load at or past the size (and drops such a store) without touching
+// memory.  Dword 3 is the gfx9-family format word for untyped raw access.
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// Four pixels of storage type T at a byte offset, as stored (float32: four floats; half
+// types: four 16-bit values packed in two dwords), and their float32 values.
+template <class T> struct Raw4 { using type = v2u; };
+template <> struct Raw4<F32> { using type = v4f; };
+template <class T> __device__ __forceinline__ typename Raw4<T>::type bload4_raw(Rsrc rs, unsigned off) {
+    return __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+}
+template <> __device__ __forceinline__ v4f bload4_raw<F32>(Rsrc rs, unsigned off) {
+    return __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
+}
+// one pixel's stored bits, zero-extended
+template <class T> __device__ __forceinline__ unsigned bload1_raw(Rsrc rs, unsigned off) {
+    return __builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, 0, 0);
+}
+template <> __device__ __forceinline__ unsigned bload1_raw<F32>(Rsrc rs, unsigned off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
+}
+// four single pixels' bits (each zero-extended) packed as bload4_raw would return them
+template <class T> __device__ __forceinline__ typename Raw4<T>::type pack4_raw(unsigned a, unsigned b, unsigned c,
+                                                                              unsigned d) {
+    return v2u{a | (b << 16), c | (d << 16)};
+}
+template <> __device__ __forceinline__ v4f pack4_raw<F32>(unsigned a, unsigned b, unsigned c, unsigned d) {
+    return v4f{__uint_as_float(a), __uint_as_float(b), __uint_as_float(c), __uint_as_float(d)};
+}
+template <class T> __device__ __forceinline__ v4f decode4(typename Raw4<T>::type r);
+template <> __device__ __forceinline__ v4f decode4<F32>(v4f r) { return r; }
+template <> __device__ __forceinline__ v4f decode4<F16>(v2u r) {
+    const v4h h = __builtin_bit_cast(v4h, r);
+    return v4f{decode(h.x), decode(h.y), decode(h.z), decode(h.w)};
+}
+template <> __device__ __forceinline__ v4f decode4<BF16>(v2u r) {
+    return v4f{__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u), __uint_as_float(r.y << 16),
+               __uint_as_float(r.y & 0xffff0000u)};
+}
+
 // ------------------------------------------------------------------ indexing
 // Closest in-range index along one axis (clamped boundary condition).
 __device__ __forceinline__ int clampi(int i, int n) { return min(max(i, 0), n - 1); }
@@ -141,5 +202,8 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned n) {
     if (n % 8u) return bid;
     return (bid % 8u) * (n / 8u) + bid / 8u;
 }
+
+// Grid padded to a multiple of 8 (xcd_remap is a permutation of such a grid).
+inline unsigned grid_pad8(long long n) { return (unsigned)((n + 7) / 8 * 8); }
 
 }  // namespace icl

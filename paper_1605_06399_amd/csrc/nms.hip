@@ -18,6 +18,10 @@
 //   stream_t{TH}: one wave per 248-column strip and TH rows (r = 1): every response row
 //                loaded once, the 3 x 3 neighbourhood from registers and DPP lane shifts;
 //                the border bands run through row4.  16-byte aligned response rows.
+//   stream_a_t{TH}: one wave per 256-column strip at a multiple of 256 and TH rows (r = 1):
+//                all 64 lanes own outputs, aligned 1 KiB row reads and 256-byte mask writes,
+//                the two outside columns as broadcast values; columns right of the last whole
+//                strip run through row4.  _sm: strip-major wave order.
 #include "harris_strip.hpp"
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
@@ -176,11 +180,123 @@ hipError_t launch_stream(const NmsArgs& a) {
     return launch_row4_bands(a, NS_XL, xr);
 }
 
+// ------------------------------------------------------------------ aligned strips, r = 1
+// One wave per 256-column strip starting at a multiple of 256 and TH rows: every lane owns
+// four output columns, so each response row is one aligned 1 KiB read and each mask row one
+// aligned 256-byte write.  The two columns just outside the strip (its neighbours' edge
+// pixels, clamped at the image border) are read as one broadcast value each and replace the
+// DPP shift's missing neighbour in lanes 0 and 63.  Columns right of the last whole strip
+// run through the row kernel.
+__device__ __forceinline__ uint32_t nms_bits_edges(v4f a, v4f b, v4f c, float al_e, float ar_e, float bl_e, float br_e,
+                                                   float cl_e, float cr_e, float tau) {
+    const float al = lane_from_left_or(a.w, al_e), ar = lane_from_right_or(a.x, ar_e);
+    const float bl = lane_from_left_or(b.w, bl_e), br = lane_from_right_or(b.x, br_e);
+    const float cl = lane_from_left_or(c.w, cl_e), cr = lane_from_right_or(c.x, cr_e);
+    const float ea[6] = {al, a.x, a.y, a.z, a.w, ar};
+    const float eb[6] = {bl, b.x, b.y, b.z, b.w, br};
+    const float ec[6] = {cl, c.x, c.y, c.z, c.w, cr};
+    uint32_t bits = 0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const float v = eb[p + 1];
+        const bool keep = (v > tau) & (v >= ea[p]) & (v >= ea[p + 1]) & (v >= ea[p + 2]) & (v >= eb[p]) &
+                          (v >= eb[p + 2]) & (v >= ec[p]) & (v >= ec[p + 1]) & (v >= ec[p + 2]);
+        bits |= (keep ? 1u : 0u) << (8 * p);
+    }
+    return bits;
+}
+
+// SM: strip-major wave order after the XCD remap (the four waves of a work-group and the
+// work-groups an XCD runs together are consecutive row blocks of one strip, so the row
+// above and below a block come from that XCD's L2); otherwise row-major (the waves running
+// together read whole image rows).
+template <int TH, bool SM>
+__global__ __launch_bounds__(256) void nms_stream_a(const float* __restrict__ R, size_t rp, uint8_t* __restrict__ M,
+                                                    size_t mp, int W, int H, float tau, int nstrips, int nwaves) {
+    const int lane = threadIdx.x & 63;
+    int strip, y0;
+    if constexpr (SM) {
+        const int wv = (int)xcd_remap(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6);
+        if (wv >= nwaves) return;   // no barrier in this kernel: a wave may leave early
+        const int nrb = nwaves / nstrips;
+        strip = wv / nrb;
+        y0 = (wv - strip * nrb) * TH;
+    } else {
+        const int wv = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+        if (wv >= nwaves) return;
+        strip = wv % nstrips;
+        y0 = (wv / nstrips) * TH;
+    }
+    const int x0 = strip * 256;
+    const int xl = x0 > 0 ? x0 - 1 : 0, xr = x0 + 256 < W ? x0 + 256 : W - 1;
+    const char* base = reinterpret_cast<const char*>(R);
+    auto row = [&](int y) { return *reinterpret_cast<const v4f*>(base + (size_t)y * rp + (size_t)(x0 + 4 * lane) * 4); };
+    auto px = [&](int y, int x) { return *reinterpret_cast<const float*>(base + (size_t)y * rp + (size_t)x * 4); };
+    uint8_t* out = M + x0 + 4 * lane;
+    if (y0 >= 1 && y0 + TH <= H - 1) {
+        // interior: output row m reads rows y0 - 1 + m + {0, 1, 2} from a ring of RING rows
+        // (row i of the block in slot i mod RING), each loaded RING - 2 rows before use
+        constexpr int RING = 8;
+        const int ybase = y0 - 1;
+        v4f ring[RING];
+        float el[RING], er[RING];
+#pragma unroll
+        for (int i = 0; i < RING; ++i) {
+            ring[i] = row(ybase + i);
+            el[i] = px(ybase + i, xl);
+            er[i] = px(ybase + i, xr);
+        }
+        static_for<TH>([&](auto m_c) {
+            constexpr int m = decltype(m_c)::value, a = m % RING, b = (m + 1) % RING, c = (m + 2) % RING;
+            const uint32_t bits = nms_bits_edges(ring[a], ring[b], ring[c], el[a], er[a], el[b], er[b], el[c], er[c], tau);
+            if constexpr (m + RING <= TH + 1) {
+                ring[a] = row(ybase + m + RING);
+                el[a] = px(ybase + m + RING, xl);
+                er[a] = px(ybase + m + RING, xr);
+            }
+            *reinterpret_cast<uint32_t*>(out + (size_t)(y0 + m) * mp) = bits;
+        });
+        return;
+    }
+    // top or bottom block: rows clamp at the image edge
+    for (int m = 0; m < TH; ++m) {
+        const int y = y0 + m;
+        if (y >= H) break;
+        const int ya = clampi(y - 1, H), yc = clampi(y + 1, H);
+        const uint32_t bits = nms_bits_edges(row(ya), row(y), row(yc), px(ya, xl), px(ya, xr), px(y, xl), px(y, xr),
+                                             px(yc, xl), px(yc, xr), tau);
+        *reinterpret_cast<uint32_t*>(out + (size_t)y * mp) = bits;
+    }
+}
+
+bool supports_stream_a(const NmsArgs& a) {
+    return a.r == 1 && a.W >= 256 && (uintptr_t)a.R % 16 == 0 && a.rp % 16 == 0 && (uintptr_t)a.M % 4 == 0 &&
+           a.mp % 4 == 0;
+}
+
+template <int TH, bool SM>
+hipError_t launch_stream_a(const NmsArgs& a) {
+    const int nstrips = a.W / 256;
+    const int rows = (a.H + TH - 1) / TH;
+    const long long nwaves = (long long)nstrips * rows;
+    if (nwaves > 0x7ffffff0LL) return hipErrorInvalidValue;
+    const long long blocks = (nwaves + 3) / 4;
+    hipLaunchKernelGGL((nms_stream_a<TH, SM>), dim3(SM ? grid_pad8(blocks) : (unsigned)blocks), dim3(256), 0, a.st,
+                       a.R, a.rp, a.M, a.mp, a.W, a.H, a.tau, nstrips, (int)nwaves);
+    if (nstrips * 256 < a.W) return launch_row4_bands(a, 0, nstrips * 256);
+    return hipGetLastError();
+}
+
 const Variant<NmsArgs> kNms[] = {
     {"plain", supports_plain, launch_plain},
     {"row4", supports_row4, launch_row4},
     {"stream_t64", supports_stream, launch_stream<64>},
     {"stream_t32", supports_stream, launch_stream<32>},
+    {"stream_a_t64", supports_stream_a, launch_stream_a<64, false>},
+    {"stream_a_t32", supports_stream_a, launch_stream_a<32, false>},
+    {"stream_a_t16", supports_stream_a, launch_stream_a<16, false>},
+    {"stream_a_t32_sm", supports_stream_a, launch_stream_a<32, true>},
+    {"stream_a_t16_sm", supports_stream_a, launch_stream_a<16, true>},
 };
 
 }  // namespace

@@ -15,12 +15,14 @@ template <int R, int TH, int CX> struct SepTile {
 };
 
 // Row pass over a staged tile: in_s [NR][LW] -> t_s [NR][TW], four columns per item.
-template <int R, int TH, int CX>
+// UNR > 0 caps the unrolling of the item loop (a trip count known at compile time is
+// otherwise unrolled whole, with every item's window in registers at once).
+template <int R, int TH, int CX, int UNR = 0>
 __device__ __forceinline__ void sep_row_pass(const float* __restrict__ in_s, float* __restrict__ t_s,
                                              const float* __restrict__ tx) {
     using G = SepTile<R, TH, CX>;
     constexpr int TW = G::TW, RA = G::RA, LW = G::LW, NR = G::NR, G4 = TW / 4;
-    for (int idx = threadIdx.x; idx < NR * G4; idx += 256) {
+    auto item = [&](int idx) {
         const int rr = idx / G4, g = idx - rr * G4;
         float win[4 + 2 * RA];
 #pragma unroll
@@ -36,13 +38,21 @@ __device__ __forceinline__ void sep_row_pass(const float* __restrict__ in_s, flo
             for (int p = 0; p < 4; ++p) o[p] = fmaf(h, win[RA - R + p + i], o[p]);
         }
         lds4(&t_s[rr * TW + 4 * g], mk4(o[0], o[1], o[2], o[3]));
+    };
+    if constexpr (UNR > 0) {
+#pragma unroll UNR
+        for (int idx = threadIdx.x; idx < NR * G4; idx += 256) item(idx);
+    } else {
+        for (int idx = threadIdx.x; idx < NR * G4; idx += 256) item(idx);
     }
 }
 
 // Column pass: lane owns 4 adjacent columns (group g of TW/4) and PYC consecutive rows;
 // the t_s rows it needs are read as float4, and the 4 outputs of a row are stored as one
 // vector when the destination rows are 4-pixel aligned (vec_out).
-template <class T, int R, int TH, int CX>
+// GROUP > 0 fences the schedule every GROUP staged rows, so that at most GROUP rows' reads are
+// in registers at a time (a kernel that must fit a register budget).
+template <class T, int R, int TH, int CX, int GROUP = 0>
 __device__ __forceinline__ void sep_col_pass(const float* __restrict__ t_s, void* __restrict__ dst, size_t dp, int W,
                                              int H, const float* __restrict__ ty, int x0, int y0, bool vec_out) {
     using G = SepTile<R, TH, CX>;
@@ -56,6 +66,7 @@ __device__ __forceinline__ void sep_col_pass(const float* __restrict__ t_s, void
     for (int py = 0; py < PYC; ++py) acc[py] = mk4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int m = 0; m < PYC + 2 * R; ++m) {
+        if (GROUP > 0 && m > 0 && m % GROUP == 0) __builtin_amdgcn_sched_barrier(0);
         const v4f v = lds4(col + m * TW);
 #pragma unroll
         for (int py = 0; py < PYC; ++py) {
