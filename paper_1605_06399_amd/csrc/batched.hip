@@ -27,25 +27,11 @@
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
 #include "sep_strip.hpp"
+#include "sep_colwalk.hpp"
 #include "sep_tile.hpp"
 #include "tile_stage.hpp"
 
 namespace icl {
-
-struct DevImage {
-    const void* src;
-    void* dst;
-    unsigned long long sp, dp;
-    const float* tx;
-    const float* ty;
-    int W, H, r, vec_ok, vec_out;
-    unsigned src_bytes;   // extent of the source rows in bytes (the column walk's buffer size; 0 if >= 2^31)
-};
-
-// A column-walk item: output columns x0 .. x0 + 63 of image img over rows y0 .. y0 + rows - 1.
-struct ColItem {
-    int img, x0, y0, rows;
-};
 
 struct BatchTile {
     int img, x0, y0, r;   // r: the image's radius (orders the tiles on the host)
@@ -151,138 +137,6 @@ __global__ __launch_bounds__(64) void sep_batched_strip_k(const DevImage* __rest
     }
 }
 
-// ------------------------------------------------------------------ column walk
-// A work-group walks one item: a 64-column strip of one image over a segment of rows, in
-// steps of 64 output rows.  A step stages only the 64 input rows it adds, row-passes them
-// into the T rows below the 2r T rows the previous step left (moved to the top), and
-// column-passes 64 + 2r T rows.  So inside a segment every input row is loaded and
-// row-passed once; a walk of separate 64 x 64 tiles loads and row-passes 64 + 2r rows per
-// 64 output rows.  The whole item body is instantiated per radius (one wave-uniform switch
-// per item), with the same row and column passes, in the same tap order, as every other
-// separable kernel.  The source is read through a buffer descriptor with 32-bit offsets.
-constexpr int CSTEP = 64;                     // output rows per step
-constexpr int CLW_MAX = 64 + 16;              // staged row length at RA = 8 (floats)
-constexpr int CT_ROWS = CSTEP + 2 * RMAX;     // T rows
-
-template <class T, int R, int NROWS>
-struct ColStage {
-    static constexpr int RA = (R + 3) & ~3, LW = 64 + 2 * RA, C4 = LW / 4;
-    static constexpr int NCH = NROWS * C4, PER = (NCH + 255) / 256;
-    typename Raw4<T>::type v[PER > 0 ? PER : 1];
-    int gy = 0;
-
-    // Staged rows gy .. gy + NROWS - 1 (clamped into the image), columns x0 - RA .. x0 + 63 + RA.
-    // inside (the columns lie in the image, rows 4-pixel aligned): straight vector loads into
-    // registers, all in flight together, written to LDS by store().  Otherwise nothing is
-    // loaded here: store() reads the chunks through the clamp itself (a strip at an image's
-    // left or right edge, one in about eight), which keeps the rare edge path out of the
-    // register budget of the prefetch.
-    __device__ __forceinline__ void load(const DevImage& d, Rsrc rs, int x0, int row0, bool inside) {
-        gy = row0;
-        if (!inside) return;
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int idx = (int)threadIdx.x + 256 * k;
-            if (NCH % 256 != 0 && idx >= NCH) break;
-            const int rr = idx / C4, c4 = idx - rr * C4;
-            const unsigned row = (unsigned)clampi(gy + rr, d.H) * (unsigned)d.sp;
-            v[k] = bload4_raw<T>(rs, row + (unsigned)(x0 - RA + 4 * c4) * T::size);
-        }
-    }
-    __device__ __forceinline__ void store(float* __restrict__ in_s, const DevImage& d, Rsrc rs, int x0,
-                                          bool inside) const {
-        if (inside) {
-#pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int idx = (int)threadIdx.x + 256 * k;
-                if (NCH % 256 != 0 && idx >= NCH) break;
-                const int rr = idx / C4, c4 = idx - rr * C4;
-                lds4(&in_s[rr * LW + 4 * c4], decode4<T>(v[k]));
-            }
-            return;
-        }
-        for (int idx = (int)threadIdx.x; idx < NCH; idx += 256) {
-            const int rr = idx / C4, c4 = idx - rr * C4;
-            const unsigned row = (unsigned)clampi(gy + rr, d.H) * (unsigned)d.sp;
-            const int x = x0 - RA + 4 * c4;
-            typename Raw4<T>::type r;
-            if (d.vec_ok && x >= 0 && x + 4 <= d.W) {
-                r = bload4_raw<T>(rs, row + (unsigned)x * T::size);
-            } else {
-                unsigned e[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) e[q] = bload1_raw<T>(rs, row + (unsigned)clampi(x + q, d.W) * T::size);
-                r = pack4_raw<T>(e[0], e[1], e[2], e[3]);
-            }
-            lds4(&in_s[rr * LW + 4 * c4], decode4<T>(r));
-        }
-    }
-};
-
-// A value every lane loaded from the same address, moved to a scalar register: the item
-// table and the images' descriptors and taps are read with vector loads (the compiler cannot
-// prove that the kernel's stores leave them unchanged), and this keeps them out of the
-// vector register budget.
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
-template <class P> __device__ __forceinline__ P* uni(P* p) {
-    const unsigned long long a = (unsigned long long)p;
-    const unsigned long long lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)a);
-    const unsigned long long hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
-    return reinterpret_cast<P*>(lo | (hi << 32));
-}
-__device__ __forceinline__ DevImage uni(const DevImage& d) {
-    DevImage u;
-    u.src = uni(d.src); u.dst = uni(d.dst);
-    u.sp = (unsigned long long)uni((int)d.sp) & 0xffffffffull;
-    u.dp = ((unsigned long long)(unsigned)uni((int)(d.dp >> 32)) << 32) | (unsigned)uni((int)d.dp);
-    u.tx = uni(d.tx); u.ty = uni(d.ty);
-    u.W = uni(d.W); u.H = uni(d.H); u.r = uni(d.r); u.vec_ok = uni(d.vec_ok); u.vec_out = uni(d.vec_out);
-    u.src_bytes = (unsigned)uni((int)d.src_bytes);
-    return u;
-}
-
-template <class T, int R>
-__device__ __forceinline__ void col_item(const DevImage& d, const ColItem& it, float* __restrict__ in_s,
-                                         float* __restrict__ t_s) {
-    constexpr int RA = (R + 3) & ~3;
-    const Rsrc rs = make_rsrc(d.src, d.src_bytes);
-    float tx[2 * R + 1], ty[2 * R + 1];
-#pragma unroll
-    for (int i = 0; i <= 2 * R; ++i) {
-        tx[i] = uni(d.tx[i]);
-        ty[i] = uni(d.ty[i]);
-    }
-    const bool inside = d.vec_ok && it.x0 - RA >= 0 && it.x0 + 64 + RA <= d.W;
-    const int nsteps = (it.rows + CSTEP - 1) / CSTEP;
-    // prologue: T rows 0 .. 2r - 1 from input rows y0 - r .. y0 + r - 1
-    ColStage<T, R, CSTEP> st;
-    if constexpr (R > 0) {
-        ColStage<T, R, 2 * R> pro;
-        pro.load(d, rs, it.x0, it.y0 - R, inside);
-        st.load(d, rs, it.x0, it.y0 + R, inside);
-        pro.store(in_s, d, rs, it.x0, inside);
-        __syncthreads();
-        sep_row_pass<R, 0, 1, 1>(in_s, t_s, tx);
-        __syncthreads();
-    } else {
-        st.load(d, rs, it.x0, it.y0 + R, inside);
-    }
-    for (int s = 0; s < nsteps; ++s) {
-        st.store(in_s, d, rs, it.x0, inside);
-        if (R > 0 && s > 0) {   // the previous step's last 2r T rows become the first
-            const int q = (int)threadIdx.x;
-            if (q < 2 * R * 16) lds4(&t_s[4 * q], lds4(&t_s[CSTEP * 64 + 4 * q]));
-        }
-        __syncthreads();
-        if (s + 1 < nsteps) st.load(d, rs, it.x0, it.y0 + CSTEP * (s + 1) + R, inside);
-        sep_row_pass<R, CSTEP - 2 * R, 1, 1>(in_s, t_s + 2 * R * 64, tx);
-        __syncthreads();
-        sep_col_pass<T, R, CSTEP, 1, 6>(t_s, d.dst, d.dp, d.W, d.H, ty, it.x0, it.y0 + CSTEP * s, d.vec_out);
-        __syncthreads();
-    }
-}
-
 // Items are ordered by decreasing radius; end[R] is one past the last item of radius R (the
 // radius-7 items come first).  A work-group takes items b, b + grid, b + 2 grid, ... of that
 // order, and the walk is split into one loop per radius, so each loop's body is compiled for
@@ -333,9 +187,9 @@ using namespace icl;
 // Tile tables of the tile-walk variants: 64-row tiles in image order, 64-row tiles with
 // the largest radius first, 32-row tiles with the largest radius first.
 constexpr int NWALKS = 3;
-// Column walks: segments of 256, 512 and 2048 rows (2048: a whole image of the usual batch).
-constexpr int NCOL = 3;
-constexpr int kColSeg[NCOL] = {256, 512, 2048};
+// Column walks: segments of 256, 512, 2048 (a whole image of the usual batch), 128 and 64 rows.
+constexpr int NCOL = 5;
+constexpr int kColSeg[NCOL] = {256, 512, 2048, 128, 64};
 constexpr int kFirstCol = 4;   // variant index of the first column walk
 
 struct icl_batch_plan {

@@ -21,7 +21,10 @@
 //                       next tile into registers while computing the current one.
 //   fused_img_t{TH}_c{CX}: the fused tile staged through one buffer descriptor per row,
 //                       whose hardware range check supplies the constant-0 boundary (the
-//                       stand-in for the paper's image-memory candidate; see below).
+//                       stand-in for the paper's image-memory candidate; see below), one pixel
+//                       per lane; fused_img4: four pixels per lane.
+//   colwalk_s{SEG}    : persistent work-groups walk 64-column strips down SEG-row segments,
+//                       staging and row-passing each input row once (sep_colwalk.hpp).
 //   strip_t{TH}       : one wave per strip of 256 - 8*ceil(r/4) output columns and TH
 //                       rows, walking down the rows with both passes in registers:
 //                       horizontal neighbours by DPP lane shifts, a ring of 2r+1
@@ -30,6 +33,7 @@
 //                       output as the tile variants.
 #include "icl_device.hpp"
 #include "icl_internal.hpp"
+#include "sep_colwalk.hpp"
 #include "sep_strip.hpp"
 #include "sep_tile.hpp"
 #include "tile_stage.hpp"
@@ -279,10 +283,51 @@ __device__ __forceinline__ void stage_rows_img(const void* __restrict__ src, siz
     }
 }
 
-template <class T, int R, int TH, int CX>
+// The same with four pixels per lane: a row's LW/4 chunks start at a multiple of 4 columns
+// (x0 - RA), so a chunk left of the image is wholly left of it, and the range check, which
+// this hardware applies to each dword of a wider load (a 16-byte load that crosses the
+// descriptor's end returns its in-range dwords and zeros), zeroes the part of a chunk past
+// W.  So for float32 (and half types with an even width, where no dword holds a pixel on
+// each side of W) the constant-0 boundary still costs no boundary arithmetic.  Clamp: a chunk
+// not wholly inside reads its pixels one by one through the clamp.
+// vec false (rows not 4-pixel aligned, or a half type with an odd width): every chunk is
+// read pixel by pixel through the same row descriptor.
+template <class T, int NR, int LW>
+__device__ __forceinline__ void stage_rows_img4(const void* __restrict__ src, size_t sp, int W, int H, int gx0,
+                                                int gy0, Border bd, float* __restrict__ in_s, bool vec) {
+    constexpr int C4 = LW / 4;
+    static_assert(C4 <= 64, "one chunk per lane");
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = (int)(threadIdx.x & 63);
+    const bool cst = bd.constant != 0, cnz = cst && bd.value != 0.f;
+    if (lane >= C4) return;   // lanes past the row's chunks have nothing to stage
+    for (int rr = wave; rr < NR; rr += 4) {
+        const int y = gy0 + rr;
+        const bool yin = y >= 0 && y < H;
+        const char* base = static_cast<const char*>(src) + (size_t)clampi(y, H) * sp;
+        const Rsrc rs = make_rsrc(base, (cst && !yin) ? 0u : (unsigned)W * T::size);
+        const int x = gx0 + 4 * lane;
+        v4f v;
+        if (vec && (cst || (x >= 0 && x + 4 <= W))) {
+            v = decode4<T>(bload4_raw<T>(rs, (unsigned)x * T::size));
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                v[q] = decode1<T>(bload1_raw<T>(rs, (unsigned)(cst ? x + q : clampi(x + q, W)) * T::size));
+        }
+        if (cnz) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (!yin || x + q < 0 || x + q >= W) v[q] = bd.value;
+        }
+        lds4(&in_s[rr * LW + 4 * lane], v);
+    }
+}
+
+template <class T, int R, int TH, int CX, bool X4>
 __global__ __launch_bounds__(256) void sep_fused_img(const void* __restrict__ src, size_t sp, void* __restrict__ dst,
                                                      size_t dp, int W, int H, const float* __restrict__ tx,
-                                                     const float* __restrict__ ty, int tiles_x, int vec_out, Border bd) {
+                                                     const float* __restrict__ ty, int tiles_x, int vec_in, int vec_out,
+                                                     Border bd) {
     using G = SepTile<R, TH, CX>;
     __shared__ __attribute__((aligned(16))) float lds[G::LDS_FLOATS];
     float* in_s = lds;
@@ -290,52 +335,119 @@ __global__ __launch_bounds__(256) void sep_fused_img(const void* __restrict__ sr
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
     const int x0 = (int)(t % (unsigned)tiles_x) * G::TW;
     const int y0 = (int)(t / (unsigned)tiles_x) * TH;
-    stage_rows_img<T, G::NR, G::LW>(src, sp, W, H, x0 - G::RA, y0 - R, bd, in_s);
+    if constexpr (X4) stage_rows_img4<T, G::NR, G::LW>(src, sp, W, H, x0 - G::RA, y0 - R, bd, in_s, vec_in != 0);
+    else stage_rows_img<T, G::NR, G::LW>(src, sp, W, H, x0 - G::RA, y0 - R, bd, in_s);
     __syncthreads();
     sep_row_pass<R, TH, CX>(in_s, t_s, tx);
     __syncthreads();
     sep_col_pass<T, R, TH, CX>(t_s, dst, dp, W, H, ty, x0, y0, vec_out != 0);
 }
 
-template <class T, int R, int TH, int CX>
+template <class T, int R, int TH, int CX, bool X4>
 hipError_t launch_img_TR(const SepArgs& a) {
     using G = SepTile<R, TH, CX>;
     const int tiles_x = (a.W + G::TW - 1) / G::TW;
     const int tiles_y = (a.H + TH - 1) / TH;
     const size_t al = 4 * (size_t)T::size;
     const int vec_out = ((uintptr_t)a.dst % al == 0) && (a.dp % al == 0);
-    hipLaunchKernelGGL((sep_fused_img<T, R, TH, CX>), dim3(tiles_x * tiles_y), dim3(256), 0, a.st, a.src, a.sp, a.dst,
-                       a.dp, a.W, a.H, a.tx, a.ty, tiles_x, vec_out, a.bd);
+    const int vec_in = ((uintptr_t)a.src % al == 0) && (a.sp % al == 0) && (T::size == 4 || a.W % 2 == 0);
+    hipLaunchKernelGGL((sep_fused_img<T, R, TH, CX, X4>), dim3(tiles_x * tiles_y), dim3(256), 0, a.st, a.src, a.sp,
+                       a.dst, a.dp, a.W, a.H, a.tx, a.ty, tiles_x, vec_in, vec_out, a.bd);
     return hipGetLastError();
 }
 
-template <class T, int TH, int CX>
+template <class T, int TH, int CX, bool X4>
 hipError_t launch_img_T(const SepArgs& a) {
     switch (a.r) {
-        case 0: return launch_img_TR<T, 0, TH, CX>(a);
-        case 1: return launch_img_TR<T, 1, TH, CX>(a);
-        case 2: return launch_img_TR<T, 2, TH, CX>(a);
-        case 3: return launch_img_TR<T, 3, TH, CX>(a);
-        case 4: return launch_img_TR<T, 4, TH, CX>(a);
-        case 5: return launch_img_TR<T, 5, TH, CX>(a);
-        case 6: return launch_img_TR<T, 6, TH, CX>(a);
-        case 7: return launch_img_TR<T, 7, TH, CX>(a);
+        case 0: return launch_img_TR<T, 0, TH, CX, X4>(a);
+        case 1: return launch_img_TR<T, 1, TH, CX, X4>(a);
+        case 2: return launch_img_TR<T, 2, TH, CX, X4>(a);
+        case 3: return launch_img_TR<T, 3, TH, CX, X4>(a);
+        case 4: return launch_img_TR<T, 4, TH, CX, X4>(a);
+        case 5: return launch_img_TR<T, 5, TH, CX, X4>(a);
+        case 6: return launch_img_TR<T, 6, TH, CX, X4>(a);
+        case 7: return launch_img_TR<T, 7, TH, CX, X4>(a);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int TH, int CX>
+template <int TH, int CX, bool X4>
 hipError_t launch_img(const SepArgs& a) {
     switch (a.dt) {
-        case ICL_F32: return launch_img_T<F32, TH, CX>(a);
-        case ICL_F16: return launch_img_T<F16, TH, CX>(a);
-        default: return launch_img_T<BF16, TH, CX>(a);
+        case ICL_F32: return launch_img_T<F32, TH, CX, X4>(a);
+        case ICL_F16: return launch_img_T<F16, TH, CX, X4>(a);
+        default: return launch_img_T<BF16, TH, CX, X4>(a);
     }
 }
 
 // the row descriptors address a row with 32-bit offsets: the row must be under 2^31 bytes
 bool supports_img(const SepArgs& a) {
     return supports_fused(a) && (size_t)a.W * (a.dt == ICL_F32 ? 4 : 2) < ((size_t)1 << 31);
+}
+
+
+// ------------------------------------------------------------------ column walk
+// Persistent work-groups take items (64-column strip, segment of SEG rows) in row-major
+// order of segments (the items running side by side are horizontal neighbours, sharing
+// their halo columns in L2) and walk each down in 64-row steps (sep_colwalk.hpp): every
+// input row of a segment is staged and row-passed once.
+template <class T, int R, int SEG>
+__global__ __launch_bounds__(256, 4) void sep_colwalk(DevImage d, int nstrips, int nitems, Border bd) {
+    __shared__ __attribute__((aligned(16))) float in_s[CSTEP * CLW_MAX];
+    __shared__ __attribute__((aligned(16))) float t_s[CT_ROWS * 64];
+    for (int i = first_tile(); i < nitems; i += (int)gridDim.x) {
+        const int seg = i / nstrips, strip = i - seg * nstrips;
+        const ColItem it{0, strip * 64, seg * SEG, min(SEG, d.H - seg * SEG)};
+        col_item<T, R>(d, it, in_s, t_s, bd);
+    }
+}
+
+template <class T, int R, int SEG>
+hipError_t launch_colwalk_TR(const SepArgs& a) {
+    const size_t al = 4 * (size_t)T::size;
+    DevImage d{};
+    d.src = a.src; d.dst = a.dst; d.sp = a.sp; d.dp = a.dp; d.tx = a.tx; d.ty = a.ty;
+    d.W = a.W; d.H = a.H; d.r = R;
+    d.vec_ok = ((uintptr_t)a.src % al == 0) && (a.sp % al == 0);
+    d.vec_out = ((uintptr_t)a.dst % al == 0) && (a.dp % al == 0);
+    d.src_bytes = (unsigned)((size_t)(a.H - 1) * a.sp + (size_t)a.W * T::size);
+    const int nstrips = (a.W + 63) / 64, nsegs = (a.H + SEG - 1) / SEG;
+    const void* k = reinterpret_cast<const void*>(&sep_colwalk<T, R, SEG>);
+    hipLaunchKernelGGL((sep_colwalk<T, R, SEG>), dim3(persistent_grid(k, 256, nstrips * nsegs)), dim3(256), 0, a.st, d,
+                       nstrips, nstrips * nsegs, a.bd);
+    return hipGetLastError();
+}
+
+template <class T, int SEG>
+hipError_t launch_colwalk_T(const SepArgs& a) {
+    switch (a.r) {
+        case 0: return launch_colwalk_TR<T, 0, SEG>(a);
+        case 1: return launch_colwalk_TR<T, 1, SEG>(a);
+        case 2: return launch_colwalk_TR<T, 2, SEG>(a);
+        case 3: return launch_colwalk_TR<T, 3, SEG>(a);
+        case 4: return launch_colwalk_TR<T, 4, SEG>(a);
+        case 5: return launch_colwalk_TR<T, 5, SEG>(a);
+        case 6: return launch_colwalk_TR<T, 6, SEG>(a);
+        case 7: return launch_colwalk_TR<T, 7, SEG>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int SEG>
+hipError_t launch_colwalk(const SepArgs& a) {
+    switch (a.dt) {
+        case ICL_F32: return launch_colwalk_T<F32, SEG>(a);
+        case ICL_F16: return launch_colwalk_T<F16, SEG>(a);
+        default: return launch_colwalk_T<BF16, SEG>(a);
+    }
+}
+
+// the source extent and pitch must fit 31-bit buffer offsets
+bool supports_colwalk(const SepArgs& a) {
+    const size_t es = a.dt == ICL_F32 ? 4 : 2;
+    return supports_fused(a) && a.sp < ((size_t)1 << 31) &&
+           (size_t)(a.H - 1) * a.sp + (size_t)a.W * es < ((size_t)1 << 31) &&
+           (long long)((a.W + 63) / 64) * ((a.H + 63) / 64) < 0x7fffffffLL;
 }
 
 // ------------------------------------------------------------------ register strips
@@ -399,8 +511,13 @@ const Variant<SepArgs> kSep[] = {
     {"strip_t32", supports_fused, launch_strip<32>},
     {"strip_t16", supports_fused, launch_strip<16>},
     {"strip_t64", supports_fused, launch_strip<64>},
-    {"fused_img_t32_c1", supports_img, launch_img<32, 1>},
-    {"fused_img_t16_c2", supports_img, launch_img<16, 2>},
+    {"fused_img_t32_c1", supports_img, launch_img<32, 1, false>},
+    {"fused_img_t16_c2", supports_img, launch_img<16, 2, false>},
+    {"fused_img4_t32_c1", supports_img, launch_img<32, 1, true>},
+    {"fused_img4_t16_c2", supports_img, launch_img<16, 2, true>},
+    {"colwalk_s64", supports_colwalk, launch_colwalk<64>},
+    {"colwalk_s128", supports_colwalk, launch_colwalk<128>},
+    {"colwalk_s256", supports_colwalk, launch_colwalk<256>},
 };
 
 }  // namespace

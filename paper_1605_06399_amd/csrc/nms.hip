@@ -295,6 +295,8 @@ const Variant<NmsArgs> kNms[] = {
     {"stream_a_t64", supports_stream_a, launch_stream_a<64, false>},
     {"stream_a_t32", supports_stream_a, launch_stream_a<32, false>},
     {"stream_a_t16", supports_stream_a, launch_stream_a<16, false>},
+    {"stream_a_t8", supports_stream_a, launch_stream_a<8, false>},
+    {"stream_a_t4", supports_stream_a, launch_stream_a<4, false>},
     {"stream_a_t32_sm", supports_stream_a, launch_stream_a<32, true>},
     {"stream_a_t16_sm", supports_stream_a, launch_stream_a<16, true>},
 };

@@ -36,7 +36,7 @@ def _nvariants(default):
         return default
 
 
-N_BATCHED = _nvariants(4)   # tile walks (image order, by radius, 32-row by radius) and the strip walk
+N_BATCHED = _nvariants(4)   # tile walks (image order, by radius, 32-row by radius), the strip walk, column walks
 
 
 @pytest.fixture(params=range(N_BATCHED))
