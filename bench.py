@@ -114,6 +114,24 @@ def kernel_variant(name):
     return None
 
 
+def calib_factors(fetch_csv, write_csv):
+    """Counter scale factors from the run's three 1 GiB device-to-device copies: the copy
+    dispatches whose WRITE_SIZE reads 1 GiB (the copy-ceiling copies of other sizes are left
+    out), paired in dispatch order with the same dispatches of the FETCH_SIZE run."""
+    import csv
+
+    def copies(p):
+        return [float(r["Counter_Value"]) for r in csv.DictReader(open(p)) if "copyBuffer" in r["Kernel_Name"]]
+
+    cf, cw = copies(fetch_csv), copies(write_csv)
+    idx = [i for i, w in enumerate(cw) if abs(w - (1 << 20)) < 0.01 * (1 << 20)]
+    if len(idx) < 1 or len(cf) != len(cw):
+        raise RuntimeError("calibration copies not found: run with --calib-copy")
+    f = [cf[i] for i in idx]
+    w = [cw[i] for i in idx]
+    return (1 << 20) / (sum(f) / len(f)), (1 << 20) / (sum(w) / len(w)), f, w
+
+
 def write_traffic(fetch_csv, write_csv, side=4096):
     """HBM bytes per dispatch: mean FETCH_SIZE / WRITE_SIZE (KiB) per kernel, each scaled so that the
     counter reads 1 GiB on the run's three 1 GiB device-to-device copies."""
@@ -127,9 +145,7 @@ def write_traffic(fetch_csv, write_csv, side=4096):
         return agg
 
     fe, wr = load(fetch_csv), load(write_csv)
-    cf = sorted(v for k, vs in fe.items() if "copyBuffer" in k for v in vs)[-3:]
-    cw = sorted(v for k, vs in wr.items() if "copyBuffer" in k for v in vs)[-3:]
-    fcal, wcal = (1 << 20) / (sum(cf) / 3), (1 << 20) / (sum(cw) / 3)
+    fcal, wcal, cf, cw = calib_factors(fetch_csv, write_csv)
     alg = 8 * side * side
     out = {"_about": "HBM bytes per dispatch from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per "
                      "dispatch, mean over dispatches), each scaled by the factor that maps the same counter on a "
@@ -166,10 +182,14 @@ WORKLOAD_KERNELS = [
      "tile_stage.hpp", "icl_device.hpp"], 4 * _B_PX),
     ("batch", r"sep_batched_strip_k<icl::(F16|BF16)>", "strip_{0}", ["batched.hip", "sep_strip.hpp",
      "icl_device.hpp"], 4 * _B_PX),
+    ("batch", r"sep_batched_col_k<icl::(F16|BF16), (\d), (\d+)>", "colwalk_cx{1}_step{2}_{0}",
+     ["batched.hip", "sep_colwalk.hpp", "sep_tile.hpp", "tile_stage.hpp", "icl_device.hpp"], 4 * _B_PX),
     ("corner", r"harris_(fused|stream)<(\d+), (\d+)>", "harris_{0}_t{2}", ["harris.hip", "harris_strip.hpp",
      "icl_device.hpp"], 8 * 8192 * 8192),
     ("corner", r"nms_stream<(\d+)>", "nms_stream_t{0}", ["nms.hip", "harris_strip.hpp", "icl_device.hpp"],
      5 * 8192 * 8192),
+    ("corner", r"nms_stream_a<(\d+), (true|false)>", "nms_stream_a_t{0}_sm:{1}", ["nms.hip", "harris_strip.hpp",
+     "icl_device.hpp"], 5 * 8192 * 8192),
     ("corner", r"corners_stream<(\d+), (\d+), 1>", "corners_stream_t{1}", ["corners.hip", "harris_strip.hpp",
      "icl_device.hpp"], 5 * 8192 * 8192),
     ("bank", r"bank_fwd_(mfma_k<4, true>|pers_k<4, true>|sse_tpre_k<4>)", "fwd_sse:{0}", ["bank.hip"],
@@ -216,9 +236,7 @@ def write_workload_traffic(root):
             cmds.append(f"rocprofv3 --pmc {ctr} --output-format csv -d {root}/tr_{wl}_{ctr} -o tr -- "
                         f"python3 bench.py --only {wl} --steps 4 --warmup 1 --no-cpu --calib-copy")
         fe, wr = load(fp), load(wp)
-        cf = sorted(v for k, vs in fe.items() if "copyBuffer" in k for v in vs)[-3:]
-        cw = sorted(v for k, vs in wr.items() if "copyBuffer" in k for v in vs)[-3:]
-        fcal, wcal = (1 << 20) / (sum(cf) / 3), (1 << 20) / (sum(cw) / 3)
+        fcal, wcal, _, _ = calib_factors(fp, wp)
         for kname in sorted(fe):
             for w2, pat, label, srcs, alg in WORKLOAD_KERNELS:
                 m = re.search(pat, kname)

@@ -686,7 +686,7 @@ int icl_variant_count(icl_op op) {
         case ICL_OP_BANK_BWD_INPUT: bank_bwd_input_variants(&c); break;
         case ICL_OP_BANK_BWD_FILTER: bank_bwd_filter_variants(&c); break;
         case ICL_OP_BANK_FWD_SSE: bank_fwd_sse_variants(&c); break;
-        case ICL_OP_CONV_SEP_BATCHED: c = 9; break;
+        case ICL_OP_CONV_SEP_BATCHED: c = 11; break;
         case ICL_OP_SSE_LOSS: c = 1; break;
         default: c = 0;
     }
@@ -712,7 +712,7 @@ const char* icl_variant_name(icl_op op, int index) {
             static const char* names[] = {"persistent_fused_t64", "persistent_strip_t32",
                                           "persistent_fused_t64_rsort", "persistent_fused_t32_rsort",
                                           "colwalk_s256", "colwalk_s512", "colwalk_s2048", "colwalk_s128",
-                                          "colwalk_s64"};
+                                          "colwalk_s64", "colwalk128_s128", "colwalk128_s256"};
             return names[index];
         }
         case ICL_OP_SSE_LOSS: return "two_stage";

@@ -146,11 +146,15 @@ struct ColRanges {
     int end[RMAX + 1];
 };
 
-template <class T>
-__global__ __launch_bounds__(256, 4) void sep_batched_col_k(const DevImage* __restrict__ imgs,
-                                                            const ColItem* __restrict__ items, ColRanges rg) {
-    __shared__ __attribute__((aligned(16))) float in_s[CSTEP * CLW_MAX];
-    __shared__ __attribute__((aligned(16))) float t_s[CT_ROWS * 64];
+// The register budget is set for the work-groups the LDS admits: four per CU for 64-column
+// strips with 64-row steps (40 KB), three for 128-column strips with 32-row steps (42 KB).
+template <class T, int CX, int STEP>
+__global__ __launch_bounds__(256, CX == 1 ? 4 : 3) void sep_batched_col_k(const DevImage* __restrict__ imgs,
+                                                                         const ColItem* __restrict__ items,
+                                                                         ColRanges rg) {
+    using G = ColGeom<CX, STEP>;
+    __shared__ __attribute__((aligned(16))) float in_s[G::IN_FLOATS];
+    __shared__ __attribute__((aligned(16))) float t_s[G::T_FLOATS];
     int i = first_tile();
     static_for<RMAX + 1>([&](auto k) {
         constexpr int R = RMAX - decltype(k)::value;
@@ -158,7 +162,7 @@ __global__ __launch_bounds__(256, 4) void sep_batched_col_k(const DevImage* __re
             const ColItem li = items[i];
             const ColItem it{uni(li.img), uni(li.x0), uni(li.y0), uni(li.rows)};
             const DevImage d = uni(imgs[it.img]);
-            col_item<T, R>(d, it, in_s, t_s);
+            col_item<T, R, CX, STEP>(d, it, in_s, t_s);
         }
     });
 }
@@ -187,9 +191,12 @@ using namespace icl;
 // Tile tables of the tile-walk variants: 64-row tiles in image order, 64-row tiles with
 // the largest radius first, 32-row tiles with the largest radius first.
 constexpr int NWALKS = 3;
-// Column walks: segments of 256, 512, 2048 (a whole image of the usual batch), 128 and 64 rows.
-constexpr int NCOL = 5;
-constexpr int kColSeg[NCOL] = {256, 512, 2048, 128, 64};
+// Column walks: 64-column strips in 64-row steps over segments of 256, 512, 2048 (a whole
+// image of the usual batch), 128 and 64 rows; 128-column strips in 32-row steps over segments
+// of 128 and 256 rows.
+constexpr int NCOL = 7;
+constexpr int kColSeg[NCOL] = {256, 512, 2048, 128, 64, 128, 256};
+constexpr int kColCx[NCOL] = {1, 1, 1, 1, 1, 2, 2};
 constexpr int kFirstCol = 4;   // variant index of the first column walk
 
 struct icl_batch_plan {
@@ -239,13 +246,15 @@ void launch_walk(const icl_batch_plan* p, int w, hipStream_t st) {
                            p->ntiles[w]);
 }
 
-const void* col_kernel_for(icl_dtype dt) {
+template <int CX, int STEP>
+const void* col_kernel_cx(icl_dtype dt) {
     switch (dt) {
-        case ICL_F32: return reinterpret_cast<const void*>(&sep_batched_col_k<F32>);
-        case ICL_F16: return reinterpret_cast<const void*>(&sep_batched_col_k<F16>);
-        default: return reinterpret_cast<const void*>(&sep_batched_col_k<BF16>);
+        case ICL_F32: return reinterpret_cast<const void*>(&sep_batched_col_k<F32, CX, STEP>);
+        case ICL_F16: return reinterpret_cast<const void*>(&sep_batched_col_k<F16, CX, STEP>);
+        default: return reinterpret_cast<const void*>(&sep_batched_col_k<BF16, CX, STEP>);
     }
 }
+const void* col_kernel_for(icl_dtype dt, int cx) { return cx == 1 ? col_kernel_cx<1, 64>(dt) : col_kernel_cx<2, 32>(dt); }
 
 const void* strip_kernel_for(icl_dtype dt) {
     switch (dt) {
@@ -391,10 +400,11 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
             std::stable_sort(o.begin(), o.end(), [&](int a, int b) {
                 return imgs[a].r != imgs[b].r ? imgs[a].r > imgs[b].r : work(a) > work(b);
             });
+            const int cw = 64 * kColCx[c];
             for (int i : o) {
                 const DevImage& d = imgs[i];
                 for (int y = 0; y < d.H; y += seg)
-                    for (int x = 0; x < d.W; x += 64) cols[c].push_back(ColItem{i, x, y, std::min(seg, d.H - y)});
+                    for (int x = 0; x < d.W; x += cw) cols[c].push_back(ColItem{i, x, y, std::min(seg, d.H - y)});
             }
         }
         for (const DevImage& d : imgs)
@@ -461,7 +471,7 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
         if (e == hipSuccess && !cols[c].empty())
             e = hipMemcpy(p->d_col[c], cols[c].data(), cols[c].size() * sizeof(ColItem), hipMemcpyHostToDevice);
     }
-    int per_cu_col = 0;
+    int per_cu_col[2] = {};
     int per_cu[NWALKS] = {}, per_cu_strip = 0, dev = 0, cus = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -469,13 +479,14 @@ icl_status icl_batch_plan_create(const icl_image_desc* descs, int count, icl_dty
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[w], kernel_for(dtype, w), 256, 0);
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_strip, strip_kernel_for(dtype), 64, 0);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_col, col_kernel_for(dtype), 256, 0);
+    for (int cx = 1; cx <= 2 && e == hipSuccess; ++cx)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_col[cx - 1], col_kernel_for(dtype, cx), 256, 0);
     if (e != hipSuccess) {
         icl_batch_plan_destroy(p);
         return hip_status(e);
     }
     for (int c = 0; c < NCOL; ++c) {
-        const long long resident = (long long)std::max(per_cu_col, 1) * std::max(cus, 1);
+        const long long resident = (long long)std::max(per_cu_col[kColCx[c] - 1], 1) * std::max(cus, 1);
         p->col_grid[c] = (int)std::min<long long>(resident, std::max(p->ncol[c], 1));
         if (p->col_grid[c] > 8) p->col_grid[c] -= p->col_grid[c] % 8;
     }
@@ -571,24 +582,30 @@ icl_status icl_batch_plan_tune(icl_batch_plan* plan, void* stream) {
 
 namespace {
 
+template <int CX, int STEP>
+void launch_col(const icl_batch_plan* plan, int c, hipStream_t st) {
+    switch (plan->dt) {
+        case ICL_F32:
+            hipLaunchKernelGGL((sep_batched_col_k<F32, CX, STEP>), dim3(plan->col_grid[c]), dim3(256), 0, st,
+                               plan->d_imgs, plan->d_col[c], plan->col_rg[c]);
+            break;
+        case ICL_F16:
+            hipLaunchKernelGGL((sep_batched_col_k<F16, CX, STEP>), dim3(plan->col_grid[c]), dim3(256), 0, st,
+                               plan->d_imgs, plan->d_col[c], plan->col_rg[c]);
+            break;
+        default:
+            hipLaunchKernelGGL((sep_batched_col_k<BF16, CX, STEP>), dim3(plan->col_grid[c]), dim3(256), 0, st,
+                               plan->d_imgs, plan->d_col[c], plan->col_rg[c]);
+            break;
+    }
+}
+
 hipError_t launch_plan(const icl_batch_plan* plan, int v, hipStream_t st) {
     if (v >= kFirstCol) {
         const int c = v - kFirstCol;
         if (!plan->col_ok) return hipErrorInvalidValue;
-        switch (plan->dt) {
-            case ICL_F32:
-                hipLaunchKernelGGL(sep_batched_col_k<F32>, dim3(plan->col_grid[c]), dim3(256), 0, st, plan->d_imgs,
-                                   plan->d_col[c], plan->col_rg[c]);
-                break;
-            case ICL_F16:
-                hipLaunchKernelGGL(sep_batched_col_k<F16>, dim3(plan->col_grid[c]), dim3(256), 0, st, plan->d_imgs,
-                                   plan->d_col[c], plan->col_rg[c]);
-                break;
-            default:
-                hipLaunchKernelGGL(sep_batched_col_k<BF16>, dim3(plan->col_grid[c]), dim3(256), 0, st, plan->d_imgs,
-                                   plan->d_col[c], plan->col_rg[c]);
-                break;
-        }
+        if (kColCx[c] == 1) launch_col<1, 64>(plan, c, st);
+        else launch_col<2, 32>(plan, c, st);
         return hipGetLastError();
     }
     if (v == 1) {

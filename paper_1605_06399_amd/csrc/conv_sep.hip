@@ -393,8 +393,9 @@ bool supports_img(const SepArgs& a) {
 // input row of a segment is staged and row-passed once.
 template <class T, int R, int SEG>
 __global__ __launch_bounds__(256, 4) void sep_colwalk(DevImage d, int nstrips, int nitems, Border bd) {
-    __shared__ __attribute__((aligned(16))) float in_s[CSTEP * CLW_MAX];
-    __shared__ __attribute__((aligned(16))) float t_s[CT_ROWS * 64];
+    using G = ColGeom<1, 64>;
+    __shared__ __attribute__((aligned(16))) float in_s[G::IN_FLOATS];
+    __shared__ __attribute__((aligned(16))) float t_s[G::T_FLOATS];
     for (int i = first_tile(); i < nitems; i += (int)gridDim.x) {
         const int seg = i / nstrips, strip = i - seg * nstrips;
         const ColItem it{0, strip * 64, seg * SEG, min(SEG, d.H - seg * SEG)};

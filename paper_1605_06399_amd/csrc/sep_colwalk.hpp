@@ -1,10 +1,10 @@
 // Column walk of the separable filter, shared by the batched and the per-image kernels.
-// A work-group walks one item: a 64-column strip of one image over a segment of rows, in
-// steps of 64 output rows.  A step stages only the 64 input rows it adds, row-passes them
-// into the T rows below the 2r T rows the previous step left (moved to the top), and
-// column-passes 64 + 2r T rows.  So inside a segment every input row is loaded and
-// row-passed once; a walk of separate 64 x 64 tiles loads and row-passes 64 + 2r rows per
-// 64 output rows.  The item body is instantiated per radius, with the same row and column
+// A work-group walks one item: a strip of 64 CX columns of one image over a segment of rows,
+// in steps of STEP output rows.  A step stages only the STEP input rows it adds, row-passes
+// them into the T rows below the 2r T rows the previous step left (moved to the top), and
+// column-passes STEP + 2r T rows.  So inside a segment every input row is loaded and
+// row-passed once; a walk of separate tiles loads and row-passes STEP + 2r rows per STEP
+// output rows.  Wider strips (CX = 2) halve the share of halo columns a strip reads.  The item body is instantiated per radius, with the same row and column
 // passes, in the same tap order, as every other separable kernel, and either boundary.  The
 // source is read through a buffer descriptor with 32-bit offsets.
 #pragma once
@@ -31,18 +31,24 @@ struct ColItem {
 
 
 constexpr int COL_RMAX = 7;
-constexpr int CSTEP = 64;                     // output rows per step
-constexpr int CLW_MAX = 64 + 16;              // staged row length at RA = 8 (floats)
-constexpr int CT_ROWS = CSTEP + 2 * COL_RMAX; // T rows
 
-template <class T, int R, int NROWS>
+// LDS of a column walk with strips of 64 CX columns and steps of STEP rows: the staged input
+// rows of a step, the T rows of a step and its halo.
+template <int CX, int STEP> struct ColGeom {
+    static constexpr int CW = 64 * CX;
+    static constexpr int LW_MAX = CW + 16;                    // staged row length at RA = 8 (floats)
+    static constexpr int IN_FLOATS = STEP * LW_MAX;
+    static constexpr int T_FLOATS = (STEP + 2 * COL_RMAX) * CW;
+};
+
+template <class T, int R, int NROWS, int CX = 1>
 struct ColStage {
-    static constexpr int RA = (R + 3) & ~3, LW = 64 + 2 * RA, C4 = LW / 4;
+    static constexpr int RA = (R + 3) & ~3, LW = 64 * CX + 2 * RA, C4 = LW / 4;
     static constexpr int NCH = NROWS * C4, PER = (NCH + 255) / 256;
     typename Raw4<T>::type v[PER > 0 ? PER : 1];
     int gy = 0;
 
-    // Staged rows gy .. gy + NROWS - 1 (read clamped into the image), columns x0 - RA .. x0 + 63 + RA.
+    // Staged rows gy .. gy + NROWS - 1 (read clamped into the image), columns x0 - RA .. x0 + 64 CX - 1 + RA.
     // inside (the columns lie in the image, rows 4-pixel aligned): straight vector loads into
     // registers, all in flight together, written to LDS by store().  Otherwise nothing is
     // loaded here: store() reads the chunks through the clamp itself (a strip at an image's
@@ -123,10 +129,10 @@ __device__ __forceinline__ DevImage uni(const DevImage& d) {
     return u;
 }
 
-template <class T, int R>
+template <class T, int R, int CX = 1, int STEP = 64>
 __device__ __forceinline__ void col_item(const DevImage& d, const ColItem& it, float* __restrict__ in_s,
                                          float* __restrict__ t_s, Border bd = {}) {
-    constexpr int RA = (R + 3) & ~3;
+    constexpr int RA = (R + 3) & ~3, CW = 64 * CX;
     const Rsrc rs = make_rsrc(d.src, d.src_bytes);
     float tx[2 * R + 1], ty[2 * R + 1];
 #pragma unroll
@@ -134,17 +140,17 @@ __device__ __forceinline__ void col_item(const DevImage& d, const ColItem& it, f
         tx[i] = uni(d.tx[i]);
         ty[i] = uni(d.ty[i]);
     }
-    const bool inside = d.vec_ok && it.x0 - RA >= 0 && it.x0 + 64 + RA <= d.W;
-    const int nsteps = (it.rows + CSTEP - 1) / CSTEP;
+    const bool inside = d.vec_ok && it.x0 - RA >= 0 && it.x0 + CW + RA <= d.W;
+    const int nsteps = (it.rows + STEP - 1) / STEP;
     // prologue: T rows 0 .. 2r - 1 from input rows y0 - r .. y0 + r - 1
-    ColStage<T, R, CSTEP> st;
+    ColStage<T, R, STEP, CX> st;
     if constexpr (R > 0) {
-        ColStage<T, R, 2 * R> pro;
+        ColStage<T, R, 2 * R, CX> pro;
         pro.load(d, rs, it.x0, it.y0 - R, inside);
         st.load(d, rs, it.x0, it.y0 + R, inside);
         pro.store(in_s, d, rs, it.x0, inside, bd);
         __syncthreads();
-        sep_row_pass<R, 0, 1, 1>(in_s, t_s, tx);
+        sep_row_pass<R, 0, CX, 1>(in_s, t_s, tx);
         __syncthreads();
     } else {
         st.load(d, rs, it.x0, it.y0 + R, inside);
@@ -152,14 +158,13 @@ __device__ __forceinline__ void col_item(const DevImage& d, const ColItem& it, f
     for (int s = 0; s < nsteps; ++s) {
         st.store(in_s, d, rs, it.x0, inside, bd);
         if (R > 0 && s > 0) {   // the previous step's last 2r T rows become the first
-            const int q = (int)threadIdx.x;
-            if (q < 2 * R * 16) lds4(&t_s[4 * q], lds4(&t_s[CSTEP * 64 + 4 * q]));
+            for (int q = (int)threadIdx.x; q < 2 * R * CW / 4; q += 256) lds4(&t_s[4 * q], lds4(&t_s[STEP * CW + 4 * q]));
         }
         __syncthreads();
-        if (s + 1 < nsteps) st.load(d, rs, it.x0, it.y0 + CSTEP * (s + 1) + R, inside);
-        sep_row_pass<R, CSTEP - 2 * R, 1, 1>(in_s, t_s + 2 * R * 64, tx);
+        if (s + 1 < nsteps) st.load(d, rs, it.x0, it.y0 + STEP * (s + 1) + R, inside);
+        sep_row_pass<R, STEP - 2 * R, CX, 1>(in_s, t_s + 2 * R * CW, tx);
         __syncthreads();
-        sep_col_pass<T, R, CSTEP, 1, 6>(t_s, d.dst, d.dp, d.W, d.H, ty, it.x0, it.y0 + CSTEP * s, d.vec_out);
+        sep_col_pass<T, R, STEP, CX, 6>(t_s, d.dst, d.dp, d.W, d.H, ty, it.x0, it.y0 + STEP * s, d.vec_out);
         __syncthreads();
     }
 }
