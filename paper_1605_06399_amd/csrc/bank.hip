@@ -45,17 +45,17 @@ template <int R> struct BankTile {
     static constexpr int WIN = BPX + 2 * RA;
 };
 
-// Stage NR rows x LW columns of a dense W-wide plane, top-left pixel (xs, ys), clamped, into
-// s[NR * LW].  A tile inside the image in x with 16-byte aligned rows issues all its float4
-// loads before the LDS writes (a load-then-write loop would wait on each load in turn); edge
-// tiles go element by element.
-template <int NR, int LW>
+// Stage NR rows x LWS columns of a dense W-wide plane, top-left pixel (xs, ys), clamped, into
+// s[NR * LW] (row stride LW >= LWS).  A tile inside the image in x with 16-byte aligned rows
+// issues all its float4 loads before the LDS writes (a load-then-write loop would wait on each
+// load in turn); edge tiles go element by element.
+template <int NR, int LW, int LWS = LW>
 __device__ __forceinline__ void stage_clamped(const float* __restrict__ xp, int W, int H, int xs, int ys,
                                               float* __restrict__ s) {
     const int tid = threadIdx.x;
-    if ((W & 3) == 0 && ((uintptr_t)xp & 15) == 0 && (xs & 3) == 0 && xs >= 0 && xs + LW <= W) {
-        static_assert(LW % 4 == 0, "vector staging needs whole float4 rows");
-        constexpr int C4 = LW / 4, NCH = NR * C4, PER = (NCH + 255) / 256;
+    if ((W & 3) == 0 && ((uintptr_t)xp & 15) == 0 && (xs & 3) == 0 && xs >= 0 && xs + LWS <= W) {
+        static_assert(LW % 4 == 0 && LWS % 4 == 0, "vector staging needs whole float4 rows");
+        constexpr int C4 = LWS / 4, NCH = NR * C4, PER = (NCH + 255) / 256;
         v4f v[PER];
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
@@ -73,9 +73,9 @@ __device__ __forceinline__ void stage_clamped(const float* __restrict__ xp, int 
         }
         return;
     }
-    for (int idx = tid; idx < NR * LW; idx += 256) {   // edge tiles
-        const int rr = idx / LW, c = idx - rr * LW;
-        s[idx] = xp[(size_t)clampi(ys + rr, H) * W + clampi(xs + c, W)];
+    for (int idx = tid; idx < NR * LWS; idx += 256) {   // edge tiles
+        const int rr = idx / LWS, c = idx - rr * LWS;
+        s[rr * LW + c] = xp[(size_t)clampi(ys + rr, H) * W + clampi(xs + c, W)];
     }
 }
 
@@ -815,14 +815,22 @@ __global__ __launch_bounds__(256) void bank_bwd_w4_k(const float* __restrict__ g
 // one partial per (filter, tap, tile), so the result is deterministic.  Up to 16 filters.
 constexpr int GWM_T = 64;
 
-template <int R, int TY>
-__global__ __launch_bounds__(256) void bank_bwd_wm_k(const float* __restrict__ gy, const float* __restrict__ x,
+// The staged rows are LWS = 64 + 2 RA pixels at a stride of LWS + 8 floats: a row stride of
+// 16 words modulo 64 puts the taps of one 16-tap block, which span up to three window rows, in
+// distinct LDS banks.  The cross-wave reduction reuses the tile's LDS once the products are
+// done, so a work-group holds one buffer (about 24 KB at r = 4: six work-groups per CU).
+// PX: step st of a row takes pixels st, 16 + st, 32 + st, 48 + st (k = pixel / 16) instead of
+// 4 st .. 4 st + 3, so each lane's 16 gy values of a row are 16 consecutive pixels, read as four
+// 16-byte vectors; the products are the same, summed in another order.
+template <int R, int TY, bool PX = false>
+__global__ __launch_bounds__(256, 4) void bank_bwd_wm_k(const float* __restrict__ gy, const float* __restrict__ x,
                                                      float* __restrict__ part, int F, int H, int W, int tiles_x,
                                                      int tiles_img, int ntiles) {
     constexpr int N = 2 * R + 1, NK = N * N, NT = (NK + 15) / 16;
-    constexpr int RA = (R + 3) & ~3, LW = GWM_T + 2 * RA, NR = GWM_T + 2 * R;
-    __shared__ __attribute__((aligned(16))) float s[NR * LW];
-    __shared__ float red[4][16][NT * 16];
+    constexpr int RA = (R + 3) & ~3, LWS = GWM_T + 2 * RA, LW = LWS + 8, NR = GWM_T + 2 * R;
+    constexpr int S_FLOATS = NR * LW, RED_FLOATS = 4 * 16 * NT * 16;
+    __shared__ __attribute__((aligned(16))) float s[S_FLOATS > RED_FLOATS ? S_FLOATS : RED_FLOATS];
+    auto red = reinterpret_cast<float (*)[16][NT * 16]>(s);
     const unsigned id = xcd_remap(blockIdx.x, gridDim.x);
     const int tile = (int)id;
     const int n = tile / tiles_img, ti = tile - n * tiles_img;
@@ -845,8 +853,28 @@ __global__ __launch_bounds__(256) void bank_bwd_wm_k(const float* __restrict__ g
     for (int t = 0; t < NT; ++t) acc[t] = mk4(0.f, 0.f, 0.f, 0.f);
     // a row's 16 x 4 gy values; pixels outside the image (and filters past F) contribute 0.
     // The load itself always reads a valid (clamped) address, so no lane branches around it.
+    const bool vec = (W & 3) == 0 && ((uintptr_t)gy & 15) == 0;
     auto gy_row = [&](int yy, float (&ga)[16]) {
         const float* grow = g + (size_t)min(yy, H - 1) * W;
+        if constexpr (PX) {
+            const int xb = x0 + 16 * q;
+            if (vec && xb + 16 <= W) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const v4f v = *reinterpret_cast<const v4f*>(grow + xb + 4 * m);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ga[4 * m + e] = (frow && yy < H) ? v[e] : 0.f;
+                }
+            } else {
+#pragma unroll
+                for (int st = 0; st < 16; ++st) {
+                    const int xx = xb + st;
+                    const float v = grow[min(xx, W - 1)];
+                    ga[st] = (frow && xx < W && yy < H) ? v : 0.f;
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int st = 0; st < 16; ++st) {
             const int xx = x0 + 4 * st + q;
@@ -854,16 +882,18 @@ __global__ __launch_bounds__(256) void bank_bwd_wm_k(const float* __restrict__ g
             ga[st] = (frow && xx < W && yy < H) ? v : 0.f;
         }
     };
+    // LDS column of step st's pixel for this lane
+    auto pcol = [&](int st) { return PX ? 16 * q + st : 4 * st + q; };
     for (int sub = 0; sub < TY; ++sub) {
         const int ys = y0 + sub * GWM_T;
         if (ys >= H) break;   // uniform over the work-group
         if (sub) __syncthreads();
         if constexpr (TY == 1) {
-            stage_clamped<NR, LW>(xp, W, H, x0 - RA, ys - R, s);
+            stage_clamped<NR, LW, LWS>(xp, W, H, x0 - RA, ys - R, s);
         } else {   // accumulators live across the sub-tiles leave no registers for a batch of loads
-            for (int idx = threadIdx.x; idx < NR * LW; idx += 256) {
-                const int rr = idx / LW, c = idx - rr * LW;
-                s[idx] = xp[(size_t)clampi(ys - R + rr, H) * W + clampi(x0 - RA + c, W)];
+            for (int idx = threadIdx.x; idx < NR * LWS; idx += 256) {
+                const int rr = idx / LWS, c = idx - rr * LWS;
+                s[rr * LW + c] = xp[(size_t)clampi(ys - R + rr, H) * W + clampi(x0 - RA + c, W)];
             }
         }
         __syncthreads();
@@ -875,7 +905,7 @@ __global__ __launch_bounds__(256) void bank_bwd_wm_k(const float* __restrict__ g
             gy_row(ys + py + 1, gb);   // the next row's gy in flight during this row's products
 #pragma unroll
             for (int st = 0; st < 16; ++st) {
-                const int base = py * LW + 4 * st + q;
+                const int base = py * LW + pcol(st);
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[st], s[base + off[t]], acc[t], 0, 0, 0);
@@ -883,14 +913,16 @@ __global__ __launch_bounds__(256) void bank_bwd_wm_k(const float* __restrict__ g
             if (row + 2 < 16) gy_row(ys + py + 2, ga);
 #pragma unroll
             for (int st = 0; st < 16; ++st) {
-                const int base = (py + 1) * LW + 4 * st + q;
+                const int base = (py + 1) * LW + pcol(st);
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gb[st], s[base + off[t]], acc[t], 0, 0, 0);
             }
         }
     }
-    // lane holds D[4 (lane / 16) + i][16 t + lane % 16] in acc[t][i]
+    // lane holds D[4 (lane / 16) + i][16 t + lane % 16] in acc[t][i]; the tile's products are
+    // done (the barrier) before its LDS takes the partial sums
+    __syncthreads();
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -904,12 +936,12 @@ __global__ __launch_bounds__(256) void bank_bwd_wm_k(const float* __restrict__ g
     }
 }
 
-template <int R, int TY>
+template <int R, int TY, bool PX = false>
 hipError_t bwd_wm_RT(const BankArgs& a) {
     const int tx = (a.w + GWM_T - 1) / GWM_T, ty = (a.h + GWM_T * TY - 1) / (GWM_T * TY);
     const int ntiles = a.n * tx * ty;
     float* part = static_cast<float*>(a.ws);
-    hipLaunchKernelGGL((bank_bwd_wm_k<R, TY>), dim3((unsigned)ntiles), dim3(256), 0, a.st, a.a, a.b, part, a.f, a.h,
+    hipLaunchKernelGGL((bank_bwd_wm_k<R, TY, PX>), dim3((unsigned)ntiles), dim3(256), 0, a.st, a.a, a.b, part, a.f, a.h,
                        a.w, tx, tx * ty, ntiles);
     const int nk = (2 * R + 1) * (2 * R + 1);
     hipLaunchKernelGGL(bank_bwd_w2_k, dim3((unsigned)(a.f * nk)), dim3(256), 0, a.st, part, a.out, ntiles, a.scale);
@@ -1020,10 +1052,16 @@ template <int R>
 hipError_t bwd_wm_R(const BankArgs& a) { return bwd_wm_RT<R, 1>(a); }
 template <int R>
 hipError_t bwd_wm4_R(const BankArgs& a) { return bwd_wm_RT<R, 4>(a); }
+template <int R>
+hipError_t bwd_wmp_R(const BankArgs& a) { return bwd_wm_RT<R, 1, true>(a); }
+template <int R>
+hipError_t bwd_wmp4_R(const BankArgs& a) { return bwd_wm_RT<R, 4, true>(a); }
 
 hipError_t launch_bwd_w4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_w4_R) }
 hipError_t launch_bwd_wm(const BankArgs& a) { ICL_BANK_SWITCH(bwd_wm_R) }
 hipError_t launch_bwd_wm4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_wm4_R) }
+hipError_t launch_bwd_wmp(const BankArgs& a) { ICL_BANK_SWITCH(bwd_wmp_R) }
+hipError_t launch_bwd_wmp4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_wmp4_R) }
 hipError_t launch_bwd_w4x4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_w4x4_R) }
 
 
@@ -1042,7 +1080,9 @@ const Variant<BankArgs> kBwdW[] = {{"wave_t32x64", supports_bwd_w, launch_bwd_w}
                                    {"block4_t64", supports_bwd_w, launch_bwd_w4},
                                    {"block4_t64x256", supports_bwd_w, launch_bwd_w4x4},
                                    {"mfma_t64", supports_bwd_wm, launch_bwd_wm},
-                                   {"mfma_t64x256", supports_bwd_wm, launch_bwd_wm4}};
+                                   {"mfma_t64x256", supports_bwd_wm, launch_bwd_wm4},
+                                   {"mfma_px_t64", supports_bwd_wm, launch_bwd_wmp},
+                                   {"mfma_px_t64x256", supports_bwd_wm, launch_bwd_wmp4}};
 
 // ------------------------------------------------------------------ forward on the matrix cores
 // y[f][p] = sum_k w[f][k] x[p + off(k)]: filters as rows, pixels as columns, taps as the
@@ -1054,8 +1094,16 @@ const Variant<BankArgs> kBwdW[] = {{"wave_t32x64", supports_bwd_w, launch_bwd_w}
 // take 16 rows each, four 16-pixel column groups at a time (four independent accumulator
 // chains).  SSE: the loss epilogue of the fused forward (gy = 2 (y - t), y on request, the
 // work-group's double partial of sum (y - t)^2).  Up to 16 filters.
-template <int R, bool SSE>
-__global__ __launch_bounds__(256) void bank_fwd_mfma_k(const float* __restrict__ x, const float* __restrict__ w,
+// WAVES > 0: the register budget of WAVES waves per SIMD (the LDS tile admits more work-groups
+// than the unconstrained allocation leaves room for).
+// PX: the operands swap roles (pixels as rows, filters as columns), which changes nothing in
+// the products or their order but puts four consecutive pixels of one filter in each lane's
+// accumulator, so the targets are read and the outputs written as 16-byte vectors (a quarter
+// of the memory instructions of the filter-major layout, where a lane holds one pixel of four
+// filters).
+template <int R, bool SSE, int WAVES = 0, bool PX = false>
+__global__ __launch_bounds__(256, WAVES > 0 ? WAVES : 1) void bank_fwd_mfma_k(const float* __restrict__ x,
+                                                                             const float* __restrict__ w,
                                                        float* __restrict__ y, const float* __restrict__ tg,
                                                        float* __restrict__ gy, double* __restrict__ part, int F,
                                                        int H, int W, int tiles_x, int tiles_img, int ntiles, int vec) {
@@ -1084,6 +1132,76 @@ __global__ __launch_bounds__(256) void bank_fwd_mfma_k(const float* __restrict__
         __syncthreads();   // the previous tile's products are done with s
         stage_plane<R, false>(x + (size_t)n * hw, W, H, x0, y0, vec, s);
         __syncthreads();
+        if constexpr (PX) {
+            // lane: filter j, pixels 16 c + 4 kq + (0..3) of the row, c = 0..3
+            const int fj = min(j, F - 1);
+            const float* tplane = SSE ? tg + ((size_t)n * F + fj) * hw : nullptr;
+#pragma unroll 1
+            for (int row = 0; row < 16; ++row) {
+                const int py = wave * 16 + row;
+                const int yg = y0 + py;
+                const size_t rowoff = (size_t)min(yg, H - 1) * W;
+                v4f tv[4];
+                if constexpr (SSE) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int xg = x0 + 16 * c + 4 * kq;
+                        if (vec && xg + 4 <= W) {
+                            tv[c] = *reinterpret_cast<const v4f*>(tplane + rowoff + xg);
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) tv[c][i] = tplane[rowoff + min(xg + i, W - 1)];
+                        }
+                    }
+                }
+                v4f acc[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] = mk4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int st = 0; st < NS; ++st)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(s[py * LW + 16 * c + j + off[st]], a[st], acc[c],
+                                                                      0, 0, 0);
+                if (yg >= H || j >= F) continue;
+                float ssum = 0.f;
+                const size_t plane = ((size_t)n * F + j) * hw + (size_t)yg * W;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int xg = x0 + 16 * c + 4 * kq;
+                    if (xg >= W) continue;
+                    const bool full = vec && xg + 4 <= W;
+                    if constexpr (SSE) {
+                        v4f d = acc[c] - tv[c];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (full || xg + i < W) ssum = fmaf(d[i], d[i], ssum);
+                        const v4f g2 = 2.f * d;
+                        if (full) {
+                            if (gy) *reinterpret_cast<v4f*>(gy + plane + xg) = g2;
+                            if (y) *reinterpret_cast<v4f*>(y + plane + xg) = acc[c];
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                if (xg + i >= W) break;
+                                if (gy) gy[plane + xg + i] = g2[i];
+                                if (y) y[plane + xg + i] = acc[c][i];
+                            }
+                        }
+                    } else {
+                        if (full) {
+                            *reinterpret_cast<v4f*>(y + plane + xg) = acc[c];
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                if (xg + i < W) y[plane + xg + i] = acc[c][i];
+                        }
+                    }
+                }
+                if constexpr (SSE) sq += (double)ssum;
+            }
+            continue;
+        }
 #pragma unroll 1
         for (int row = 0; row < 16; ++row) {
             const int py = wave * 16 + row;
@@ -1137,24 +1255,28 @@ __global__ __launch_bounds__(256) void bank_fwd_mfma_k(const float* __restrict__
     if constexpr (SSE) block_sum_store(sq, red, part);
 }
 
-template <int R>
+template <int R, bool PX = false>
 hipError_t fwd_mfma_R(const BankArgs& a) {
     const int tx = (a.w + BT - 1) / BT, ty = (a.h + BT - 1) / BT;
     const int ntiles = a.n * tx * ty;
-    const void* k = reinterpret_cast<const void*>(&bank_fwd_mfma_k<R, false>);
-    hipLaunchKernelGGL((bank_fwd_mfma_k<R, false>), dim3(persistent_grid(k, 256, ntiles)), dim3(256), 0, a.st, a.a,
-                       a.b, a.out, nullptr, nullptr, nullptr, a.f, a.h, a.w, tx, tx * ty, ntiles,
+    const void* k = reinterpret_cast<const void*>(&bank_fwd_mfma_k<R, false, 0, PX>);
+    hipLaunchKernelGGL((bank_fwd_mfma_k<R, false, 0, PX>), dim3(persistent_grid(k, 256, ntiles)), dim3(256), 0, a.st,
+                       a.a, a.b, a.out, nullptr, nullptr, nullptr, a.f, a.h, a.w, tx, tx * ty, ntiles,
                        bank_vec(a.a, a.out, a.w));
     return hipGetLastError();
 }
+template <int R>
+hipError_t fwd_mfma_px_R(const BankArgs& a) { return fwd_mfma_R<R, true>(a); }
 
 hipError_t launch_fwd_mfma(const BankArgs& a) { ICL_BANK_SWITCH(fwd_mfma_R) }
+hipError_t launch_fwd_mfma_px(const BankArgs& a) { ICL_BANK_SWITCH(fwd_mfma_px_R) }
 bool supports_mfma16(const BankArgs& a) { return supports_bank(a) && a.f <= 16; }
 
 const Variant<BankArgs> kFwd[] = {{"plain", supports_bank, launch_fwd_plain},
                                    {"tile64_p4x4", supports_bank, launch_fwd},
                                    {"pers_p4x4", supports_pers, launch_fwd_pers},
-                                   {"mfma_t64", supports_mfma16, launch_fwd_mfma}};
+                                   {"mfma_t64", supports_mfma16, launch_fwd_mfma},
+                                   {"mfma_px_t64", supports_mfma16, launch_fwd_mfma_px}};
 // ------------------------------------------------------------------ sum of squares loss
 constexpr int SSE_BLOCKS = 2048;
 
@@ -1297,25 +1419,26 @@ bool supports_sse(const BankSseArgs& a) {
 bool supports_sse_pers(const BankSseArgs& a) { return supports_sse(a) && a.f <= PERS_FMAX; }
 bool supports_sse_mfma(const BankSseArgs& a) { return supports_sse(a) && a.f <= 16; }
 
-template <int R>
+template <int R, int WAVES = 0, bool PX = false>
 hipError_t fwd_sse_mfma_R(const BankSseArgs& a) {
     double* part = static_cast<double*>(a.ws);
     const int tx = (a.wd + BT - 1) / BT, ty = (a.h + BT - 1) / BT;
     const int ntiles = a.n * tx * ty;
-    const void* k = reinterpret_cast<const void*>(&bank_fwd_mfma_k<R, true>);
+    const void* k = reinterpret_cast<const void*>(&bank_fwd_mfma_k<R, true, WAVES, PX>);
     const int grid = std::min(persistent_grid(k, 256, ntiles), FWD_SSE_PARTS);
-    hipLaunchKernelGGL((bank_fwd_mfma_k<R, true>), dim3(grid), dim3(256), 0, a.st, a.x, a.w, a.y, a.t, a.gy, part, a.f,
+    hipLaunchKernelGGL((bank_fwd_mfma_k<R, true, WAVES, PX>), dim3(grid), dim3(256), 0, a.st, a.x, a.w, a.y, a.t, a.gy, part, a.f,
                        a.h, a.wd, tx, tx * ty, ntiles, sse_vec(a));
     hipLaunchKernelGGL(sse_final_k, dim3(1), dim3(256), 0, a.st, part, grid, a.loss);
     return hipGetLastError();
 }
 
+template <int WAVES = 0, bool PX = false>
 hipError_t launch_fwd_sse_mfma(const BankSseArgs& a) {
     switch (a.r) {
-        case 1: return fwd_sse_mfma_R<1>(a);
-        case 2: return fwd_sse_mfma_R<2>(a);
-        case 3: return fwd_sse_mfma_R<3>(a);
-        case 4: return fwd_sse_mfma_R<4>(a);
+        case 1: return fwd_sse_mfma_R<1, WAVES, PX>(a);
+        case 2: return fwd_sse_mfma_R<2, WAVES, PX>(a);
+        case 3: return fwd_sse_mfma_R<3, WAVES, PX>(a);
+        case 4: return fwd_sse_mfma_R<4, WAVES, PX>(a);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1325,7 +1448,9 @@ hipError_t launch_fwd_sse_mfma(const BankSseArgs& a) {
 const Variant<BankSseArgs> kFwdSse[] = {{"plain", supports_sse, launch_fwd_sse_plain},
                                         {"pers_p4x4", supports_sse_pers, launch_fwd_sse_pers<false>},
                                         {"pers_p4x4_tpre", supports_sse_pers, launch_fwd_sse_pers<true>},
-                                        {"mfma_t64", supports_sse_mfma, launch_fwd_sse_mfma}};
+                                        {"mfma_t64", supports_sse_mfma, launch_fwd_sse_mfma<0>},
+                                        {"mfma_t64_w4", supports_sse_mfma, launch_fwd_sse_mfma<4>},
+                                        {"mfma_px_t64", supports_sse_mfma, launch_fwd_sse_mfma<0, true>}};
 
 }  // namespace
 
