@@ -1502,13 +1502,15 @@ const Variant<BankArgs>* bank_bwd_filter_variants(int* count) {
     return kBwdW;
 }
 
-int bank_fwd_default(const BankArgs& a) { return supports_mfma16(a) ? 3 : supports_pers(a) ? 2 : 1; }
+int bank_fwd_default(const BankArgs& a) { return supports_mfma16(a) ? 4 : supports_pers(a) ? 2 : 1; }   // mfma_px_t64
 int bank_bwd_input_default(const BankArgs& a) { return supports_pers(a) ? 2 : 1; }
-int bank_bwd_filter_default(const BankArgs& a) { return a.f <= 16 ? 3 : 2; }   // mfma_t64, else block4_t64x256
+int bank_bwd_filter_default(const BankArgs& a) { return a.f <= 16 ? 6 : 2; }   // mfma_px_t64x256, else block4_t64x256
 const Variant<BankSseArgs>* bank_fwd_sse_variants(int* count) {
     *count = (int)(sizeof(kFwdSse) / sizeof(kFwdSse[0]));
     return kFwdSse;
 }
-int bank_fwd_sse_default(const BankSseArgs& a) { return supports_sse_mfma(a) ? 3 : supports_sse_pers(a) ? 1 : 0; }
+int bank_fwd_sse_default(const BankSseArgs& a) {   // mfma_px_t64, else pers_p4x4, else plain
+    return supports_sse_mfma(a) ? 5 : supports_sse_pers(a) ? 1 : 0;
+}
 
 }  // namespace icl

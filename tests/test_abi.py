@@ -375,7 +375,7 @@ def test_problem_tuning_validation(no_gpu):
     assert P(B.ICL_OP_CONV3D_SEP, B.ICL_F32, 1, 64, 64, depth=64) == B.ICL_ERR_NO_DEVICE
     # defaults of the problem form: the matrix-core forward and filter adjoint up to 16 filters
     st, v = B.icl_selected_variant_problem(B.ICL_OP_BANK_FWD, B.ICL_F32, 4, 1024, 1024, n=32, f=16)
-    assert st == B.ICL_OK and B.icl_variant_name(B.ICL_OP_BANK_FWD, v) == "mfma_t64"
+    assert st == B.ICL_OK and B.icl_variant_name(B.ICL_OP_BANK_FWD, v) == "mfma_px_t64"
     st, v = B.icl_selected_variant_problem(B.ICL_OP_BANK_BWD_FILTER, B.ICL_F32, 4, 1024, 1024, n=32, f=32)
     assert st == B.ICL_OK and B.icl_variant_name(B.ICL_OP_BANK_BWD_FILTER, v) == "block4_t64x256"
     assert B.icl_batch_plan_tune(0) == B.ICL_ERR_INVALID_VALUE
