@@ -105,7 +105,10 @@ def kernel_variant(name):
             ("2d", r"conv2d_mfma_k<icl::F32, (\d+)>", "mfma_f16x3"),
             ("sep", r"sep_pers<icl::F32, (\d+), (\d+), (\d+)>", "pers_t{1}_c{2}"),
             ("sep", r"sep_fused<icl::F32, (\d+), (\d+), (\d+)>", "fused_t{1}_c{2}"),
-            ("sep", r"sep_strip<icl::F32, (\d+), (\d+)>", "strip_t{1}")]
+            ("sep", r"sep_strip<icl::F32, (\d+), (\d+)>", "strip_t{1}"),
+            ("sep", r"sep_fused_img<icl::F32, (\d+), (\d+), (\d+), false>", "fused_img_t{1}_c{2}"),
+            ("sep", r"sep_fused_img<icl::F32, (\d+), (\d+), (\d+), true>", "fused_img4_t{1}_c{2}"),
+            ("sep", r"sep_colwalk<icl::F32, (\d+), (\d+)>", "colwalk_s{1}")]
     for kind, pat, fmt in pats:
         m = re.search(pat, name)
         if m:
@@ -152,7 +155,7 @@ def write_traffic(fetch_csv, write_csv, side=4096):
                      "1 GiB device-to-device copy to 1 GiB; source_hash covers the kernel's source files and "
                      "bench.py reports traffic only while it matches.",
            "commands": [f"rocprofv3 --pmc {ctr} --output-format csv -d {os.path.dirname(csv_path)} -o {tag} -- "
-                        "python3 bench.py --only 2d7,sep7 --steps 3 --warmup 1 --no-extras --no-cpu --calib-copy"
+                        "python3 bench.py --steps 3 --warmup 1 --no-extras --no-cpu --calib-copy"
                         for ctr, csv_path, tag in (("FETCH_SIZE", fetch_csv, "fetch"), ("WRITE_SIZE", write_csv, "write"))],
            "calibration": {"fetch_factor": round(fcal, 4), "write_factor": round(wcal, 4),
                            "copy_fetch_kib": [round(v, 1) for v in cf], "copy_write_kib": [round(v, 1) for v in cw]}}
@@ -192,11 +195,12 @@ WORKLOAD_KERNELS = [
      "icl_device.hpp"], 5 * 8192 * 8192),
     ("corner", r"corners_stream<(\d+), (\d+), 1>", "corners_stream_t{1}", ["corners.hip", "harris_strip.hpp",
      "icl_device.hpp"], 5 * 8192 * 8192),
-    ("bank", r"bank_fwd_(mfma_k<4, true>|pers_k<4, true>|sse_tpre_k<4>)", "fwd_sse:{0}", ["bank.hip"],
+    ("bank", r"bank_fwd_(mfma_k<4, true, \d+, (?:true|false)>|pers_k<4, true>|sse_tpre_k<4>)", "fwd_sse:{0}",
+     ["bank.hip"],
      4 * (_BANK[0] * _BANK[2] + 2 * _BANK[0] * _BANK[1] * _BANK[2])),
     ("bank", r"bank_bwd_in_(pers_k|k)<4>", "bwd_input:{0}", ["bank.hip"],
      4 * (_BANK[0] * _BANK[1] * _BANK[2] + _BANK[0] * _BANK[2])),
-    ("bank", r"bank_bwd_(wm_k<4, \d>|w4_k<4, \d, 16>)", "bwd_filter:{0}", ["bank.hip"],
+    ("bank", r"bank_bwd_(wm_k<4, \d, (?:true|false)>|w4_k<4, \d, 16>)", "bwd_filter:{0}", ["bank.hip"],
      4 * (_BANK[0] * _BANK[1] * _BANK[2] + _BANK[0] * _BANK[2])),
     ("paper", r"sep_(fused|pers)<icl::F32, 2, (\d+), (\d+)>", "sep5_constant:{0}_t{1}_c{2}",
      KERNEL_SOURCES["sep"], 8 * 4096 * 4096),
@@ -204,6 +208,8 @@ WORKLOAD_KERNELS = [
      2 * 8192 * 8192),
     ("volume", r"sep3_stream<icl::F32, (\d+), (\d+)>", "sep3d_r{0}:stream_z{1}", ["conv3d.hip", "icl_device.hpp"],
      8 * 256 ** 3),
+    ("volume", r"sep3_stream2<icl::F32, (\d+), (\d+), (\d+)>", "sep3d_r{0}:stream2_z{1}_h{2}",
+     ["conv3d.hip", "icl_device.hpp"], 8 * 256 ** 3),
 ]
 
 

@@ -204,6 +204,152 @@ __global__ __launch_bounds__(256) void sep3_stream(const void* __restrict__ src,
     });
 }
 
+// Tiles of 64 x TH (TH = 16 or 32) with two staged slices: the next slice goes into the idle
+// buffer right after this slice's y pass (its last reader, the previous row pass, finished
+// before the barrier that precedes the y pass), so a slice costs two work-group barriers
+// instead of three, and the loads of the slice after it are issued then.  A lane takes four
+// columns of TH / 16 consecutive rows; the y pass reads each row-pass row once for all of them.
+template <class T, int R, int TZ, int TH>
+__global__ __launch_bounds__(256) void sep3_stream2(const void* __restrict__ src, size_t srp, size_t ssp,
+                                                    void* __restrict__ dst, size_t drp, size_t dsp, int W, int H,
+                                                    int D, const float* __restrict__ tx, const float* __restrict__ ty,
+                                                    const float* __restrict__ tz, int tiles_x, int tiles_xy,
+                                                    int vec_ok, int vec_out, Border bd) {
+    using G = SepTile<R, TH, 1>;
+    constexpr int TW = G::TW, RA = G::RA, LW = G::LW, NR = G::NR, PY = TH / 16;
+    constexpr int KZ = TZ + 2 * R;   // input slices walked
+    constexpr int DZ = 2 * R + 1;    // pending output slices
+    __shared__ __attribute__((aligned(16))) float in_s[2][NR * LW];
+    __shared__ __attribute__((aligned(16))) float t_s[NR * TW];
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = (int)(t % (unsigned)tiles_xy);
+    const int z0 = (int)(t / (unsigned)tiles_xy) * TZ;
+    const int x0 = (tile % tiles_x) * TW, y0 = (tile / tiles_x) * TH;
+    Stage<T, NR, LW> st;
+    auto load_slice = [&](int kz) {
+        const int z = z0 - R + kz;
+        if (bd.constant && (z < 0 || z >= D)) {
+            st.fill(bd.value);
+        } else {
+            const char* base = static_cast<const char*>(src) + (size_t)clampi(z, D) * ssp;
+            st.load(base, srp, W, H, x0 - RA, y0 - R, vec_ok, bd);
+        }
+    };
+    const int g = threadIdx.x % 16, rg = threadIdx.x / 16;
+    const int x = x0 + 4 * g, ya = y0 + PY * rg;
+    float hz[DZ];
+#pragma unroll
+    for (int k = 0; k < DZ; ++k) hz[k] = tz[k];
+    v4f acc[DZ][PY];
+#pragma unroll
+    for (int k = 0; k < DZ; ++k)
+#pragma unroll
+        for (int p = 0; p < PY; ++p) acc[k][p] = mk4(0.f, 0.f, 0.f, 0.f);
+    load_slice(0);
+    st.store(in_s[0]);
+    if constexpr (KZ > 1) load_slice(1);
+    __syncthreads();
+    static_for<KZ>([&](auto k_c) {
+        constexpr int kz = decltype(k_c)::value, cur = kz & 1;
+        sep_row_pass<R, TH, 1>(in_s[cur], t_s, tx);
+        __syncthreads();   // t_s holds this slice's row pass
+        // y pass of this lane's PY rows of four voxels
+        v4f v[PY];
+#pragma unroll
+        for (int p = 0; p < PY; ++p) v[p] = mk4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int m = 0; m < PY + 2 * R; ++m) {
+            const v4f q = lds4(t_s + (PY * rg + m) * TW + 4 * g);
+#pragma unroll
+            for (int p = 0; p < PY; ++p) {
+                const int j = m - p;
+                if (j < 0 || j > 2 * R) continue;
+                const float c = ty[j];
+                v[p].x = fmaf(c, q.x, v[p].x);
+                v[p].y = fmaf(c, q.y, v[p].y);
+                v[p].z = fmaf(c, q.z, v[p].z);
+                v[p].w = fmaf(c, q.w, v[p].w);
+            }
+        }
+        if constexpr (kz + 1 < KZ) {
+            st.store(in_s[cur ^ 1]);
+            if constexpr (kz + 2 < KZ) load_slice(kz + 2);   // in flight during the next slice
+        }
+        // z pass: input slice kz feeds output slices kz - k, k = 0 .. 2r
+#pragma unroll
+        for (int k = 0; k < DZ; ++k) {
+            const int m = kz - k;
+            if (m < 0 || m >= TZ) continue;
+            const int slot = ((kz - k) % DZ + DZ) % DZ;
+#pragma unroll
+            for (int p = 0; p < PY; ++p) {
+                v4f& a = acc[slot][p];
+                a.x = fmaf(hz[k], v[p].x, a.x);
+                a.y = fmaf(hz[k], v[p].y, a.y);
+                a.z = fmaf(hz[k], v[p].z, a.z);
+                a.w = fmaf(hz[k], v[p].w, a.w);
+            }
+        }
+        if constexpr (kz >= 2 * R) {
+            constexpr int m = kz - 2 * R;   // output slice z0 + m is complete
+            constexpr int slot = m % DZ;
+            const int z = z0 + m;
+#pragma unroll
+            for (int p = 0; p < PY; ++p) {
+                const int y = ya + p;
+                if (z < D && y < H) {
+                    const size_t row = (size_t)z * dsp + (size_t)y * drp;
+                    const v4f a = acc[slot][p];
+                    if (vec_out && x + 4 <= W) {
+                        store4<T>(dst, row + (size_t)x * T::size, a);
+                    } else {
+                        if (x < W) store_px<T>(dst, row + (size_t)x * T::size, a.x);
+                        if (x + 1 < W) store_px<T>(dst, row + (size_t)(x + 1) * T::size, a.y);
+                        if (x + 2 < W) store_px<T>(dst, row + (size_t)(x + 2) * T::size, a.z);
+                        if (x + 3 < W) store_px<T>(dst, row + (size_t)(x + 3) * T::size, a.w);
+                    }
+                }
+                acc[slot][p] = mk4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+        __syncthreads();   // the y pass is done with t_s and the next slice is staged
+    });
+}
+
+template <class T, int R, int TZ, int TH>
+hipError_t launch_stream2_TR(const Sep3Args& a) {
+    const int tiles_x = (a.W + 63) / 64, tiles_y = (a.H + TH - 1) / TH, zb = (a.D + TZ - 1) / TZ;
+    const long long blocks = (long long)tiles_x * tiles_y * zb;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const size_t al = 4 * (size_t)T::size;
+    const int vec_ok = ((uintptr_t)a.src % al == 0) && (a.srp % al == 0) && (a.ssp % al == 0);
+    const int vec_out = ((uintptr_t)a.dst % al == 0) && (a.drp % al == 0) && (a.dsp % al == 0);
+    hipLaunchKernelGGL((sep3_stream2<T, R, TZ, TH>), dim3((unsigned)blocks), dim3(256), 0, a.st, a.src, a.srp,
+                       a.ssp, a.dst, a.drp, a.dsp, a.W, a.H, a.D, a.tx, a.ty, a.tz, tiles_x, tiles_x * tiles_y,
+                       vec_ok, vec_out, a.bd);
+    return hipGetLastError();
+}
+
+template <class T, int TZ, int TH>
+hipError_t launch_stream2_T(const Sep3Args& a) {
+    switch (a.r) {
+        case 0: return launch_stream2_TR<T, 0, TZ, TH>(a);
+        case 1: return launch_stream2_TR<T, 1, TZ, TH>(a);
+        case 2: return launch_stream2_TR<T, 2, TZ, TH>(a);
+        case 3: return launch_stream2_TR<T, 3, TZ, TH>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int TZ, int TH>
+hipError_t launch_stream2(const Sep3Args& a) {
+    switch (a.dt) {
+        case ICL_F32: return launch_stream2_T<F32, TZ, TH>(a);
+        case ICL_F16: return launch_stream2_T<F16, TZ, TH>(a);
+        default: return launch_stream2_T<BF16, TZ, TH>(a);
+    }
+}
+
 template <class T, int R, int TZ>
 hipError_t launch_stream_TR(const Sep3Args& a) {
     const int tiles_x = (a.W + 63) / 64, tiles_y = (a.H + 15) / 16, zb = (a.D + TZ - 1) / TZ;
@@ -245,6 +391,10 @@ const Variant<Sep3Args> kSep3[] = {
     {"stream_z16", supports_stream, launch_stream<16>},
     {"stream_z32", supports_stream, launch_stream<32>},
     {"stream_z8", supports_stream, launch_stream<8>},
+    {"stream2_z16_h16", supports_stream, launch_stream2<16, 16>},
+    {"stream2_z8_h16", supports_stream, launch_stream2<8, 16>},
+    {"stream2_z16_h32", supports_stream, launch_stream2<16, 32>},
+    {"stream2_z8_h32", supports_stream, launch_stream2<8, 32>},
 };
 
 }  // namespace
@@ -256,6 +406,8 @@ const Variant<Sep3Args>* sep3d_variants(int* count) {
     return kSep3;
 }
 
-int sep3d_default(const Sep3Args& a) { return supports_stream(a) ? 1 : 0; }
+// untuned choice: z blocks of 8 slices over 64 x 16 tiles up to r = 1, 64 x 32 tiles beyond
+// (the taller tile halves the y halo that a wider window costs)
+int sep3d_default(const Sep3Args& a) { return supports_stream(a) ? (a.r <= 1 ? 5 : 7) : 0; }
 
 }  // namespace icl
