@@ -54,6 +54,13 @@ def parse():
     p.add_argument("--write-workload-traffic", metavar="DIR",
                    help="turn the per-workload FETCH_SIZE / WRITE_SIZE runs under DIR into profiles/traffic.json "
                         "entries and profiles/hbm_traffic_workloads.md, and exit")
+    p.add_argument("--write-trace-summary", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
+                   help="turn a rocprofv3 --kernel-trace --stats run of bench.py (its csv directory and the bench "
+                        "line it printed) into profiles/kernel_trace_sweep_4096_f32.md and "
+                        "profiles/kernel_trace_workloads.md, and exit")
+    p.add_argument("--write-counter-summary", nargs="+", metavar="DIR",
+                   help="turn rocprofv3 --pmc SQ_* runs (one counter_collection.csv per DIR) into "
+                        "profiles/sq_counters.md, and exit")
     p.add_argument("--calib-copy", action="store_true",
                    help="also run three 1 GiB device-to-device copies (a known byte count for counter calibration)")
     return p.parse_args()
@@ -278,8 +285,178 @@ def write_workload_traffic(root):
     print(f"wrote {path} and profiles/hbm_traffic_workloads.md ({len(rows)} kernels)")
 
 
+def _short_kernel(name):
+    """A kernel symbol without its namespaces and parameter list."""
+    import re
+    n = name.replace("void ", "", 1).replace("(anonymous namespace)::", "").replace("icl::", "")
+    depth, cut = 0, len(n)
+    for i, ch in enumerate(n):   # the parameter list starts at the first '(' outside template brackets
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = i
+            break
+    return re.sub(r"\s+", " ", n[:cut]).strip()
+
+
+def write_trace_summary(trace_dir, bench_json):
+    """Kernel-trace summaries of one profiled default bench run: the sweep's calls (trace means of the
+    timed dispatches beside bench.py's event means) and every kernel of the extra workloads."""
+    import csv
+    import glob
+    line = [ln for ln in open(bench_json).read().splitlines() if ln.startswith("{")][-1]
+    d = json.loads(line)
+    steps = int(d["steps"])
+    trace = glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0]
+    stats = glob.glob(os.path.join(trace_dir, "*kernel_stats.csv"))[0]
+    disp = [(r["Kernel_Name"], (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+            for r in csv.DictReader(open(trace))]
+    prof = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/kt -o kt -- "
+            "python3 bench.py --no-cpu > gpurun_out/kt_bench.json")
+    summ = "python3 bench.py --write-trace-summary gpurun_out/kt gpurun_out/kt_bench.json"
+    md = ["# Kernel trace: convolution sweep 4096x4096 float32", "",
+          "Commands (repository root, one MI355X):", "", "```", prof, summ, "```", "",
+          f"The profiled run is the default bench (tuning, {d['warmup']} warmup and {steps} timed steps, the "
+          "plain-variant steps, then the extra workloads).  bench.py times each call as one HIP-event pair "
+          f"around its {steps} back-to-back launches (rotating buffers, so every launch reads its input from "
+          "HBM); the timed dispatches are the first run of exactly that many consecutive dispatches of the "
+          "call's kernel in the trace.  The all-dispatch mean also holds the tuner's timing launches and "
+          "the later workloads' launches of the same kernel.", "",
+          "| call | variant | kernel | trace mean, timed dispatches (us) | bench.py event mean (us) | "
+          "trace mean, all dispatches (us) | min (us) | dispatches |", "|---|---|---|---|---|---|---|---|"]
+    dom = None
+    for c in d["per_call"]:
+        kind, r = c["call"][:-1], int(c["call"][-1])
+        sym = next((k for k, _ in disp if kernel_variant(k) == (kind, r, c["variant"])), None)
+        if sym is None:
+            md.append(f"| {c['call']} | {c['variant']} | (not found) | | {c['us']} | | | |")
+            continue
+        idx = [i for i, (k, _) in enumerate(disp) if k == sym]
+        runs, cur = [], [idx[0]]
+        for i in idx[1:]:
+            if i == cur[-1] + 1:
+                cur.append(i)
+            else:
+                runs.append(cur)
+                cur = [i]
+        runs.append(cur)
+        # the timed launches: the first run of exactly `steps` consecutive dispatches (the tuner's
+        # runs hold 43, the warmup's 1, and later workloads may time the same kernel again)
+        timed = [rn for rn in runs if len(rn) == steps]
+        tmean = float(np.mean([disp[i][1] for i in timed[0]])) if timed else float("nan")
+        allt = [disp[i][1] for i in idx]
+        md.append(f"| {c['call']} | {c['variant']} | `{_short_kernel(sym)}` | {tmean:.2f} | {c['us']:.2f} | "
+                  f"{np.mean(allt):.2f} | {min(allt):.2f} | {len(allt)} |")
+        if c["call"] == d["roofline"].get("kernel", "").split(":")[0]:
+            dom = (c["call"], c["variant"], tmean, d["roofline"].get("launch_us"))
+    md += ["", f"The bench line under the profiler: {d['value']} {d['unit']}, {d['ms_per_step']} ms/step."]
+    if dom:
+        md += ["", f"Roofline kernel ({dom[0]}:{dom[1]}): {dom[2]:.2f} us per timed dispatch in the trace against "
+                   f"bench.py's event-timed {dom[3]} us per launch."]
+    with open(os.path.join(ROOT, "profiles", "kernel_trace_sweep_4096_f32.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    rows = sorted(csv.DictReader(open(stats)), key=lambda r: _short_kernel(r["Name"]))
+    torch_rows = [r for r in rows if r["Name"].startswith("at::") or r["Name"].startswith("void at::")]
+    rows = [r for r in rows if r not in torch_rows]
+    ex = d.get("extras", {})
+    md = ["# Kernel trace: every kernel of the profiled default bench run", "",
+          "Commands (repository root, one MI355X):", "", "```", prof, summ, "```", "",
+          "bench.py times every variant of every workload (forced) beside its tuned choice, and the tuner "
+          "times the candidates, so each kernel appears; the extra workloads' figures are below the table.", "",
+          "| kernel | calls | mean (us) | min (us) | max (us) |", "|---|---|---|---|---|"]
+    for r in rows:
+        md.append(f"| `{_short_kernel(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                  f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} |")
+    md += ["", f"Not listed: {sum(int(r['Calls']) for r in torch_rows)} dispatches of {len(torch_rows)} PyTorch "
+           "kernels (input uploads, dtype conversions and the bench's own equality checks).",
+           "", "bench.py's extra-workload figures in the profiled run:", "", "| workload | time | variant |",
+           "|---|---|---|"]
+    for k, v in ex.items():
+        if not isinstance(v, dict):
+            continue
+        t = f"{v['ms']} ms" if "ms" in v else (f"{v['us']} us" if "us" in v else "")
+        var = v.get("variant") or v.get("harris_variant") or ""
+        if k == "filter_bank_fwd_bwd":
+            var = ", ".join(f"{p}: {q['variant']} {q['ms']} ms" for p, q in v.get("phases", {}).items())
+        md.append(f"| {k} | {t} | {var} |")
+    with open(os.path.join(ROOT, "profiles", "kernel_trace_workloads.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("wrote profiles/kernel_trace_sweep_4096_f32.md and profiles/kernel_trace_workloads.md")
+
+
+# SQ counter passes (at most 8 SQ counters each) and the bench runs they profile
+SQ_PASSES = {"A": "SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_MFMA "
+                  "SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_SALU",
+             "B": "SQ_INSTS_LDS SQ_ACTIVE_INST_LDS SQ_WAIT_INST_LDS SQ_LDS_BANK_CONFLICT SQ_WAIT_INST_ANY "
+                  "SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_WAVE_CYCLES"}
+SQ_RUNS = {"sweep": "--steps 3 --warmup 1 --no-extras --no-cpu", "bank": "--only bank --steps 4 --warmup 1 --no-cpu",
+           "batch": "--only batch --steps 4 --warmup 1 --no-cpu", "corner": "--only corner --steps 4 --warmup 1 --no-cpu"}
+SQ_KERNELS = (r"conv2d_pers<F32, [1-7], ", r"sep_(fused|pers)<F32, [1-7], ", r"bank_(fwd_mfma_k<4, true, 0, true>|"
+              r"bwd_in_pers_k<4>|bwd_wm_k<4, 4, true>)", r"sep_batched_col_k<F16, 1, 64>", r"harris_stream<2, 16>",
+              r"nms_stream_a<4, false>", r"corners_stream<2, 12, 1>")
+
+
+def write_counter_summary(dirs):
+    """Per-kernel SQ counter ratios from rocprofv3 --pmc passes (directories named sq{pass}_{run})."""
+    import collections
+    import csv
+    import glob
+    import re
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for dd in dirs:
+        for path in glob.glob(os.path.join(dd, "*counter_collection.csv")):
+            for r in csv.DictReader(open(path)):
+                k = _short_kernel(r["Kernel_Name"])
+                if not any(re.search(p, k) for p in SQ_KERNELS):
+                    continue
+                agg[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+                agg[k]["_us"].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    cmds = [f"rocprofv3 --pmc {ctrs} --output-format csv -d gpurun_out/sq{ps}_{run} -o sq -- python3 bench.py {args}"
+            for ps, ctrs in SQ_PASSES.items() for run, args in SQ_RUNS.items()]
+    md = ["# SQ counters: what the main kernels spend their time on", "", "Commands (repository root, one MI355X), one "
+          "pass of at most eight SQ counters per run:", "", "```", *cmds,
+          "python3 bench.py --write-counter-summary " + " ".join(f"gpurun_out/sq{ps}_{run}" for ps in SQ_PASSES
+                                                                  for run in SQ_RUNS), "```", "",
+          "Per kernel, the mean per dispatch over every dispatch of the profiled runs (the tuner's included).  "
+          "Ratios: `valu/cyc` = VALU instructions x 4 / (SIMD count x kernel cycles at 2.4 GHz), the share of "
+          "the vector units' issue a wave64 FP32 instruction takes at 16 lanes a cycle (over 1 where some "
+          "instructions take fewer cycles, or the clock runs higher); `mfma busy` = SQ_VALU_MFMA_BUSY_CYCLES / "
+          "(SIMD count x kernel cycles); `lds conflict` = bank-conflict cycles per cycle of LDS instruction "
+          "activity; `lds wait`, `any wait` = SQ_WAIT_INST_LDS and SQ_WAIT_INST_ANY over SQ_WAVE_CYCLES (the "
+          "share of wave time spent waiting); `lds/valu` = LDS instructions per VALU instruction.  Kernel "
+          "times run longer under counter collection than in the bench.", "",
+          "| kernel | us | VALU instr | valu/cyc | MFMA instr | mfma busy | LDS instr | lds/valu | lds conflict | "
+          "lds wait | any wait |", "|---|---|---|---|---|---|---|---|---|---|---|"]
+    simds, clk = 1024, 2.4e3   # SIMDs; cycles per us
+    for k in sorted(agg):
+        c = {n: float(np.mean(v)) for n, v in agg[k].items()}
+        us = c["_us"]
+        g = c.get
+        cyc = simds * us * clk
+
+        def ratio(a, b):
+            return f"{a / b:.2f}" if a is not None and b else ""
+        md.append(f"| `{k}` | {us:.1f} | {g('SQ_INSTS_VALU', 0):.3g} | {ratio(4 * g('SQ_INSTS_VALU', 0), cyc)} | "
+                  f"{g('SQ_INSTS_MFMA', 0):.3g} | {ratio(g('SQ_VALU_MFMA_BUSY_CYCLES'), cyc)} | "
+                  f"{g('SQ_INSTS_LDS', 0):.3g} | {ratio(g('SQ_INSTS_LDS'), g('SQ_INSTS_VALU'))} | "
+                  f"{ratio(g('SQ_LDS_BANK_CONFLICT'), g('SQ_ACTIVE_INST_LDS'))} | "
+                  f"{ratio(g('SQ_WAIT_INST_LDS'), g('SQ_WAVE_CYCLES'))} | "
+                  f"{ratio(g('SQ_WAIT_INST_ANY'), g('SQ_WAVE_CYCLES'))} |")
+    with open(os.path.join(ROOT, "profiles", "sq_counters.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print(f"wrote profiles/sq_counters.md ({len(agg)} kernels)")
+
+
 def main():
     a = parse()
+    if a.write_counter_summary:
+        write_counter_summary(a.write_counter_summary)
+        return
+    if a.write_trace_summary:
+        write_trace_summary(*a.write_trace_summary)
+        return
     if a.write_traffic:
         write_traffic(*a.write_traffic, side=a.side)
         return
