@@ -822,11 +822,19 @@ constexpr int GWM_T = 64;
 // PX: step st of a row takes pixels st, 16 + st, 32 + st, 48 + st (k = pixel / 16) instead of
 // 4 st .. 4 st + 3, so each lane's 16 gy values of a row are 16 consecutive pixels, read as four
 // 16-byte vectors; the products are the same, summed in another order.
-template <int R, int TY, bool PX = false>
+// TAIL (for (2r+1)^2 = 1 mod 16, r = 3 and 4): the last tap, alone in its 16-tap block, is summed
+// by each lane with vector FMAs after each row's products (its own gy times the row's x at that
+// tap, four 16-byte LDS reads where aligned) instead of a block of matrix products that is 15/16
+// padding, and its four pixel groups are added with two cross-lane shuffles.  At four waves per
+// SIMD the edge strips' per-step column offsets go to scratch (52 bytes per lane at r = 4,
+// reloaded only on the scalar edge path).
+template <int R, int TY, bool PX = false, bool TAIL = false>
 __global__ __launch_bounds__(256, 4) void bank_bwd_wm_k(const float* __restrict__ gy, const float* __restrict__ x,
                                                      float* __restrict__ part, int F, int H, int W, int tiles_x,
                                                      int tiles_img, int ntiles) {
     constexpr int N = 2 * R + 1, NK = N * N, NT = (NK + 15) / 16;
+    constexpr bool TV = TAIL && NK % 16 == 1;
+    constexpr int NTM = TV ? NT - 1 : NT;   // 16-tap blocks on the matrix cores
     constexpr int RA = (R + 3) & ~3, LWS = GWM_T + 2 * RA, LW = LWS + 8, NR = GWM_T + 2 * R;
     constexpr int S_FLOATS = NR * LW, RED_FLOATS = 4 * 16 * NT * 16;
     __shared__ __attribute__((aligned(16))) float s[S_FLOATS > RED_FLOATS ? S_FLOATS : RED_FLOATS];
@@ -848,9 +856,11 @@ __global__ __launch_bounds__(256, 4) void bank_bwd_wm_k(const float* __restrict_
         const int k = min(16 * t + fl, NK - 1);
         off[t] = (k / N) * LW + (k % N) + RA - R;
     }
-    v4f acc[NT];
+    v4f acc[NTM];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = mk4(0.f, 0.f, 0.f, 0.f);
+    for (int t = 0; t < NTM; ++t) acc[t] = mk4(0.f, 0.f, 0.f, 0.f);
+    constexpr int OFFL = ((NK - 1) / N) * LW + (NK - 1) % N + RA - R;   // the last tap's LDS offset
+    float accl = 0.f;
     // a row's 16 x 4 gy values; pixels outside the image (and filters past F) contribute 0.
     // The load itself always reads a valid (clamped) address, so no lane branches around it.
     const bool vec = (W & 3) == 0 && ((uintptr_t)gy & 15) == 0;
@@ -884,6 +894,22 @@ __global__ __launch_bounds__(256, 4) void bank_bwd_wm_k(const float* __restrict_
     };
     // LDS column of step st's pixel for this lane
     auto pcol = [&](int st) { return PX ? 16 * q + st : 4 * st + q; };
+    // the last tap over a row's 16 steps: with pixel-strided steps its 16 x values are
+    // consecutive, read as four 16-byte vectors where the offset allows
+    auto tail = [&](int py, const float (&g)[16]) {
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (PX && (LW % 4 == 0) && (OFFL % 4 == 0)) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const v4f v = lds4(&s[py * LW + 16 * q + OFFL + 4 * m]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) accl = fmaf(g[4 * m + e], v[e], accl);
+            }
+        } else {
+#pragma unroll
+            for (int st = 0; st < 16; ++st) accl = fmaf(g[st], s[py * LW + pcol(st) + OFFL], accl);
+        }
+    };
     for (int sub = 0; sub < TY; ++sub) {
         const int ys = y0 + sub * GWM_T;
         if (ys >= H) break;   // uniform over the work-group
@@ -907,26 +933,34 @@ __global__ __launch_bounds__(256, 4) void bank_bwd_wm_k(const float* __restrict_
             for (int st = 0; st < 16; ++st) {
                 const int base = py * LW + pcol(st);
 #pragma unroll
-                for (int t = 0; t < NT; ++t)
+                for (int t = 0; t < NTM; ++t)
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[st], s[base + off[t]], acc[t], 0, 0, 0);
             }
+            if constexpr (TV) tail(py, ga);
             if (row + 2 < 16) gy_row(ys + py + 2, ga);
 #pragma unroll
             for (int st = 0; st < 16; ++st) {
                 const int base = (py + 1) * LW + pcol(st);
 #pragma unroll
-                for (int t = 0; t < NT; ++t)
+                for (int t = 0; t < NTM; ++t)
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gb[st], s[base + off[t]], acc[t], 0, 0, 0);
             }
+            if constexpr (TV) tail(py + 1, gb);
         }
     }
     // lane holds D[4 (lane / 16) + i][16 t + lane % 16] in acc[t][i]; the tile's products are
     // done (the barrier) before its LDS takes the partial sums
+    if constexpr (TV) {   // lane (filter fl, pixel group q): add the four pixel groups
+        accl += __shfl_xor(accl, 16, 64);
+        accl += __shfl_xor(accl, 32, 64);
+    }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < NTM; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i) red[wave][4 * q + i][16 * t + fl] = acc[t][i];
+    if constexpr (TV)
+        if (q == 0) red[wave][fl][NK - 1] = accl;
     __syncthreads();
     for (int e = threadIdx.x; e < 16 * NK; e += 256) {
         const int f = e / NK, k = e - f * NK;
@@ -936,12 +970,12 @@ __global__ __launch_bounds__(256, 4) void bank_bwd_wm_k(const float* __restrict_
     }
 }
 
-template <int R, int TY, bool PX = false>
+template <int R, int TY, bool PX = false, bool TAIL = false>
 hipError_t bwd_wm_RT(const BankArgs& a) {
     const int tx = (a.w + GWM_T - 1) / GWM_T, ty = (a.h + GWM_T * TY - 1) / (GWM_T * TY);
     const int ntiles = a.n * tx * ty;
     float* part = static_cast<float*>(a.ws);
-    hipLaunchKernelGGL((bank_bwd_wm_k<R, TY, PX>), dim3((unsigned)ntiles), dim3(256), 0, a.st, a.a, a.b, part, a.f, a.h,
+    hipLaunchKernelGGL((bank_bwd_wm_k<R, TY, PX, TAIL>), dim3((unsigned)ntiles), dim3(256), 0, a.st, a.a, a.b, part, a.f, a.h,
                        a.w, tx, tx * ty, ntiles);
     const int nk = (2 * R + 1) * (2 * R + 1);
     hipLaunchKernelGGL(bank_bwd_w2_k, dim3((unsigned)(a.f * nk)), dim3(256), 0, a.st, part, a.out, ntiles, a.scale);
@@ -1056,12 +1090,15 @@ template <int R>
 hipError_t bwd_wmp_R(const BankArgs& a) { return bwd_wm_RT<R, 1, true>(a); }
 template <int R>
 hipError_t bwd_wmp4_R(const BankArgs& a) { return bwd_wm_RT<R, 4, true>(a); }
+template <int R>
+hipError_t bwd_wmpt4_R(const BankArgs& a) { return bwd_wm_RT<R, 4, true, true>(a); }
 
 hipError_t launch_bwd_w4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_w4_R) }
 hipError_t launch_bwd_wm(const BankArgs& a) { ICL_BANK_SWITCH(bwd_wm_R) }
 hipError_t launch_bwd_wm4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_wm4_R) }
 hipError_t launch_bwd_wmp(const BankArgs& a) { ICL_BANK_SWITCH(bwd_wmp_R) }
 hipError_t launch_bwd_wmp4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_wmp4_R) }
+hipError_t launch_bwd_wmpt4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_wmpt4_R) }
 hipError_t launch_bwd_w4x4(const BankArgs& a) { ICL_BANK_SWITCH(bwd_w4x4_R) }
 
 
@@ -1082,7 +1119,8 @@ const Variant<BankArgs> kBwdW[] = {{"wave_t32x64", supports_bwd_w, launch_bwd_w}
                                    {"mfma_t64", supports_bwd_wm, launch_bwd_wm},
                                    {"mfma_t64x256", supports_bwd_wm, launch_bwd_wm4},
                                    {"mfma_px_t64", supports_bwd_wm, launch_bwd_wmp},
-                                   {"mfma_px_t64x256", supports_bwd_wm, launch_bwd_wmp4}};
+                                   {"mfma_px_t64x256", supports_bwd_wm, launch_bwd_wmp4},
+                                   {"mfma_px_tail_t64x256", supports_bwd_wm, launch_bwd_wmpt4}};
 
 // ------------------------------------------------------------------ forward on the matrix cores
 // y[f][p] = sum_k w[f][k] x[p + off(k)]: filters as rows, pixels as columns, taps as the
@@ -1504,7 +1542,7 @@ const Variant<BankArgs>* bank_bwd_filter_variants(int* count) {
 
 int bank_fwd_default(const BankArgs& a) { return supports_mfma16(a) ? 4 : supports_pers(a) ? 2 : 1; }   // mfma_px_t64
 int bank_bwd_input_default(const BankArgs& a) { return supports_pers(a) ? 2 : 1; }
-int bank_bwd_filter_default(const BankArgs& a) { return a.f <= 16 ? 6 : 2; }   // mfma_px_t64x256, else block4_t64x256
+int bank_bwd_filter_default(const BankArgs& a) { return a.f <= 16 ? 7 : 2; }   // mfma_px_tail_t64x256, else block4_t64x256
 const Variant<BankSseArgs>* bank_fwd_sse_variants(int* count) {
     *count = (int)(sizeof(kFwdSse) / sizeof(kFwdSse[0]));
     return kFwdSse;
