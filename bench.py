@@ -161,9 +161,10 @@ def write_traffic(fetch_csv, write_csv, side=4096):
                      "dispatch, mean over dispatches), each scaled by the factor that maps the same counter on a "
                      "1 GiB device-to-device copy to 1 GiB; source_hash covers the kernel's source files and "
                      "bench.py reports traffic only while it matches.",
-           "commands": [f"rocprofv3 --pmc {ctr} --output-format csv -d {os.path.dirname(csv_path)} -o {tag} -- "
+           "commands": [f"rocprofv3 --pmc {ctr} --output-format csv -d {os.path.dirname(csv_path)} -o "
+                        f"{os.path.basename(csv_path).split('_counter_collection')[0]} -- "
                         "python3 bench.py --steps 3 --warmup 1 --no-extras --no-cpu --calib-copy"
-                        for ctr, csv_path, tag in (("FETCH_SIZE", fetch_csv, "fetch"), ("WRITE_SIZE", write_csv, "write"))],
+                        for ctr, csv_path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv))],
            "calibration": {"fetch_factor": round(fcal, 4), "write_factor": round(wcal, 4),
                            "copy_fetch_kib": [round(v, 1) for v in cf], "copy_write_kib": [round(v, 1) for v in cw]}}
     for k in fe:
@@ -179,7 +180,23 @@ def write_traffic(fetch_csv, write_csv, side=4096):
     path = os.path.join(ROOT, "profiles", "traffic.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
-    print(f"wrote {path}")
+    md = [f"# HBM traffic per launch: the {side}x{side} float32 sweep, every variant the tuner times", "",
+          "Commands (repository root, one MI355X), one counter per pass:", "", "```", *out["commands"],
+          f"python3 bench.py --write-traffic {fetch_csv} {write_csv}", "```", "",
+          f"Calibration on the same runs: three 1 GiB device-to-device copies read FETCH_SIZE = "
+          f"{np.mean(cf):.0f} KiB and WRITE_SIZE = {np.mean(cw):.0f} KiB per dispatch, so FETCH_SIZE is scaled by "
+          f"{fcal:.4f} and WRITE_SIZE by {wcal:.4f}.  Algorithmic bytes per launch: {alg // 2:,} B read + "
+          f"{alg // 2:,} B written.  The mean is over every dispatch of the kernel in the run (the tuner's "
+          "timing launches and the timed steps).", "",
+          "| call:variant | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | HBM bytes / launch | / algorithmic |",
+          "|---|---|---|---|---|"]
+    for k, v in out.items():
+        if isinstance(v, dict) and "ratio" in v:
+            md.append(f"| {k} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | {v['bytes_per_launch']:,} | "
+                      f"{v['ratio']:.3f} |")
+    with open(os.path.join(ROOT, "profiles", f"hbm_traffic_sweep_{side}_f32.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print(f"wrote {path} and profiles/hbm_traffic_sweep_{side}_f32.md")
 
 
 # Kernels of the extra workloads whose HBM traffic is summarised: (workload, symbol pattern, label,
@@ -207,7 +224,8 @@ WORKLOAD_KERNELS = [
      4 * (_BANK[0] * _BANK[2] + 2 * _BANK[0] * _BANK[1] * _BANK[2])),
     ("bank", r"bank_bwd_in_(pers_k|k)<4>", "bwd_input:{0}", ["bank.hip"],
      4 * (_BANK[0] * _BANK[1] * _BANK[2] + _BANK[0] * _BANK[2])),
-    ("bank", r"bank_bwd_(wm_k<4, \d, (?:true|false)>|w4_k<4, \d, 16>)", "bwd_filter:{0}", ["bank.hip"],
+    ("bank", r"bank_bwd_(wm_k<4, \d, (?:true|false)(?:, (?:true|false))?>|w4_k<4, \d, 16>)", "bwd_filter:{0}",
+     ["bank.hip"],
      4 * (_BANK[0] * _BANK[1] * _BANK[2] + _BANK[0] * _BANK[2])),
     ("paper", r"sep_(fused|pers)<icl::F32, 2, (\d+), (\d+)>", "sep5_constant:{0}_t{1}_c{2}",
      KERNEL_SOURCES["sep"], 8 * 4096 * 4096),
@@ -394,7 +412,7 @@ SQ_PASSES = {"A": "SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU SQ_ACTIV
 SQ_RUNS = {"sweep": "--steps 3 --warmup 1 --no-extras --no-cpu", "bank": "--only bank --steps 4 --warmup 1 --no-cpu",
            "batch": "--only batch --steps 4 --warmup 1 --no-cpu", "corner": "--only corner --steps 4 --warmup 1 --no-cpu"}
 SQ_KERNELS = (r"conv2d_pers<F32, [1-7], ", r"sep_(fused|pers)<F32, [1-7], ", r"bank_(fwd_mfma_k<4, true, 0, true>|"
-              r"bwd_in_pers_k<4>|bwd_wm_k<4, 4, true>)", r"sep_batched_col_k<F16, 1, 64>", r"harris_stream<2, 16>",
+              r"bwd_in_pers_k<4>|bwd_wm_k<4, 4, true, (?:true|false)>)", r"sep_batched_col_k<F16, 1, 64>", r"harris_stream<2, 16>",
               r"nms_stream_a<4, false>", r"corners_stream<2, 12, 1>")
 
 
