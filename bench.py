@@ -319,7 +319,7 @@ def _short_kernel(name):
     return re.sub(r"\s+", " ", n[:cut]).strip()
 
 
-def write_trace_summary(trace_dir, bench_json):
+def write_trace_summary(trace_dir, bench_json, out_dir=None):
     """Kernel-trace summaries of one profiled default bench run: the sweep's calls (trace means of the
     timed dispatches beside bench.py's event means) and every kernel of the extra workloads."""
     import csv
@@ -373,7 +373,8 @@ def write_trace_summary(trace_dir, bench_json):
     if dom:
         md += ["", f"Roofline kernel ({dom[0]}:{dom[1]}): {dom[2]:.2f} us per timed dispatch in the trace against "
                    f"bench.py's event-timed {dom[3]} us per launch."]
-    with open(os.path.join(ROOT, "profiles", "kernel_trace_sweep_4096_f32.md"), "w") as fh:
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    with open(os.path.join(out_dir, "kernel_trace_sweep_4096_f32.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
     rows = sorted(csv.DictReader(open(stats)), key=lambda r: _short_kernel(r["Name"]))
     torch_rows = [r for r in rows if r["Name"].startswith("at::") or r["Name"].startswith("void at::")]
@@ -399,9 +400,9 @@ def write_trace_summary(trace_dir, bench_json):
         if k == "filter_bank_fwd_bwd":
             var = ", ".join(f"{p}: {q['variant']} {q['ms']} ms" for p, q in v.get("phases", {}).items())
         md.append(f"| {k} | {t} | {var} |")
-    with open(os.path.join(ROOT, "profiles", "kernel_trace_workloads.md"), "w") as fh:
+    with open(os.path.join(out_dir, "kernel_trace_workloads.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
-    print("wrote profiles/kernel_trace_sweep_4096_f32.md and profiles/kernel_trace_workloads.md")
+    print(f"wrote kernel_trace_sweep_4096_f32.md and kernel_trace_workloads.md in {out_dir}")
 
 
 # SQ counter passes (at most 8 SQ counters each) and the bench runs they profile
@@ -416,7 +417,7 @@ SQ_KERNELS = (r"conv2d_pers<F32, [1-7], ", r"sep_(fused|pers)<F32, [1-7], ", r"b
               r"nms_stream_a<4, false>", r"corners_stream<2, 12, 1>")
 
 
-def write_counter_summary(dirs):
+def write_counter_summary(dirs, out_dir=None):
     """Per-kernel SQ counter ratios from rocprofv3 --pmc passes (directories named sq{pass}_{run})."""
     import collections
     import csv
@@ -462,9 +463,9 @@ def write_counter_summary(dirs):
                   f"{ratio(g('SQ_LDS_BANK_CONFLICT'), g('SQ_ACTIVE_INST_LDS'))} | "
                   f"{ratio(g('SQ_WAIT_INST_LDS'), g('SQ_WAVE_CYCLES'))} | "
                   f"{ratio(g('SQ_WAIT_INST_ANY'), g('SQ_WAVE_CYCLES'))} |")
-    with open(os.path.join(ROOT, "profiles", "sq_counters.md"), "w") as fh:
+    with open(os.path.join(out_dir or os.path.join(ROOT, "profiles"), "sq_counters.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
-    print(f"wrote profiles/sq_counters.md ({len(agg)} kernels)")
+    print(f"wrote sq_counters.md in {out_dir or os.path.join(ROOT, 'profiles')} ({len(agg)} kernels)")
 
 
 def main():
