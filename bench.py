@@ -331,9 +331,10 @@ def write_trace_summary(trace_dir, bench_json, out_dir=None):
     stats = glob.glob(os.path.join(trace_dir, "*kernel_stats.csv"))[0]
     disp = [(r["Kernel_Name"], (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
             for r in csv.DictReader(open(trace))]
-    prof = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/kt -o kt -- "
-            "python3 bench.py --no-cpu > gpurun_out/kt_bench.json")
-    summ = "python3 bench.py --write-trace-summary gpurun_out/kt gpurun_out/kt_bench.json"
+    tag = os.path.basename(trace).split("_kernel_trace")[0]
+    prof = (f"rocprofv3 --kernel-trace --stats --output-format csv -d {trace_dir} -o {tag} -- "
+            f"python3 bench.py --no-cpu > {bench_json}")
+    summ = f"python3 bench.py --write-trace-summary {trace_dir} {bench_json}"
     md = ["# Kernel trace: convolution sweep 4096x4096 float32", "",
           "Commands (repository root, one MI355X):", "", "```", prof, summ, "```", "",
           f"The profiled run is the default bench (tuning, {d['warmup']} warmup and {steps} timed steps, the "
@@ -432,12 +433,16 @@ def write_counter_summary(dirs, out_dir=None):
                     continue
                 agg[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
                 agg[k]["_us"].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-    cmds = [f"rocprofv3 --pmc {ctrs} --output-format csv -d gpurun_out/sq{ps}_{run} -o sq -- python3 bench.py {args}"
-            for ps, ctrs in SQ_PASSES.items() for run, args in SQ_RUNS.items()]
+    # one run per directory, named sq<pass>_<run> (a pass of SQ_PASSES over a run of SQ_RUNS)
+    cmds = []
+    for dd in dirs:
+        ps, _, run = os.path.basename(os.path.normpath(dd))[2:].partition("_")
+        if ps in SQ_PASSES and run in SQ_RUNS:
+            cmds.append(f"rocprofv3 --pmc {SQ_PASSES[ps]} --output-format csv -d {dd} -o sq -- "
+                        f"python3 bench.py {SQ_RUNS[run]}")
     md = ["# SQ counters: what the main kernels spend their time on", "", "Commands (repository root, one MI355X), one "
           "pass of at most eight SQ counters per run:", "", "```", *cmds,
-          "python3 bench.py --write-counter-summary " + " ".join(f"gpurun_out/sq{ps}_{run}" for ps in SQ_PASSES
-                                                                  for run in SQ_RUNS), "```", "",
+          "python3 bench.py --write-counter-summary " + " ".join(dirs), "```", "",
           "Per kernel, the mean per dispatch over every dispatch of the profiled runs (the tuner's included).  "
           "Ratios: `valu/cyc` = VALU instructions x 4 / (SIMD count x kernel cycles at 2.4 GHz), the share of "
           "the vector units' issue a wave64 FP32 instruction takes at 16 lanes a cycle (over 1 where some "

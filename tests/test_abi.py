@@ -253,7 +253,7 @@ def test_batch_plan_validation(no_gpu):
 
 
 def test_no_device_or_launch_path(L):
-    """A valid call either reports that no GPU is visible (CPU container) or succeeds (GPU machine)."""
+    """A valid call either reports that no GPU is visible or succeeds (a GPU is present)."""
     import torch
     if torch.cuda.is_available():
         pytest.skip("GPU present: compute calls are covered by the gpu tests")
