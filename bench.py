@@ -412,10 +412,11 @@ SQ_PASSES = {"A": "SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU SQ_ACTIV
              "B": "SQ_INSTS_LDS SQ_ACTIVE_INST_LDS SQ_WAIT_INST_LDS SQ_LDS_BANK_CONFLICT SQ_WAIT_INST_ANY "
                   "SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_WAVE_CYCLES"}
 SQ_RUNS = {"sweep": "--steps 3 --warmup 1 --no-extras --no-cpu", "bank": "--only bank --steps 4 --warmup 1 --no-cpu",
-           "batch": "--only batch --steps 4 --warmup 1 --no-cpu", "corner": "--only corner --steps 4 --warmup 1 --no-cpu"}
+           "batch": "--only batch --steps 4 --warmup 1 --no-cpu", "corner": "--only corner --steps 4 --warmup 1 --no-cpu",
+           "paper": "--only paper --steps 4 --warmup 1 --no-cpu"}
 SQ_KERNELS = (r"conv2d_pers<F32, [1-7], ", r"sep_(fused|pers)<F32, [1-7], ", r"bank_(fwd_mfma_k<4, true, 0, true>|"
               r"bwd_in_pers_k<4>|bwd_wm_k<4, 4, true, (?:true|false)>)", r"sep_batched_col_k<F16, 1, 64>", r"harris_stream<2, 16>",
-              r"nms_stream_a<4, false>", r"corners_stream<2, 12, 1>")
+              r"nms_stream_a<4, false>", r"corners_stream<2, 12, 1>", r"u8_strip<2, \d+, \d>")
 
 
 def write_counter_summary(dirs, out_dir=None):
