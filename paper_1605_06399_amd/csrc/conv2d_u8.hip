@@ -107,14 +107,17 @@ template <int PX> struct RowWords { uint32_t w[PX / 4]; };
 // r + 1 packed dot products against tap pairs (taps[j][t], taps[j][t+1]) aligned to its
 // column parity.  The sums start from the rounding bias, so the output is
 // med3(acc >> shift, 0, 255).
-template <int R, int TH, int PX, bool EDGE>
+// QD > 0: QD input rows in flight ahead instead of the default eight (the _q16 variants hold
+// all but a few rows of a short strip in flight from its start).
+template <int R, int TH, int PX, bool EDGE, int QD = 0>
 __device__ __forceinline__ void u8_strip_body(const uint8_t* __restrict__ src, size_t sp, uint8_t* __restrict__ dst,
                                               size_t dp, int W, int H, const int* __restrict__ tw, int shift,
                                               int bias, int c, int y0, int cmode, int cval) {
     using G = U8Strip<R, PX>;
     constexpr int HL = G::HL, NWL = G::NWL, NW = G::NW, OFF = G::OFF, D = G::D;
     constexpr int K = TH + 2 * R;
-    constexpr int Q = K < G::Q ? K : G::Q;
+    constexpr int QQ = QD > 0 ? QD : G::Q;
+    constexpr int Q = K < QQ ? K : QQ;
     const int lane = threadIdx.x & 63;
     const uint32_t cword = (uint32_t)cval * 0x01010101u;
 
@@ -221,7 +224,7 @@ __device__ __forceinline__ void u8_strip_body(const uint8_t* __restrict__ src, s
     });
 }
 
-template <int R, int TH, int PX>
+template <int R, int TH, int PX, int QD = 0>
 __global__ __launch_bounds__(64) void u8_strip(const uint8_t* __restrict__ src, size_t sp, uint8_t* __restrict__ dst,
                                                size_t dp, int W, int H, const int16_t* __restrict__ taps, int shift,
                                                int nstrips, int vec, int cmode, int cval) {
@@ -247,12 +250,12 @@ __global__ __launch_bounds__(64) void u8_strip(const uint8_t* __restrict__ src, 
     const int bias = shift > 0 ? 1 << (shift - 1) : 0;
     const bool interior = vec && x0 >= 0 && x0 + 64 * PX <= W;
     if (interior)
-        u8_strip_body<R, TH, PX, false>(src, sp, dst, dp, W, H, tw, shift, bias, c, y0, cmode, cval);
+        u8_strip_body<R, TH, PX, false, QD>(src, sp, dst, dp, W, H, tw, shift, bias, c, y0, cmode, cval);
     else
-        u8_strip_body<R, TH, PX, true>(src, sp, dst, dp, W, H, tw, shift, bias, c, y0, cmode, cval);
+        u8_strip_body<R, TH, PX, true, QD>(src, sp, dst, dp, W, H, tw, shift, bias, c, y0, cmode, cval);
 }
 
-template <int R, int TH, int PX>
+template <int R, int TH, int PX, int QD = 0>
 hipError_t launch_strip_R(const U8Args& a) {
     using G = U8Strip<R, PX>;
     const int nstrips = (a.W + G::SW - 1) / G::SW;
@@ -261,21 +264,21 @@ hipError_t launch_strip_R(const U8Args& a) {
     // interior strips use PX-byte vector loads and stores: both images' rows must be aligned
     const int vec = ((uintptr_t)a.src % PX == 0) && (a.sp % PX == 0) && ((uintptr_t)a.dst % PX == 0) &&
                     (a.dp % PX == 0);
-    hipLaunchKernelGGL((u8_strip<R, TH, PX>), dim3((unsigned)blocks), dim3(64), 0, a.st, a.src, a.sp, a.dst, a.dp,
+    hipLaunchKernelGGL((u8_strip<R, TH, PX, QD>), dim3((unsigned)blocks), dim3(64), 0, a.st, a.src, a.sp, a.dst, a.dp,
                        a.W, a.H, a.taps, a.shift, nstrips, vec, a.cmode, a.cval);
     return hipGetLastError();
 }
 
 constexpr int U8_STRIP_MAX_R = 4;
 
-template <int TH, int PX>
+template <int TH, int PX, int QD = 0>
 hipError_t launch_strip(const U8Args& a) {
     switch (a.r) {
-        case 0: return launch_strip_R<0, TH, PX>(a);
-        case 1: return launch_strip_R<1, TH, PX>(a);
-        case 2: return launch_strip_R<2, TH, PX>(a);
-        case 3: return launch_strip_R<3, TH, PX>(a);
-        case 4: return launch_strip_R<4, TH, PX>(a);
+        case 0: return launch_strip_R<0, TH, PX, QD>(a);
+        case 1: return launch_strip_R<1, TH, PX, QD>(a);
+        case 2: return launch_strip_R<2, TH, PX, QD>(a);
+        case 3: return launch_strip_R<3, TH, PX, QD>(a);
+        case 4: return launch_strip_R<4, TH, PX, QD>(a);
         default: return hipErrorInvalidValue;
     }
 }
@@ -289,6 +292,8 @@ const Variant<U8Args> kConv2dU8[] = {
     {"strip_p8_t16", supports_strip, launch_strip<16, 8>},
     {"strip_p8_t32", supports_strip, launch_strip<32, 8>},
     {"strip_p4_t24", supports_strip, launch_strip<24, 4>},
+    {"strip_p4_t16_q16", supports_strip, launch_strip<16, 4, 16>},
+    {"strip_p4_t12_q16", supports_strip, launch_strip<12, 4, 16>},
 };
 
 }  // namespace

@@ -204,7 +204,7 @@ def u8_supports(variant, r):
     return name == "plain" or r <= 4
 
 
-@pytest.mark.parametrize("variant", range(8))
+@pytest.mark.parametrize("variant", range(12))
 @pytest.mark.parametrize("r", [0, 1, 2, 3, 4, 5, 7])
 def test_conv2d_u8_variants_bit_exact(force, variant, r):
     if variant >= B.icl_variant_count(B.ICL_OP_CONV2D_U8):
