@@ -229,7 +229,7 @@ WORKLOAD_KERNELS = [
      4 * (_BANK[0] * _BANK[1] * _BANK[2] + _BANK[0] * _BANK[2])),
     ("paper", r"sep_(fused|pers)<icl::F32, 2, (\d+), (\d+)>", "sep5_constant:{0}_t{1}_c{2}",
      KERNEL_SOURCES["sep"], 8 * 4096 * 4096),
-    ("paper", r"u8_strip<2, (\d+), (\d+)>", "u8_5x5:strip_p{1}_t{0}", ["conv2d_u8.hip", "icl_device.hpp"],
+    ("paper", r"u8_strip<2, (\d+), (\d+), (\d+)>", "u8_5x5:strip_p{1}_t{0}_q{2}", ["conv2d_u8.hip", "icl_device.hpp"],
      2 * 8192 * 8192),
     ("volume", r"sep3_stream<icl::F32, (\d+), (\d+)>", "sep3d_r{0}:stream_z{1}", ["conv3d.hip", "icl_device.hpp"],
      8 * 256 ** 3),
@@ -416,7 +416,7 @@ SQ_RUNS = {"sweep": "--steps 3 --warmup 1 --no-extras --no-cpu", "bank": "--only
            "paper": "--only paper --steps 4 --warmup 1 --no-cpu"}
 SQ_KERNELS = (r"conv2d_pers<F32, [1-7], ", r"sep_(fused|pers)<F32, [1-7], ", r"bank_(fwd_mfma_k<4, true, 0, true>|"
               r"bwd_in_pers_k<4>|bwd_wm_k<4, 4, true, (?:true|false)>)", r"sep_batched_col_k<F16, 1, 64>", r"harris_stream<2, 16>",
-              r"nms_stream_a<4, false>", r"corners_stream<2, 12, 1>", r"u8_strip<2, \d+, \d>")
+              r"nms_stream_a<4, false>", r"corners_stream<2, 12, 1>", r"u8_strip<2, \d+, \d+, \d+>")
 
 
 def write_counter_summary(dirs, out_dir=None):
