@@ -28,6 +28,7 @@ def _nvariants(op, default):
 
 N_SEP = _nvariants(B.ICL_OP_CONV_SEP, 16)
 N_2D = _nvariants(B.ICL_OP_CONV2D, 16)
+N_U8 = _nvariants(B.ICL_OP_CONV2D_U8, 8)
 SHAPES = [(389, 517), (1, 1), (1, 70), (70, 1), (3, 5), (64, 64), (33, 200)]
 CONSTANTS = [0.0, 0.37, -2.5]
 
@@ -204,7 +205,7 @@ def u8_supports(variant, r):
     return name == "plain" or r <= 4
 
 
-@pytest.mark.parametrize("variant", range(12))
+@pytest.mark.parametrize("variant", range(N_U8))
 @pytest.mark.parametrize("r", [0, 1, 2, 3, 4, 5, 7])
 def test_conv2d_u8_variants_bit_exact(force, variant, r):
     if variant >= B.icl_variant_count(B.ICL_OP_CONV2D_U8):
