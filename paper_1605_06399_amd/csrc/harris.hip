@@ -395,6 +395,7 @@ const Variant<HarrisArgs> kHarris[] = {
     {"stream_t64", supports_stream, launch_stream<64>},
     {"stream_t32", supports_stream, launch_stream<32>},
     {"stream_t16", supports_stream, launch_stream<16>},
+    {"stream_t12", supports_stream, launch_stream<12>},
 };
 
 }  // namespace
