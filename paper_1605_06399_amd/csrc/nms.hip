@@ -235,13 +235,15 @@ __global__ __launch_bounds__(256) void nms_stream_a(const float* __restrict__ R,
     uint8_t* out = M + x0 + 4 * lane;
     if (y0 >= 1 && y0 + TH <= H - 1) {
         // interior: output row m reads rows y0 - 1 + m + {0, 1, 2} from a ring of RING rows
-        // (row i of the block in slot i mod RING), each loaded RING - 2 rows before use
-        constexpr int RING = 8;
+        // (row i of the block in slot i mod RING), each loaded RING - 2 rows before use; a
+        // block of fewer than RING - 2 rows loads only its TH + 2 rows (the rows after them
+        // may lie past the image)
+        constexpr int RING = 8, NPRE = TH + 2 < RING ? TH + 2 : RING;
         const int ybase = y0 - 1;
         v4f ring[RING];
         float el[RING], er[RING];
 #pragma unroll
-        for (int i = 0; i < RING; ++i) {
+        for (int i = 0; i < NPRE; ++i) {
             ring[i] = row(ybase + i);
             el[i] = px(ybase + i, xl);
             er[i] = px(ybase + i, xr);
